@@ -1,0 +1,321 @@
+"""FP64 oracle of the render path -- TEST INFRASTRUCTURE ONLY.
+
+Plain PyTorch CPU operations in float64, written from the paper's equations
+with no blocking or fusion.  Gradients of this forward (through
+``torch.autograd``) are the reference gradients; finite differences of the
+same forward pin them.  Only ``tests/``, the smoke check and the CPU baseline
+of the benchmark use this module.
+
+Integer decisions whose FP32 result is compared bit for bit (the back-face
+flag, tile lists) come from the FP32 mirror in ``rga_oracle.c``; this module
+takes the back-face flag as an input so that both oracles agree on which
+Gaussians exist.
+"""
+
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+f64 = torch.float64
+
+
+def t64(a) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        return a.to(f64)
+    return torch.as_tensor(np.asarray(a), dtype=f64)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1, deformation: forward linear blend skinning.
+# x' = sum_j w_j (R_j x + t_j); the linear part A = sum_j w_j R_j carries the
+# normal (n' = A n) and the covariance factor (A R S).
+# ---------------------------------------------------------------------------
+def lbs(skin, jidx, jw, x, nrm=None):
+    """skin [J,12] (rows [R|t]); jidx, jw [4,n]; x, nrm [3,n] -> x', n', A [9,n]."""
+    S = t64(skin).reshape(-1, 3, 4)
+    jidx = torch.as_tensor(np.asarray(jidx), dtype=torch.long)
+    jw = t64(jw)
+    x = t64(x) if not isinstance(x, torch.Tensor) else x
+    Rsel = S[jidx][..., :3]                      # [4,n,3,3]
+    tsel = S[jidx][..., 3]                       # [4,n,3]
+    A = torch.einsum("jn,jnab->nab", jw, Rsel)   # [n,3,3]
+    t = torch.einsum("jn,jna->na", jw, tsel)     # [n,3]
+    xp = torch.einsum("nab,bn->an", A, x) + t.T
+    npr = None
+    if nrm is not None:
+        npr = torch.einsum("nab,bn->an", A, nrm)
+    return xp, npr, A.reshape(-1, 9).T
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1: the environment map is a lat-long grid of He x We area lights.
+# Texel (r, c): polar angle (r + 1/2) pi / He from +Y, azimuth (c + 1/2) 2 pi / We;
+# its area A is the exact solid angle of the texel.
+# ---------------------------------------------------------------------------
+def env_geometry(he: int, we: int):
+    r = torch.arange(he, dtype=f64)
+    c = torch.arange(we, dtype=f64)
+    th = (r + 0.5) * math.pi / he
+    ph = (c + 0.5) * 2.0 * math.pi / we
+    TH, PH = torch.meshgrid(th, ph, indexing="ij")
+    dirs = torch.stack([torch.sin(TH) * torch.sin(PH), torch.cos(TH),
+                        torch.sin(TH) * torch.cos(PH)], dim=-1).reshape(-1, 3)
+    band = (2.0 * math.pi / we) * (torch.cos(r * math.pi / he) - torch.cos((r + 1) * math.pi / he))
+    solid = band[:, None].expand(he, we).reshape(-1)
+    return dirs, solid
+
+
+def texel_view(he: int, we: int, hv: int, wv: int) -> torch.Tensor:
+    """View used for texel (r, c) when the visibility views form a coarser
+    Hv x Wv lat-long grid that divides the He x We map."""
+    r = torch.arange(he)[:, None].expand(he, we)
+    c = torch.arange(we)[None, :].expand(he, we)
+    return ((r * hv) // he * wv + (c * wv) // we).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# App. A: simplified Disney BRDF (Karis' real-time forms).
+# ---------------------------------------------------------------------------
+F0 = 0.04
+
+
+def ggx_d(nh, alpha):
+    a2 = alpha * alpha
+    return a2 / (math.pi * (nh * nh * (a2 - 1.0) + 1.0) ** 2)
+
+
+def fresnel(oh):
+    return F0 + (1.0 - F0) * torch.pow(torch.as_tensor(2.0, dtype=f64),
+                                       (-5.55473 * oh - 6.98316) * oh)
+
+
+def smith_g1(x, k):
+    return x / (x * (1.0 - k) + k)
+
+
+def brdf(wi, wo, n, albedo, gamma, tint):
+    """R(w_i, w_o, n) of App. A for unit vectors [...,3]; albedo [...,3]."""
+    h = wi + wo
+    h = h / torch.linalg.norm(h, dim=-1, keepdim=True)
+    ci = (n * wi).sum(-1)
+    co = (n * wo).sum(-1)
+    nh = (n * h).sum(-1)
+    oh = (wo * h).sum(-1)
+    alpha = gamma * gamma
+    k = (gamma + 1.0) ** 2 / 8.0
+    spec = ggx_d(nh, alpha) * fresnel(oh) * smith_g1(ci, k) * smith_g1(co, k) / (4.0 * ci * co)
+    return albedo / math.pi + (tint * spec)[..., None]
+
+
+def srgb_oetf(x):
+    """Gamma correction of the output radiance: the sRGB transfer curve."""
+    lo = 12.92 * x
+    hi = 1.055 * torch.pow(torch.clamp(x, min=0.0031308), 1.0 / 2.4) - 0.055
+    return torch.where(x <= 0.0031308, lo, hi)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1, rendering equation: L_o = sum_k L^k A^k R v_g[k] max(0, w_i^k . n).
+# Sec. 3.2 / Eq. interpolate: v_g[k] = sum_j u_j count[vertex_j][view(k)] / K_v.
+# ---------------------------------------------------------------------------
+def shade(xp, npr, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env, cam_pos,
+          front, chunk: int = 4096):
+    """Returns (colour [3,n], L_o [3,n]) in float64.  ``front`` [n] (0/1) is the
+    FP32 back-face decision; non-front Gaussians get colour 0."""
+    xp, npr, albedo, rough, tint = (t64(v) for v in (xp, npr, albedo, rough, tint))
+    n = xp.shape[1]
+    dirs, solid = env_geometry(he, we)
+    vk = texel_view(he, we, hv, wv)
+    env = t64(env)
+    E = env * solid[:, None]                                      # [K,3]
+    count = torch.as_tensor(np.asarray(count), dtype=f64)         # [nv,V]
+    vidx = torch.as_tensor(np.asarray(vidx), dtype=torch.long)
+    vw = t64(vw)
+    cam = t64(cam_pos)
+    front = torch.as_tensor(np.asarray(front)).to(torch.bool)
+    outs = []
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        nn = npr[:, s:e].T
+        nn = nn / torch.linalg.norm(nn, dim=1, keepdim=True)       # [m,3]
+        wo = cam[None, :] - xp[:, s:e].T
+        wo = wo / torch.linalg.norm(wo, dim=1, keepdim=True)
+        vis = sum(vw[j, s:e, None] * count[vidx[j, s:e]][:, vk] for j in range(3)) / kv
+        ci = nn @ dirs.T                                           # [m,K]
+        live = (ci > 0) & (vis > 0)
+        ci_s = torch.where(live, ci, torch.ones_like(ci))
+        co = (nn * wo).sum(1).clamp(min=1e-300)[:, None]
+        h = dirs[None, :, :] + wo[:, None, :]
+        h = h / torch.linalg.norm(h, dim=-1, keepdim=True)
+        nh = (h * nn[:, None, :]).sum(-1)
+        oh = (h * wo[:, None, :]).sum(-1)
+        g = rough[s:e, None]
+        alpha = g * g
+        k = (g + 1.0) ** 2 / 8.0
+        spec = ggx_d(nh, alpha) * fresnel(oh) * smith_g1(ci_s, k) * smith_g1(co, k) / (4.0 * ci_s * co)
+        wgt = torch.where(live, vis * ci_s, torch.zeros_like(ci))  # v * max(0, w.n)
+        diff_sum = wgt @ E                                         # [m,3]
+        spec_sum = (wgt * spec) @ E
+        Lo = albedo[:, s:e].T / math.pi * diff_sum + tint[s:e, None] * spec_sum
+        Lo = torch.where(front[s:e, None], Lo, torch.zeros_like(Lo))
+        outs.append(Lo)
+    Lo = torch.cat(outs, 0).T
+    col = torch.where(front[None, :], srgb_oetf(Lo), torch.zeros_like(Lo))
+    return col, Lo
+
+
+# ---------------------------------------------------------------------------
+# Splatting (the 3DGS method): EWA projection, front-to-back compositing.
+# ---------------------------------------------------------------------------
+def quat_to_rot(q):
+    """q [4,n] (w, x, y, z), normalised here -> [n,3,3]."""
+    q = q / torch.linalg.norm(q, dim=0, keepdim=True)
+    w, x, y, z = q
+    return torch.stack([
+        torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        torch.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        torch.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1),
+    ], -2)
+
+
+def project(cam, xp, A, quat, log_s, opac, front):
+    """Camera-space projection of every Gaussian.  Returns a dict with mean2d
+    [2,n], conic [3,n] (A, B, C of the inverse covariance), sigma [3,n] (the
+    2D covariance a, b, c), depth [n] and valid [n] (bool)."""
+    R = t64(cam.R)
+    tc = t64(cam.t)
+    Xc = R @ xp + tc[:, None]
+    X, Y, Z = Xc
+    front = torch.as_tensor(np.asarray(front)).to(torch.bool)
+    valid = (Z > 0.2) & front & (opac >= 1.0 / 255.0)
+    Zs = torch.where(valid, Z, torch.ones_like(Z))
+    s = torch.exp(log_s)                                          # [3,n]
+    Rq = quat_to_rot(quat)                                        # [n,3,3]
+    Am = A.T.reshape(-1, 3, 3)
+    M = Am @ Rq * s.T[:, None, :]                                 # A R diag(s)
+    V = R[None] @ M
+    zero = torch.zeros_like(Zs)
+    J = torch.stack([torch.stack([cam.fx / Zs, zero, -cam.fx * X / Zs ** 2], -1),
+                     torch.stack([zero, cam.fy / Zs, -cam.fy * Y / Zs ** 2], -1)], -2)
+    T = J @ V                                                     # [n,2,3]
+    Sig = T @ T.transpose(1, 2)
+    a = Sig[:, 0, 0] + 0.3
+    b = Sig[:, 0, 1]
+    c = Sig[:, 1, 1] + 0.3
+    det = a * c - b * b
+    valid = valid & (det > 0)
+    dets = torch.where(valid, det, torch.ones_like(det))
+    conic = torch.stack([c / dets, -b / dets, a / dets])
+    mean2d = torch.stack([cam.fx * X / Zs + cam.cx, cam.fy * Y / Zs + cam.cy])
+    return dict(mean2d=mean2d, conic=conic, sigma=torch.stack([a, b, c]), depth=Z, valid=valid)
+
+
+def composite(cam, proj, opac, color, pixels: Optional[np.ndarray] = None):
+    """Front-to-back alpha compositing over Gaussians in (depth, index) order.
+
+    Per pixel centre p: alpha = min(0.99, o exp(-d^T Conic d / 2)), d = mean - p;
+    skip if the exponent is positive or alpha < 1/255; stop before the entry
+    that takes the transmittance below 1e-4; C = sum c alpha T, T_final = T.
+    Black background.  Only pixels inside a Gaussian's alpha >= 1/255 ellipse
+    box can receive it, so (pixel, Gaussian) pairs are enumerated from those
+    boxes; ``pixels`` optionally restricts to a subset of flat pixel indices.
+    Returns (image [3, P], T_final [P]) where P = H*W or len(pixels).
+    """
+    H, W = cam.height, cam.width
+    valid = proj["valid"]
+    gid = torch.nonzero(valid).flatten()
+    if pixels is None:
+        pix_list = None
+        P = H * W
+    else:
+        pix_list = torch.as_tensor(np.asarray(pixels), dtype=torch.long)
+        P = len(pix_list)
+    if len(gid) == 0:
+        return torch.zeros(3, P, dtype=f64), torch.ones(P, dtype=f64)
+    depth = proj["depth"].detach()[gid]
+    order = torch.argsort(depth, stable=True)          # ties keep index order
+    rank = torch.empty_like(order)
+    rank[order] = torch.arange(len(order))
+    m = proj["mean2d"].detach()[:, gid]
+    sig = proj["sigma"].detach()[:, gid]
+    o = opac.detach()[gid]
+    r2 = 2.0 * torch.log(255.0 * o)
+    hx = torch.sqrt(r2 * sig[0]) + 1.0
+    hy = torch.sqrt(r2 * sig[2]) + 1.0
+    x0 = torch.clamp(torch.floor(m[0] - hx - 0.5), 0, W - 1).long()
+    x1 = torch.clamp(torch.ceil(m[0] + hx - 0.5), 0, W - 1).long()
+    y0 = torch.clamp(torch.floor(m[1] - hy - 0.5), 0, H - 1).long()
+    y1 = torch.clamp(torch.ceil(m[1] + hy - 0.5), 0, H - 1).long()
+    onscreen = (m[0] + hx > 0) & (m[0] - hx < W) & (m[1] + hy > 0) & (m[1] - hy < H)
+    nx = torch.where(onscreen, x1 - x0 + 1, torch.zeros_like(x0))
+    ny = torch.where(onscreen, y1 - y0 + 1, torch.zeros_like(y0))
+    cnt = nx * ny
+    if pix_list is not None:
+        # keep only pairs that land on the requested pixels
+        lut = torch.full((H * W,), -1, dtype=torch.long)
+        lut[pix_list] = torch.arange(P)
+    gi = torch.repeat_interleave(torch.arange(len(gid)), cnt)
+    start = torch.cumsum(cnt, 0) - cnt
+    local = torch.arange(int(cnt.sum())) - start[gi]
+    px = x0[gi] + local % nx[gi]
+    py = y0[gi] + local // nx[gi]
+    flat = py * W + px
+    if pix_list is not None:
+        slot = lut[flat]
+        keep_pair = slot >= 0
+        gi, px, py, slot = gi[keep_pair], px[keep_pair], py[keep_pair], slot[keep_pair]
+    else:
+        slot = flat
+    key = slot * len(gid) + rank[gi]
+    srt = torch.argsort(key)
+    gi, px, py, slot = gi[srt], px[srt], py[srt], slot[srt]
+    g = gid[gi]
+    mean = proj["mean2d"][:, g]
+    con = proj["conic"][:, g]
+    dx = mean[0] - (px.to(f64) + 0.5)
+    dy = mean[1] - (py.to(f64) + 0.5)
+    q = con[0] * dx * dx + 2.0 * con[1] * dx * dy + con[2] * dy * dy
+    power = -0.5 * q
+    araw = opac[g] * torch.exp(power)
+    alpha = torch.minimum(araw, torch.full_like(araw, 0.99))
+    keep = (power <= 0) & (alpha >= 1.0 / 255.0)
+    a_eff = torch.where(keep, alpha, torch.zeros_like(alpha))
+    l1m = torch.log1p(-a_eff)
+    # per-pixel running sums of log(1 - alpha), one padded row per pixel
+    seg_start = torch.ones_like(slot, dtype=torch.bool)
+    seg_start[1:] = slot[1:] != slot[:-1]
+    first = torch.nonzero(seg_start).flatten()
+    seg_id = torch.cumsum(seg_start.long(), 0) - 1
+    pos = torch.arange(len(slot)) - first[seg_id]
+    incl_parts = []
+    nseg = len(first)
+    lmax_all = int(pos.max()) + 1
+    block = max(1, 4_000_000 // lmax_all)
+    for b0 in range(0, nseg, block):
+        b1 = min(nseg, b0 + block)
+        lo = int(first[b0])
+        hi = int(first[b1]) if b1 < nseg else len(slot)
+        sid = seg_id[lo:hi] - b0
+        ps = pos[lo:hi]
+        pad = torch.zeros(b1 - b0, lmax_all, dtype=f64)
+        pad = pad.index_put((sid, ps), l1m[lo:hi])
+        incl_parts.append(torch.cumsum(pad, 1)[sid, ps])
+    incl = torch.cat(incl_parts)
+    excl = incl - l1m
+    T_incl = torch.exp(incl)
+    T_excl = torch.exp(excl)
+    active = keep & (T_incl >= 1e-4)
+    w = torch.where(active, a_eff * T_excl, torch.zeros_like(a_eff))
+    img = torch.zeros(3, P, dtype=f64)
+    img = img.index_add(1, slot, color[:, g] * w[None, :])
+    logT = torch.zeros(P, dtype=f64).index_add(0, slot, torch.where(active, l1m, torch.zeros_like(l1m)))
+    return img, torch.exp(logT)
+
+
+def l1_loss(image, target):
+    """Mean absolute error over all 3HW values (the L1 term of the image loss)."""
+    return (image - t64(target)).abs().mean()

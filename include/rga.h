@@ -1,0 +1,234 @@
+/*
+ * rga.h -- C ABI of the relightable Gaussian-avatar render-and-train path
+ * (Zhan et al., "Interactive Rendering of Relightable and Animatable Gaussian
+ * Avatars"), implemented as hand-written HIP kernels for gfx950 (MI355X).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers owned by the caller, except the
+ *    camera struct and cam_pos, which live in host memory.  The library never
+ *    allocates device memory and keeps no state between calls; scratch space
+ *    is a caller-provided workspace whose size the *_workspace functions give.
+ *  - Per-item arrays are structure-of-arrays planes: "[C][n]" means C
+ *    contiguous planes of n float32 (or int32) values each.  Device pointers
+ *    must be 16-byte aligned.
+ *  - Every call is asynchronous on the HIP stream `stream` (hipStream_t passed
+ *    as void*; NULL is the default stream).  No entry point synchronises the
+ *    device except splat_read_count.
+ *  - Return value: RGA_OK (0) or a negative error code; rga_last_error()
+ *    returns a thread-local message for the last failure.  Argument checks
+ *    happen on the host before any launch; on error nothing is launched.
+ *  - Backward entry points OVERWRITE their gradient outputs, except where an
+ *    argument is documented as accumulating.
+ *  - Index inputs (joint, vertex, neighbour indices) must be in range; they
+ *    are clamped on the device for memory safety, which silently changes the
+ *    result of out-of-range input rather than faulting.
+ */
+#ifndef RGA_H
+#define RGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RGA_OK 0
+#define RGA_EINVAL (-1)        /* null pointer, bad size or misalignment     */
+#define RGA_ECAPACITY (-2)     /* workspace too small                        */
+#define RGA_EHIP (-3)          /* HIP launch or runtime error                */
+#define RGA_EUNSUPPORTED (-4)  /* configuration outside the supported range  */
+
+#define RGA_FP32 0             /* shading contraction in FP32 on VALU        */
+#define RGA_BF16X3 1           /* shading contraction on BF16 MFMA, hi+lo split */
+
+/* Pinhole camera, world -> camera x_c = R x + t (row-major R), camera frame
+ * x right, y down, z forward; pixel (i, j) has its centre at (i+0.5, j+0.5). */
+typedef struct rga_camera {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+} rga_camera;
+
+const char* rga_last_error(void);
+int rga_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Sec. 3.1 (deformation): forward linear blend skinning of canonical points
+ * (Gaussians or mesh vertices) to the posed space, with four joints per point.
+ *   x' = x + sum_j w_j ((R_j - I) x + t_j)      (= sum_j w_j (R_j x + t_j))
+ *   A  = I + sum_j w_j (R_j - I)                 (blended linear part)
+ *   n' = A n                                     (unnormalised normal)
+ * skin   [n_joints][3][4]  row-major [R_j | t_j], n_joints in 1..256
+ * jidx   [4][n] int32, jw [4][n]: joint indices and weights (sum 1)
+ * x      [3][n]  canonical positions;  nrm [3][n] canonical normals or NULL
+ * x_out  [3][n]; n_out [3][n] or NULL (needs nrm); A_out [9][n] or NULL
+ * The sums run in joint-slot order with fused multiply-adds, so the result is
+ * reproducible bit for bit.                                                 */
+int lbs_skin(void* stream, int n, int n_joints, const float* skin, const int32_t* jidx,
+             const float* jw, const float* x, const float* nrm, float* x_out, float* n_out,
+             float* A_out);
+
+/* Adjoint of lbs_skin with respect to x and nrm (pose gradients are not
+ * produced):  dx = A^T dx_out,  dn = A^T dn_out.
+ * dn_out / dn may both be NULL.  Overwrites dx and dn.                      */
+int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
+                      const int32_t* jidx, const float* jw, const float* dx_out,
+                      const float* dn_out, float* dx, float* dn);
+
+/* ------------------------------------------------------------------------
+ * Sec. 3.2 (visibility computation): orthographic rasterization of the posed
+ * mesh along each of V view directions into a res x res triangle-index image;
+ * the three vertices of every triangle that wins a sample are visible; then
+ * mean(median(median(V))) over the kv nearest vertices (filter equations).
+ * verts     [3][nv] posed vertex positions;  faces [nf][3] int32
+ * view_dirs [V][3] unit directions (from the body toward the light)
+ * res       raster resolution, 1..128
+ * knn       [nv][kv] int32 nearest canonical vertices of each vertex (the
+ *           vertex itself included), kv odd, 1..31
+ * raw_bits  [nv][ceil(V/32)] uint32 raw visibility bits (bit k&31 of word
+ *           k>>5 for view k), or NULL
+ * count     [nv][V] uint8 filtered visibility in 0..kv (the mean filter's
+ *           value is count/kv)
+ * ws        device workspace of at least mesh_visibility_workspace(nv, V) bytes
+ * Raster rules: the frame is the posed mesh's bounding box centre and 1.01x
+ * half its diagonal; projected coordinates snap to 1/256 pixel; samples at
+ * pixel centres; triangles are two-sided, zero-area ones skipped; a sample on
+ * an edge belongs to the edge's owner by a fixed tie rule; the nearest
+ * triangle wins, ties to the lower index.  Outputs are bit-exact.           */
+size_t mesh_visibility_workspace(int nv, int V);
+int mesh_visibility(void* stream, int nv, int nf, const float* verts, const int32_t* faces,
+                    int V, const float* view_dirs, int res, const int32_t* knn, int kv,
+                    uint32_t* raw_bits, uint8_t* count, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Sec. 3.1, rendering equation, and App. A (BRDF): per-Gaussian shading
+ *   L_o = sum_k L^k A^k R(w_k, w_o, n) v_g[k] max(0, w_k . n),
+ *   R = a/pi + p D F G / (4 (n.w_i)(n.w_o)),  GGX D with alpha = gamma^2,
+ *   F = F0 + (1-F0) 2^((-5.55473 oh - 6.98316) oh), F0 = 0.04,
+ *   G = G1(w_i) G1(w_o), G1(x) = x / (x (1-k) + k), k = (gamma+1)^2 / 8,
+ * then colour = sRGB transfer curve of L_o (gamma correction).  Gaussians
+ * whose normal faces away from the camera (n'.(cam - x') <= 0 in FP32) get
+ * front = 0 and colour 0.
+ * x, nrm     [3][n] posed positions and (unnormalised) normals
+ * albedo [3][n], rough [n] (gamma > 0), tint [n] (specular tint p)
+ * vidx [3][n] int32, vw [3][n]: the K_g = 3 nearest mesh vertices of each
+ *            Gaussian and their normalised inverse-distance weights (Eq.
+ *            interpolate): v_g[k] = sum_j vw_j count[vidx_j][view(k)] / kv
+ * count      [nv][V] uint8 from mesh_visibility, V = hv * wv
+ * env        [he*we][3] radiance of the lat-long map; texel (r, c) has polar
+ *            angle (r+0.5) pi/he from +Y, azimuth (c+0.5) 2pi/we, direction
+ *            (sin th sin ph, cos th, sin th cos ph), area = its solid angle
+ * hv, wv     the view grid (a coarser lat-long grid dividing he x we): texel
+ *            (r, c) uses view (r*hv/he)*wv + c*wv/we
+ * cam_pos    host float[3], camera centre in world space
+ * precision  RGA_FP32 or RGA_BF16X3
+ * color      [3][n] out;  front [n] uint8 out                               */
+int shade_gaussians(void* stream, int n, const float* x, const float* nrm, const float* albedo,
+                    const float* rough, const float* tint, const int32_t* vidx, const float* vw,
+                    const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,
+                    const float* env, const float* cam_pos, int precision, float* color,
+                    uint8_t* front);
+
+/* Adjoint of shade_gaussians.  Recomputes the BRDF weights; L_o is recovered
+ * from `color` (the forward output) by inverting the transfer curve.
+ * dcolor [3][n] in.  Outputs: dx [3][n] (ACCUMULATES: dx += d/dx'),
+ * dn [3][n], dalbedo [3][n], drough [n], dtint [n] (overwritten),
+ * denv [he*we][3] (overwritten).  ws: shade_gaussians_workspace bytes.      */
+size_t shade_gaussians_workspace(int n, int he, int we);
+int shade_gaussians_backward(void* stream, int n, const float* x, const float* nrm,
+                             const float* albedo, const float* rough, const float* tint,
+                             const int32_t* vidx, const float* vw, const uint8_t* count, int nv,
+                             int kv, int he, int we, int hv, int wv, const float* env,
+                             const float* cam_pos, int precision, const float* color,
+                             const uint8_t* front, const float* dcolor, float* dx, float* dn,
+                             float* dalbedo, float* drough, float* dtint, float* denv, void* ws,
+                             size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Sec. 3.1, last paragraph: splatting with the 3DGS tile rasterizer.
+ * Projection: X = R x' + t; culled if Z <= 0.2, front == 0, opacity < 1/255
+ * or the 2D covariance is not positive definite.  Covariance factor
+ * M = A R(q/|q|) diag(exp(log_s)); Sigma2D = J R M M^T R^T J^T + 0.3 I with
+ * the perspective Jacobian J at the centre.  Near-degenerate splats
+ * (det <= 2^-12 a c in FP32) take the 2x2 covariance, determinant and
+ * inverse in FP64.  Each splat is binned into the 16x16-pixel tiles of the
+ * box bounding its alpha >= 1/255 ellipse; per tile, splats are ordered by
+ * (float bits of Z, index); pixels composite front to back with
+ * alpha = min(0.99, o exp(-d^T Conic d / 2)), skipping alpha < 1/255 and
+ * stopping before the transmittance drops below 1e-4; black background.
+ * Inputs: x [3][n], A [9][n] (from lbs_skin), quat [4][n] (w,x,y,z),
+ * log_s [3][n], opac [n], color [3][n], front [n].
+ * capacity   maximum number of (splat, tile) duplicates D the workspace holds
+ * ws         splat_workspace_size(n, width, height, capacity) bytes; holds the
+ *            per-splat records, sorted lists and tile ranges that
+ *            splat_backward and splat_state read.  Keep it alive and
+ *            unmodified until the backward pass.
+ * image [3][H][W], T_final [H][W] out.
+ * No host synchronisation: if D exceeds capacity the lists are truncated, the
+ * image is wrong, and splat_read_count reports D > capacity (retry larger). */
+size_t splat_workspace_size(int n, int width, int height, int64_t capacity);
+int splat_forward(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
+                  const float* quat, const float* log_s, const float* opac, const float* color,
+                  const uint8_t* front, void* ws, size_t ws_bytes, int64_t capacity,
+                  float* image, float* T_final);
+
+/* Synchronises `stream` and returns the duplicate count D of the last
+ * splat_forward that used ws (may exceed capacity: then re-run larger).    */
+int splat_read_count(void* stream, const void* ws, int n, int width, int height,
+                     int64_t capacity, int64_t* D);
+
+/* Device pointers into a splat workspace (valid after splat_forward):
+ * mean2d [2][n] f32, conic [3][n] f32 (A, B, C of the inverse covariance),
+ * depth [n] f32, rect [4][n] int32 (tx0, ty0, tx1, ty1), touched [n] int32,
+ * fp64 [n] uint8, sorted [D] int32 splat indices per tile in tile order,
+ * ranges [tiles][2] int32 [start, end), count: device int64 D.             */
+typedef struct rga_splat_state {
+  float* mean2d;
+  float* conic;
+  float* depth;
+  int32_t* rect;
+  int32_t* touched;
+  uint8_t* fp64;
+  int32_t* sorted;
+  int32_t* ranges;
+  int64_t* count;
+  int32_t tiles_x, tiles_y;
+} rga_splat_state;
+int splat_state(void* ws, int n, int width, int height, int64_t capacity, rga_splat_state* st);
+
+/* Adjoint of splat_forward given dL/dimage.  Re-walks every tile list front to
+ * back recomputing the transmittance (nothing per (pixel, splat) is stored);
+ * `image` is the forward output.  Outputs (overwritten): dx [3][n],
+ * dquat [4][n], dlog_s [3][n], dopac [n], dcolor [3][n].  Gradients with
+ * respect to A are not produced.                                           */
+int splat_backward(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
+                   const float* quat, const float* log_s, const float* opac,
+                   const float* color, const uint8_t* front, void* ws, size_t ws_bytes,
+                   int64_t capacity, const float* image, const float* dimage, float* dx,
+                   float* dquat, float* dlog_s, float* dopac, float* dcolor);
+
+/* ------------------------------------------------------------------------
+ * Sec. 3.3, image loss (its L1 term): loss = mean |image - target| over
+ * `count` values; dimage = sign(image - target) / count (sign(0) = 0).
+ * loss: device float[1]; dimage may be NULL.  ws: l1_loss_workspace bytes.  */
+size_t l1_loss_workspace(int64_t count);
+int l1_loss(void* stream, int64_t count, const float* image, const float* target, float* loss,
+            float* dimage, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing with HIP events, for measurement.  While enabled, every
+ * kernel launch is bracketed by events on its stream; rga_timing_read
+ * synchronises and returns the summed milliseconds and launch count of the
+ * kernels whose name matches `kernel` exactly.                              */
+int rga_timing_enable(int on);
+int rga_timing_reset(void);
+int rga_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGA_H */

@@ -1,0 +1,58 @@
+// Internal helpers shared by the HIP sources of the library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rga.h"
+
+namespace rga {
+
+// Record an error message for rga_last_error() and return `code`.
+int fail(int code, const char* fmt, ...);
+// Check the launch that was just issued; returns RGA_OK or RGA_EHIP.
+int check_launch(const char* what);
+
+// Optional event timing around kernel launches (see rga_timing_enable).
+bool timing_on();
+void timing_mark(const char* name, hipStream_t s, bool start);
+
+struct TimedLaunch {
+  const char* name;
+  hipStream_t s;
+  bool on;
+  TimedLaunch(const char* n, hipStream_t st) : name(n), s(st), on(timing_on()) {
+    if (on) timing_mark(name, s, true);
+  }
+  ~TimedLaunch() {
+    if (on) timing_mark(name, s, false);
+  }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Launch `kernel` under an optional timing scope and check for launch errors.
+#define RGA_LAUNCH(name, kernel, grid, block, shmem, stream, ...)                \
+  do {                                                                          \
+    ::rga::TimedLaunch _rga_tl((name), (stream));                               \
+    hipLaunchKernelGGL((kernel), (grid), (block), (shmem), (stream), __VA_ARGS__); \
+  } while (0)
+
+#define RGA_CHECK_LAUNCH(name)                     \
+  do {                                             \
+    int _rc = ::rga::check_launch(name);           \
+    if (_rc != RGA_OK) return _rc;                 \
+  } while (0)
+
+// ---- device helpers ------------------------------------------------------
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+}  // namespace rga

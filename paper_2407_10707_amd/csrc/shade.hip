@@ -1,0 +1,534 @@
+// Per-Gaussian shading (Sec. 3.1 rendering equation, App. A BRDF) and its
+// adjoint, FP32 form.
+//
+// Work mapping: one wave64 per Gaussian, lanes over light directions.  Per
+// chunk of 64 directions each lane evaluates n.w_k and the interpolated
+// visibility v_g[k] (three coalesced byte loads from the vertex-major count
+// rows); a wave ballot compacts the live directions (n.w_k > 0 and
+// v_g[k] > 0) into a 128-slot LDS ring, and the BRDF weights are evaluated
+// only for full waves of live directions.  For a typical body roughly a
+// third of the K directions are live, so the expensive part (GGX, Fresnel,
+// Smith) runs at full SIMD width on that third only.  The per-lane sums are
+// reduced across the wave once per Gaussian.
+//
+// The direction table (unit direction, radiance x solid angle, view index)
+// is built in LDS by every workgroup; workgroups are persistent and loop
+// over Gaussians.
+#include "common.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int kWaves = 8;
+constexpr int kThreads = kWaves * 64;
+constexpr int kRing = 128;
+constexpr float kPi = 3.14159265358979323846f;
+
+struct ShadeArgs {
+  int n, nv, V, kv, he, we, hv, wv, K;
+  float cam[3];
+  const float *x, *nrm, *albedo, *rough, *tint, *vw, *env;
+  const int32_t* vidx;
+  const uint8_t* count;
+};
+
+// Table layout in LDS: dir x,y,z | E r,g,b | view (int) | area, each [K].
+__device__ inline void build_table(const ShadeArgs& a, float* tab, int with_area) {
+  const int K = a.K;
+  const float dth = kPi / (float)a.he, dph = 2.f * kPi / (float)a.we;
+  // exact solid angle of a texel row: (2 pi / we) * 2 sin(theta_r) sin(pi / (2 he))
+  const float band = (2.f * kPi / (float)a.we) * 2.f * sinf(0.5f * dth);
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const int r = k / a.we, c = k - r * a.we;
+    float st, ct, sp, cp;
+    sincosf(((float)r + 0.5f) * dth, &st, &ct);
+    sincosf(((float)c + 0.5f) * dph, &sp, &cp);
+    const float area = band * st;
+    tab[k] = st * sp;
+    tab[K + k] = ct;
+    tab[2 * K + k] = st * cp;
+    tab[3 * K + k] = a.env[3 * k] * area;
+    tab[4 * K + k] = a.env[3 * k + 1] * area;
+    tab[5 * K + k] = a.env[3 * k + 2] * area;
+    reinterpret_cast<int*>(tab)[6 * K + k] = ((r * a.hv) / a.he) * a.wv + (c * a.wv) / a.we;
+    if (with_area) tab[7 * K + k] = area;
+  }
+}
+
+struct GaussCtx {
+  float nn[3], wo[3], co, a2, kG, Go, inn, iwo, alpha, gamma;
+  float u0, u1, u2;
+  const uint8_t *r0, *r1, *r2;
+  bool front;
+};
+
+__device__ inline void gauss_setup(const ShadeArgs& a, int g, GaussCtx& G) {
+  const int n = a.n;
+  const float x0 = a.x[g], x1 = a.x[n + g], x2 = a.x[2 * n + g];
+  const float m0 = a.nrm[g], m1 = a.nrm[n + g], m2 = a.nrm[2 * n + g];
+  const float w0 = a.cam[0] - x0, w1 = a.cam[1] - x1, w2 = a.cam[2] - x2;
+  // back-face decision in FP32 with a fixed operation order
+  const float dotf = fmaf(m2, w2, fmaf(m1, w1, m0 * w0));
+  G.front = dotf > 0.f;
+  G.inn = 1.f / sqrtf(fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));
+  G.nn[0] = m0 * G.inn;
+  G.nn[1] = m1 * G.inn;
+  G.nn[2] = m2 * G.inn;
+  G.iwo = 1.f / sqrtf(fmaf(w2, w2, fmaf(w1, w1, w0 * w0)));
+  G.wo[0] = w0 * G.iwo;
+  G.wo[1] = w1 * G.iwo;
+  G.wo[2] = w2 * G.iwo;
+  G.co = fmaf(G.nn[2], G.wo[2], fmaf(G.nn[1], G.wo[1], G.nn[0] * G.wo[0]));
+  G.gamma = a.rough[g];
+  G.alpha = G.gamma * G.gamma;
+  G.a2 = G.alpha * G.alpha;
+  G.kG = (G.gamma + 1.f) * (G.gamma + 1.f) * 0.125f;
+  G.Go = 1.f / fmaf(G.co, 1.f - G.kG, G.kG);
+  const float ikv = 1.f / (float)a.kv;
+  G.u0 = a.vw[g] * ikv;
+  G.u1 = a.vw[n + g] * ikv;
+  G.u2 = a.vw[2 * n + g] * ikv;
+  const int nvm = a.nv - 1;
+  G.r0 = a.count + (size_t)rga::clampi(a.vidx[g], 0, nvm) * a.V;
+  G.r1 = a.count + (size_t)rga::clampi(a.vidx[n + g], 0, nvm) * a.V;
+  G.r2 = a.count + (size_t)rga::clampi(a.vidx[2 * n + g], 0, nvm) * a.V;
+}
+
+// Live-direction test for direction k; returns the visibility (0 if dead).
+__device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int k) {
+  const float d0 = tab[k], d1 = tab[K + k], d2 = tab[2 * K + k];
+  const float ci = fmaf(G.nn[2], d2, fmaf(G.nn[1], d1, G.nn[0] * d0));
+  if (!(ci > 0.f)) return 0.f;
+  const int view = reinterpret_cast<const int*>(tab)[6 * K + k];
+  const float c0 = (float)G.r0[view], c1 = (float)G.r1[view], c2 = (float)G.r2[view];
+  return fmaf(G.u2, c2, fmaf(G.u1, c1, G.u0 * c0));
+}
+
+struct Pair {
+  float d[3], E[3], ci, ok, hh, nht, s2, den, invh, nh, oh, e2, F, D, G1i, deni, W0, Ws, Wd;
+};
+
+// BRDF weights of one live (Gaussian, direction) pair.  The GGX denominator
+// 1 - nh^2 (1 - alpha^2) is formed as (|n x h~|^2 + (n.h~)^2 alpha^2)/|h~|^2
+// with h~ = w_k + w_o, which keeps its relative accuracy when nh -> 1.
+__device__ inline void pair_eval(const GaussCtx& G, const float* tab, int K, int k, float v,
+                                 Pair& P) {
+  P.d[0] = tab[k];
+  P.d[1] = tab[K + k];
+  P.d[2] = tab[2 * K + k];
+  P.E[0] = tab[3 * K + k];
+  P.E[1] = tab[4 * K + k];
+  P.E[2] = tab[5 * K + k];
+  P.ci = fmaf(G.nn[2], P.d[2], fmaf(G.nn[1], P.d[1], G.nn[0] * P.d[0]));
+  P.ok = fmaf(G.wo[2], P.d[2], fmaf(G.wo[1], P.d[1], G.wo[0] * P.d[0]));
+  const float h0 = P.d[0] + G.wo[0], h1 = P.d[1] + G.wo[1], h2 = P.d[2] + G.wo[2];
+  P.hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
+  P.nht = P.ci + G.co;
+  const float s0 = G.nn[1] * h2 - G.nn[2] * h1;
+  const float s1 = G.nn[2] * h0 - G.nn[0] * h2;
+  const float s2 = G.nn[0] * h1 - G.nn[1] * h0;
+  P.s2 = fmaf(s2, s2, fmaf(s1, s1, s0 * s0));
+  P.den = fmaf(P.nht * P.nht, G.a2, P.s2);           // (1 - nh^2 (1 - a^2)) |h~|^2
+  P.invh = 1.f / sqrtf(P.hh);
+  P.nh = P.nht * P.invh;
+  P.oh = (1.f + P.ok) * P.invh;
+  P.e2 = exp2f((-5.55473f * P.oh - 6.98316f) * P.oh);
+  P.F = 0.04f + 0.96f * P.e2;
+  const float hd = P.hh / P.den;
+  P.D = G.a2 * hd * hd * (1.f / kPi);
+  P.deni = fmaf(P.ci, 1.f - G.kG, G.kG);
+  P.G1i = P.ci / P.deni;
+  P.W0 = v * P.D * P.F * G.Go * 0.25f;
+  P.Ws = P.W0 * P.G1i;
+  P.Wd = v * P.ci;
+}
+
+__device__ inline float srgb(float L) {
+  return L <= 0.0031308f ? 12.92f * L : 1.055f * powf(L, 1.f / 2.4f) - 0.055f;
+}
+
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kThreads)
+shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ front) {
+  extern __shared__ __align__(16) float tab[];
+  __shared__ int qk[kWaves][kRing];
+  __shared__ float qv[kWaves][kRing];
+  build_table(a, tab, 0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int K = a.K, n = a.n;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int gi = blockIdx.x * kWaves + wave; gi < n; gi += gridDim.x * kWaves) {
+    const int g = __builtin_amdgcn_readfirstlane(gi);
+    GaussCtx G;
+    gauss_setup(a, g, G);
+    if (!G.front) {
+      if (lane < 3) color[(size_t)lane * n + g] = 0.f;
+      if (lane == 0) front[g] = 0;
+      continue;
+    }
+    float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
+    int head = 0, tail = 0;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      const int k = k0 + lane;
+      const float v = k < K ? live_vis(G, tab, K, k) : 0.f;
+      const bool live = v > 0.f;
+      const uint64_t m = __ballot(live);
+      if (live) {
+        const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
+        qk[wave][slot] = k;
+        qv[wave][slot] = v;
+      }
+      tail += __popcll(m);
+      if (tail - head >= 64) {
+        wave_fence();
+        const int slot = (head + lane) & (kRing - 1);
+        Pair P;
+        pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
+        sd0 = fmaf(P.Wd, P.E[0], sd0);
+        sd1 = fmaf(P.Wd, P.E[1], sd1);
+        sd2 = fmaf(P.Wd, P.E[2], sd2);
+        ss0 = fmaf(P.Ws, P.E[0], ss0);
+        ss1 = fmaf(P.Ws, P.E[1], ss1);
+        ss2 = fmaf(P.Ws, P.E[2], ss2);
+        head += 64;
+        wave_fence();
+      }
+    }
+    if (tail > head) {
+      wave_fence();
+      if (lane < tail - head) {
+        const int slot = (head + lane) & (kRing - 1);
+        Pair P;
+        pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
+        sd0 = fmaf(P.Wd, P.E[0], sd0);
+        sd1 = fmaf(P.Wd, P.E[1], sd1);
+        sd2 = fmaf(P.Wd, P.E[2], sd2);
+        ss0 = fmaf(P.Ws, P.E[0], ss0);
+        ss1 = fmaf(P.Ws, P.E[1], ss1);
+        ss2 = fmaf(P.Ws, P.E[2], ss2);
+      }
+      wave_fence();
+    }
+    sd0 = rga::wave_sum(sd0);
+    sd1 = rga::wave_sum(sd1);
+    sd2 = rga::wave_sum(sd2);
+    ss0 = rga::wave_sum(ss0);
+    ss1 = rga::wave_sum(ss1);
+    ss2 = rga::wave_sum(ss2);
+    if (lane < 3) {
+      const float sd = lane == 0 ? sd0 : (lane == 1 ? sd1 : sd2);
+      const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
+      const float alb = a.albedo[(size_t)lane * n + g];
+      const float Lo = alb * (1.f / kPi) * sd + a.tint[g] * ss;
+      color[(size_t)lane * n + g] = srgb(Lo);
+    }
+    if (lane == 0) front[g] = 1;
+  }
+}
+
+// ---- adjoint -----------------------------------------------------------------
+struct BwdAcc {
+  float gn[3], gw[3], gco, gga, sd[3], ts;
+};
+
+__device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv_lds, int K, int k,
+                                float v, const float* qd, const float* dLo, float tint,
+                                const float* aop, BwdAcc& acc) {
+  Pair P;
+  pair_eval(G, tab, K, k, v, P);
+  // upstream weights of W_d and W_s
+  const float gWd = fmaf(qd[2], P.E[2], fmaf(qd[1], P.E[1], qd[0] * P.E[0]));
+  const float sE = fmaf(dLo[2], P.E[2], fmaf(dLo[1], P.E[1], dLo[0] * P.E[0]));
+  const float gWs = tint * sE;
+  acc.sd[0] = fmaf(P.Wd, P.E[0], acc.sd[0]);
+  acc.sd[1] = fmaf(P.Wd, P.E[1], acc.sd[1]);
+  acc.sd[2] = fmaf(P.Wd, P.E[2], acc.sd[2]);
+  acc.ts = fmaf(P.Ws, sE, acc.ts);
+  // environment: dL/d(L_k,c A_k) = dLo_c (a_c/pi W_d + p W_s); the area
+  // factor is applied when the per-workgroup sums are reduced
+  atomicAdd(&denv_lds[3 * k + 0], dLo[0] * fmaf(aop[0], P.Wd, tint * P.Ws));
+  atomicAdd(&denv_lds[3 * k + 1], dLo[1] * fmaf(aop[1], P.Wd, tint * P.Ws));
+  atomicAdd(&denv_lds[3 * k + 2], dLo[2] * fmaf(aop[2], P.Wd, tint * P.Ws));
+  // logarithmic derivatives of D (in nh and alpha), F (in oh), G1
+  const float one_m_a2 = 1.f - G.a2;
+  const float dn = P.den / P.hh;                     // 1 - nh^2 (1 - a^2)
+  const float dlnD_dnh = 4.f * P.nh * one_m_a2 / dn;
+  const float dlnD_da = 2.f / G.alpha - 4.f * G.alpha * P.nh * P.nh / dn;
+  const float dlnF_doh = 0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) / P.F;
+  const float gs = gWs * P.Ws;
+  const float ih3 = P.invh * P.invh * P.invh;
+  const float gci = gWd * v + gWs * P.W0 * G.kG / (P.deni * P.deni) + gs * dlnD_dnh * P.invh;
+  const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
+  const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
+  const float dlnG_dk = -(1.f - P.ci) / P.deni - (1.f - G.co) * G.Go;
+  const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
+  acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
+  acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
+  acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
+  acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
+  acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
+  acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
+  acc.gco += gco;
+  acc.gga += gga;
+}
+
+__global__ void __launch_bounds__(kThreads)
+shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __restrict__ dcolor,
+                 float* __restrict__ dx, float* __restrict__ dn, float* __restrict__ dalbedo,
+                 float* __restrict__ drough, float* __restrict__ dtint,
+                 float* __restrict__ denv_part /*[grid][K][3]*/) {
+  extern __shared__ __align__(16) float tab[];
+  __shared__ int qk[kWaves][kRing];
+  __shared__ float qv[kWaves][kRing];
+  const int K = a.K, n = a.n;
+  float* denv_lds = tab + 7 * K;
+  build_table(a, tab, 0);
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int gi = blockIdx.x * kWaves + wave; gi < n; gi += gridDim.x * kWaves) {
+    const int g = __builtin_amdgcn_readfirstlane(gi);
+    GaussCtx G;
+    gauss_setup(a, g, G);
+    if (!G.front) {
+      if (lane < 3) {
+        dn[(size_t)lane * n + g] = 0.f;
+        dalbedo[(size_t)lane * n + g] = 0.f;
+      }
+      if (lane == 0) {
+        drough[g] = 0.f;
+        dtint[g] = 0.f;
+      }
+      continue;
+    }
+    // recover L_o from the colour and form dL/dL_o
+    float dLo[3], aop[3], qd[3];
+    for (int c = 0; c < 3; ++c) {
+      const float col = color[(size_t)c * n + g];
+      const float dc = dcolor[(size_t)c * n + g];
+      if (col <= 0.04045f) {
+        dLo[c] = dc * 12.92f;
+      } else {
+        const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
+        dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
+      }
+      aop[c] = a.albedo[(size_t)c * n + g] * (1.f / kPi);
+      qd[c] = dLo[c] * aop[c];
+    }
+    const float tint = a.tint[g];
+    BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
+    int head = 0, tail = 0;
+    for (int k0 = 0; k0 < K; k0 += 64) {
+      const int k = k0 + lane;
+      const float v = k < K ? live_vis(G, tab, K, k) : 0.f;
+      const bool live = v > 0.f;
+      const uint64_t m = __ballot(live);
+      if (live) {
+        const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
+        qk[wave][slot] = k;
+        qv[wave][slot] = v;
+      }
+      tail += __popcll(m);
+      if (tail - head >= 64) {
+        wave_fence();
+        const int slot = (head + lane) & (kRing - 1);
+        pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
+        head += 64;
+        wave_fence();
+      }
+    }
+    if (tail > head) {
+      wave_fence();
+      if (lane < tail - head) {
+        const int slot = (head + lane) & (kRing - 1);
+        pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
+      }
+      wave_fence();
+    }
+    float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
+                   acc.gco, acc.gga, acc.sd[0], acc.sd[1], acc.sd[2], acc.ts};
+#pragma unroll
+    for (int i = 0; i < 12; ++i) r[i] = rga::wave_sum(r[i]);
+    if (lane == 0) {
+      const float gco = r[6];
+      float gn[3] = {r[0] + gco * G.wo[0], r[1] + gco * G.wo[1], r[2] + gco * G.wo[2]};
+      float gw[3] = {r[3] + gco * G.nn[0], r[4] + gco * G.nn[1], r[5] + gco * G.nn[2]};
+      const float pn = gn[0] * G.nn[0] + gn[1] * G.nn[1] + gn[2] * G.nn[2];
+      const float pw = gw[0] * G.wo[0] + gw[1] * G.wo[1] + gw[2] * G.wo[2];
+      for (int c = 0; c < 3; ++c) {
+        dn[(size_t)c * n + g] = (gn[c] - G.nn[c] * pn) * G.inn;
+        // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
+        dx[(size_t)c * n + g] += -(gw[c] - G.wo[c] * pw) * G.iwo;
+        dalbedo[(size_t)c * n + g] = dLo[c] * r[8 + c] * (1.f / kPi);
+      }
+      drough[g] = r[7];
+      dtint[g] = r[11];
+    }
+  }
+  __syncthreads();
+  float* out = denv_part + (size_t)blockIdx.x * 3 * K;
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) out[i] = denv_lds[i];
+}
+
+// denv[k][c] = area_k * sum over workgroups (fixed order)
+__global__ void __launch_bounds__(256)
+denv_reduce_kernel(int K, int he, int we, int parts, const float* __restrict__ part,
+                   float* __restrict__ denv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * K) return;
+  float s = 0.f;
+  for (int p = 0; p < parts; ++p) s += part[(size_t)p * 3 * K + i];
+  const int k = i / 3, r = k / we;
+  const float dth = kPi / (float)he;
+  const float area = (2.f * kPi / (float)we) * 2.f * sinf(0.5f * dth) * sinf(((float)r + 0.5f) * dth);
+  denv[i] = s * area;
+}
+
+int grid_for(int n, size_t lds) {
+  static int ncu = 0;
+  if (ncu == 0) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+      ncu = 256;
+  }
+  const int per_cu = lds <= 20 * 1024 ? 4 : (lds <= 40 * 1024 ? 3 : (lds <= 76 * 1024 ? 2 : 1));
+  int grid = ncu * per_cu;
+  const int need = (int)rga::ceil_div(n, kWaves);
+  return grid < need ? grid : (need > 0 ? need : 1);
+}
+
+int check_args(const char* fn, int n, const float* x, const float* nrm, const float* albedo,
+               const float* rough, const float* tint, const int32_t* vidx, const float* vw,
+               const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,
+               const float* env, const float* cam_pos, int precision) {
+  if (n < 0) return rga::fail(RGA_EINVAL, "%s: n < 0", fn);
+  if (he < 1 || we < 1 || hv < 1 || wv < 1 || he % hv || we % wv)
+    return rga::fail(RGA_EINVAL, "%s: view grid %dx%d must divide the map %dx%d", fn, hv, wv, he, we);
+  if ((int64_t)he * we > 3584)
+    return rga::fail(RGA_EUNSUPPORTED, "%s: at most 3584 light directions (LDS table)", fn);
+  if (nv < 1 || kv < 1) return rga::fail(RGA_EINVAL, "%s: nv, kv >= 1", fn);
+  if (!cam_pos || !env) return rga::fail(RGA_EINVAL, "%s: null env or cam_pos", fn);
+  if (precision != RGA_FP32 && precision != RGA_BF16X3)
+    return rga::fail(RGA_EINVAL, "%s: unknown precision %d", fn, precision);
+  if (n > 0 && (!x || !nrm || !albedo || !rough || !tint || !vidx || !vw || !count))
+    return rga::fail(RGA_EINVAL, "%s: null input", fn);
+  return RGA_OK;
+}
+
+ShadeArgs make_args(int n, const float* x, const float* nrm, const float* albedo,
+                    const float* rough, const float* tint, const int32_t* vidx, const float* vw,
+                    const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,
+                    const float* env, const float* cam_pos) {
+  ShadeArgs a;
+  a.n = n;
+  a.nv = nv;
+  a.V = hv * wv;
+  a.kv = kv;
+  a.he = he;
+  a.we = we;
+  a.hv = hv;
+  a.wv = wv;
+  a.K = he * we;
+  for (int i = 0; i < 3; ++i) a.cam[i] = cam_pos[i];
+  a.x = x;
+  a.nrm = nrm;
+  a.albedo = albedo;
+  a.rough = rough;
+  a.tint = tint;
+  a.vw = vw;
+  a.env = env;
+  a.vidx = vidx;
+  a.count = count;
+  return a;
+}
+
+}  // namespace
+
+extern "C" int shade_gaussians(void* stream, int n, const float* x, const float* nrm,
+                               const float* albedo, const float* rough, const float* tint,
+                               const int32_t* vidx, const float* vw, const uint8_t* count, int nv,
+                               int kv, int he, int we, int hv, int wv, const float* env,
+                               const float* cam_pos, int precision, float* color,
+                               uint8_t* front) {
+  int rc = check_args("shade_gaussians", n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv,
+                      he, we, hv, wv, env, cam_pos, precision);
+  if (rc) return rc;
+  if (n == 0) return RGA_OK;
+  if (!color || !front) return rga::fail(RGA_EINVAL, "shade_gaussians: null output");
+  if (precision == RGA_BF16X3)
+    return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 form not built yet");
+  ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
+                          env, cam_pos);
+  const size_t lds = (size_t)7 * a.K * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(shade_fwd_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    attr = true;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RGA_LAUNCH("shade_fwd", shade_fwd_kernel, dim3(grid_for(n, lds)), dim3(kThreads), lds, s, a,
+             color, front);
+  RGA_CHECK_LAUNCH("shade_gaussians");
+  return RGA_OK;
+}
+
+extern "C" size_t shade_gaussians_workspace(int n, int he, int we) {
+  if (n < 0 || he < 1 || we < 1) return 0;
+  const size_t K = (size_t)he * we;
+  // at most 4 workgroups per CU on up to 512 CUs
+  return 4 * 512 * 3 * K * sizeof(float);
+}
+
+extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, const float* nrm,
+                                        const float* albedo, const float* rough, const float* tint,
+                                        const int32_t* vidx, const float* vw, const uint8_t* count,
+                                        int nv, int kv, int he, int we, int hv, int wv,
+                                        const float* env, const float* cam_pos, int precision,
+                                        const float* color, const uint8_t* front,
+                                        const float* dcolor, float* dx, float* dn,
+                                        float* dalbedo, float* drough, float* dtint, float* denv,
+                                        void* ws, size_t ws_bytes) {
+  (void)front;
+  int rc = check_args("shade_gaussians_backward", n, x, nrm, albedo, rough, tint, vidx, vw, count,
+                      nv, kv, he, we, hv, wv, env, cam_pos, precision);
+  if (rc) return rc;
+  if (!denv) return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null denv");
+  if (n > 0 && (!color || !dcolor || !dx || !dn || !dalbedo || !drough || !dtint))
+    return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null pointer");
+  if (precision == RGA_BF16X3)
+    return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 form not built yet");
+  ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
+                          env, cam_pos);
+  const size_t lds = (size_t)10 * a.K * sizeof(float);
+  const int grid = grid_for(n, lds);
+  if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
+    return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(shade_bwd_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    attr = true;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  float* part = static_cast<float*>(ws);
+  if (n > 0) {
+    RGA_LAUNCH("shade_bwd", shade_bwd_kernel, dim3(grid), dim3(kThreads), lds, s, a, color, dcolor,
+               dx, dn, dalbedo, drough, dtint, part);
+  }
+  RGA_LAUNCH("shade_denv", denv_reduce_kernel, dim3(rga::ceil_div(3 * a.K, 256)), dim3(256), 0, s,
+             a.K, he, we, n > 0 ? grid : 0, part, denv);
+  RGA_CHECK_LAUNCH("shade_gaussians_backward");
+  return RGA_OK;
+}

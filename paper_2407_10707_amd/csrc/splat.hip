@@ -1,0 +1,1012 @@
+// Tile-based Gaussian splatting (the 3DGS rasterizer used in Sec. 3.1 of the
+// paper): projection, tile binning, depth + tile radix sort, front-to-back
+// alpha compositing, and the hand-written adjoint.
+//
+// Pipeline on one stream, no host synchronisation:
+//   preprocess        1 thread / splat: camera transform, covariance, conic,
+//                     opacity-aware tile rectangle, packed 48-byte record
+//   depth sort        stable LSD radix sort of (depth bits, index) over n
+//                     (4 passes x [upsweep histogram, per-bin scan, ranked
+//                     scatter]); culled splats carry key 0xFFFFFFFF
+//   offsets           exclusive scan of tiles-touched in depth order -> D
+//   duplicate         one (tile, splat) entry per touched tile, emitted in
+//                     depth order
+//   tile sort         stable LSD radix sort of the entries by tile id
+//                     (ceil(log2 tiles / 8) passes) -> per tile, entries in
+//                     (depth bits, index) order
+//   ranges            tile boundaries in the sorted entries
+//   blend             1 workgroup of 256 threads per 16x16 tile; splat
+//                     records staged through LDS in batches of 256
+// Stable ranking inside a radix pass uses wave64 ballots (8 ballots give the
+// lanes that share a digit) and mbcnt-style lane masks.
+#include "common.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int kTile = 16;
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 16;  // per thread
+constexpr int kRadixBlock = kRadixThreads * kRadixItems;
+
+struct Layout {
+  size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
+  size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, grad, total;
+  int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
+};
+
+Layout make_layout(int n, int width, int height, int64_t cap) {
+  Layout L{};
+  L.tiles_x = (width + kTile - 1) / kTile;
+  L.tiles_y = (height + kTile - 1) / kTile;
+  const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
+  L.nb_n = (int)rga::ceil_div(n > 0 ? n : 1, kRadixBlock);
+  L.nb_cap = (int)rga::ceil_div(cap > 0 ? cap : 1, kRadixBlock);
+  L.nb_max = L.nb_n > L.nb_cap ? L.nb_n : L.nb_cap;
+  int bits = 0;
+  while ((1ll << bits) < tiles) ++bits;
+  L.tile_passes = bits <= 8 ? 1 : (bits <= 16 ? 2 : 3);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = rga::align_up(o + bytes, 256);
+    return at;
+  };
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  const size_t C = (size_t)(cap > 0 ? cap : 1);
+  L.rec = take(N * 48);
+  L.mean2d = take(N * 8);
+  L.conic = take(N * 12);
+  L.depth = take(N * 4);
+  L.rect = take(N * 16);
+  L.touched = take(N * 4);
+  L.fp64 = take(N);
+  L.keys0 = take(N * 4);
+  L.vals0 = take(N * 4);
+  L.keys1 = take(N * 4);
+  L.vals1 = take(N * 4);
+  L.offs = take(N * 4);
+  L.tk0 = take(C * 4);
+  L.tv0 = take(C * 4);
+  L.tk1 = take(C * 4);
+  L.tv1 = take(C * 4);
+  L.ranges = take((size_t)tiles * 8);
+  L.hist = take((size_t)L.nb_max * 256 * 4);
+  L.binoff = take((size_t)L.nb_max * 256 * 4);
+  L.bintot = take(256 * 4);
+  L.bsum = take((size_t)L.nb_n * 4);
+  L.boff = take((size_t)L.nb_n * 4);
+  L.count = take(16);
+  L.grad = take(N * 5 * 4);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+__device__ __host__ inline T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+struct CamDev {
+  float R[9], t[3], fx, fy, cx, cy;
+  int W, H;
+};
+
+CamDev to_dev(const rga_camera* c) {
+  CamDev d;
+  for (int i = 0; i < 9; ++i) d.R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c->t[i];
+  d.fx = c->fx;
+  d.fy = c->fy;
+  d.cx = c->cx;
+  d.cy = c->cy;
+  d.W = c->width;
+  d.H = c->height;
+  return d;
+}
+
+// exp for the scales: Cody-Waite reduction by ln 2, degree-7 Taylor
+// polynomial, fixed FP32 operation order (reproducible bit for bit).
+__device__ inline float exp_repro(float x) {
+  x = fminf(fmaxf(x, -87.f), 88.f);
+  const float k = rintf(x * 1.44269502f);
+  float r = fmaf(-k, 0.693145752f, x);
+  r = fmaf(-k, 1.42860677e-6f, r);
+  float p = 1.f / 5040.f;
+  p = fmaf(p, r, 1.f / 720.f);
+  p = fmaf(p, r, 1.f / 120.f);
+  p = fmaf(p, r, 1.f / 24.f);
+  p = fmaf(p, r, 1.f / 6.f);
+  p = fmaf(p, r, 0.5f);
+  p = fmaf(p, r, 1.f);
+  p = fmaf(p, r, 1.f);
+  return ldexpf(p, (int)k);
+}
+
+// Upper bound of ln y (y >= 1) from exact operations: y = m 2^e, m in [1,2),
+// ln y <= e ln 2 + (m - 1) / sqrt(m).
+__device__ inline float ln_upper(float y) {
+  int e;
+  const float m = frexpf(y, &e) * 2.f;
+  return (float)(e - 1) * 0.693147182f + (m - 1.f) / sqrtf(m);
+}
+
+// ---- forward geometry shared by preprocess and its adjoint ----------------
+struct Geo {
+  float X, Y, Z, xzr, yzr, J00, J11, J02, J12;
+  float s[3], q[4], inv, Rq[9], A[9], M[9], V[9], T[6];
+  float a, b, c;
+};
+
+__device__ inline void geo_forward(const CamDev& cam, const float* __restrict__ x,
+                                   const float* __restrict__ A, const float* __restrict__ quat,
+                                   const float* __restrict__ log_s, int n, int g, Geo& G,
+                                   bool& ok_quat) {
+  const float* Rc = cam.R;
+  const float x0 = x[g], x1 = x[n + g], x2 = x[2 * n + g];
+  G.X = fmaf(Rc[2], x2, fmaf(Rc[1], x1, fmaf(Rc[0], x0, cam.t[0])));
+  G.Y = fmaf(Rc[5], x2, fmaf(Rc[4], x1, fmaf(Rc[3], x0, cam.t[1])));
+  G.Z = fmaf(Rc[8], x2, fmaf(Rc[7], x1, fmaf(Rc[6], x0, cam.t[2])));
+  for (int j = 0; j < 3; ++j) G.s[j] = exp_repro(log_s[j * n + g]);
+  const float q0 = quat[g], q1 = quat[n + g], q2 = quat[2 * n + g], q3 = quat[3 * n + g];
+  const float qq = fmaf(q3, q3, fmaf(q2, q2, fmaf(q1, q1, q0 * q0)));
+  ok_quat = qq > 0.f;
+  G.inv = 1.f / sqrtf(ok_quat ? qq : 1.f);
+  const float qw = q0 * G.inv, qx = q1 * G.inv, qy = q2 * G.inv, qz = q3 * G.inv;
+  G.q[0] = qw;
+  G.q[1] = qx;
+  G.q[2] = qy;
+  G.q[3] = qz;
+  const float xx = qx * qx, yy = qy * qy, zz = qz * qz;
+  const float xy = qx * qy, xz = qx * qz, yz = qy * qz;
+  const float wx = qw * qx, wy = qw * qy, wz = qw * qz;
+  G.Rq[0] = 1.f - 2.f * (yy + zz);
+  G.Rq[1] = 2.f * (xy - wz);
+  G.Rq[2] = 2.f * (xz + wy);
+  G.Rq[3] = 2.f * (xy + wz);
+  G.Rq[4] = 1.f - 2.f * (xx + zz);
+  G.Rq[5] = 2.f * (yz - wx);
+  G.Rq[6] = 2.f * (xz - wy);
+  G.Rq[7] = 2.f * (yz + wx);
+  G.Rq[8] = 1.f - 2.f * (xx + yy);
+  for (int k = 0; k < 9; ++k) G.A[k] = A[k * n + g];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      G.M[3 * i + j] = fmaf(G.A[3 * i + 2], G.Rq[6 + j],
+                            fmaf(G.A[3 * i + 1], G.Rq[3 + j], G.A[3 * i] * G.Rq[j])) * G.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      G.V[3 * i + j] = fmaf(Rc[3 * i + 2], G.M[6 + j], fmaf(Rc[3 * i + 1], G.M[3 + j], Rc[3 * i] * G.M[j]));
+  G.xzr = G.X / G.Z;
+  G.yzr = G.Y / G.Z;
+  G.J00 = cam.fx / G.Z;
+  G.J11 = cam.fy / G.Z;
+  G.J02 = -(G.J00 * G.xzr);
+  G.J12 = -(G.J11 * G.yzr);
+  for (int j = 0; j < 3; ++j) {
+    G.T[j] = fmaf(G.J02, G.V[6 + j], G.J00 * G.V[j]);
+    G.T[3 + j] = fmaf(G.J12, G.V[6 + j], G.J11 * G.V[3 + j]);
+  }
+  G.a = fmaf(G.T[2], G.T[2], fmaf(G.T[1], G.T[1], G.T[0] * G.T[0])) + 0.3f;
+  G.b = fmaf(G.T[2], G.T[5], fmaf(G.T[1], G.T[4], G.T[0] * G.T[3]));
+  G.c = fmaf(G.T[5], G.T[5], fmaf(G.T[4], G.T[4], G.T[3] * G.T[3])) + 0.3f;
+}
+
+// FP64 2x2 covariance of a near-degenerate splat from the same FP32 inputs.
+struct Geo64 {
+  double M[9], V[9], T[6], J00, J11, J02, J12, a, b, c, det;
+};
+
+__device__ inline void geo_forward64(const CamDev& cam, const Geo& G, Geo64& D) {
+  const float* Rc = cam.R;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      D.M[3 * i + j] = fma((double)G.A[3 * i + 2], (double)G.Rq[6 + j],
+                           fma((double)G.A[3 * i + 1], (double)G.Rq[3 + j],
+                               (double)G.A[3 * i] * (double)G.Rq[j])) * (double)G.s[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      D.V[3 * i + j] = fma((double)Rc[3 * i + 2], D.M[6 + j],
+                           fma((double)Rc[3 * i + 1], D.M[3 + j], (double)Rc[3 * i] * D.M[j]));
+  const double Zd = (double)G.Z;
+  D.J00 = (double)cam.fx / Zd;
+  D.J11 = (double)cam.fy / Zd;
+  D.J02 = -(D.J00 * ((double)G.X / Zd));
+  D.J12 = -(D.J11 * ((double)G.Y / Zd));
+  for (int j = 0; j < 3; ++j) {
+    D.T[j] = fma(D.J02, D.V[6 + j], D.J00 * D.V[j]);
+    D.T[3 + j] = fma(D.J12, D.V[6 + j], D.J11 * D.V[3 + j]);
+  }
+  D.a = fma(D.T[2], D.T[2], fma(D.T[1], D.T[1], D.T[0] * D.T[0])) + 0.3;
+  D.b = fma(D.T[2], D.T[5], fma(D.T[1], D.T[4], D.T[0] * D.T[3]));
+  D.c = fma(D.T[5], D.T[5], fma(D.T[4], D.T[4], D.T[3] * D.T[3])) + 0.3;
+  D.det = fma(D.a, D.c, -(D.b * D.b));
+}
+
+// ---- preprocess -------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x,
+                  const float* __restrict__ A, const float* __restrict__ quat,
+                  const float* __restrict__ log_s, const float* __restrict__ opac,
+                  const float* __restrict__ color, const uint8_t* __restrict__ front,
+                  float4* __restrict__ rec, float* __restrict__ mean2d, float* __restrict__ conic,
+                  float* __restrict__ depth, int32_t* __restrict__ rect,
+                  int32_t* __restrict__ touched, uint8_t* __restrict__ fp64,
+                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Geo G;
+  bool okq;
+  geo_forward(cam, x, A, quat, log_s, n, g, G, okq);
+  const float o = opac[g];
+  bool valid = (G.Z > 0.2f) && front[g] && (o >= 1.f / 255.f) && okq;
+  float ca = 0.f, cb = 0.f, cc = 0.f;
+  uint8_t used64 = 0;
+  if (valid) {
+    const float det = fmaf(G.a, G.c, -(G.b * G.b));
+    if (det <= (G.a * G.c) * 0x1p-12f) {
+      Geo64 D;
+      geo_forward64(cam, G, D);
+      if (D.det > 0.0) {
+        ca = (float)(D.c / D.det);
+        cb = (float)(-D.b / D.det);
+        cc = (float)(D.a / D.det);
+        used64 = 1;
+      } else {
+        valid = false;
+      }
+    } else {
+      ca = G.c / det;
+      cb = -G.b / det;
+      cc = G.a / det;
+    }
+  }
+  const float u = fmaf(cam.fx, G.xzr, cam.cx);
+  const float v = fmaf(cam.fy, G.yzr, cam.cy);
+  int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1, cnt = 0;
+  if (valid) {
+    const float r2 = 2.f * ln_upper(255.f * o);
+    const float hx = sqrtf(r2 * G.a) * 1.001f + 1e-3f;
+    const float hy = sqrtf(r2 * G.c) * 1.001f + 1e-3f;
+    float fx0 = floorf((u - hx) * 0.0625f), fx1 = floorf((u + hx) * 0.0625f);
+    float fy0 = floorf((v - hy) * 0.0625f), fy1 = floorf((v + hy) * 0.0625f);
+    const bool finite = (fx0 == fx0) && (fx1 == fx1) && (fy0 == fy0) && (fy1 == fy1);
+    fx0 = fmaxf(fx0, 0.f);
+    fy0 = fmaxf(fy0, 0.f);
+    fx1 = fminf(fx1, (float)(TX - 1));
+    fy1 = fminf(fy1, (float)(TY - 1));
+    if (finite && fx0 <= fx1 && fy0 <= fy1) {
+      tx0 = (int)fx0;
+      ty0 = (int)fy0;
+      tx1 = (int)fx1;
+      ty1 = (int)fy1;
+      cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    }
+  }
+  rec[3 * g + 0] = make_float4(u, v, ca, cb);
+  rec[3 * g + 1] = make_float4(cc, o, color[g], color[n + g]);
+  rec[3 * g + 2] = make_float4(color[2 * n + g], 0.f, 0.f, 0.f);
+  mean2d[g] = valid ? u : 0.f;
+  mean2d[n + g] = valid ? v : 0.f;
+  conic[g] = ca;
+  conic[n + g] = cb;
+  conic[2 * n + g] = cc;
+  depth[g] = G.Z;
+  rect[g] = tx0;
+  rect[n + g] = ty0;
+  rect[2 * n + g] = tx1;
+  rect[3 * n + g] = ty1;
+  touched[g] = cnt;
+  fp64[g] = used64;
+  keys[g] = cnt > 0 ? __float_as_uint(G.Z) : 0xFFFFFFFFu;
+  vals[g] = (uint32_t)g;
+}
+
+// ---- radix sort (reduce-then-scan, stable) ----------------------------------
+__device__ inline int64_t live_count(const int64_t* cnt_ptr, int64_t fixed, int64_t cap) {
+  int64_t c = cnt_ptr ? *cnt_ptr : fixed;
+  return c < cap ? c : cap;
+}
+
+__global__ void __launch_bounds__(kRadixThreads)
+radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t fixed,
+              int64_t cap, int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t count = live_count(cnt_ptr, fixed, cap);
+  const int64_t base = (int64_t)blockIdx.x * kRadixBlock;
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = base + (int64_t)r * kRadixThreads + threadIdx.x;
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+}
+
+// One workgroup per digit: exclusive scan of that digit's counts over blocks.
+__global__ void __launch_bounds__(256)
+radix_binscan(const uint32_t* __restrict__ hist, int nb, uint32_t* __restrict__ binoff,
+              uint32_t* __restrict__ bintot) {
+  __shared__ uint32_t part[256];
+  const int bin = blockIdx.x;
+  const int chunk = (nb + 255) / 256;
+  const int j0 = threadIdx.x * chunk;
+  const int j1 = min(nb, j0 + chunk);
+  uint32_t s = 0;
+  for (int j = j0; j < j1; ++j) s += hist[(size_t)j * 256 + bin];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over 256 partial sums
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int j = j0; j < j1; ++j) {
+    const uint32_t c = hist[(size_t)j * 256 + bin];
+    binoff[(size_t)j * 256 + bin] = run;
+    run += c;
+  }
+  if (threadIdx.x == 255) bintot[bin] = part[255];
+}
+
+__global__ void __launch_bounds__(kRadixThreads)
+radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
+                const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[4][256];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // global exclusive offset of each digit + this block's offset inside it
+  base[tid] = bintot[tid];
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint32_t v = tid >= o ? base[tid - o] : 0u;
+    __syncthreads();
+    base[tid] += v;
+    __syncthreads();
+  }
+  uint32_t excl = (tid ? base[tid - 1] : 0u) + binoff[(size_t)blockIdx.x * 256 + tid];
+  __syncthreads();
+  base[tid] = excl;
+  const int64_t count = live_count(cnt_ptr, fixed, cap);
+  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = blk + (int64_t)r * kRadixThreads + tid;
+    const bool ok = i < count;
+    const uint32_t key = ok ? kin[i] : 0u;
+    const uint32_t val = ok ? vin[i] : 0u;
+    const uint32_t d = (key >> shift) & 255u;
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    wcnt[0][tid] = 0;
+    wcnt[1][tid] = 0;
+    wcnt[2][tid] = 0;
+    wcnt[3][tid] = 0;
+    __syncthreads();
+    if (ok && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    {
+      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+      const uint32_t b0 = base[tid];
+      wcnt[0][tid] = b0;
+      wcnt[1][tid] = b0 + c0;
+      wcnt[2][tid] = b0 + c0 + c1;
+      wcnt[3][tid] = b0 + c0 + c1 + c2;
+      base[tid] = b0 + c0 + c1 + c2 + c3;
+    }
+    __syncthreads();
+    if (ok) {
+      const uint32_t pos = wcnt[wave][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- exclusive scan of tiles-touched in depth order -> offsets, D ---------
+__global__ void __launch_bounds__(kRadixThreads)
+touched_blocksum(int n, const uint32_t* __restrict__ order, const int32_t* __restrict__ touched,
+                 uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t red[kRadixThreads];
+  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
+  uint32_t s = 0;
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = blk + (int64_t)r * kRadixThreads + threadIdx.x;
+    if (i < n) s += (uint32_t)touched[order[i]];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kRadixThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256)
+touched_blockscan(int nb, const uint32_t* __restrict__ bsum, uint32_t* __restrict__ boff,
+                  int64_t* __restrict__ count) {
+  __shared__ uint64_t part[256];
+  const int chunk = (nb + 255) / 256;
+  const int j0 = threadIdx.x * chunk, j1 = min(nb, j0 + chunk);
+  uint64_t s = 0;
+  for (int j = j0; j < j1; ++j) s += bsum[j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+  for (int j = j0; j < j1; ++j) {
+    boff[j] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
+    run += bsum[j];
+  }
+  if (threadIdx.x == 255) count[0] = (int64_t)part[255];
+}
+
+__global__ void __launch_bounds__(kRadixThreads)
+duplicate_kernel(int n, int TX, int64_t cap, const uint32_t* __restrict__ order,
+                 const int32_t* __restrict__ touched, const int32_t* __restrict__ rect,
+                 const uint32_t* __restrict__ boff, uint32_t* __restrict__ tkeys,
+                 uint32_t* __restrict__ tvals) {
+  // in-block exclusive scan of tiles-touched, then emission
+  __shared__ uint32_t sc[kRadixThreads];
+  const int tid = threadIdx.x;
+  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
+  uint32_t loc[kRadixItems];
+  uint32_t s = 0;
+  // thread tid owns items blk + tid*kRadixItems + r (contiguous run)
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = blk + (int64_t)tid * kRadixItems + r;
+    loc[r] = i < n ? (uint32_t)touched[order[i]] : 0u;
+    s += loc[r];
+  }
+  sc[tid] = s;
+  __syncthreads();
+  for (int o = 1; o < kRadixThreads; o <<= 1) {
+    uint32_t v = tid >= o ? sc[tid - o] : 0u;
+    __syncthreads();
+    sc[tid] += v;
+    __syncthreads();
+  }
+  uint64_t off = (uint64_t)boff[blockIdx.x] + (tid ? sc[tid - 1] : 0u);
+  for (int r = 0; r < kRadixItems; ++r) {
+    const int64_t i = blk + (int64_t)tid * kRadixItems + r;
+    if (i >= n || loc[r] == 0) continue;
+    const uint32_t g = order[i];
+    const int x0 = rect[g], y0 = rect[n + g], x1 = rect[2 * n + g], y1 = rect[3 * n + g];
+    for (int ty = y0; ty <= y1; ++ty)
+      for (int tx = x0; tx <= x1; ++tx) {
+        if ((int64_t)off < cap) {
+          tkeys[off] = (uint32_t)(ty * TX + tx);
+          tvals[off] = g;
+        }
+        ++off;
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+fill_u32(uint32_t* __restrict__ p, int64_t count, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256)
+tile_ranges_kernel(const uint32_t* __restrict__ tkeys, const int64_t* cnt_ptr, int64_t cap,
+                   int32_t* __restrict__ ranges) {
+  const int64_t count = live_count(cnt_ptr, 0, cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t t = tkeys[i];
+  if (i == 0 || tkeys[i - 1] != t) ranges[2 * t] = (int32_t)i;
+  if (i == count - 1 || tkeys[i + 1] != t) ranges[2 * t + 1] = (int32_t)(i + 1);
+}
+
+// ---- blend ------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+blend_fwd_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+                 const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                 float* __restrict__ image, float* __restrict__ Tfinal) {
+  __shared__ float4 s0[256], s1[256], s2[256];
+  const int t = blockIdx.x;
+  const int tx = t % TX, ty = t / TX;
+  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < W && py < H;
+  const int start = ranges[2 * t], end = ranges[2 * t + 1];
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool done = !inside;
+  for (int b = start; b < end; b += 256) {
+    if (__syncthreads_count(done) == 256) break;
+    const int e = b + threadIdx.x;
+    if (e < end) {
+      const uint32_t g = sorted[e];
+      s0[threadIdx.x] = rec[3 * g];
+      s1[threadIdx.x] = rec[3 * g + 1];
+      s2[threadIdx.x] = rec[3 * g + 2];
+    }
+    __syncthreads();
+    const int cnt = min(256, end - b);
+    for (int j = 0; j < cnt && !done; ++j) {
+      const float4 a = s0[j], c1 = s1[j];
+      const float dx = a.x - fpx, dy = a.y - fpy;
+      const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
+      const float power = -0.5f * qf;
+      if (power > 0.f) continue;
+      const float alpha = fminf(0.99f, c1.y * expf(power));
+      if (alpha < 1.f / 255.f) continue;
+      const float Tn = T * (1.f - alpha);
+      if (Tn < 1e-4f) {
+        done = true;
+        break;
+      }
+      const float w = alpha * T;
+      C0 = fmaf(c1.z, w, C0);
+      C1 = fmaf(c1.w, w, C1);
+      C2 = fmaf(s2[j].x, w, C2);
+      T = Tn;
+    }
+  }
+  if (inside) {
+    const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
+    image[p] = C0;
+    image[HW + p] = C1;
+    image[2 * HW + p] = C2;
+    Tfinal[p] = T;
+  }
+}
+
+// ---- adjoint: blend ----------------------------------------------------------
+// Per pixel, walking the same list front to back with the same decisions:
+//   dL/dc_i     = alpha_i T_i g
+//   dL/dalpha_i = sum_c g_c (c_ic T_i - (C_c - C_<=i,c) / (1 - alpha_i))
+// with C the forward colour, then alpha = o exp(power) (unless clamped).
+// Per-splat sums over the tile's pixels: wave reduction, then the four
+// waves' partials are added in LDS and one set of atomics per (tile, splat).
+__global__ void __launch_bounds__(256)
+blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
+                 const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                 const float* __restrict__ image, const float* __restrict__ dimage,
+                 float* __restrict__ gmean_conic /*[5][n]*/, float* __restrict__ dopac,
+                 float* __restrict__ dcolor) {
+  __shared__ float4 s0[256], s1[256], s2[256];
+  __shared__ uint32_t sg[256];
+  __shared__ float part[4][9][64];
+  const int t = blockIdx.x;
+  const int tx = t % TX, ty = t / TX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < W && py < H;
+  const int start = ranges[2 * t], end = ranges[2 * t + 1];
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  float Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
+  if (inside) {
+    const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
+    Cf0 = image[p];
+    Cf1 = image[HW + p];
+    Cf2 = image[2 * HW + p];
+    g0 = dimage[p];
+    g1 = dimage[HW + p];
+    g2 = dimage[2 * HW + p];
+  }
+  float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
+  bool done = !inside;
+  for (int b = start; b < end; b += 256) {
+    if (__syncthreads_count(done) == 256) break;
+    const int e = b + threadIdx.x;
+    if (e < end) {
+      const uint32_t g = sorted[e];
+      sg[threadIdx.x] = g;
+      s0[threadIdx.x] = rec[3 * g];
+      s1[threadIdx.x] = rec[3 * g + 1];
+      s2[threadIdx.x] = rec[3 * g + 2];
+    }
+    __syncthreads();
+    const int cnt = min(256, end - b);
+    for (int j0 = 0; j0 < cnt; j0 += 64) {
+      const int jn = min(64, cnt - j0);
+      for (int jj = 0; jj < jn; ++jj) {
+        const int j = j0 + jj;
+        float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bool contrib = false;
+        if (!done) {
+          const float4 a = s0[j], c1 = s1[j];
+          const float dx = a.x - fpx, dy = a.y - fpy;
+          const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
+          const float power = -0.5f * qf;
+          if (power <= 0.f) {
+            const float G = expf(power);
+            const float araw = c1.y * G;
+            const float alpha = fminf(0.99f, araw);
+            if (alpha >= 1.f / 255.f) {
+              const float Tn = T * (1.f - alpha);
+              if (Tn < 1e-4f) {
+                done = true;
+              } else {
+                contrib = true;
+                const float col0 = c1.z, col1 = c1.w, col2 = s2[j].x;
+                const float w = alpha * T;
+                A0 = fmaf(col0, w, A0);
+                A1 = fmaf(col1, w, A1);
+                A2 = fmaf(col2, w, A2);
+                v[6] = w * g0;
+                v[7] = w * g1;
+                v[8] = w * g2;
+                const float inv1m = 1.f / (1.f - alpha);
+                const float dal = g0 * (col0 * T - (Cf0 - A0) * inv1m) +
+                                  g1 * (col1 * T - (Cf1 - A1) * inv1m) +
+                                  g2 * (col2 * T - (Cf2 - A2) * inv1m);
+                if (araw <= 0.99f) {
+                  v[5] = dal * G;                       // d/d opacity
+                  const float dp = dal * alpha;         // d/d power
+                  v[0] = -dp * (a.z * dx + a.w * dy);   // d/d mean x
+                  v[1] = -dp * (a.w * dx + c1.x * dy);  // d/d mean y
+                  v[2] = -0.5f * dp * dx * dx;          // d/d conic A
+                  v[3] = -dp * dx * dy;                 // d/d conic B
+                  v[4] = -0.5f * dp * dy * dy;          // d/d conic C
+                }
+                T = Tn;
+              }
+            }
+          }
+        }
+        const bool any = __ballot(contrib) != 0ull;
+        if (any) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) v[k] = rga::wave_sum(v[k]);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) part[wave][k][jj] = any ? v[k] : 0.f;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < jn) {
+        const int jj = threadIdx.x;
+        const uint32_t g = sg[j0 + jj];
+        float s[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s[k] = part[0][k][jj] + part[1][k][jj] + part[2][k][jj] + part[3][k][jj];
+        bool nz = false;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) nz |= s[k] != 0.f;
+        if (nz) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) atomicAdd(&gmean_conic[(size_t)k * n + g], s[k]);
+          atomicAdd(&dopac[g], s[5]);
+          atomicAdd(&dcolor[g], s[6]);
+          atomicAdd(&dcolor[(size_t)n + g], s[7]);
+          atomicAdd(&dcolor[(size_t)2 * n + g], s[8]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---- adjoint: projection --------------------------------------------------
+template <typename R>
+struct Chain {
+  // Inputs: forward quantities in precision R and upstream gradients.
+  // Outputs: camera-space gradient gXYZ, dRq (3x3), ds (3).
+  static __device__ void run(const CamDev& cam, const R* Tm, const R* Vm, R J00, R J11, R J02,
+                             R J12, R X, R Y, R Z, R ca, R cb, R cc, R dca, R dcb, R dcc, R du,
+                             R dv, R* gM /*3x3 out*/, R* gXYZ) {
+    const R h = dcb * R(0.5);
+    const R P00 = dca * ca + h * cb, P01 = dca * cb + h * cc;
+    const R P10 = h * ca + dcc * cb, P11 = h * cb + dcc * cc;
+    const R S00 = -(ca * P00 + cb * P10);
+    const R S01 = -(ca * P01 + cb * P11);
+    const R S11 = -(cb * P01 + cc * P11);
+    R gT[6];
+    for (int j = 0; j < 3; ++j) {
+      gT[j] = R(2) * (S00 * Tm[j] + S01 * Tm[3 + j]);
+      gT[3 + j] = R(2) * (S01 * Tm[j] + S11 * Tm[3 + j]);
+    }
+    R gJ00 = 0, gJ02 = 0, gJ11 = 0, gJ12 = 0;
+    for (int j = 0; j < 3; ++j) {
+      gJ00 += gT[j] * Vm[j];
+      gJ02 += gT[j] * Vm[6 + j];
+      gJ11 += gT[3 + j] * Vm[3 + j];
+      gJ12 += gT[3 + j] * Vm[6 + j];
+    }
+    R gV[9];
+    for (int j = 0; j < 3; ++j) {
+      gV[j] = J00 * gT[j];
+      gV[3 + j] = J11 * gT[3 + j];
+      gV[6 + j] = J02 * gT[j] + J12 * gT[3 + j];
+    }
+    const R fx = (R)cam.fx, fy = (R)cam.fy;
+    const R iz = R(1) / Z, iz2 = iz * iz, iz3 = iz2 * iz;
+    R gX = gJ02 * (-fx * iz2) + du * fx * iz;
+    R gY = gJ12 * (-fy * iz2) + dv * fy * iz;
+    R gZ = gJ00 * (-fx * iz2) + gJ02 * (R(2) * fx * X * iz3) + gJ11 * (-fy * iz2) +
+           gJ12 * (R(2) * fy * Y * iz3) - du * fx * X * iz2 - dv * fy * Y * iz2;
+    gXYZ[0] = gX;
+    gXYZ[1] = gY;
+    gXYZ[2] = gZ;
+    // gM = Rc^T gV
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        gM[3 * i + j] = (R)cam.R[i] * gV[j] + (R)cam.R[3 + i] * gV[3 + j] + (R)cam.R[6 + i] * gV[6 + j];
+  }
+};
+
+__global__ void __launch_bounds__(256)
+preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const float* __restrict__ A,
+                      const float* __restrict__ quat, const float* __restrict__ log_s,
+                      const float* __restrict__ opac, const uint8_t* __restrict__ front,
+                      const float* __restrict__ gmc, float* __restrict__ dx,
+                      float* __restrict__ dquat, float* __restrict__ dlog_s) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  Geo G;
+  bool okq;
+  geo_forward(cam, x, A, quat, log_s, n, g, G, okq);
+  bool valid = (G.Z > 0.2f) && front[g] && (opac[g] >= 1.f / 255.f) && okq;
+  float gM[9], gXYZ[3];
+  if (valid) {
+    const float du = gmc[g], dv = gmc[(size_t)n + g];
+    const float dca = gmc[(size_t)2 * n + g], dcb = gmc[(size_t)3 * n + g], dcc = gmc[(size_t)4 * n + g];
+    const float det = fmaf(G.a, G.c, -(G.b * G.b));
+    if (det <= (G.a * G.c) * 0x1p-12f) {
+      Geo64 D;
+      geo_forward64(cam, G, D);
+      if (D.det > 0.0) {
+        const double ca = D.c / D.det, cb = -D.b / D.det, cc = D.a / D.det;
+        double gM64[9], g64[3];
+        Chain<double>::run(cam, D.T, D.V, D.J00, D.J11, D.J02, D.J12, (double)G.X, (double)G.Y,
+                           (double)G.Z, ca, cb, cc, dca, dcb, dcc, du, dv, gM64, g64);
+        for (int k = 0; k < 9; ++k) gM[k] = (float)gM64[k];
+        for (int k = 0; k < 3; ++k) gXYZ[k] = (float)g64[k];
+      } else {
+        valid = false;
+      }
+    } else {
+      const float ca = G.c / det, cb = -G.b / det, cc = G.a / det;
+      Chain<float>::run(cam, G.T, G.V, G.J00, G.J11, G.J02, G.J12, G.X, G.Y, G.Z, ca, cb, cc, dca,
+                        dcb, dcc, du, dv, gM, gXYZ);
+    }
+  }
+  if (!valid) {
+    for (int k = 0; k < 3; ++k) dx[(size_t)k * n + g] = 0.f;
+    for (int k = 0; k < 4; ++k) dquat[(size_t)k * n + g] = 0.f;
+    for (int k = 0; k < 3; ++k) dlog_s[(size_t)k * n + g] = 0.f;
+    return;
+  }
+  // x' -> camera: dx' = Rc^T gXYZ
+  for (int k = 0; k < 3; ++k)
+    dx[(size_t)k * n + g] = cam.R[k] * gXYZ[0] + cam.R[3 + k] * gXYZ[1] + cam.R[6 + k] * gXYZ[2];
+  // M = (A Rq) diag(s)
+  float B[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      B[3 * i + j] = G.A[3 * i] * G.Rq[j] + G.A[3 * i + 1] * G.Rq[3 + j] + G.A[3 * i + 2] * G.Rq[6 + j];
+  float gB[9];
+  for (int j = 0; j < 3; ++j) {
+    float gs = 0.f;
+    for (int i = 0; i < 3; ++i) {
+      gs += gM[3 * i + j] * B[3 * i + j];
+      gB[3 * i + j] = gM[3 * i + j] * G.s[j];
+    }
+    dlog_s[(size_t)j * n + g] = gs * G.s[j];
+  }
+  // gRq = A^T gB
+  float gR[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      gR[3 * i + j] = G.A[i] * gB[j] + G.A[3 + i] * gB[3 + j] + G.A[6 + i] * gB[6 + j];
+  const float w = G.q[0], qx = G.q[1], qy = G.q[2], qz = G.q[3];
+  float gw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+  float gx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - w * gR[5] +
+                    qz * gR[6] + w * gR[7] - 2.f * qx * gR[8]);
+  float gy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + w * gR[2] + qx * gR[3] + qz * gR[5] -
+                    w * gR[6] + qz * gR[7] - 2.f * qy * gR[8]);
+  float gz = 2.f * (-2.f * qz * gR[0] - w * gR[1] + qx * gR[2] + w * gR[3] - 2.f * qz * gR[4] +
+                    qy * gR[5] + qx * gR[6] + qy * gR[7]);
+  const float dot = w * gw + qx * gx + qy * gy + qz * gz;
+  dquat[g] = (gw - w * dot) * G.inv;
+  dquat[(size_t)n + g] = (gx - qx * dot) * G.inv;
+  dquat[(size_t)2 * n + g] = (gy - qy * dot) * G.inv;
+  dquat[(size_t)3 * n + g] = (gz - qz * dot) * G.inv;
+}
+
+__global__ void __launch_bounds__(256)
+zero_f32(float* __restrict__ a, int64_t na, float* __restrict__ b, int64_t nb,
+         float* __restrict__ c, int64_t nc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < na) a[i] = 0.f;
+  if (i < nb) b[i] = 0.f;
+  if (i < nc) c[i] = 0.f;
+}
+
+int check_common(const char* fn, int n, const rga_camera* cam, const void* ws, size_t ws_bytes,
+                 int64_t cap, Layout& L) {
+  if (n < 0) return rga::fail(RGA_EINVAL, "%s: n < 0", fn);
+  if (!cam) return rga::fail(RGA_EINVAL, "%s: null camera", fn);
+  if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
+    return rga::fail(RGA_EINVAL, "%s: image size must be in 1..16384", fn);
+  if (cap < 1 || cap > 0x7FFFFFFFll) return rga::fail(RGA_EINVAL, "%s: capacity must be in 1..2^31-1", fn);
+  if (n > 0x7FFFFFFF / 16) return rga::fail(RGA_EUNSUPPORTED, "%s: n too large", fn);
+  L = make_layout(n, cam->width, cam->height, cap);
+  if (!ws) return rga::fail(RGA_EINVAL, "%s: null workspace", fn);
+  if (!rga::aligned16(ws)) return rga::fail(RGA_EINVAL, "%s: workspace must be 16-byte aligned", fn);
+  if (ws_bytes < L.total)
+    return rga::fail(RGA_ECAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, L.total);
+  return RGA_OK;
+}
+
+}  // namespace
+
+extern "C" size_t splat_workspace_size(int n, int width, int height, int64_t capacity) {
+  if (n < 0 || width < 1 || height < 1 || capacity < 1) return 0;
+  return make_layout(n, width, height, capacity).total;
+}
+
+extern "C" int splat_state(void* ws, int n, int width, int height, int64_t capacity,
+                           rga_splat_state* st) {
+  if (!ws || !st || n < 0 || width < 1 || height < 1 || capacity < 1)
+    return rga::fail(RGA_EINVAL, "splat_state: bad argument");
+  Layout L = make_layout(n, width, height, capacity);
+  st->mean2d = at<float>(ws, L.mean2d);
+  st->conic = at<float>(ws, L.conic);
+  st->depth = at<float>(ws, L.depth);
+  st->rect = at<int32_t>(ws, L.rect);
+  st->touched = at<int32_t>(ws, L.touched);
+  st->fp64 = at<uint8_t>(ws, L.fp64);
+  // after the tile sort the entries sit in the buffer of the final pass
+  st->sorted = at<int32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
+  st->ranges = at<int32_t>(ws, L.ranges);
+  st->count = at<int64_t>(ws, L.count);
+  st->tiles_x = L.tiles_x;
+  st->tiles_y = L.tiles_y;
+  return RGA_OK;
+}
+
+extern "C" int splat_read_count(void* stream, const void* ws, int n, int width, int height,
+                                int64_t capacity, int64_t* D) {
+  if (!ws || !D || n < 0 || width < 1 || height < 1 || capacity < 1)
+    return rga::fail(RGA_EINVAL, "splat_read_count: bad argument");
+  Layout L = make_layout(n, width, height, capacity);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int64_t h = 0;
+  if (hipMemcpyAsync(&h, at<int64_t>(const_cast<void*>(ws), L.count), sizeof(int64_t),
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return rga::fail(RGA_EHIP, "splat_read_count: copy failed");
+  *D = h;
+  return RGA_OK;
+}
+
+extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const float* x,
+                             const float* A, const float* quat, const float* log_s,
+                             const float* opac, const float* color, const uint8_t* front,
+                             void* ws, size_t ws_bytes, int64_t capacity, float* image,
+                             float* T_final) {
+  Layout L;
+  int rc = check_common("splat_forward", n, cam, ws, ws_bytes, capacity, L);
+  if (rc) return rc;
+  if (!image || !T_final) return rga::fail(RGA_EINVAL, "splat_forward: null output");
+  if (n > 0 && (!x || !A || !quat || !log_s || !opac || !color || !front))
+    return rga::fail(RGA_EINVAL, "splat_forward: null input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const CamDev cd = to_dev(cam);
+  const int W = cam->width, H = cam->height;
+  const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
+  int64_t* cnt = at<int64_t>(ws, L.count);
+  uint32_t* k0 = at<uint32_t>(ws, L.keys0);
+  uint32_t* v0 = at<uint32_t>(ws, L.vals0);
+  uint32_t* k1 = at<uint32_t>(ws, L.keys1);
+  uint32_t* v1 = at<uint32_t>(ws, L.vals1);
+  uint32_t* hist = at<uint32_t>(ws, L.hist);
+  uint32_t* binoff = at<uint32_t>(ws, L.binoff);
+  uint32_t* bintot = at<uint32_t>(ws, L.bintot);
+  int32_t* ranges = at<int32_t>(ws, L.ranges);
+  // ranges := empty; count := 0 (for n == 0)
+  RGA_LAUNCH("splat_fill", fill_u32, dim3(rga::ceil_div(2 * tiles + 4, 256)), dim3(256), 0, s,
+             reinterpret_cast<uint32_t*>(ranges), 2 * tiles, 0u);
+  RGA_LAUNCH("splat_fill", fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt),
+             (int64_t)2, 0u);
+  if (n > 0) {
+    RGA_LAUNCH("splat_preprocess", preprocess_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
+               n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, color, front,
+               at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
+               at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
+               at<uint8_t>(ws, L.fp64), k0, v0);
+    // depth sort: 4 passes of 8 bits over n keys
+    for (int pass = 0; pass < 4; ++pass) {
+      const int shift = 8 * pass;
+      RGA_LAUNCH("radix_upsweep", radix_upsweep, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+                 (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
+      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_n, binoff,
+                 bintot);
+      RGA_LAUNCH("radix_downsweep", radix_downsweep, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+                 v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot);
+      uint32_t* t = k0; k0 = k1; k1 = t;
+      t = v0; v0 = v1; v1 = t;
+    }
+    // after 4 passes the (depth, index)-ordered splat indices are in v0 (= vals0)
+    uint32_t* bsum = at<uint32_t>(ws, L.bsum);
+    uint32_t* boff = at<uint32_t>(ws, L.boff);
+    RGA_LAUNCH("touched_blocksum", touched_blocksum, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n, v0,
+               at<int32_t>(ws, L.touched), bsum);
+    RGA_LAUNCH("touched_blockscan", touched_blockscan, dim3(1), dim3(256), 0, s, L.nb_n, bsum, boff,
+               cnt);
+    uint32_t* tk0 = at<uint32_t>(ws, L.tk0);
+    uint32_t* tv0 = at<uint32_t>(ws, L.tv0);
+    uint32_t* tk1 = at<uint32_t>(ws, L.tk1);
+    uint32_t* tv1 = at<uint32_t>(ws, L.tv1);
+    RGA_LAUNCH("splat_duplicate", duplicate_kernel, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n,
+               L.tiles_x, capacity, v0, at<int32_t>(ws, L.touched), at<int32_t>(ws, L.rect), boff,
+               tk0, tv0);
+    for (int pass = 0; pass < L.tile_passes; ++pass) {
+      const int shift = 8 * pass;
+      RGA_LAUNCH("radix_upsweep", radix_upsweep, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+                 (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);
+      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_cap, binoff,
+                 bintot);
+      RGA_LAUNCH("radix_downsweep", radix_downsweep, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+                 tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot);
+      uint32_t* t = tk0; tk0 = tk1; tk1 = t;
+      t = tv0; tv0 = tv1; tv1 = t;
+    }
+    RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
+               s, tk0, (const int64_t*)cnt, capacity, ranges);
+    RGA_LAUNCH("blend_fwd", blend_fwd_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x, ranges,
+               tv0, at<float4>(ws, L.rec), image, T_final);
+  } else {
+    RGA_LAUNCH("blend_fwd", blend_fwd_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x, ranges,
+               at<uint32_t>(ws, L.tv0), at<float4>(ws, L.rec), image, T_final);
+  }
+  RGA_CHECK_LAUNCH("splat_forward");
+  return RGA_OK;
+}
+
+extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const float* x,
+                              const float* A, const float* quat, const float* log_s,
+                              const float* opac, const float* color, const uint8_t* front,
+                              void* ws, size_t ws_bytes, int64_t capacity, const float* image,
+                              const float* dimage, float* dx, float* dquat, float* dlog_s,
+                              float* dopac, float* dcolor) {
+  (void)color;
+  Layout L;
+  int rc = check_common("splat_backward", n, cam, ws, ws_bytes, capacity, L);
+  if (rc) return rc;
+  if (n == 0) return RGA_OK;
+  if (!x || !A || !quat || !log_s || !opac || !front || !image || !dimage || !dx || !dquat ||
+      !dlog_s || !dopac || !dcolor)
+    return rga::fail(RGA_EINVAL, "splat_backward: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const CamDev cd = to_dev(cam);
+  const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
+  float* gmc = at<float>(ws, L.grad);
+  const int64_t nz = 5 * (int64_t)n;
+  RGA_LAUNCH("splat_zero", zero_f32, dim3(rga::ceil_div(nz, 256)), dim3(256), 0, s, gmc, nz, dopac,
+             (int64_t)n, dcolor, 3 * (int64_t)n);
+  const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
+  RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(tiles), dim3(256), 0, s, cam->width, cam->height,
+             L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec), image, dimage,
+             gmc, dopac, dcolor);
+  RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
+             n, cd, x, A, quat, log_s, opac, front, gmc, dx, dquat, dlog_s);
+  RGA_CHECK_LAUNCH("splat_backward");
+  return RGA_OK;
+}

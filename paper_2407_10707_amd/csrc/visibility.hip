@@ -1,0 +1,376 @@
+// Per-vertex visibility from orthographic rasterization of the posed mesh
+// (Sec. 3.2 of the paper), bit-exact.
+//
+//   raster     one workgroup per view: the res x res z-buffer of 64-bit keys
+//              (float bits of depth << 32 | triangle id) lives in LDS
+//              (128 KB at 128^2, within gfx950's 160 KB), filled with LDS
+//              64-bit atomic-min; winning triangles mark their three
+//              vertices in an LDS bitmask that is written out view-major
+//   transpose  32x32 bit-matrix transposes -> vertex-major words
+//              raw[v][w] whose bit b is view 32w + b
+//   filter     bit-sliced: one 32-bit word carries 32 views, so the median
+//              of kv neighbours is a bitwise majority vote computed with a
+//              5-plane ripple counter (two passes), and the final pass
+//              expands the counter planes into count bytes [nv][V]
+#include "common.h"
+
+namespace {
+
+constexpr int kMaxRes = 128;
+constexpr int kRasterThreads = 1024;
+
+__device__ inline void basis(const float* d, float* t, float* b) {
+  const float sgn = copysignf(1.f, d[2]);
+  const float a = -1.f / (sgn + d[2]);
+  const float bb = (d[0] * d[1]) * a;
+  t[0] = 1.f + ((sgn * d[0]) * d[0]) * a;
+  t[1] = sgn * bb;
+  t[2] = -(sgn * d[0]);
+  b[0] = bb;
+  b[1] = sgn + (d[1] * d[1]) * a;
+  b[2] = -d[1];
+}
+
+__device__ inline int64_t edge(int64_t ax, int64_t ay, int64_t bx, int64_t by, int64_t sx,
+                               int64_t sy) {
+  return (bx - ax) * (sy - ay) - (by - ay) * (sx - ax);
+}
+
+__device__ inline bool owns(int64_t ax, int64_t ay, int64_t bx, int64_t by) {
+  const int64_t dx = bx - ax, dy = by - ay;
+  return dy > 0 || (dy == 0 && dx < 0);
+}
+
+__device__ inline int64_t fdiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+struct Proj {
+  float c[3], rho, t[3], b[3], d[3], scale;
+};
+
+__device__ inline void project(const Proj& P, const float* __restrict__ v, int nv, int i,
+                               int64_t& U, int64_t& V, float& z) {
+  const float q0 = v[i] - P.c[0], q1 = v[nv + i] - P.c[1], q2 = v[2 * nv + i] - P.c[2];
+  const float pu = fmaf(P.t[2], q2, fmaf(P.t[1], q1, P.t[0] * q0));
+  const float pv = fmaf(P.b[2], q2, fmaf(P.b[1], q1, P.b[0] * q0));
+  const float pd = fmaf(P.d[2], q2, fmaf(P.d[1], q1, P.d[0] * q0));
+  const float u = (pu / P.rho + 1.f) * P.scale;
+  const float w = (pv / P.rho + 1.f) * P.scale;
+  U = (int64_t)(int32_t)rintf(u * 256.f);
+  V = (int64_t)(int32_t)rintf(w * 256.f);
+  z = P.rho - pd;
+}
+
+// frame[0..2] = centre, frame[3] = rho of the posed mesh's bounding box
+__global__ void __launch_bounds__(1024)
+frame_kernel(int nv, const float* __restrict__ v, float* __restrict__ frame) {
+  __shared__ float lo[3][1024], hi[3][1024];
+  for (int a = 0; a < 3; ++a) {
+    float l = v[a * nv], h = v[a * nv];
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+      l = fminf(l, v[a * nv + i]);
+      h = fmaxf(h, v[a * nv + i]);
+    }
+    lo[a][threadIdx.x] = l;
+    hi[a][threadIdx.x] = h;
+  }
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int a = 0; a < 3; ++a) {
+        lo[a][threadIdx.x] = fminf(lo[a][threadIdx.x], lo[a][threadIdx.x + o]);
+        hi[a][threadIdx.x] = fmaxf(hi[a][threadIdx.x], hi[a][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float e[3];
+    for (int a = 0; a < 3; ++a) {
+      frame[a] = (lo[a][0] + hi[a][0]) * 0.5f;
+      e[a] = hi[a][0] - lo[a][0];
+    }
+    float r = 1.01f * (0.5f * sqrtf(fmaf(e[2], e[2], fmaf(e[1], e[1], e[0] * e[0]))));
+    if (!(r > 0.f)) r = 1.f;
+    frame[3] = r;
+  }
+}
+
+__global__ void __launch_bounds__(kRasterThreads)
+raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __restrict__ faces,
+              const float* __restrict__ dirs, int res, const float* __restrict__ frame,
+              uint32_t* __restrict__ bits_vm /*[V][nwv]*/, int nwv) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  unsigned long long* zb = reinterpret_cast<unsigned long long*>(smem);
+  uint32_t* mark = reinterpret_cast<uint32_t*>(smem + sizeof(unsigned long long) * res * res);
+  const int view = blockIdx.x;
+  Proj P;
+  P.c[0] = frame[0];
+  P.c[1] = frame[1];
+  P.c[2] = frame[2];
+  P.rho = frame[3];
+  P.d[0] = dirs[3 * view];
+  P.d[1] = dirs[3 * view + 1];
+  P.d[2] = dirs[3 * view + 2];
+  basis(P.d, P.t, P.b);
+  P.scale = 0.5f * (float)res;
+  for (int p = threadIdx.x; p < res * res; p += blockDim.x) zb[p] = ~0ull;
+  for (int w = threadIdx.x; w < nwv; w += blockDim.x) mark[w] = 0u;
+  __syncthreads();
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const int i0 = rga::clampi(faces[3 * f], 0, nv - 1);
+    const int i1 = rga::clampi(faces[3 * f + 1], 0, nv - 1);
+    const int i2 = rga::clampi(faces[3 * f + 2], 0, nv - 1);
+    int64_t x0, y0, x1, y1, x2, y2;
+    float z0, z1, z2;
+    project(P, verts, nv, i0, x0, y0, z0);
+    project(P, verts, nv, i1, x1, y1, z1);
+    project(P, verts, nv, i2, x2, y2, z2);
+    int64_t area = edge(x0, y0, x1, y1, x2, y2);
+    if (area == 0) continue;
+    if (area < 0) {
+      int64_t tx = x1, ty = y1;
+      x1 = x2; y1 = y2; x2 = tx; y2 = ty;
+      float tz = z1; z1 = z2; z2 = tz;
+      area = -area;
+    }
+    int64_t mnx = min(x0, min(x1, x2)), mxx = max(x0, max(x1, x2));
+    int64_t mny = min(y0, min(y1, y2)), mxy = max(y0, max(y1, y2));
+    int64_t i_lo = -fdiv(-(mnx - 128), 256), i_hi = fdiv(mxx - 128, 256);
+    int64_t j_lo = -fdiv(-(mny - 128), 256), j_hi = fdiv(mxy - 128, 256);
+    if (i_lo < 0) i_lo = 0;
+    if (j_lo < 0) j_lo = 0;
+    if (i_hi > res - 1) i_hi = res - 1;
+    if (j_hi > res - 1) j_hi = res - 1;
+    const bool o12 = owns(x1, y1, x2, y2), o20 = owns(x2, y2, x0, y0), o01 = owns(x0, y0, x1, y1);
+    const float fa = (float)area;
+    for (int64_t j = j_lo; j <= j_hi; ++j) {
+      const int64_t sy = 256 * j + 128;
+      for (int64_t i = i_lo; i <= i_hi; ++i) {
+        const int64_t sx = 256 * i + 128;
+        const int64_t w0 = edge(x1, y1, x2, y2, sx, sy);
+        const int64_t w1 = edge(x2, y2, x0, y0, sx, sy);
+        const int64_t w2 = edge(x0, y0, x1, y1, sx, sy);
+        const bool in0 = w0 > 0 || (w0 == 0 && o12);
+        const bool in1 = w1 > 0 || (w1 == 0 && o20);
+        const bool in2 = w2 > 0 || (w2 == 0 && o01);
+        if (!(in0 && in1 && in2)) continue;
+        const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) / fa;
+        const unsigned long long key =
+            ((unsigned long long)__float_as_uint(bz) << 32) | (unsigned long long)(uint32_t)f;
+        atomicMin(&zb[j * res + i], key);
+      }
+    }
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < res * res; p += blockDim.x) {
+    const unsigned long long k = zb[p];
+    if (k == ~0ull) continue;
+    const int f = (int)(uint32_t)(k & 0xffffffffull);
+    for (int c = 0; c < 3; ++c) {
+      const int vi = rga::clampi(faces[3 * f + c], 0, nv - 1);
+      atomicOr(&mark[vi >> 5], 1u << (vi & 31));
+    }
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < nwv; w += blockDim.x) bits_vm[(size_t)view * nwv + w] = mark[w];
+}
+
+// 32x32 bit-matrix transpose (in registers).
+__device__ inline void transpose32(uint32_t* a) {
+  uint32_t m = 0x0000FFFFu;
+  for (int j = 16; j != 0; j >>= 1, m ^= (m << j)) {
+    for (int k = 0; k < 32; k = ((k | j) + 1) & ~j) {
+      const uint32_t t = (a[k] ^ (a[k | j] >> j)) & m;
+      a[k] ^= t;
+      a[k | j] ^= (t << j);
+    }
+  }
+}
+
+// view-major [V][nwv] (bit i&31 of word i>>5 = vertex i) -> vertex-major
+// [nv][nwV] (bit k&31 of word k>>5 = view k)
+__global__ void __launch_bounds__(256)
+transpose_kernel(int nv, int V, int nwv, int nwV, const uint32_t* __restrict__ vm,
+                 uint32_t* __restrict__ out) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nwv * nwV;
+  if (id >= total) return;
+  const int vw = (int)(id / nwV);  // word of vertices
+  const int kw = (int)(id % nwV);  // word of views
+  uint32_t a[32];
+  // row r of the block = view 32 kw + r; bit c = vertex 32 vw + c
+  for (int r = 0; r < 32; ++r) {
+    const int k = 32 * kw + r;
+    a[r] = k < V ? vm[(size_t)k * nwv + vw] : 0u;
+  }
+  // transpose32 treats a[r] bit (31 - c) as column c; reverse bits so that
+  // column c maps to bit c, transpose, then reverse back.
+  for (int r = 0; r < 32; ++r) a[r] = __brev(a[r]);
+  transpose32(a);
+  for (int r = 0; r < 32; ++r) a[r] = __brev(a[r]);
+  for (int c = 0; c < 32; ++c) {
+    const int i = 32 * vw + c;
+    if (i < nv) out[(size_t)i * nwV + kw] = a[c];
+  }
+}
+
+struct Planes {
+  uint32_t p[5];
+};
+
+__device__ inline void add_word(Planes& s, uint32_t x) {
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t c = s.p[k] & x;
+    s.p[k] ^= x;
+    x = c;
+  }
+}
+
+// lanes whose 5-bit count >= thr
+__device__ inline uint32_t at_least(const Planes& s, int thr) {
+  uint32_t ge = 0u, eq = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 4; k >= 0; --k) {
+    if ((thr >> k) & 1) {
+      eq &= s.p[k];
+    } else {
+      ge |= eq & s.p[k];
+      eq &= ~s.p[k];
+    }
+  }
+  return ge | eq;
+}
+
+__global__ void __launch_bounds__(256)
+majority_kernel(int nv, int nwV, const int32_t* __restrict__ knn, int kv,
+                const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)nv * nwV) return;
+  const int i = (int)(id / nwV), w = (int)(id % nwV);
+  Planes s = {{0u, 0u, 0u, 0u, 0u}};
+  for (int j = 0; j < kv; ++j) {
+    const int nb = rga::clampi(knn[(size_t)i * kv + j], 0, nv - 1);
+    add_word(s, src[(size_t)nb * nwV + w]);
+  }
+  dst[id] = at_least(s, (kv + 1) / 2);
+}
+
+__global__ void __launch_bounds__(256)
+count_kernel(int nv, int V, int nwV, const int32_t* __restrict__ knn, int kv,
+             const uint32_t* __restrict__ src, uint8_t* __restrict__ count) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)nv * nwV) return;
+  const int i = (int)(id / nwV), w = (int)(id % nwV);
+  Planes s = {{0u, 0u, 0u, 0u, 0u}};
+  for (int j = 0; j < kv; ++j) {
+    const int nb = rga::clampi(knn[(size_t)i * kv + j], 0, nv - 1);
+    add_word(s, src[(size_t)nb * nwV + w]);
+  }
+  uint32_t words[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    uint32_t packed = 0u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int lanebit = 4 * q + b;
+      uint32_t v = 0u;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) v |= ((s.p[k] >> lanebit) & 1u) << k;
+      packed |= v << (8 * b);
+    }
+    words[q] = packed;
+  }
+  uint8_t* row = count + (size_t)i * V;
+  const int k0 = 32 * w;
+  if ((V & 15) == 0 && k0 + 32 <= V) {
+    uint4* dst = reinterpret_cast<uint4*>(row + k0);
+    dst[0] = make_uint4(words[0], words[1], words[2], words[3]);
+    dst[1] = make_uint4(words[4], words[5], words[6], words[7]);
+  } else {
+    for (int b = 0; b < 32 && k0 + b < V; ++b) row[k0 + b] = (uint8_t)((words[b >> 2] >> (8 * (b & 3))) & 0xFFu);
+  }
+}
+
+struct VisLayout {
+  size_t frame, vm, raw, m1, m2, total;
+  int nwv, nwV;
+};
+
+VisLayout vis_layout(int nv, int V) {
+  VisLayout L{};
+  L.nwv = (nv + 31) / 32;
+  L.nwV = (V + 31) / 32;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t a = o;
+    o = rga::align_up(o + bytes, 256);
+    return a;
+  };
+  L.frame = take(16);
+  L.vm = take((size_t)V * L.nwv * 4);
+  L.raw = take((size_t)nv * L.nwV * 4);
+  L.m1 = take((size_t)nv * L.nwV * 4);
+  L.m2 = take((size_t)nv * L.nwV * 4);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+extern "C" size_t mesh_visibility_workspace(int nv, int V) {
+  if (nv < 1 || V < 1) return 0;
+  return vis_layout(nv, V).total;
+}
+
+extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
+                               const int32_t* faces, int V, const float* view_dirs, int res,
+                               const int32_t* knn, int kv, uint32_t* raw_bits, uint8_t* count,
+                               void* ws, size_t ws_bytes) {
+  if (nv < 1 || nf < 0 || V < 1) return rga::fail(RGA_EINVAL, "mesh_visibility: nv >= 1, nf >= 0, V >= 1");
+  if (res < 1 || res > kMaxRes)
+    return rga::fail(RGA_EUNSUPPORTED, "mesh_visibility: res must be in 1..%d", kMaxRes);
+  if (kv < 1 || kv > 31 || (kv & 1) == 0)
+    return rga::fail(RGA_EINVAL, "mesh_visibility: kv must be odd and in 1..31");
+  if (!verts || (nf > 0 && !faces) || !view_dirs || !knn || !count || !ws)
+    return rga::fail(RGA_EINVAL, "mesh_visibility: null pointer");
+  if (!rga::aligned16(ws) || !rga::aligned16(count))
+    return rga::fail(RGA_EINVAL, "mesh_visibility: ws and count must be 16-byte aligned");
+  VisLayout L = vis_layout(nv, V);
+  if (ws_bytes < L.total)
+    return rga::fail(RGA_ECAPACITY, "mesh_visibility: workspace %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  float* frame = reinterpret_cast<float*>(w + L.frame);
+  uint32_t* vm = reinterpret_cast<uint32_t*>(w + L.vm);
+  uint32_t* raw = raw_bits ? raw_bits : reinterpret_cast<uint32_t*>(w + L.raw);
+  uint32_t* m1 = reinterpret_cast<uint32_t*>(w + L.m1);
+  uint32_t* m2 = reinterpret_cast<uint32_t*>(w + L.m2);
+  const size_t lds = sizeof(unsigned long long) * (size_t)res * res + 4 * (size_t)L.nwv;
+  if (lds > 160 * 1024)
+    return rga::fail(RGA_EUNSUPPORTED, "mesh_visibility: %d vertices need too much LDS", nv);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(raster_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  RGA_LAUNCH("vis_frame", frame_kernel, dim3(1), dim3(1024), 0, s, nv, verts, frame);
+  RGA_LAUNCH("vis_raster", raster_kernel, dim3(V), dim3(kRasterThreads), lds, s, nv, nf, verts,
+             faces, view_dirs, res, frame, vm, L.nwv);
+  const int64_t tw = (int64_t)L.nwv * L.nwV;
+  RGA_LAUNCH("vis_transpose", transpose_kernel, dim3(rga::ceil_div(tw, 256)), dim3(256), 0, s, nv,
+             V, L.nwv, L.nwV, vm, raw);
+  const int64_t nw = (int64_t)nv * L.nwV;
+  RGA_LAUNCH("vis_majority", majority_kernel, dim3(rga::ceil_div(nw, 256)), dim3(256), 0, s, nv,
+             L.nwV, knn, kv, raw, m1);
+  RGA_LAUNCH("vis_majority", majority_kernel, dim3(rga::ceil_div(nw, 256)), dim3(256), 0, s, nv,
+             L.nwV, knn, kv, m1, m2);
+  RGA_LAUNCH("vis_count", count_kernel, dim3(rga::ceil_div(nw, 256)), dim3(256), 0, s, nv, V,
+             L.nwV, knn, kv, m2, count);
+  RGA_CHECK_LAUNCH("mesh_visibility");
+  return RGA_OK;
+}

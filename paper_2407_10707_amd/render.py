@@ -1,0 +1,135 @@
+"""Render-and-train path on top of the C ABI (marshalling only).
+
+Per frame (Sec. 3.1-3.2 of the paper):
+  lbs_skin(mesh) -> mesh_visibility          (once per pose, no gradient)
+  lbs_skin(Gaussians) -> shade_gaussians -> splat_forward -> image
+and the adjoint
+  splat_backward -> shade_gaussians_backward (accumulates into dx') ->
+  lbs_skin_backward.
+Every arithmetic step runs in librga.so; this module only owns buffers.
+"""
+
+from __future__ import annotations
+
+from typing import Dict, Optional
+
+import numpy as np
+import torch
+
+from . import rga
+
+TRAINABLE = ("pos", "nrm", "quat", "log_s", "opac", "albedo", "rough", "tint", "env")
+STATIC_F32 = ("verts", "mesh_jw", "skin", "jw", "vw", "view_dirs", "target")
+STATIC_I32 = ("faces", "mesh_jidx", "knn_v", "jidx", "vidx")
+
+
+def upload(scene: dict, device="cuda") -> Dict[str, torch.Tensor]:
+    """Copy a synthetic scene's arrays to the device (float32 / int32)."""
+    out = {}
+    for k in TRAINABLE + STATIC_F32:
+        out[k] = torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.float32)).to(device)
+    for k in STATIC_I32:
+        out[k] = torch.as_tensor(np.ascontiguousarray(scene[k], dtype=np.int32)).to(device)
+    return out
+
+
+class Renderer:
+    """Holds the static inputs and workspaces of one scene/camera."""
+
+    def __init__(self, scene: dict, dev: Dict[str, torch.Tensor], capacity: Optional[int] = None,
+                 precision: str = "fp32"):
+        self.s = scene
+        self.d = dev
+        self.cam = scene["cam"]
+        self.cam_pos = [float(v) for v in np.asarray(self.cam.centre, dtype=np.float32)]
+        self.n = int(scene["n"])
+        self.precision = precision
+        cap = capacity if capacity is not None else max(1 << 16, 24 * self.n)
+        self.ws = rga.SplatWorkspace(self.n, self.cam.width, self.cam.height, cap,
+                                     dev["pos"].device)
+        self.vis_ws = None
+        self.shade_ws = None
+        self.l1_ws = None
+
+    # ------------------------------------------------------------------ per pose
+    def visibility(self):
+        d, s = self.d, self.s
+        vx, _, _ = rga.lbs_skin(d["skin"], d["mesh_jidx"], d["mesh_jw"], d["verts"], None,
+                                want_A=False)
+        count, _ = rga.mesh_visibility(vx, d["faces"], d["view_dirs"], s["vis_res"], d["knn_v"],
+                                       ws=self.vis_ws)
+        return count
+
+    def ensure_capacity(self):
+        """Synchronises; grows the splat workspace if the last frame overflowed.
+        Returns True if the frame must be re-rendered."""
+        D = self.ws.count()
+        if D > self.ws.capacity:
+            self.ws = rga.SplatWorkspace(self.n, self.cam.width, self.cam.height,
+                                         int(D * 1.25) + 1024, self.d["pos"].device)
+            return True
+        return False
+
+    # ------------------------------------------------------------------ forward
+    def forward(self, p: Dict[str, torch.Tensor], count: torch.Tensor):
+        d, s = self.d, self.s
+        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"])
+        color, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
+                                           d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
+                                           s["wv"], p["env"], self.cam_pos, self.precision)
+        image, T = rga.splat_forward(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], color,
+                                     front, self.ws)
+        ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count)
+        return image, T, ctx
+
+    # ------------------------------------------------------------------ backward
+    def backward(self, p: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor):
+        d, s = self.d, self.s
+        g = rga.splat_backward(self.cam, ctx["xo"], ctx["A"], p["quat"], p["log_s"], p["opac"],
+                               ctx["color"], ctx["front"], self.ws, ctx["image"], dimage)
+        sh = rga.shade_gaussians_backward(
+            ctx["xo"], ctx["no"], p["albedo"], p["rough"], p["tint"], d["vidx"], d["vw"],
+            ctx["count"], s["kv"], s["he"], s["we"], s["hv"], s["wv"], p["env"], self.cam_pos,
+            ctx["color"], ctx["front"], g["dcolor"], dx_accum=g["dx"], precision=self.precision,
+            ws=self.shade_ws)
+        dpos, dnrm = rga.lbs_skin_backward(d["skin"], d["jidx"], d["jw"], sh["dx"], sh["dn"])
+        return dict(pos=dpos, nrm=dnrm, quat=g["dquat"], log_s=g["dlog_s"], opac=g["dopac"],
+                    albedo=sh["dalbedo"], rough=sh["drough"], tint=sh["dtint"], env=sh["denv"],
+                    color=g["dcolor"])
+
+    def loss(self, image: torch.Tensor, target: torch.Tensor):
+        return rga.l1_loss(image, target, ws=self.l1_ws)
+
+    def train_step(self, p, count, target):
+        """fwd + L1 loss + bwd; returns (loss [1] on device, grads)."""
+        image, _, ctx = self.forward(p, count)
+        loss, dimage = self.loss(image, target)
+        grads = self.backward(p, ctx, dimage)
+        return loss, grads
+
+
+class RenderFunction(torch.autograd.Function):
+    """image = render(pos, nrm, quat, log_s, opac, albedo, rough, tint, env)
+    with the hand-written adjoint of librga.so as its backward."""
+
+    @staticmethod
+    def forward(ctx, renderer: Renderer, count, pos, nrm, quat, log_s, opac, albedo, rough, tint,
+                env):
+        p = dict(pos=pos, nrm=nrm, quat=quat, log_s=log_s, opac=opac, albedo=albedo,
+                 rough=rough, tint=tint, env=env)
+        image, T, c = renderer.forward(p, count)
+        ctx.renderer = renderer
+        ctx.p = p
+        ctx.c = c
+        ctx.mark_non_differentiable(T)
+        return image, T
+
+    @staticmethod
+    def backward(ctx, dimage, dT):
+        g = ctx.renderer.backward(ctx.p, ctx.c, dimage.contiguous())
+        return (None, None, g["pos"], g["nrm"], g["quat"], g["log_s"], g["opac"], g["albedo"],
+                g["rough"], g["tint"], g["env"])
+
+
+def render(renderer: Renderer, count, p: Dict[str, torch.Tensor]):
+    return RenderFunction.apply(renderer, count, *[p[k] for k in TRAINABLE])

@@ -1,0 +1,338 @@
+"""ctypes binding of librga.so: argument marshalling only.
+
+Every function here checks tensor placement/shape/dtype, allocates outputs
+with torch (device memory and streams are PyTorch's), and calls the C entry
+point of the same name on the current HIP stream.  There is no fallback: if
+the library is not built, ``lib()`` raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librga.so")
+_lib = None
+
+RGA_FP32 = 0
+RGA_BF16X3 = 1
+PRECISIONS = {"fp32": RGA_FP32, "bf16x3": RGA_BF16X3}
+
+_VP = C.c_void_p
+_I = C.c_int
+_I64 = C.c_int64
+_SZ = C.c_size_t
+
+_SIGS = {
+    "rga_last_error": (C.c_char_p, []),
+    "rga_abi_version": (_I, []),
+    "lbs_skin": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbs_skin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "mesh_visibility_workspace": (_SZ, [_I, _I]),
+    "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
+    "shade_gaussians": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _I,
+                             _I, _VP, _VP, _I, _VP, _VP]),
+    "shade_gaussians_workspace": (_SZ, [_I, _I, _I]),
+    "shade_gaussians_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I,
+                                      _I, _I, _I, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                      _VP, _VP, _VP, _SZ]),
+    "splat_workspace_size": (_SZ, [_I, _I, _I, _I64]),
+    "splat_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
+                           _VP]),
+    "splat_read_count": (_I, [_VP, _VP, _I, _I, _I, _I64, _VP]),
+    "splat_state": (_I, [_VP, _I, _I, _I, _I64, _VP]),
+    "splat_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
+                            _VP, _VP, _VP, _VP, _VP, _VP]),
+    "l1_loss_workspace": (_SZ, [_I64]),
+    "l1_loss": (_I, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _SZ]),
+    "rga_timing_enable": (_I, [_I]),
+    "rga_timing_reset": (_I, []),
+    "rga_timing_read": (_I, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+}
+
+
+class RgaError(RuntimeError):
+    pass
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_float * 9), ("t", C.c_float * 3), ("fx", C.c_float),
+                ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class SplatState(C.Structure):
+    _fields_ = [("mean2d", _VP), ("conic", _VP), ("depth", _VP), ("rect", _VP),
+                ("touched", _VP), ("fp64", _VP), ("sorted", _VP), ("ranges", _VP),
+                ("count", _VP), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32)]
+
+
+def lib():
+    """Load librga.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().rga_last_error().decode()
+
+
+def _check(rc: int, name: str):
+    if rc != 0:
+        raise RgaError(f"{name} failed ({rc}): {last_error()}")
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise RgaError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise RgaError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise RgaError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise RgaError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def camera(cam) -> Camera:
+    c = Camera()
+    R = [float(v) for v in torch.as_tensor(cam.R).reshape(-1).tolist()]
+    c.R[:] = R
+    c.t[:] = [float(v) for v in torch.as_tensor(cam.t).reshape(-1).tolist()]
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _f32(t, name, shape=None):
+    return _dev(t, torch.float32, name, shape)
+
+
+def _i32(t, name, shape=None):
+    return _dev(t, torch.int32, name, shape)
+
+
+def _u8(t, name, shape=None):
+    return _dev(t, torch.uint8, name, shape)
+
+
+# ----------------------------------------------------------------------------- LBS
+def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True):
+    n = x.shape[1]
+    J = skin.shape[0]
+    _f32(skin, "skin", (J, 12))
+    _i32(jidx, "jidx", (4, n))
+    _f32(jw, "jw", (4, n))
+    _f32(x, "x", (3, n))
+    if nrm is not None:
+        _f32(nrm, "nrm", (3, n))
+    xo = torch.empty_like(x)
+    no = torch.empty_like(nrm) if nrm is not None else None
+    Ao = torch.empty((9, n), dtype=torch.float32, device=x.device) if want_A else None
+    _check(lib().lbs_skin(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(x), _p(nrm), _p(xo),
+                          _p(no), _p(Ao)), "lbs_skin")
+    return xo, no, Ao
+
+
+def lbs_skin_backward(skin, jidx, jw, dx_out, dn_out=None):
+    n = dx_out.shape[1]
+    J = skin.shape[0]
+    _f32(dx_out, "dx_out", (3, n))
+    dx = torch.empty_like(dx_out)
+    dn = torch.empty_like(dn_out) if dn_out is not None else None
+    _check(lib().lbs_skin_backward(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(dx_out),
+                                   _p(dn_out), _p(dx), _p(dn)), "lbs_skin_backward")
+    return dx, dn
+
+
+# ----------------------------------------------------------------------------- visibility
+def mesh_visibility(verts, faces, view_dirs, res: int, knn, want_raw: bool = False, ws=None):
+    nv = verts.shape[1]
+    nf = faces.shape[0]
+    V = view_dirs.shape[0]
+    kv = knn.shape[1]
+    _f32(verts, "verts", (3, nv))
+    _i32(faces, "faces", (nf, 3))
+    _f32(view_dirs, "view_dirs", (V, 3))
+    _i32(knn, "knn", (nv, kv))
+    need = int(lib().mesh_visibility_workspace(nv, V))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=verts.device)
+    count = torch.empty((nv, V), dtype=torch.uint8, device=verts.device)
+    raw = torch.empty((nv, (V + 31) // 32), dtype=torch.int32, device=verts.device) if want_raw else None
+    _check(lib().mesh_visibility(_stream(), nv, nf, _p(verts), _p(faces), V, _p(view_dirs), res,
+                                 _p(knn), kv, _p(raw), _p(count), _p(ws), ws.numel()),
+           "mesh_visibility")
+    return count, raw
+
+
+# ----------------------------------------------------------------------------- shading
+def shade_gaussians(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env,
+                    cam_pos, precision: str = "fp32"):
+    n = x.shape[1]
+    nv = count.shape[0]
+    _f32(x, "x", (3, n))
+    _f32(nrm, "nrm", (3, n))
+    _f32(albedo, "albedo", (3, n))
+    _f32(rough, "rough", (n,))
+    _f32(tint, "tint", (n,))
+    _i32(vidx, "vidx", (3, n))
+    _f32(vw, "vw", (3, n))
+    _u8(count, "count", (nv, hv * wv))
+    _f32(env, "env", (he * we, 3))
+    color = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    front = torch.empty((n,), dtype=torch.uint8, device=x.device)
+    cp = (C.c_float * 3)(*[float(v) for v in cam_pos])
+    _check(lib().shade_gaussians(_stream(), n, _p(x), _p(nrm), _p(albedo), _p(rough), _p(tint),
+                                 _p(vidx), _p(vw), _p(count), nv, kv, he, we, hv, wv, _p(env),
+                                 C.cast(cp, C.c_void_p), PRECISIONS[precision], _p(color),
+                                 _p(front)), "shade_gaussians")
+    return color, front
+
+
+def shade_gaussians_backward(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv,
+                             env, cam_pos, color, front, dcolor, dx_accum=None,
+                             precision: str = "fp32", ws=None):
+    n = x.shape[1]
+    nv = count.shape[0]
+    _f32(dcolor, "dcolor", (3, n))
+    dx = torch.zeros((3, n), dtype=torch.float32, device=x.device) if dx_accum is None else dx_accum
+    dn = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    dalb = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    drough = torch.empty((n,), dtype=torch.float32, device=x.device)
+    dtint = torch.empty((n,), dtype=torch.float32, device=x.device)
+    denv = torch.empty((he * we, 3), dtype=torch.float32, device=x.device)
+    need = int(lib().shade_gaussians_workspace(n, he, we))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    cp = (C.c_float * 3)(*[float(v) for v in cam_pos])
+    _check(lib().shade_gaussians_backward(
+        _stream(), n, _p(x), _p(nrm), _p(albedo), _p(rough), _p(tint), _p(vidx), _p(vw),
+        _p(count), nv, kv, he, we, hv, wv, _p(env), C.cast(cp, C.c_void_p), PRECISIONS[precision],
+        _p(color), _p(front), _p(dcolor), _p(dx), _p(dn), _p(dalb), _p(drough), _p(dtint),
+        _p(denv), _p(ws), ws.numel()), "shade_gaussians_backward")
+    return dict(dx=dx, dn=dn, dalbedo=dalb, drough=drough, dtint=dtint, denv=denv)
+
+
+# ----------------------------------------------------------------------------- splatting
+class SplatWorkspace:
+    """Device workspace of splat_forward/splat_backward for one (n, image,
+    capacity); grows when a frame needs more duplicates than it holds."""
+
+    def __init__(self, n: int, width: int, height: int, capacity: int, device):
+        self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
+        self.bytes = int(lib().splat_workspace_size(n, width, height, self.capacity))
+        self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+
+    def count(self) -> int:
+        D = C.c_int64()
+        _check(lib().splat_read_count(_stream(), _p(self.buf), self.n, self.width, self.height,
+                                      self.capacity, C.byref(D)), "splat_read_count")
+        return int(D.value)
+
+    def view(self, ptr: int, shape, dtype: torch.dtype) -> torch.Tensor:
+        """Tensor view of a region of the workspace (for inspection)."""
+        off = int(ptr) - self.buf.data_ptr()
+        nbytes = int(np.prod(shape)) * torch.empty((), dtype=dtype).element_size()
+        if off < 0 or off + nbytes > self.bytes:
+            raise RgaError("pointer outside the splat workspace")
+        return self.buf[off:off + nbytes].view(dtype).reshape(shape)
+
+    def state(self) -> SplatState:
+        st = SplatState()
+        _check(lib().splat_state(_p(self.buf), self.n, self.width, self.height, self.capacity,
+                                 C.byref(st)), "splat_state")
+        return st
+
+
+def splat_forward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace):
+    n = x.shape[1]
+    _f32(x, "x", (3, n))
+    _f32(A, "A", (9, n))
+    _f32(quat, "quat", (4, n))
+    _f32(log_s, "log_s", (3, n))
+    _f32(opac, "opac", (n,))
+    _f32(color, "color", (3, n))
+    _u8(front, "front", (n,))
+    H, W = int(cam.height), int(cam.width)
+    if (ws.n, ws.width, ws.height) != (n, W, H):
+        raise RgaError("splat workspace was sized for another problem")
+    image = torch.empty((3, H, W), dtype=torch.float32, device=x.device)
+    T = torch.empty((H, W), dtype=torch.float32, device=x.device)
+    c = camera(cam)
+    _check(lib().splat_forward(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s),
+                               _p(opac), _p(color), _p(front), _p(ws.buf), ws.bytes, ws.capacity,
+                               _p(image), _p(T)), "splat_forward")
+    return image, T
+
+
+def splat_backward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace, image,
+                   dimage):
+    n = x.shape[1]
+    _f32(dimage, "dimage", tuple(image.shape))
+    dx = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    dq = torch.empty((4, n), dtype=torch.float32, device=x.device)
+    ds = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    do = torch.empty((n,), dtype=torch.float32, device=x.device)
+    dc = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    c = camera(cam)
+    _check(lib().splat_backward(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s),
+                                _p(opac), _p(color), _p(front), _p(ws.buf), ws.bytes,
+                                ws.capacity, _p(image), _p(dimage), _p(dx), _p(dq), _p(ds),
+                                _p(do), _p(dc)), "splat_backward")
+    return dict(dx=dx, dquat=dq, dlog_s=ds, dopac=do, dcolor=dc)
+
+
+# ----------------------------------------------------------------------------- loss
+def l1_loss(image, target, want_grad: bool = True, ws=None):
+    _f32(image, "image")
+    _f32(target, "target", tuple(image.shape))
+    cnt = image.numel()
+    loss = torch.empty((1,), dtype=torch.float32, device=image.device)
+    dimage = torch.empty_like(image) if want_grad else None
+    need = int(lib().l1_loss_workspace(cnt))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=image.device)
+    _check(lib().l1_loss(_stream(), cnt, _p(image), _p(target), _p(loss), _p(dimage), _p(ws),
+                         ws.numel()), "l1_loss")
+    return loss, dimage
+
+
+# ----------------------------------------------------------------------------- timing
+def timing_enable(on: bool = True):
+    _check(lib().rga_timing_enable(int(on)), "rga_timing_enable")
+
+
+def timing_reset():
+    _check(lib().rga_timing_reset(), "rga_timing_reset")
+
+
+def timing_read(kernel: str) -> Tuple[float, int]:
+    ms = C.c_double()
+    cnt = C.c_int64()
+    _check(lib().rga_timing_read(kernel.encode(), C.byref(ms), C.byref(cnt)), "rga_timing_read")
+    return float(ms.value), int(cnt.value)

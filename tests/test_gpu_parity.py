@@ -1,0 +1,257 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+Bit-exact: posed positions/normals/A, raw visibility bits and filtered counts,
+back-face flags, per-splat tile rectangles and depth keys, D, tile ranges and
+per-tile lists.  Tolerances: shaded colours vs the FP64 oracle
+|d| <= 1e-5 |ref| + 1e-7; pixels vs the FP32 mirror |d| <= 1e-5 |ref| + 1e-6
+(pixels whose compositing decisions sit within 1e-4 of a threshold are
+exempt and counted); gradients vs the FP64 oracle's autograd, per tensor.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cpu, ref64
+from paper_2407_10707_amd import render, rga, synth
+from tests import helpers
+from tests.conftest import scene
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    rga.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _scenes():
+    return {
+        "cfg1": lambda: scene(1),
+        "cfg1_identity": lambda: scene(1, identity_pose=True),
+        "micro_odd": lambda: synth.micro_scene(11, 333, 37, 53),
+        "micro_ragged": lambda: synth.micro_scene(12, 900, 100, 161, log_scale_mean=-3.0),
+    }
+
+
+# ------------------------------------------------------------------ LBS
+@pytest.mark.parametrize("name", list(_scenes()))
+def test_lbs_bit_exact(name):
+    print(f"[lbs] {name}", flush=True)
+    s = _scenes()[name]()
+    xo, no, Ao = rga.lbs_skin(dev(s["skin"]), dev(s["jidx"]), dev(s["jw"]), dev(s["pos"]),
+                              dev(s["nrm"]))
+    ex, en, eA = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    assert np.array_equal(host(xo), ex)
+    assert np.array_equal(host(no), en)
+    assert np.array_equal(host(Ao), eA)
+
+
+def test_lbs_backward_is_A_transpose():
+    s = scene(1)
+    rng = np.random.default_rng(0)
+    gx = rng.normal(size=(3, s["n"])).astype(np.float32)
+    gn = rng.normal(size=(3, s["n"])).astype(np.float32)
+    dx, dn = rga.lbs_skin_backward(dev(s["skin"]), dev(s["jidx"]), dev(s["jw"]), dev(gx), dev(gn))
+    _, _, A64 = ref64.lbs(s["skin"], s["jidx"], s["jw"], s["pos"])
+    A = A64.numpy().T.reshape(-1, 3, 3)
+    assert np.allclose(host(dx), np.einsum("nba,bn->an", A, gx), atol=2e-6)
+    assert np.allclose(host(dn), np.einsum("nba,bn->an", A, gn), atol=2e-6)
+
+
+def test_lbs_empty_and_errors():
+    s = scene(1)
+    x = torch.empty((3, 0), device="cuda")
+    out = rga.lbs_skin(dev(s["skin"]), torch.empty((4, 0), dtype=torch.int32, device="cuda"),
+                       torch.empty((4, 0), device="cuda"), x, None)
+    assert out[0].shape == (3, 0)
+    L = rga.lib()
+    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None) == -1
+    assert "n_joints" in rga.last_error()
+
+
+# ------------------------------------------------------------------ visibility
+@pytest.mark.parametrize("name", ["cfg1", "micro_odd"])
+def test_visibility_bit_exact(name):
+    print(f"[vis] {name}", flush=True)
+    s = _scenes()[name]()
+    vx, _, _ = cpu.lbs_f32(s["skin"], s["mesh_jidx"], s["mesh_jw"], s["verts"])
+    count, raw = rga.mesh_visibility(dev(vx), dev(s["faces"]), dev(s["view_dirs"]), s["vis_res"],
+                                     dev(s["knn_v"]), want_raw=True)
+    eraw, ecnt = cpu.mesh_visibility(vx, s["faces"], s["view_dirs"], s["vis_res"], s["knn_v"])
+    assert np.array_equal(host(raw).view(np.uint32), eraw)
+    assert np.array_equal(host(count), ecnt)
+
+
+def test_visibility_bit_exact_avatar_scale():
+    """7k-vertex / 14k-triangle mesh, 512 views at 128^2 (the avatar workload)."""
+    print("[vis] avatar scale", flush=True)
+    s = scene(2, n_gauss=1000)
+    vx, _, _ = cpu.lbs_f32(s["skin"], s["mesh_jidx"], s["mesh_jw"], s["verts"])
+    count, raw = rga.mesh_visibility(dev(vx), dev(s["faces"]), dev(s["view_dirs"]), s["vis_res"],
+                                     dev(s["knn_v"]), want_raw=True)
+    eraw, ecnt = cpu.mesh_visibility(vx, s["faces"], s["view_dirs"], s["vis_res"], s["knn_v"])
+    assert np.array_equal(host(raw).view(np.uint32), eraw)
+    assert np.array_equal(host(count), ecnt)
+
+
+# ------------------------------------------------------------------ shading
+@pytest.mark.parametrize("name", ["cfg1", "micro_odd"])
+def test_shading_matches_fp64(name):
+    print(f"[shade] {name}", flush=True)
+    s = _scenes()[name]()
+    xo, no, _ = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    _, _, cnt = helpers.oracle_visibility(s)
+    campos = s["cam"].centre.astype(np.float32)
+    col, front = rga.shade_gaussians(dev(xo), dev(no), dev(s["albedo"]), dev(s["rough"]),
+                                     dev(s["tint"]), dev(s["vidx"]), dev(s["vw"]), dev(cnt),
+                                     s["kv"], s["he"], s["we"], s["hv"], s["wv"], dev(s["env"]),
+                                     campos)
+    efront = cpu.front_f32(xo, no, campos)
+    assert np.array_equal(host(front), efront)
+    ecol, _ = ref64.shade(ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"],
+                          s["vidx"], s["vw"], cnt, s["kv"], s["he"], s["we"], s["hv"], s["wv"],
+                          s["env"], campos.astype(np.float64), efront)
+    ecol = ecol.numpy()
+    got = host(col)
+    err = np.abs(got - ecol)
+    assert np.all(err <= 1e-5 * np.abs(ecol) + 1e-7), err.max()
+
+
+# ------------------------------------------------------------------ splatting
+def _splat_case(s, color):
+    xo, no, Ao = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    front = cpu.front_f32(xo, no, s["cam"].centre.astype(np.float32))
+    return xo, Ao, front
+
+
+@pytest.mark.parametrize("name", list(_scenes()))
+def test_splat_forward_parity(name):
+    print(f"[splat] {name}", flush=True)
+    s = _scenes()[name]()
+    rng = np.random.default_rng(1)
+    col = rng.random((3, s["n"])).astype(np.float32)
+    xo, Ao, front = _splat_case(s, col)
+    cam = s["cam"]
+    ws = rga.SplatWorkspace(s["n"], cam.width, cam.height, 64 * s["n"] + 1024, "cuda")
+    img, T = rga.splat_forward(cam, dev(xo), dev(Ao), dev(s["quat"]), dev(s["log_s"]),
+                               dev(s["opac"]), dev(col), dev(front), ws)
+    pre = cpu.splat_preprocess(cam, xo, Ao, s["quat"], s["log_s"], s["opac"], front)
+    keys, vals, ranges = cpu.splat_bin(cam, pre)
+    eimg, eT, margin = cpu.composite_tiles(cam, ranges, vals, pre, s["opac"], col)
+    D = ws.count()
+    assert D == len(keys)
+    st = ws.state()
+    n = s["n"]
+
+    tdt = {np.int32: torch.int32, np.float32: torch.float32, np.uint8: torch.uint8}
+
+    def grab(ptr, shape, dtype):
+        return host(ws.view(ptr, shape, tdt[dtype]))
+
+    touched = grab(st.touched, (n,), np.int32)
+    assert np.array_equal(touched, pre["touched"])
+    rect = grab(st.rect, (4, n), np.int32)
+    live = touched > 0
+    assert np.array_equal(rect[:, live], pre["rect"][:, live])
+    depth = grab(st.depth, (n,), np.float32)
+    assert np.array_equal(depth.view(np.uint32)[live], pre["depth"].view(np.uint32)[live])
+    gm = grab(st.mean2d, (2, n), np.float32)
+    assert np.array_equal(gm[:, live], pre["mean2d"][:, live])
+    gfp = grab(st.fp64, (n,), np.uint8)
+    assert np.array_equal(gfp[live], pre["fp64"][live])
+    tiles = st.tiles_x * st.tiles_y
+    granges = grab(st.ranges, (tiles, 2), np.int32)
+    nonempty = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(granges[nonempty], ranges[nonempty])
+    assert np.all(granges[~nonempty, 1] == granges[~nonempty, 0])
+    if D:
+        gvals = grab(st.sorted, (D,), np.int32)
+        assert np.array_equal(gvals, vals)
+        # keys rebuilt from the GPU's own tile ranges and depths
+        tile_of = np.repeat(np.arange(tiles), granges[:, 1] - granges[:, 0])
+        gkeys = (tile_of.astype(np.uint64) << np.uint64(32)) | depth.view(np.uint32)[gvals].astype(np.uint64)
+        assert np.array_equal(gkeys, keys)
+    gi, gT = host(img), host(T)
+    ok = margin > 1e-4
+    tol = 1e-5 * np.abs(eimg) + 1e-6
+    assert np.all(np.abs(gi - eimg)[:, ok] <= tol[:, ok])
+    assert np.all(np.abs(gT - eT)[ok] <= 1e-5 * eT[ok] + 1e-6)
+    print(f"  D={D} exempt={int((~ok).sum())}/{ok.size}", flush=True)
+
+
+def test_splat_empty_and_all_culled():
+    cam = synth.default_camera(40, 24)
+    ws = rga.SplatWorkspace(0, 40, 24, 16, "cuda")
+    z = lambda *sh: torch.zeros(sh, device="cuda")
+    img, T = rga.splat_forward(cam, z(3, 0), z(9, 0), z(4, 0), z(3, 0), z(0), z(3, 0),
+                               torch.zeros(0, dtype=torch.uint8, device="cuda"), ws)
+    assert torch.all(img == 0) and torch.all(T == 1)
+    # all Gaussians behind the camera
+    n = 50
+    x = torch.zeros(3, n, device="cuda")
+    x[2] = 10.0
+    A = torch.eye(3, device="cuda").reshape(9, 1).repeat(1, n).contiguous()
+    q = torch.zeros(4, n, device="cuda")
+    q[0] = 1
+    ws = rga.SplatWorkspace(n, 40, 24, 1024, "cuda")
+    img, T = rga.splat_forward(cam, x, A, q, z(3, n) - 3, z(n) + 0.5, z(3, n) + 1,
+                               torch.ones(n, dtype=torch.uint8, device="cuda"), ws)
+    assert torch.all(img == 0) and torch.all(T == 1)
+    assert ws.count() == 0
+
+
+def test_splat_capacity_overflow_is_reported():
+    s = scene(1)
+    col = np.ones((3, s["n"]), np.float32)
+    xo, Ao, front = _splat_case(s, col)
+    cam = s["cam"]
+    ws = rga.SplatWorkspace(s["n"], cam.width, cam.height, 16, "cuda")
+    rga.splat_forward(cam, dev(xo), dev(Ao), dev(s["quat"]), dev(s["log_s"]), dev(s["opac"]),
+                      dev(col), dev(front), ws)
+    assert ws.count() > 16
+
+
+# ------------------------------------------------------------------ gradients
+def _grad_case(seed=5):
+    s = synth.micro_scene(seed, 60, 48, 64, he=4, we=8, hv=4, wv=8, log_scale_mean=-3.0)
+    _, _, cnt = helpers.oracle_visibility(s)
+    front = helpers.front_flags(s)
+    w = np.random.default_rng(seed).random((3, s["height"], s["width"]))
+    return s, cnt, front, w
+
+
+def test_gradients_match_fp64_oracle():
+    print("[grad] micro", flush=True)
+    s, cnt, front, w = _grad_case()
+    p = helpers.params64(s, requires_grad=True)
+    img, _ = helpers.render64(s, p, cnt, front)
+    (img * torch.tensor(w.reshape(3, -1))).sum().backward()
+    d = render.upload(s)
+    R = render.Renderer(s, d)
+    pd = {k: d[k] for k in render.TRAINABLE}
+    image, T, ctx = R.forward(pd, dev(cnt))
+    g = R.backward(pd, ctx, dev(w.astype(np.float32)))
+    # forward image against the FP64 oracle as a sanity check of the chain
+    assert np.abs(host(image).reshape(3, -1) - img.detach().numpy()).max() < 2e-5
+    for k in render.TRAINABLE:
+        ref = p[k].grad.numpy()
+        got = host(g[k])
+        rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
+        print(f"  {k:7s} relL2={rel:.2e}", flush=True)
+        assert rel < 2e-3, (k, rel)

@@ -1,0 +1,288 @@
+"""Benchmark of the render-and-train step on one MI355X.
+
+One step = the whole hot path over one frame of the avatar workload
+(100k Gaussians, 7k-vertex / 14k-triangle body mesh, 24 joints, 16x32
+environment = 512 light directions, visibility from 512 views at 128^2,
+one 512x512 camera):
+  skin the mesh -> visibility (raster + filters) -> skin the Gaussians ->
+  shade -> splat forward -> L1 loss and gradient -> splat backward ->
+  shade backward -> skinning backward.
+Inputs are synthetic (seeded) and resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is the fwd+bwd time per step (ms/iter);
+`render_fps` is the forward-only frame rate with visibility recomputed per
+frame, `render_fps_no_vis` with visibility cached per pose.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("fwd+bwd ms/iter and render fps at 512²/100k Gaussians; BF16-MFMA vs FP32 at PSNR")
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (published, with packed issue)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--kernel", default=None, help="kernel timed for the roofline entry")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--all-kernels", action="store_true", help="time every kernel (diagnostic)")
+    return ap.parse_args()
+
+
+def shade_flops(live_pairs: float, tested_pairs: float, backward: bool) -> float:
+    """Algorithmic FP32 operations of the shading sum: per tested (Gaussian,
+    direction) pair the horizon and visibility test (n.w: 5, visibility
+    interpolation: 5, compare: 1); per live pair the BRDF weights and the
+    accumulation (forward 72, backward 171; counted from the formulas, an
+    FMA as 2)."""
+    per_live = 171.0 if backward else 72.0
+    return tested_pairs * 11.0 + live_pairs * per_live
+
+
+def shading_pairs(s, R, p, count):
+    """Count (front-facing Gaussian, direction) pairs and the live ones
+    (w.n > 0 and interpolated visibility > 0) of this frame -- bookkeeping for
+    the roofline entry, outside the timed region."""
+    import torch
+    from paper_2407_10707_amd import rga
+    xo, no, _ = rga.lbs_skin(R.d["skin"], R.d["jidx"], R.d["jw"], p["pos"], p["nrm"])
+    _, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], R.d["vidx"],
+                                   R.d["vw"], count, s["kv"], s["he"], s["we"], s["hv"], s["wv"],
+                                   p["env"], R.cam_pos)
+    he, we, hv, wv = s["he"], s["we"], s["hv"], s["wv"]
+    r = (torch.arange(he, device="cuda", dtype=torch.float64) + 0.5) * math.pi / he
+    c = (torch.arange(we, device="cuda", dtype=torch.float64) + 0.5) * 2 * math.pi / we
+    th, ph = torch.meshgrid(r, c, indexing="ij")
+    dirs = torch.stack([th.sin() * ph.sin(), th.cos(), th.sin() * ph.cos()], -1).reshape(-1, 3)
+    rr = torch.arange(he, device="cuda")[:, None].expand(he, we)
+    cc = torch.arange(we, device="cuda")[None, :].expand(he, we)
+    view = ((rr * hv) // he * wv + (cc * wv) // we).reshape(-1)
+    live = 0
+    tested = 0
+    f = front.bool()
+    for a in range(0, s["n"], 16384):
+        b = min(s["n"], a + 16384)
+        nn = no[:, a:b].T.double()
+        nn = nn / nn.norm(dim=1, keepdim=True)
+        ci = nn @ dirs.T
+        anyv = (count[R.d["vidx"][:, a:b].long()] > 0).any(0)[:, view]
+        m = (ci > 0) & anyv & f[a:b, None]
+        live += int(m.sum())
+        tested += int(f[a:b].sum()) * he * we
+    return {"live": live, "tested": tested}
+
+
+def cpu_baseline(s):
+    """The oracle, as it stands, timed on the host on a bounded sample of one
+    step: FP32-mirror skinning of mesh and Gaussians (all), visibility for
+    16 of the views, FP64 shading forward+backward for 1000 Gaussians,
+    FP32-mirror projection/binning/compositing of the whole frame, and FP64
+    compositing forward+backward for 4096 of the pixels.  Each part's time
+    is scaled to the full step."""
+    import numpy as np
+    import torch
+    from oracle import cpu, ref64
+    cam = s["cam"]
+    n, H, W = s["n"], s["height"], s["width"]
+    V = s["view_dirs"].shape[0]
+    parts = {}
+    t = time.perf_counter()
+    vx, _, _ = cpu.lbs_f32(s["skin"], s["mesh_jidx"], s["mesh_jw"], s["verts"])
+    xo, no, Ao = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    parts["lbs"] = time.perf_counter() - t
+    vs = 16
+    t = time.perf_counter()
+    cpu.mesh_visibility(vx, s["faces"], s["view_dirs"][:vs], s["vis_res"], s["knn_v"])
+    parts["visibility"] = (time.perf_counter() - t) * V / vs
+    # the FP64 shading oracle evaluates every (Gaussian, light) pair whatever
+    # the visibility, so a constant count stands in for the full visibility
+    campos = cam.centre.astype(np.float32)
+    front = cpu.front_f32(xo, no, campos)
+    ns = 1000
+    idx = np.nonzero(front)[0][:ns]
+    cnt_full = np.full((s["nv"], V), s["kv"] // 2, np.uint8)
+    t = time.perf_counter()
+    xs = torch.tensor(xo[:, idx].astype(np.float64), requires_grad=True)
+    nsv = torch.tensor(no[:, idx].astype(np.float64), requires_grad=True)
+    alb = torch.tensor(s["albedo"][:, idx].astype(np.float64), requires_grad=True)
+    rough = torch.tensor(s["rough"][idx].astype(np.float64), requires_grad=True)
+    tint = torch.tensor(s["tint"][idx].astype(np.float64), requires_grad=True)
+    env = torch.tensor(s["env"].astype(np.float64), requires_grad=True)
+    col, _ = ref64.shade(xs, nsv, alb, rough, tint, s["vidx"][:, idx], s["vw"][:, idx], cnt_full,
+                         s["kv"], s["he"], s["we"], s["hv"], s["wv"], env, campos.astype(np.float64),
+                         front[idx])
+    col.sum().backward()
+    parts["shading"] = (time.perf_counter() - t) * n / len(idx)
+    colf = np.random.default_rng(0).random((3, n)).astype(np.float32)
+    t = time.perf_counter()
+    pre = cpu.splat_preprocess(cam, xo, Ao, s["quat"], s["log_s"], s["opac"], front)
+    keys, vals, ranges = cpu.splat_bin(cam, pre)
+    cpu.composite_tiles(cam, ranges, vals, pre, s["opac"], colf)
+    parts["splat_fp32"] = time.perf_counter() - t
+    npx = 4096
+    pix = np.random.default_rng(1).choice(H * W, npx, replace=False)
+    t = time.perf_counter()
+    q = {k: torch.tensor(np.asarray(s[k], np.float64), requires_grad=True)
+         for k in ("quat", "log_s", "opac")}
+    xt = torch.tensor(xo.astype(np.float64), requires_grad=True)
+    ct = torch.tensor(colf.astype(np.float64), requires_grad=True)
+    proj = ref64.project(cam, xt, torch.tensor(Ao.astype(np.float64)), q["quat"], q["log_s"],
+                         q["opac"], front)
+    img, _ = ref64.composite(cam, proj, q["opac"], ct, pixels=pix)
+    img.sum().backward()
+    parts["splat_fp64_fwd_bwd"] = (time.perf_counter() - t) * (H * W) / npx
+    total_ms = sum(parts.values()) * 1e3
+    return {"value": round(total_ms, 1), "unit": "ms/iter", "cores": max(cpu.num_threads(),
+                                                                          torch.get_num_threads()),
+            "kind": "oracle",
+            "sample": f"one step of the same workload, timed in parts and scaled: skinning (all), "
+                      f"visibility {vs}/{V} views, FP64 shading fwd+bwd {len(idx)}/{n} Gaussians, "
+                      f"FP32 projection+binning+compositing (all), FP64 compositing fwd+bwd "
+                      f"{npx}/{H * W} pixels",
+            "parts_s": {k: round(v, 3) for k, v in parts.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2407_10707_amd import render, rga, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rga.lib()
+    s = synth.make_scene(args.config)
+    cfg = s["cfg"]
+    d = render.upload(s)
+    R = render.Renderer(s, d, precision=args.precision)
+    p = {k: d[k] for k in render.TRAINABLE}
+    target = d["target"]
+
+    def step():
+        count = R.visibility()
+        loss, grads = R.train_step(p, count, target)
+        return loss
+
+    def fwd(with_vis, count=None):
+        if with_vis:
+            count = R.visibility()
+        image, _, _ = R.forward(p, count)
+        return image
+
+    # first frame: size the splat workspace to the real duplicate count
+    step()
+    while R.ensure_capacity():
+        step()
+    D = R.ws.count()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    kernel = args.kernel or "shade_bwd"
+    rga.timing_reset()
+    rga.timing_filter(None if args.all_kernels else kernel)
+    rga.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rga.timing_enable(False)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    k_ms, k_n = rga.timing_read(kernel)
+    k_avg = k_ms / max(k_n, 1)
+    per_kernel = {}
+    if args.all_kernels:
+        for name in ("lbs_fwd", "vis_frame", "vis_raster", "vis_transpose", "vis_majority",
+                     "vis_count", "shade_fwd", "splat_fill", "splat_preprocess", "radix_upsweep",
+                     "radix_binscan", "radix_downsweep", "touched_blocksum", "touched_blockscan",
+                     "splat_duplicate", "tile_ranges", "blend_fwd", "l1_partial", "l1_final",
+                     "splat_zero", "blend_bwd", "preprocess_bwd", "shade_bwd", "shade_denv",
+                     "lbs_bwd"):
+            ms, cnt = rga.timing_read(name)
+            if cnt:
+                per_kernel[name] = round(ms / args.steps, 4)
+
+    # forward-only frame rates (visibility per frame, and cached per pose)
+    count = R.visibility()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd(True)
+    torch.cuda.synchronize()
+    fps = args.steps / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd(False, count)
+    torch.cuda.synchronize()
+    fps_nv = args.steps / (time.perf_counter() - t0)
+
+    # algorithmic work of the timed kernel (shading): live / tested pairs
+    wl = shading_pairs(s, R, p, count)
+    roof = None
+    if kernel in ("shade_bwd", "shade_fwd"):
+        flops = shade_flops(wl["live"], wl["tested"], kernel == "shade_bwd")
+        ach = flops / (k_avg * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": kernel, "kernel_ms": round(k_avg, 4),
+                "work": {"tested_pairs": wl["tested"], "live_pairs": wl["live"],
+                         "flops_per_launch": flops}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(s)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_step, 4),
+        "unit": "ms/iter",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": cfg.name, "gaussians": s["n"], "mesh_vertices": s["nv"],
+                   "mesh_triangles": s["nf"], "joints": 24, "light_directions": cfg.he * cfg.we,
+                   "vis_views": cfg.hv * cfg.wv, "vis_res": cfg.vis_res,
+                   "image": [s["height"], s["width"]], "precision": args.precision},
+        "render_fps": round(fps, 2),
+        "render_fps_no_vis": round(fps_nv, 2),
+        "duplicates": D,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if per_kernel:
+        out["per_kernel_ms_per_step"] = per_kernel
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -224,6 +224,8 @@ int l1_loss(void* stream, int64_t count, const float* image, const float* target
  * synchronises and returns the summed milliseconds and launch count of the
  * kernels whose name matches `kernel` exactly.                              */
 int rga_timing_enable(int on);
+/* Restrict timing to kernels named `kernel` (NULL or "" times every kernel). */
+int rga_timing_filter(const char* kernel);
 int rga_timing_reset(void);
 int rga_timing_read(const char* kernel, double* total_ms, int64_t* launches);
 

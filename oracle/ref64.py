@@ -253,23 +253,29 @@ def composite(cam, proj, opac, color, pixels: Optional[np.ndarray] = None):
     onscreen = (m[0] + hx > 0) & (m[0] - hx < W) & (m[1] + hy > 0) & (m[1] - hy < H)
     nx = torch.where(onscreen, x1 - x0 + 1, torch.zeros_like(x0))
     ny = torch.where(onscreen, y1 - y0 + 1, torch.zeros_like(y0))
-    cnt = nx * ny
-    if pix_list is not None:
-        # keep only pairs that land on the requested pixels
-        lut = torch.full((H * W,), -1, dtype=torch.long)
-        lut[pix_list] = torch.arange(P)
-    gi = torch.repeat_interleave(torch.arange(len(gid)), cnt)
-    start = torch.cumsum(cnt, 0) - cnt
-    local = torch.arange(int(cnt.sum())) - start[gi]
-    px = x0[gi] + local % nx[gi]
-    py = y0[gi] + local // nx[gi]
-    flat = py * W + px
-    if pix_list is not None:
-        slot = lut[flat]
-        keep_pair = slot >= 0
-        gi, px, py, slot = gi[keep_pair], px[keep_pair], py[keep_pair], slot[keep_pair]
+    if pix_list is None:
+        cnt = nx * ny
+        gi = torch.repeat_interleave(torch.arange(len(gid)), cnt)
+        start = torch.cumsum(cnt, 0) - cnt
+        local = torch.arange(int(cnt.sum())) - start[gi]
+        px = x0[gi] + local % nx[gi]
+        py = y0[gi] + local // nx[gi]
+        slot = py * W + px
     else:
-        slot = flat
+        # only the requested pixels: test every box against each pixel
+        qx, qy = pix_list % W, pix_list // W
+        parts = []
+        for a in range(0, P, 256):
+            b = min(P, a + 256)
+            inside = ((qx[a:b, None] >= x0[None]) & (qx[a:b, None] <= x0[None] + nx[None] - 1) &
+                      (qy[a:b, None] >= y0[None]) & (qy[a:b, None] <= y0[None] + ny[None] - 1))
+            sl, g = torch.nonzero(inside, as_tuple=True)
+            parts.append((g, sl + a))
+        gi = torch.cat([t[0] for t in parts])
+        slot = torch.cat([t[1] for t in parts])
+        px, py = qx[slot], qy[slot]
+    if len(slot) == 0:
+        return torch.zeros(3, P, dtype=f64), torch.ones(P, dtype=f64)
     key = slot * len(gid) + rank[gi]
     srt = torch.argsort(key)
     gi, px, py, slot = gi[srt], px[srt], py[srt], slot[srt]

@@ -35,6 +35,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+std::string g_filter;           // empty: time every kernel
 std::vector<Rec> g_recs;        // completed or pending start/stop pairs
 std::vector<hipEvent_t> g_pool; // reusable events
 std::vector<std::pair<std::string, std::pair<double, int64_t>>> g_sums;
@@ -76,6 +77,7 @@ bool timing_on() { return g_on; }
 
 void timing_mark(const char* name, hipStream_t s, bool start) {
   std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_filter.empty() && g_filter != name) return;
   if (start) {
     Rec r;
     r.name = name;
@@ -104,6 +106,12 @@ int rga_abi_version(void) { return 1; }
 int rga_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(rga::g_mu);
   rga::g_on = on != 0;
+  return RGA_OK;
+}
+
+int rga_timing_filter(const char* kernel) {
+  std::lock_guard<std::mutex> lk(rga::g_mu);
+  rga::g_filter = kernel ? kernel : "";
   return RGA_OK;
 }
 

@@ -52,6 +52,7 @@ _SIGS = {
     "l1_loss": (_I, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "rga_timing_enable": (_I, [_I]),
     "rga_timing_reset": (_I, []),
+    "rga_timing_filter": (_I, [C.c_char_p]),
     "rga_timing_read": (_I, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
 }
 
@@ -325,6 +326,10 @@ def l1_loss(image, target, want_grad: bool = True, ws=None):
 # ----------------------------------------------------------------------------- timing
 def timing_enable(on: bool = True):
     _check(lib().rga_timing_enable(int(on)), "rga_timing_enable")
+
+
+def timing_filter(kernel: Optional[str]):
+    _check(lib().rga_timing_filter(kernel.encode() if kernel else None), "rga_timing_filter")
 
 
 def timing_reset():

@@ -219,12 +219,14 @@ def main():
         for name in ("lbs_fwd", "vis_frame", "vis_raster", "vis_transpose", "vis_majority",
                      "vis_count", "shade_fwd", "splat_fill", "splat_preprocess", "radix_upsweep",
                      "radix_binscan", "radix_downsweep", "touched_blocksum", "touched_blockscan",
-                     "splat_duplicate", "tile_ranges", "blend_fwd", "l1_partial", "l1_final",
+                     "splat_duplicate", "tile_ranges", "chunk_index", "blend_chunk",
+                     "blend_combine", "l1_partial", "l1_final",
                      "splat_zero", "blend_bwd", "preprocess_bwd", "shade_bwd", "shade_denv",
                      "lbs_bwd"):
             ms, cnt = rga.timing_read(name)
             if cnt:
                 per_kernel[name] = round(ms / args.steps, 4)
+        per_kernel["sum_of_kernels"] = round(sum(per_kernel.values()), 4)
 
     # forward-only frame rates (visibility per frame, and cached per pose)
     count = R.visibility()

@@ -56,18 +56,63 @@ __device__ inline void build_table(const ShadeArgs& a, float* tab, int with_area
   }
 }
 
+// Per-Gaussian inputs, loaded one Gaussian ahead of its use.
+struct Attr {
+  float x[3], m[3], alb[3], rough, tint, vw[3];
+  int vidx[3];
+};
+
+__device__ inline void attr_load(const ShadeArgs& a, int g, Attr& A) {
+  const int n = a.n, nvm = a.nv - 1;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    A.x[c] = a.x[(size_t)c * n + g];
+    A.m[c] = a.nrm[(size_t)c * n + g];
+    A.alb[c] = a.albedo[(size_t)c * n + g];
+    A.vw[c] = a.vw[(size_t)c * n + g];
+    A.vidx[c] = rga::clampi(a.vidx[(size_t)c * n + g], 0, nvm);
+  }
+  A.rough = a.rough[g];
+  A.tint = a.tint[g];
+}
+
+// The three visibility-count rows of a Gaussian (3 V bytes, V % 16 == 0) are
+// copied straight from global memory into the wave's LDS slot with
+// global_load_lds (16 bytes per lane, NQ = ceil(3 V / 1024) per lane), one
+// Gaussian ahead, into the other half of a double buffer.
+template <int NQ>
+__device__ inline void rows_dma(const ShadeArgs& a, const Attr& A, uint8_t* lds, int lane) {
+  const int nq = 3 * a.V / 16;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = lane + 64 * i;
+    if (q < nq) {
+      const int byte = 16 * q;
+      const int j = byte / a.V;
+      const int off = byte - j * a.V;
+      const int vi = j == 0 ? A.vidx[0] : (j == 1 ? A.vidx[1] : A.vidx[2]);
+      __builtin_amdgcn_global_load_lds(a.count + (size_t)vi * a.V + off, lds + 1024 * i, 16, 0, 0);
+    }
+  }
+}
+
+// Wait for every outstanding memory operation of the wave (the row copies).
+__device__ inline void wait_all() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 struct GaussCtx {
   float nn[3], wo[3], co, a2, kG, Go, inn, iwo, alpha, gamma;
   float u0, u1, u2;
-  const uint8_t *r0, *r1, *r2;
+  const uint8_t* rows;   // LDS copy of the three count rows
   bool front;
 };
 
-__device__ inline void gauss_setup(const ShadeArgs& a, int g, GaussCtx& G) {
-  const int n = a.n;
-  const float x0 = a.x[g], x1 = a.x[n + g], x2 = a.x[2 * n + g];
-  const float m0 = a.nrm[g], m1 = a.nrm[n + g], m2 = a.nrm[2 * n + g];
-  const float w0 = a.cam[0] - x0, w1 = a.cam[1] - x1, w2 = a.cam[2] - x2;
+__device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint8_t* rows,
+                                   GaussCtx& G) {
+  const float m0 = A.m[0], m1 = A.m[1], m2 = A.m[2];
+  const float w0 = a.cam[0] - A.x[0], w1 = a.cam[1] - A.x[1], w2 = a.cam[2] - A.x[2];
   // back-face decision in FP32 with a fixed operation order
   const float dotf = fmaf(m2, w2, fmaf(m1, w1, m0 * w0));
   G.front = dotf > 0.f;
@@ -80,28 +125,26 @@ __device__ inline void gauss_setup(const ShadeArgs& a, int g, GaussCtx& G) {
   G.wo[1] = w1 * G.iwo;
   G.wo[2] = w2 * G.iwo;
   G.co = fmaf(G.nn[2], G.wo[2], fmaf(G.nn[1], G.wo[1], G.nn[0] * G.wo[0]));
-  G.gamma = a.rough[g];
+  G.gamma = A.rough;
   G.alpha = G.gamma * G.gamma;
   G.a2 = G.alpha * G.alpha;
   G.kG = (G.gamma + 1.f) * (G.gamma + 1.f) * 0.125f;
   G.Go = 1.f / fmaf(G.co, 1.f - G.kG, G.kG);
   const float ikv = 1.f / (float)a.kv;
-  G.u0 = a.vw[g] * ikv;
-  G.u1 = a.vw[n + g] * ikv;
-  G.u2 = a.vw[2 * n + g] * ikv;
-  const int nvm = a.nv - 1;
-  G.r0 = a.count + (size_t)rga::clampi(a.vidx[g], 0, nvm) * a.V;
-  G.r1 = a.count + (size_t)rga::clampi(a.vidx[n + g], 0, nvm) * a.V;
-  G.r2 = a.count + (size_t)rga::clampi(a.vidx[2 * n + g], 0, nvm) * a.V;
+  G.u0 = A.vw[0] * ikv;
+  G.u1 = A.vw[1] * ikv;
+  G.u2 = A.vw[2] * ikv;
+  G.rows = rows;
 }
 
 // Live-direction test for direction k; returns the visibility (0 if dead).
-__device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int k) {
+__device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int V, int k) {
   const float d0 = tab[k], d1 = tab[K + k], d2 = tab[2 * K + k];
   const float ci = fmaf(G.nn[2], d2, fmaf(G.nn[1], d1, G.nn[0] * d0));
   if (!(ci > 0.f)) return 0.f;
   const int view = reinterpret_cast<const int*>(tab)[6 * K + k];
-  const float c0 = (float)G.r0[view], c1 = (float)G.r1[view], c2 = (float)G.r2[view];
+  const float c0 = (float)G.rows[view], c1 = (float)G.rows[V + view],
+              c2 = (float)G.rows[2 * V + view];
   return fmaf(G.u2, c2, fmaf(G.u1, c1, G.u0 * c0));
 }
 
@@ -154,83 +197,106 @@ __device__ inline void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int NQ>
 __global__ void __launch_bounds__(kThreads)
 shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ front) {
   extern __shared__ __align__(16) float tab[];
   __shared__ int qk[kWaves][kRing];
   __shared__ float qv[kWaves][kRing];
   build_table(a, tab, 0);
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int K = a.K, n = a.n;
+  const int K = a.K, n = a.n, V = a.V;
+  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 7 * K) + (size_t)wave * 6 * V;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int gi = blockIdx.x * kWaves + wave; gi < n; gi += gridDim.x * kWaves) {
-    const int g = __builtin_amdgcn_readfirstlane(gi);
+  const int stride = gridDim.x * kWaves;
+  int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
+  Attr A;
+  int cur = 0;
+  if (g < n) {
+    attr_load(a, g, A);
+    rows_dma<NQ>(a, A, rows0, lane);
+  }
+  wait_all();
+  __syncthreads();
+  while (g < n) {
+    const int gn = g + stride;
+    uint8_t* rows = rows0 + cur * 3 * V;
+    // fetch the next Gaussian's inputs while this one is shaded
+    Attr An;
+    if (gn < n) {
+      attr_load(a, gn, An);
+      rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
+    }
     GaussCtx G;
-    gauss_setup(a, g, G);
+    gauss_setup(a, A, rows, G);
     if (!G.front) {
       if (lane < 3) color[(size_t)lane * n + g] = 0.f;
       if (lane == 0) front[g] = 0;
-      continue;
-    }
-    float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
-    int head = 0, tail = 0;
-    for (int k0 = 0; k0 < K; k0 += 64) {
-      const int k = k0 + lane;
-      const float v = k < K ? live_vis(G, tab, K, k) : 0.f;
-      const bool live = v > 0.f;
-      const uint64_t m = __ballot(live);
-      if (live) {
-        const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
-        qk[wave][slot] = k;
-        qv[wave][slot] = v;
+    } else {
+      float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
+      int head = 0, tail = 0;
+      for (int k0 = 0; k0 < K; k0 += 64) {
+        const int k = k0 + lane;
+        const float v = k < K ? live_vis(G, tab, K, V, k) : 0.f;
+        const bool live = v > 0.f;
+        const uint64_t m = __ballot(live);
+        if (live) {
+          const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
+          qk[wave][slot] = k;
+          qv[wave][slot] = v;
+        }
+        tail += __popcll(m);
+        if (tail - head >= 64) {
+          wave_fence();
+          const int slot = (head + lane) & (kRing - 1);
+          Pair P;
+          pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
+          sd0 = fmaf(P.Wd, P.E[0], sd0);
+          sd1 = fmaf(P.Wd, P.E[1], sd1);
+          sd2 = fmaf(P.Wd, P.E[2], sd2);
+          ss0 = fmaf(P.Ws, P.E[0], ss0);
+          ss1 = fmaf(P.Ws, P.E[1], ss1);
+          ss2 = fmaf(P.Ws, P.E[2], ss2);
+          head += 64;
+          wave_fence();
+        }
       }
-      tail += __popcll(m);
-      if (tail - head >= 64) {
+      if (tail > head) {
         wave_fence();
-        const int slot = (head + lane) & (kRing - 1);
-        Pair P;
-        pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
-        sd0 = fmaf(P.Wd, P.E[0], sd0);
-        sd1 = fmaf(P.Wd, P.E[1], sd1);
-        sd2 = fmaf(P.Wd, P.E[2], sd2);
-        ss0 = fmaf(P.Ws, P.E[0], ss0);
-        ss1 = fmaf(P.Ws, P.E[1], ss1);
-        ss2 = fmaf(P.Ws, P.E[2], ss2);
-        head += 64;
+        if (lane < tail - head) {
+          const int slot = (head + lane) & (kRing - 1);
+          Pair P;
+          pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
+          sd0 = fmaf(P.Wd, P.E[0], sd0);
+          sd1 = fmaf(P.Wd, P.E[1], sd1);
+          sd2 = fmaf(P.Wd, P.E[2], sd2);
+          ss0 = fmaf(P.Ws, P.E[0], ss0);
+          ss1 = fmaf(P.Ws, P.E[1], ss1);
+          ss2 = fmaf(P.Ws, P.E[2], ss2);
+        }
         wave_fence();
       }
-    }
-    if (tail > head) {
-      wave_fence();
-      if (lane < tail - head) {
-        const int slot = (head + lane) & (kRing - 1);
-        Pair P;
-        pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
-        sd0 = fmaf(P.Wd, P.E[0], sd0);
-        sd1 = fmaf(P.Wd, P.E[1], sd1);
-        sd2 = fmaf(P.Wd, P.E[2], sd2);
-        ss0 = fmaf(P.Ws, P.E[0], ss0);
-        ss1 = fmaf(P.Ws, P.E[1], ss1);
-        ss2 = fmaf(P.Ws, P.E[2], ss2);
+      sd0 = rga::wave_sum(sd0);
+      sd1 = rga::wave_sum(sd1);
+      sd2 = rga::wave_sum(sd2);
+      ss0 = rga::wave_sum(ss0);
+      ss1 = rga::wave_sum(ss1);
+      ss2 = rga::wave_sum(ss2);
+      if (lane < 3) {
+        const float sd = lane == 0 ? sd0 : (lane == 1 ? sd1 : sd2);
+        const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
+        const float alb = lane == 0 ? A.alb[0] : (lane == 1 ? A.alb[1] : A.alb[2]);
+        const float Lo = alb * (1.f / kPi) * sd + A.tint * ss;
+        color[(size_t)lane * n + g] = srgb(Lo);
       }
-      wave_fence();
+      if (lane == 0) front[g] = 1;
     }
-    sd0 = rga::wave_sum(sd0);
-    sd1 = rga::wave_sum(sd1);
-    sd2 = rga::wave_sum(sd2);
-    ss0 = rga::wave_sum(ss0);
-    ss1 = rga::wave_sum(ss1);
-    ss2 = rga::wave_sum(ss2);
-    if (lane < 3) {
-      const float sd = lane == 0 ? sd0 : (lane == 1 ? sd1 : sd2);
-      const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
-      const float alb = a.albedo[(size_t)lane * n + g];
-      const float Lo = alb * (1.f / kPi) * sd + a.tint[g] * ss;
-      color[(size_t)lane * n + g] = srgb(Lo);
-    }
-    if (lane == 0) front[g] = 1;
+    wait_all();
+    wave_fence();
+    if (gn < n) A = An;
+    cur ^= 1;
+    g = gn;
   }
 }
 
@@ -280,6 +346,7 @@ __device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv
   acc.gga += gga;
 }
 
+template <int NQ>
 __global__ void __launch_bounds__(kThreads)
 shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __restrict__ dcolor,
                  float* __restrict__ dx, float* __restrict__ dn, float* __restrict__ dalbedo,
@@ -288,18 +355,35 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   extern __shared__ __align__(16) float tab[];
   __shared__ int qk[kWaves][kRing];
   __shared__ float qv[kWaves][kRing];
-  const int K = a.K, n = a.n;
+  const int K = a.K, n = a.n, V = a.V;
   float* denv_lds = tab + 7 * K;
-  build_table(a, tab, 0);
-  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
-  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 10 * K) + (size_t)wave * 6 * V;
+  build_table(a, tab, 0);
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  for (int gi = blockIdx.x * kWaves + wave; gi < n; gi += gridDim.x * kWaves) {
-    const int g = __builtin_amdgcn_readfirstlane(gi);
+  const int stride = gridDim.x * kWaves;
+  int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
+  Attr A;
+  int cur = 0;
+  if (g < n) {
+    attr_load(a, g, A);
+    rows_dma<NQ>(a, A, rows0, lane);
+  }
+  wait_all();
+  __syncthreads();
+  while (g < n) {
+    const int gn = g + stride;
+    uint8_t* rows = rows0 + cur * 3 * V;
+    // fetch the next Gaussian's inputs while this one is shaded
+    Attr An;
+    if (gn < n) {
+      attr_load(a, gn, An);
+      rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
+    }
     GaussCtx G;
-    gauss_setup(a, g, G);
+    gauss_setup(a, A, rows, G);
     if (!G.front) {
       if (lane < 3) {
         dn[(size_t)lane * n + g] = 0.f;
@@ -309,92 +393,134 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
         drough[g] = 0.f;
         dtint[g] = 0.f;
       }
-      continue;
-    }
-    // recover L_o from the colour and form dL/dL_o
-    float dLo[3], aop[3], qd[3];
-    for (int c = 0; c < 3; ++c) {
-      const float col = color[(size_t)c * n + g];
-      const float dc = dcolor[(size_t)c * n + g];
-      if (col <= 0.04045f) {
-        dLo[c] = dc * 12.92f;
-      } else {
-        const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
-        dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
-      }
-      aop[c] = a.albedo[(size_t)c * n + g] * (1.f / kPi);
-      qd[c] = dLo[c] * aop[c];
-    }
-    const float tint = a.tint[g];
-    BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
-    int head = 0, tail = 0;
-    for (int k0 = 0; k0 < K; k0 += 64) {
-      const int k = k0 + lane;
-      const float v = k < K ? live_vis(G, tab, K, k) : 0.f;
-      const bool live = v > 0.f;
-      const uint64_t m = __ballot(live);
-      if (live) {
-        const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
-        qk[wave][slot] = k;
-        qv[wave][slot] = v;
-      }
-      tail += __popcll(m);
-      if (tail - head >= 64) {
-        wave_fence();
-        const int slot = (head + lane) & (kRing - 1);
-        pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
-        head += 64;
-        wave_fence();
-      }
-    }
-    if (tail > head) {
-      wave_fence();
-      if (lane < tail - head) {
-        const int slot = (head + lane) & (kRing - 1);
-        pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
-      }
-      wave_fence();
-    }
-    float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
-                   acc.gco, acc.gga, acc.sd[0], acc.sd[1], acc.sd[2], acc.ts};
+    } else {
+      // recover L_o from the colour and form dL/dL_o
+      float dLo[3], aop[3], qd[3];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) r[i] = rga::wave_sum(r[i]);
-    if (lane == 0) {
-      const float gco = r[6];
-      float gn[3] = {r[0] + gco * G.wo[0], r[1] + gco * G.wo[1], r[2] + gco * G.wo[2]};
-      float gw[3] = {r[3] + gco * G.nn[0], r[4] + gco * G.nn[1], r[5] + gco * G.nn[2]};
-      const float pn = gn[0] * G.nn[0] + gn[1] * G.nn[1] + gn[2] * G.nn[2];
-      const float pw = gw[0] * G.wo[0] + gw[1] * G.wo[1] + gw[2] * G.wo[2];
       for (int c = 0; c < 3; ++c) {
-        dn[(size_t)c * n + g] = (gn[c] - G.nn[c] * pn) * G.inn;
-        // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
-        dx[(size_t)c * n + g] += -(gw[c] - G.wo[c] * pw) * G.iwo;
-        dalbedo[(size_t)c * n + g] = dLo[c] * r[8 + c] * (1.f / kPi);
+        const float col = color[(size_t)c * n + g];
+        const float dc = dcolor[(size_t)c * n + g];
+        if (col <= 0.04045f) {
+          dLo[c] = dc * 12.92f;
+        } else {
+          const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
+          dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
+        }
+        aop[c] = A.alb[c] * (1.f / kPi);
+        qd[c] = dLo[c] * aop[c];
       }
-      drough[g] = r[7];
-      dtint[g] = r[11];
+      const float tint = A.tint;
+      BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
+      int head = 0, tail = 0;
+      for (int k0 = 0; k0 < K; k0 += 64) {
+        const int k = k0 + lane;
+        const float v = k < K ? live_vis(G, tab, K, V, k) : 0.f;
+        const bool live = v > 0.f;
+        const uint64_t m = __ballot(live);
+        if (live) {
+          const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
+          qk[wave][slot] = k;
+          qv[wave][slot] = v;
+        }
+        tail += __popcll(m);
+        if (tail - head >= 64) {
+          wave_fence();
+          const int slot = (head + lane) & (kRing - 1);
+          pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
+          head += 64;
+          wave_fence();
+        }
+      }
+      if (tail > head) {
+        wave_fence();
+        if (lane < tail - head) {
+          const int slot = (head + lane) & (kRing - 1);
+          pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
+        }
+        wave_fence();
+      }
+      float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
+                     acc.gco, acc.gga, acc.sd[0], acc.sd[1], acc.sd[2], acc.ts};
+#pragma unroll
+      for (int i = 0; i < 12; ++i) r[i] = rga::wave_sum(r[i]);
+      if (lane == 0) {
+        const float gco = r[6];
+        float gn3[3] = {r[0] + gco * G.wo[0], r[1] + gco * G.wo[1], r[2] + gco * G.wo[2]};
+        float gw[3] = {r[3] + gco * G.nn[0], r[4] + gco * G.nn[1], r[5] + gco * G.nn[2]};
+        const float pn = gn3[0] * G.nn[0] + gn3[1] * G.nn[1] + gn3[2] * G.nn[2];
+        const float pw = gw[0] * G.wo[0] + gw[1] * G.wo[1] + gw[2] * G.wo[2];
+        for (int c = 0; c < 3; ++c) {
+          dn[(size_t)c * n + g] = (gn3[c] - G.nn[c] * pn) * G.inn;
+          // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
+          dx[(size_t)c * n + g] += -(gw[c] - G.wo[c] * pw) * G.iwo;
+          dalbedo[(size_t)c * n + g] = dLo[c] * r[8 + c] * (1.f / kPi);
+        }
+        drough[g] = r[7];
+        dtint[g] = r[11];
+      }
     }
+    wait_all();
+    wave_fence();
+    if (gn < n) A = An;
+    cur ^= 1;
+    g = gn;
   }
   __syncthreads();
   float* out = denv_part + (size_t)blockIdx.x * 3 * K;
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) out[i] = denv_lds[i];
 }
 
-// denv[k][c] = area_k * sum over workgroups (fixed order)
-__global__ void __launch_bounds__(256)
+// denv[k][c] = area_k * sum over workgroups.  Each block owns 64 outputs;
+// its 1024 threads split the partials into 16 interleaved groups and the
+// groups are added in a fixed tree order (deterministic).
+__global__ void __launch_bounds__(1024)
 denv_reduce_kernel(int K, int he, int we, int parts, const float* __restrict__ part,
                    float* __restrict__ denv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * K) return;
-  float s = 0.f;
-  for (int p = 0; p < parts; ++p) s += part[(size_t)p * 3 * K + i];
-  const int k = i / 3, r = k / we;
-  const float dth = kPi / (float)he;
-  const float area = (2.f * kPi / (float)we) * 2.f * sinf(0.5f * dth) * sinf(((float)r + 0.5f) * dth);
-  denv[i] = s * area;
+  __shared__ float red[16][64];
+  const int o = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + o;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (i < 3 * K) {
+    int p = grp;
+    for (; p + 48 < parts; p += 64) {
+      s0 += part[(size_t)p * 3 * K + i];
+      s1 += part[(size_t)(p + 16) * 3 * K + i];
+      s2 += part[(size_t)(p + 32) * 3 * K + i];
+      s3 += part[(size_t)(p + 48) * 3 * K + i];
+    }
+    for (; p < parts; p += 16) s0 += part[(size_t)p * 3 * K + i];
+  }
+  red[grp][o] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  for (int h = 8; h > 0; h >>= 1) {
+    if (grp < h) red[grp][o] += red[grp + h][o];
+    __syncthreads();
+  }
+  if (grp == 0 && i < 3 * K) {
+    const int k = i / 3, r = k / we;
+    const float dth = kPi / (float)he;
+    const float area = (2.f * kPi / (float)we) * 2.f * sinf(0.5f * dth) * sinf(((float)r + 0.5f) * dth);
+    denv[i] = red[0][o] * area;
+  }
+}
+
+void set_lds_limits() {
+  static bool done = false;
+  if (done) return;
+  const void* ks[] = {reinterpret_cast<const void*>(shade_fwd_kernel<1>),
+                      reinterpret_cast<const void*>(shade_fwd_kernel<2>),
+                      reinterpret_cast<const void*>(shade_fwd_kernel<3>),
+                      reinterpret_cast<const void*>(shade_fwd_kernel<6>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<1>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<2>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<3>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<6>)};
+  for (const void* k : ks) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  done = true;
 }
 
 int grid_for(int n, size_t lds) {
+  set_lds_limits();
   static int ncu = 0;
   if (ncu == 0) {
     int dev = 0;
@@ -418,6 +544,10 @@ int check_args(const char* fn, int n, const float* x, const float* nrm, const fl
   if ((int64_t)he * we > 3584)
     return rga::fail(RGA_EUNSUPPORTED, "%s: at most 3584 light directions (LDS table)", fn);
   if (nv < 1 || kv < 1) return rga::fail(RGA_EINVAL, "%s: nv, kv >= 1", fn);
+  if ((hv * wv) % 16 != 0 || hv * wv > 2048)
+    return rga::fail(RGA_EUNSUPPORTED, "%s: the view count must be a multiple of 16, at most 2048", fn);
+  if (count && !rga::aligned16(count))
+    return rga::fail(RGA_EINVAL, "%s: count must be 16-byte aligned", fn);
   if (!cam_pos || !env) return rga::fail(RGA_EINVAL, "%s: null env or cam_pos", fn);
   if (precision != RGA_FP32 && precision != RGA_BF16X3)
     return rga::fail(RGA_EINVAL, "%s: unknown precision %d", fn, precision);
@@ -470,16 +600,16 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 form not built yet");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
-  const size_t lds = (size_t)7 * a.K * sizeof(float);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(shade_fwd_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    attr = true;
-  }
+  const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  RGA_LAUNCH("shade_fwd", shade_fwd_kernel, dim3(grid_for(n, lds)), dim3(kThreads), lds, s, a,
-             color, front);
+  const int nq = (int)rga::ceil_div(3 * a.V, 1024);
+  const dim3 grid(grid_for(n, lds));
+  switch (nq) {
+    case 1: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<1>, grid, dim3(kThreads), lds, s, a, color, front); break;
+    case 2: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<2>, grid, dim3(kThreads), lds, s, a, color, front); break;
+    case 3: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<3>, grid, dim3(kThreads), lds, s, a, color, front); break;
+    default: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<6>, grid, dim3(kThreads), lds, s, a, color, front); break;
+  }
   RGA_CHECK_LAUNCH("shade_gaussians");
   return RGA_OK;
 }
@@ -511,23 +641,26 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 form not built yet");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
-  const size_t lds = (size_t)10 * a.K * sizeof(float);
+  const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
   const int grid = grid_for(n, lds);
   if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
     return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(shade_bwd_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    attr = true;
-  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* part = static_cast<float*>(ws);
   if (n > 0) {
-    RGA_LAUNCH("shade_bwd", shade_bwd_kernel, dim3(grid), dim3(kThreads), lds, s, a, color, dcolor,
-               dx, dn, dalbedo, drough, dtint, part);
+    const int nq = (int)rga::ceil_div(3 * a.V, 1024);
+#define RGA_SHADE_BWD(NQV)                                                                    \
+  RGA_LAUNCH("shade_bwd", shade_bwd_kernel<NQV>, dim3(grid), dim3(kThreads), lds, s, a, color, \
+             dcolor, dx, dn, dalbedo, drough, dtint, part)
+    switch (nq) {
+      case 1: RGA_SHADE_BWD(1); break;
+      case 2: RGA_SHADE_BWD(2); break;
+      case 3: RGA_SHADE_BWD(3); break;
+      default: RGA_SHADE_BWD(6); break;
+    }
+#undef RGA_SHADE_BWD
   }
-  RGA_LAUNCH("shade_denv", denv_reduce_kernel, dim3(rga::ceil_div(3 * a.K, 256)), dim3(256), 0, s,
+  RGA_LAUNCH("shade_denv", denv_reduce_kernel, dim3(rga::ceil_div(3 * a.K, 64)), dim3(1024), 0, s,
              a.K, he, we, n > 0 ? grid : 0, part, denv);
   RGA_CHECK_LAUNCH("shade_gaussians_backward");
   return RGA_OK;

@@ -29,11 +29,14 @@ constexpr int kTile = 16;
 constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;  // per thread
 constexpr int kRadixBlock = kRadixThreads * kRadixItems;
+constexpr int kChunk = 256;      // splats per blend work item
 
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
-  size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, grad, total;
+  size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, grad;
+  size_t item_off, item_tile, item_chunk, cstate, total;
   int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
+  int64_t max_items;
 };
 
 Layout make_layout(int n, int width, int height, int64_t cap) {
@@ -79,6 +82,11 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.boff = take((size_t)L.nb_n * 4);
   L.count = take(16);
   L.grad = take(N * 5 * 4);
+  L.max_items = rga::ceil_div(cap > 0 ? cap : 1, kChunk) + tiles;
+  L.item_off = take(((size_t)tiles + 1) * 4);
+  L.item_tile = take((size_t)L.max_items * 4);
+  L.item_chunk = take((size_t)L.max_items * 4);
+  L.cstate = take((size_t)L.max_items * 4 * 256 * 4);
   L.total = o;
   return L;
 }
@@ -521,48 +529,191 @@ tile_ranges_kernel(const uint32_t* __restrict__ tkeys, const int64_t* cnt_ptr, i
 }
 
 // ---- blend ------------------------------------------------------------------
+// Work items are (tile, chunk of <= 256 consecutive list entries); heavy
+// tiles therefore spread over many workgroups.  Pass 1 composites each chunk
+// independently (transmittance starting at 1); the combine pass walks a
+// tile's chunks front to back per pixel: a chunk whose end transmittance
+// keeps T_in * T_chunk >= 1e-4 cannot contain the stop (T is monotone), so
+// it contributes T_in * C_chunk; the first chunk that may contain the stop
+// is re-walked sequentially from T_in with the exact stop rule.  The
+// combine leaves (C before the chunk, T_in) per (chunk, pixel) for the
+// adjoint, and T_in = -1 for chunks past the stop.
+
+// alpha of one entry for the pixel centre (px, py): returns < 0 if skipped
+__device__ inline float entry_alpha(const float4& a, const float4& c1, float px, float py,
+                                    float& dx, float& dy, float& G, float& araw) {
+  dx = a.x - px;
+  dy = a.y - py;
+  const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
+  const float power = -0.5f * qf;
+  if (power > 0.f) return -1.f;
+  G = expf(power);
+  araw = c1.y * G;
+  const float alpha = fminf(0.99f, araw);
+  return alpha < 1.f / 255.f ? -1.f : alpha;
+}
+
+__global__ void __launch_bounds__(1024)
+chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __restrict__ item_off,
+                   uint32_t* __restrict__ item_tile, uint32_t* __restrict__ item_chunk,
+                   int64_t max_items, int64_t* __restrict__ counters) {
+  __shared__ uint32_t part[1024];
+  const int per = (tiles + 1023) / 1024;
+  const int t0 = threadIdx.x * per, t1 = min(tiles, t0 + per);
+  uint32_t s = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int len = ranges[2 * t + 1] - ranges[2 * t];
+    s += (uint32_t)((len + kChunk - 1) / kChunk);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t off = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int t = t0; t < t1; ++t) {
+    item_off[t] = off;
+    const int len = ranges[2 * t + 1] - ranges[2 * t];
+    const int nch = (len + kChunk - 1) / kChunk;
+    for (int j = 0; j < nch; ++j)
+      if ((int64_t)(off + j) < max_items) {
+        item_tile[off + j] = (uint32_t)t;
+        item_chunk[off + j] = (uint32_t)j;
+      }
+    off += nch;
+  }
+  if (threadIdx.x == 1023) {
+    item_off[tiles] = part[1023];
+    counters[1] = (int64_t)part[1023];
+  }
+}
+
 __global__ void __launch_bounds__(256)
-blend_fwd_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
-                 const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
-                 float* __restrict__ image, float* __restrict__ Tfinal) {
-  __shared__ float4 s0[256], s1[256], s2[256];
-  const int t = blockIdx.x;
+blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+                   const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                   const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
+                   const int64_t* __restrict__ counters, int64_t max_items,
+                   float* __restrict__ cstate) {
+  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  const int64_t nitems = min(counters[1], max_items);
+  const int b = blockIdx.x;
+  if (b >= nitems) return;
+  const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
-  const bool inside = px < W && py < H;
-  const int start = ranges[2 * t], end = ranges[2 * t + 1];
+  const int e0 = ranges[2 * t] + j * kChunk;
+  const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+  if ((int)threadIdx.x < cnt) {
+    const uint32_t g = sorted[e0 + threadIdx.x];
+    s0[threadIdx.x] = rec[3 * g];
+    s1[threadIdx.x] = rec[3 * g + 1];
+    s2[threadIdx.x] = rec[3 * g + 2];
+  }
+  __syncthreads();
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool done = !inside;
-  for (int b = start; b < end; b += 256) {
-    if (__syncthreads_count(done) == 256) break;
-    const int e = b + threadIdx.x;
-    if (e < end) {
-      const uint32_t g = sorted[e];
-      s0[threadIdx.x] = rec[3 * g];
-      s1[threadIdx.x] = rec[3 * g + 1];
-      s2[threadIdx.x] = rec[3 * g + 2];
-    }
-    __syncthreads();
-    const int cnt = min(256, end - b);
-    for (int j = 0; j < cnt && !done; ++j) {
-      const float4 a = s0[j], c1 = s1[j];
-      const float dx = a.x - fpx, dy = a.y - fpy;
-      const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
-      const float power = -0.5f * qf;
-      if (power > 0.f) continue;
-      const float alpha = fminf(0.99f, c1.y * expf(power));
-      if (alpha < 1.f / 255.f) continue;
+  bool sat = false;
+  if (px < W && py < H) {
+    for (int k = 0; k < cnt; ++k) {
+      const float4 a = s0[k], c1 = s1[k];
+      float dx, dy, G, araw;
+      const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
+      if (alpha < 0.f) continue;
       const float Tn = T * (1.f - alpha);
       if (Tn < 1e-4f) {
-        done = true;
+        sat = true;
         break;
       }
       const float w = alpha * T;
       C0 = fmaf(c1.z, w, C0);
       C1 = fmaf(c1.w, w, C1);
-      C2 = fmaf(s2[j].x, w, C2);
+      C2 = fmaf(s2[k].x, w, C2);
       T = Tn;
+    }
+  }
+  float* st = cstate + (size_t)b * 1024;
+  st[threadIdx.x] = C0;
+  st[256 + threadIdx.x] = C1;
+  st[512 + threadIdx.x] = C2;
+  st[768 + threadIdx.x] = sat ? -1.f : T;
+}
+
+__global__ void __launch_bounds__(256)
+blend_combine_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+                     const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                     const uint32_t* __restrict__ item_off, float* __restrict__ cstate,
+                     int64_t max_items, float* __restrict__ image, float* __restrict__ Tfinal) {
+  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  const int t = blockIdx.x;
+  const int tx = t % TX, ty = t / TX;
+  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const bool inside = px < W && py < H;
+  const int64_t i0 = item_off[t];
+  const int nch = (int)min((int64_t)item_off[t + 1], max_items) - (int)min(i0, max_items);
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  float Tin = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  bool active = inside;
+  for (int j = 0; j < nch; ++j) {
+    float* st = cstate + (size_t)(i0 + j) * 1024;
+    float Cj0 = 0.f, Cj1 = 0.f, Cj2 = 0.f, Tj = 1.f;
+    if (active) {
+      Cj0 = st[threadIdx.x];
+      Cj1 = st[256 + threadIdx.x];
+      Cj2 = st[512 + threadIdx.x];
+      Tj = st[768 + threadIdx.x];
+    }
+    const bool need = active && (Tj < 0.f || Tin * Tj < 1e-4f);
+    // state for the adjoint: colour before this chunk and its incoming T
+    st[threadIdx.x] = C0;
+    st[256 + threadIdx.x] = C1;
+    st[512 + threadIdx.x] = C2;
+    st[768 + threadIdx.x] = active ? Tin : -1.f;
+    if (__syncthreads_or(need)) {
+      const int e0 = ranges[2 * t] + j * kChunk;
+      const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+      if ((int)threadIdx.x < cnt) {
+        const uint32_t g = sorted[e0 + threadIdx.x];
+        s0[threadIdx.x] = rec[3 * g];
+        s1[threadIdx.x] = rec[3 * g + 1];
+        s2[threadIdx.x] = rec[3 * g + 2];
+      }
+      __syncthreads();
+      if (need) {
+        float T = Tin;
+        bool stopped = false;
+        for (int k = 0; k < cnt; ++k) {
+          const float4 a = s0[k], c1 = s1[k];
+          float dx, dy, G, araw;
+          const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
+          if (alpha < 0.f) continue;
+          const float Tn = T * (1.f - alpha);
+          if (Tn < 1e-4f) {
+            stopped = true;
+            break;
+          }
+          const float w = alpha * T;
+          C0 = fmaf(c1.z, w, C0);
+          C1 = fmaf(c1.w, w, C1);
+          C2 = fmaf(s2[k].x, w, C2);
+          T = Tn;
+        }
+        Tin = T;
+        active = !stopped;
+      } else if (active) {
+        C0 = fmaf(Tin, Cj0, C0);
+        C1 = fmaf(Tin, Cj1, C1);
+        C2 = fmaf(Tin, Cj2, C2);
+        Tin *= Tj;
+      }
+      __syncthreads();
+    } else if (active) {
+      C0 = fmaf(Tin, Cj0, C0);
+      C1 = fmaf(Tin, Cj1, C1);
+      C2 = fmaf(Tin, Cj2, C2);
+      Tin *= Tj;
     }
   }
   if (inside) {
@@ -570,35 +721,67 @@ blend_fwd_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
     image[p] = C0;
     image[HW + p] = C1;
     image[2 * HW + p] = C2;
-    Tfinal[p] = T;
+    Tfinal[p] = Tin;
   }
 }
 
 // ---- adjoint: blend ----------------------------------------------------------
-// Per pixel, walking the same list front to back with the same decisions:
+// Per work item (tile, chunk) and pixel, starting from the chunk's incoming
+// transmittance T_in and colour C_before left by the combine pass, the
+// entries are re-walked front to back with the same decisions:
 //   dL/dc_i     = alpha_i T_i g
 //   dL/dalpha_i = sum_c g_c (c_ic T_i - (C_c - C_<=i,c) / (1 - alpha_i))
 // with C the forward colour, then alpha = o exp(power) (unless clamped).
-// Per-splat sums over the tile's pixels: wave reduction, then the four
-// waves' partials are added in LDS and one set of atomics per (tile, splat).
+// Per-splat sums over the tile's pixels: DPP wave reduction, the four waves'
+// partials are added in LDS, then one set of atomics per (item, splat).
+
+// Sum over the 64 lanes with DPP row shifts and row broadcasts; the total is
+// returned in every lane.
+__device__ inline float wave_sum_dpp(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                  const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
-                 const float* __restrict__ image, const float* __restrict__ dimage,
-                 float* __restrict__ gmean_conic /*[5][n]*/, float* __restrict__ dopac,
-                 float* __restrict__ dcolor) {
-  __shared__ float4 s0[256], s1[256], s2[256];
-  __shared__ uint32_t sg[256];
+                 const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
+                 const int64_t* __restrict__ counters, int64_t max_items,
+                 const float* __restrict__ cstate, const float* __restrict__ image,
+                 const float* __restrict__ dimage, float* __restrict__ gmean_conic /*[5][n]*/,
+                 float* __restrict__ dopac, float* __restrict__ dcolor) {
+  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  __shared__ uint32_t sg[kChunk];
   __shared__ float part[4][9][64];
-  const int t = blockIdx.x;
+  const int64_t nitems = min(counters[1], max_items);
+  const int b = blockIdx.x;
+  if (b >= nitems) return;
+  const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
-  const int start = ranges[2 * t], end = ranges[2 * t + 1];
+  const int e0 = ranges[2 * t] + j * kChunk;
+  const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+  if ((int)threadIdx.x < cnt) {
+    const uint32_t g = sorted[e0 + threadIdx.x];
+    sg[threadIdx.x] = g;
+    s0[threadIdx.x] = rec[3 * g];
+    s1[threadIdx.x] = rec[3 * g + 1];
+    s2[threadIdx.x] = rec[3 * g + 2];
+  }
+  const float* st = cstate + (size_t)b * 1024;
+  float T = st[768 + threadIdx.x];
+  float A0 = st[threadIdx.x], A1 = st[256 + threadIdx.x], A2 = st[512 + threadIdx.x];
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  if (inside) {
+  bool done = !inside || T < 0.f;
+  if (!done) {
     const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
     Cf0 = image[p];
     Cf1 = image[HW + p];
@@ -607,97 +790,77 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     g1 = dimage[HW + p];
     g2 = dimage[2 * HW + p];
   }
-  float T = 1.f, A0 = 0.f, A1 = 0.f, A2 = 0.f;
-  bool done = !inside;
-  for (int b = start; b < end; b += 256) {
+  __syncthreads();
+  for (int j0 = 0; j0 < cnt; j0 += 64) {
     if (__syncthreads_count(done) == 256) break;
-    const int e = b + threadIdx.x;
-    if (e < end) {
-      const uint32_t g = sorted[e];
-      sg[threadIdx.x] = g;
-      s0[threadIdx.x] = rec[3 * g];
-      s1[threadIdx.x] = rec[3 * g + 1];
-      s2[threadIdx.x] = rec[3 * g + 2];
-    }
-    __syncthreads();
-    const int cnt = min(256, end - b);
-    for (int j0 = 0; j0 < cnt; j0 += 64) {
-      const int jn = min(64, cnt - j0);
-      for (int jj = 0; jj < jn; ++jj) {
-        const int j = j0 + jj;
-        float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        bool contrib = false;
-        if (!done) {
-          const float4 a = s0[j], c1 = s1[j];
-          const float dx = a.x - fpx, dy = a.y - fpy;
-          const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
-          const float power = -0.5f * qf;
-          if (power <= 0.f) {
-            const float G = expf(power);
-            const float araw = c1.y * G;
-            const float alpha = fminf(0.99f, araw);
-            if (alpha >= 1.f / 255.f) {
-              const float Tn = T * (1.f - alpha);
-              if (Tn < 1e-4f) {
-                done = true;
-              } else {
-                contrib = true;
-                const float col0 = c1.z, col1 = c1.w, col2 = s2[j].x;
-                const float w = alpha * T;
-                A0 = fmaf(col0, w, A0);
-                A1 = fmaf(col1, w, A1);
-                A2 = fmaf(col2, w, A2);
-                v[6] = w * g0;
-                v[7] = w * g1;
-                v[8] = w * g2;
-                const float inv1m = 1.f / (1.f - alpha);
-                const float dal = g0 * (col0 * T - (Cf0 - A0) * inv1m) +
-                                  g1 * (col1 * T - (Cf1 - A1) * inv1m) +
-                                  g2 * (col2 * T - (Cf2 - A2) * inv1m);
-                if (araw <= 0.99f) {
-                  v[5] = dal * G;                       // d/d opacity
-                  const float dp = dal * alpha;         // d/d power
-                  v[0] = -dp * (a.z * dx + a.w * dy);   // d/d mean x
-                  v[1] = -dp * (a.w * dx + c1.x * dy);  // d/d mean y
-                  v[2] = -0.5f * dp * dx * dx;          // d/d conic A
-                  v[3] = -dp * dx * dy;                 // d/d conic B
-                  v[4] = -0.5f * dp * dy * dy;          // d/d conic C
-                }
-                T = Tn;
-              }
+    const int jn = min(64, cnt - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      const int k = j0 + jj;
+      float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bool contrib = false;
+      if (!done) {
+        const float4 a = s0[k], c1 = s1[k];
+        float dx, dy, G, araw;
+        const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
+        if (alpha >= 0.f) {
+          const float Tn = T * (1.f - alpha);
+          if (Tn < 1e-4f) {
+            done = true;
+          } else {
+            contrib = true;
+            const float col0 = c1.z, col1 = c1.w, col2 = s2[k].x;
+            const float w = alpha * T;
+            A0 = fmaf(col0, w, A0);
+            A1 = fmaf(col1, w, A1);
+            A2 = fmaf(col2, w, A2);
+            v[6] = w * g0;
+            v[7] = w * g1;
+            v[8] = w * g2;
+            const float inv1m = 1.f / (1.f - alpha);
+            const float dal = g0 * (col0 * T - (Cf0 - A0) * inv1m) +
+                              g1 * (col1 * T - (Cf1 - A1) * inv1m) +
+                              g2 * (col2 * T - (Cf2 - A2) * inv1m);
+            if (araw <= 0.99f) {
+              v[5] = dal * G;                       // d/d opacity
+              const float dp = dal * alpha;         // d/d power
+              v[0] = -dp * (a.z * dx + a.w * dy);   // d/d mean x
+              v[1] = -dp * (a.w * dx + c1.x * dy);  // d/d mean y
+              v[2] = -0.5f * dp * dx * dx;          // d/d conic A
+              v[3] = -dp * dx * dy;                 // d/d conic B
+              v[4] = -0.5f * dp * dy * dy;          // d/d conic C
             }
+            T = Tn;
           }
         }
-        const bool any = __ballot(contrib) != 0ull;
-        if (any) {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) v[k] = rga::wave_sum(v[k]);
-        }
-        if (lane == 0) {
-#pragma unroll
-          for (int k = 0; k < 9; ++k) part[wave][k][jj] = any ? v[k] : 0.f;
-        }
       }
-      __syncthreads();
-      if (threadIdx.x < jn) {
-        const int jj = threadIdx.x;
-        const uint32_t g = sg[j0 + jj];
-        float s[9];
+      const bool any = __ballot(contrib) != 0ull;
+      if (any) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s[k] = part[0][k][jj] + part[1][k][jj] + part[2][k][jj] + part[3][k][jj];
-        bool nz = false;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) nz |= s[k] != 0.f;
-        if (nz) {
-#pragma unroll
-          for (int k = 0; k < 5; ++k) atomicAdd(&gmean_conic[(size_t)k * n + g], s[k]);
-          atomicAdd(&dopac[g], s[5]);
-          atomicAdd(&dcolor[g], s[6]);
-          atomicAdd(&dcolor[(size_t)n + g], s[7]);
-          atomicAdd(&dcolor[(size_t)2 * n + g], s[8]);
-        }
+        for (int q = 0; q < 9; ++q) v[q] = wave_sum_dpp(v[q]);
       }
-      __syncthreads();
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) part[wave][q][jj] = any ? v[q] : 0.f;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < jn) {
+      const int jj = threadIdx.x;
+      const uint32_t g = sg[j0 + jj];
+      float sum[9];
+#pragma unroll
+      for (int q = 0; q < 9; ++q) sum[q] = part[0][q][jj] + part[1][q][jj] + part[2][q][jj] + part[3][q][jj];
+      bool nz = false;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) nz |= sum[q] != 0.f;
+      if (nz) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) atomicAdd(&gmean_conic[(size_t)q * n + g], sum[q]);
+        atomicAdd(&dopac[g], sum[5]);
+        atomicAdd(&dcolor[g], sum[6]);
+        atomicAdd(&dcolor[(size_t)n + g], sum[7]);
+        atomicAdd(&dcolor[(size_t)2 * n + g], sum[8]);
+      }
     }
   }
 }
@@ -924,7 +1087,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   RGA_LAUNCH("splat_fill", fill_u32, dim3(rga::ceil_div(2 * tiles + 4, 256)), dim3(256), 0, s,
              reinterpret_cast<uint32_t*>(ranges), 2 * tiles, 0u);
   RGA_LAUNCH("splat_fill", fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt),
-             (int64_t)2, 0u);
+             (int64_t)4, 0u);
   if (n > 0) {
     RGA_LAUNCH("splat_preprocess", preprocess_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
                n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, color, front,
@@ -970,12 +1133,18 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     }
     RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
                s, tk0, (const int64_t*)cnt, capacity, ranges);
-    RGA_LAUNCH("blend_fwd", blend_fwd_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x, ranges,
-               tv0, at<float4>(ws, L.rec), image, T_final);
-  } else {
-    RGA_LAUNCH("blend_fwd", blend_fwd_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x, ranges,
-               at<uint32_t>(ws, L.tv0), at<float4>(ws, L.rec), image, T_final);
   }
+  // work items (tile, chunk), chunk composites, front-to-back combine
+  const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
+  RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
+             at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
+             at<uint32_t>(ws, L.item_chunk), L.max_items, cnt);
+  RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(L.max_items), dim3(256), 0, s, W, H, L.tiles_x,
+             ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
+             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate));
+  RGA_LAUNCH("blend_combine", blend_combine_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
+             ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_off),
+             at<float>(ws, L.cstate), L.max_items, image, T_final);
   RGA_CHECK_LAUNCH("splat_forward");
   return RGA_OK;
 }
@@ -996,15 +1165,16 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
     return rga::fail(RGA_EINVAL, "splat_backward: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const CamDev cd = to_dev(cam);
-  const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
   float* gmc = at<float>(ws, L.grad);
   const int64_t nz = 5 * (int64_t)n;
   RGA_LAUNCH("splat_zero", zero_f32, dim3(rga::ceil_div(nz, 256)), dim3(256), 0, s, gmc, nz, dopac,
              (int64_t)n, dcolor, 3 * (int64_t)n);
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
-  RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(tiles), dim3(256), 0, s, cam->width, cam->height,
-             L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec), image, dimage,
-             gmc, dopac, dcolor);
+  RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(L.max_items), dim3(256), 0, s, cam->width,
+             cam->height, L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec),
+             at<uint32_t>(ws, L.item_tile), at<uint32_t>(ws, L.item_chunk),
+             at<int64_t>(ws, L.count), L.max_items, at<float>(ws, L.cstate), image, dimage, gmc,
+             dopac, dcolor);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
              n, cd, x, A, quat, log_s, opac, front, gmc, dx, dquat, dlog_s);
   RGA_CHECK_LAUNCH("splat_backward");

@@ -300,7 +300,142 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   }
 }
 
-// ---- adjoint -----------------------------------------------------------------
+// ---- BF16X3 form: the contraction on MFMA -----------------------------------
+// A wave owns 16 Gaussians (MFMA rows) and walks the light directions 32 at
+// a time (the MFMA reduction dimension).  Lane l evaluates the BRDF weights of
+// Gaussian l % 16 for the 8 directions 8 (l / 16) .. + 7 of the step -- exactly
+// its slots of the A operand -- on VALU, splits each weight into bf16 hi + lo,
+// and the contraction with B = [E_hi | E_lo] (columns 0-2 and 3-5) runs on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
+//   S_c = A_hi E_hi + A_hi E_lo + A_lo E_hi + A_lo E_lo (columns c and c+3).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMWaves = 4;
+constexpr int kMThreads = kMWaves * 64;
+
+// LDS: dir x,y,z | E r,g,b | view (int) [K each], then B [16 cols][K] bf16
+__device__ inline void build_btab(const float* tab, int K, __bf16* bt) {
+  for (int i = threadIdx.x; i < 16 * K; i += blockDim.x) {
+    const int col = i / K, k = i - col * K;
+    float v = 0.f;
+    if (col < 3) {
+      v = (float)(__bf16)tab[(3 + col) * K + k];
+    } else if (col < 6) {
+      const float e = tab[(3 + col - 3) * K + k];
+      v = e - (float)(__bf16)e;
+    }
+    bt[i] = (__bf16)v;
+  }
+}
+
+// visibility bytes of 8 consecutive directions k..k+7 (k % 8 == 0, same
+// texel row) for one count row: identity view map or two texels per view
+__device__ inline void vis8(const uint8_t* row, const int* view, int k, int ratio, float* c) {
+  if (ratio == 1) {
+    const uint2 w = *reinterpret_cast<const uint2*>(row + view[k]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c[i] = (float)((w.x >> (8 * i)) & 0xFFu);
+      c[4 + i] = (float)((w.y >> (8 * i)) & 0xFFu);
+    }
+  } else if (ratio == 2) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(row + view[k]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = (float)((w >> (8 * (i >> 1))) & 0xFFu);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c[i] = (float)row[view[k + i]];
+  }
+}
+
+__global__ void __launch_bounds__(kMThreads)
+shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
+                      uint8_t* __restrict__ front) {
+  extern __shared__ __align__(16) float tab[];
+  const int K = a.K, n = a.n, V = a.V;
+  __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
+  float* stage = reinterpret_cast<float*>(bt + 16 * K) + (threadIdx.x >> 6) * 512;
+  build_table(a, tab, 0);
+  __syncthreads();
+  build_btab(tab, K, bt);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, kg = lane >> 4;
+  const int* view = reinterpret_cast<const int*>(tab) + 6 * K;
+  const int ntiles = (n + 15) / 16;
+  for (int tile = blockIdx.x * kMWaves + wave; tile < ntiles; tile += gridDim.x * kMWaves) {
+    const int g = tile * 16 + row;
+    const bool have = g < n;
+    Attr A;
+    attr_load(a, have ? g : n - 1, A);
+    GaussCtx G;
+    gauss_setup(a, A, nullptr, G);
+    const bool on = have && G.front;
+    const uint8_t* r0 = a.count + (size_t)A.vidx[0] * V;
+    const uint8_t* r1 = a.count + (size_t)A.vidx[1] * V;
+    const uint8_t* r2 = a.count + (size_t)A.vidx[2] * V;
+    f32x4 accD = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kb = k0 + 8 * kg;
+      float c0[8], c1[8], c2[8];
+      vis8(r0, view, kb, ratio, c0);
+      vis8(r1, view, kb, ratio, c1);
+      vis8(r2, view, kb, ratio, c2);
+      bf16x8 dh, dl, sh, sl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = kb + i;
+        float Wd = 0.f, Ws = 0.f;
+        const float ci = fmaf(G.nn[2], tab[2 * K + k], fmaf(G.nn[1], tab[K + k], G.nn[0] * tab[k]));
+        const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
+        if (on && ci > 0.f && v > 0.f) {
+          Pair P;
+          pair_eval(G, tab, K, k, v, P);
+          Wd = P.Wd;
+          Ws = P.Ws;
+        }
+        const __bf16 hd = (__bf16)Wd, hs = (__bf16)Ws;
+        dh[i] = hd;
+        dl[i] = (__bf16)(Wd - (float)hd);
+        sh[i] = hs;
+        sl[i] = (__bf16)(Ws - (float)hs);
+      }
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (size_t)row * K + kb);
+      accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, b, accD, 0, 0, 0);
+      accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl, b, accD, 0, 0, 0);
+      accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, b, accS, 0, 0, 0);
+      accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, b, accS, 0, 0, 0);
+    }
+    // D[row 4 kg + i][col] -> stage; then one lane per (Gaussian, channel)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      stage[(4 * kg + i) * 16 + row] = accD[i];
+      stage[256 + (4 * kg + i) * 16 + row] = accS[i];
+    }
+    wave_fence();
+    if (lane < 48) {
+      const int gr = lane / 3, c = lane - 3 * gr;
+      const int gg = tile * 16 + gr;
+      if (gg < n) {
+        const float sd = stage[gr * 16 + c] + stage[gr * 16 + 3 + c];
+        const float ss = stage[256 + gr * 16 + c] + stage[256 + gr * 16 + 3 + c];
+        // this Gaussian's inputs (lane gr of the tile holds them)
+        const float alb = a.albedo[(size_t)c * n + gg];
+        const float tnt = a.tint[gg];
+        const float m0 = a.nrm[gg], m1 = a.nrm[n + gg], m2 = a.nrm[2 * n + gg];
+        const float w0 = a.cam[0] - a.x[gg], w1 = a.cam[1] - a.x[n + gg],
+                    w2 = a.cam[2] - a.x[2 * n + gg];
+        const bool fr = fmaf(m2, w2, fmaf(m1, w1, m0 * w0)) > 0.f;
+        color[(size_t)c * n + gg] = fr ? srgb(alb * (1.f / kPi) * sd + tnt * ss) : 0.f;
+        if (c == 0) front[gg] = fr ? 1 : 0;
+      }
+    }
+    wave_fence();
+  }
+}
+
+// ---- adjoint ------------------------------------------------------------
 struct BwdAcc {
   float gn[3], gw[3], gco, gga, sd[3], ts;
 };
@@ -344,6 +479,228 @@ __device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv
   acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
   acc.gco += gco;
   acc.gga += gga;
+}
+
+// BF16X3 adjoint.  Same tiling (16 Gaussians x 32 directions per step).  On
+// MFMA: the per-Gaussian sums S_d = W_d E and S_s = W_s E (for the albedo and
+// tint gradients, 16x16x32 as in the forward), and the environment gradient
+// dE[k][c] = sum_g W_d[g][k] Qd[g][c] + W_s[g][k] Qs[g][c] with
+// Qd = dL/dL_o a / pi, Qs = dL/dL_o p -- a reduction over Gaussians, so W is
+// transposed through LDS and fed to v_mfma_f32_32x32x16_bf16 (A = W^T,
+// 32 directions x 16 Gaussians; B = [Q_hi | Q_lo]).  The direction-dependent
+// derivative terms of the BRDF weights stay on VALU in FP32.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__global__ void __launch_bounds__(kMThreads)
+shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
+                      const float* __restrict__ dcolor, float* __restrict__ dx,
+                      float* __restrict__ dn, float* __restrict__ dalbedo,
+                      float* __restrict__ drough, float* __restrict__ dtint,
+                      float* __restrict__ denv_part) {
+  extern __shared__ __align__(16) float tab[];
+  const int K = a.K, n = a.n, V = a.V;
+  __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
+  float* denv_lds = reinterpret_cast<float*>(bt + 16 * K);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // per-wave scratch: W^T stage (4 x [32 k][16 g] bf16 = 4 KB), Q (16 x 6 f32),
+  // per-Gaussian sums (2 x 256 f32)
+  char* wbase = reinterpret_cast<char*>(denv_lds + 3 * K) + (size_t)wave * (4096 + 384 + 2048);
+  __bf16* wt = reinterpret_cast<__bf16*>(wbase);
+  float* qst = reinterpret_cast<float*>(wbase + 4096);
+  float* stage = reinterpret_cast<float*>(wbase + 4096 + 384);
+  build_table(a, tab, 0);
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
+  __syncthreads();
+  build_btab(tab, K, bt);
+  __syncthreads();
+  const int row = lane & 15, kg = lane >> 4;
+  const int* view = reinterpret_cast<const int*>(tab) + 6 * K;
+  const int ntiles = (n + 15) / 16;
+  for (int tile = blockIdx.x * kMWaves + wave; tile < ntiles; tile += gridDim.x * kMWaves) {
+    const int g = tile * 16 + row;
+    const bool have = g < n;
+    const int gc = have ? g : n - 1;
+    Attr A;
+    attr_load(a, gc, A);
+    GaussCtx G;
+    gauss_setup(a, A, nullptr, G);
+    const bool on = have && G.front;
+    float dLo[3], aop[3], qd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float col = color[(size_t)c * n + gc];
+      const float dc = on ? dcolor[(size_t)c * n + gc] : 0.f;
+      if (col <= 0.04045f) {
+        dLo[c] = dc * 12.92f;
+      } else {
+        const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
+        dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
+      }
+      aop[c] = A.alb[c] * (1.f / kPi);
+      qd[c] = dLo[c] * aop[c];
+    }
+    const float tint = A.tint;
+    // B operand of the environment contraction: Q of the tile's 16 Gaussians
+    if (kg == 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        qst[row * 6 + c] = qd[c];
+        qst[row * 6 + 3 + c] = dLo[c] * tint;
+      }
+    }
+    wave_fence();
+    bf16x8 bqd, bqs;   // B [16 g][32 cols]: lane holds col lane % 32, g = 8 (lane / 32) + i
+    {
+      const int col = lane & 31, g0 = 8 * (lane >> 5);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        float vd = 0.f, vs = 0.f;
+        if (col < 6) {
+          const float qdv = qst[(g0 + i) * 6 + (col % 3)];
+          const float qsv = qst[(g0 + i) * 6 + 3 + (col % 3)];
+          vd = col < 3 ? (float)(__bf16)qdv : qdv - (float)(__bf16)qdv;
+          vs = col < 3 ? (float)(__bf16)qsv : qsv - (float)(__bf16)qsv;
+        }
+        bqd[i] = (__bf16)vd;
+        bqs[i] = (__bf16)vs;
+      }
+    }
+    const uint8_t* r0 = a.count + (size_t)A.vidx[0] * V;
+    const uint8_t* r1 = a.count + (size_t)A.vidx[1] * V;
+    const uint8_t* r2 = a.count + (size_t)A.vidx[2] * V;
+    f32x4 accD = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
+    BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+      const int kb = k0 + 8 * kg;
+      float c0[8], c1[8], c2[8];
+      vis8(r0, view, kb, ratio, c0);
+      vis8(r1, view, kb, ratio, c1);
+      vis8(r2, view, kb, ratio, c2);
+      bf16x8 dh, dl, sh, sl;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = kb + i;
+        float Wd = 0.f, Ws = 0.f;
+        const float ci = fmaf(G.nn[2], tab[2 * K + k], fmaf(G.nn[1], tab[K + k], G.nn[0] * tab[k]));
+        const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
+        if (on && ci > 0.f && v > 0.f) {
+          Pair P;
+          pair_eval(G, tab, K, k, v, P);
+          Wd = P.Wd;
+          Ws = P.Ws;
+          const float gWd = fmaf(qd[2], P.E[2], fmaf(qd[1], P.E[1], qd[0] * P.E[0]));
+          const float sE = fmaf(dLo[2], P.E[2], fmaf(dLo[1], P.E[1], dLo[0] * P.E[0]));
+          const float gWs = tint * sE;
+          const float one_m_a2 = 1.f - G.a2;
+          const float dnn = P.den / P.hh;
+          const float dlnD_dnh = 4.f * P.nh * one_m_a2 / dnn;
+          const float dlnD_da = 2.f / G.alpha - 4.f * G.alpha * P.nh * P.nh / dnn;
+          const float dlnF_doh =
+              0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) / P.F;
+          const float gs = gWs * P.Ws;
+          const float ih3 = P.invh * P.invh * P.invh;
+          const float gci = gWd * v + gWs * P.W0 * G.kG / (P.deni * P.deni) + gs * dlnD_dnh * P.invh;
+          const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
+          const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
+          const float dlnG_dk = -(1.f - P.ci) / P.deni - (1.f - G.co) * G.Go;
+          const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
+          acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
+          acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
+          acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
+          acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
+          acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
+          acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
+          acc.gco += gco;
+          acc.gga += gga;
+        }
+        const __bf16 hd = (__bf16)Wd, hs = (__bf16)Ws;
+        dh[i] = hd;
+        dl[i] = (__bf16)(Wd - (float)hd);
+        sh[i] = hs;
+        sl[i] = (__bf16)(Ws - (float)hs);
+        // W^T stage [k local][g]
+        const int kl = 8 * kg + i;
+        wt[0 * 512 + kl * 16 + row] = dh[i];
+        wt[1 * 512 + kl * 16 + row] = dl[i];
+        wt[2 * 512 + kl * 16 + row] = sh[i];
+        wt[3 * 512 + kl * 16 + row] = sl[i];
+      }
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (size_t)row * K + kb);
+      accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, b, accD, 0, 0, 0);
+      accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl, b, accD, 0, 0, 0);
+      accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, b, accS, 0, 0, 0);
+      accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, b, accS, 0, 0, 0);
+      wave_fence();
+      // environment: A = W^T [32 k][16 g]; lane holds k = lane % 32, g = 8 (lane / 32) + i
+      const int kr = lane & 31, gq = 8 * (lane >> 5);
+      const bf16x8 adh = *reinterpret_cast<const bf16x8*>(wt + 0 * 512 + kr * 16 + gq);
+      const bf16x8 adl = *reinterpret_cast<const bf16x8*>(wt + 1 * 512 + kr * 16 + gq);
+      const bf16x8 ash = *reinterpret_cast<const bf16x8*>(wt + 2 * 512 + kr * 16 + gq);
+      const bf16x8 asl = *reinterpret_cast<const bf16x8*>(wt + 3 * 512 + kr * 16 + gq);
+      f32x16 de;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) de[i] = 0.f;
+      de = __builtin_amdgcn_mfma_f32_32x32x16_bf16(adh, bqd, de, 0, 0, 0);
+      de = __builtin_amdgcn_mfma_f32_32x32x16_bf16(adl, bqd, de, 0, 0, 0);
+      de = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ash, bqs, de, 0, 0, 0);
+      de = __builtin_amdgcn_mfma_f32_32x32x16_bf16(asl, bqs, de, 0, 0, 0);
+      // D[k][col]: lane holds col = lane % 32, rows 8 (i / 4) + 4 (lane / 32) + i % 4
+      const int col = lane & 31;
+      if (col < 6) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int kk = k0 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+          atomicAdd(&denv_lds[3 * kk + (col % 3)], de[i]);
+        }
+      }
+      wave_fence();
+    }
+    // per-Gaussian sums from the forward-style MFMA: D[row 4 kg + i][col]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      stage[(4 * kg + i) * 16 + row] = accD[i];
+      stage[256 + (4 * kg + i) * 16 + row] = accS[i];
+    }
+    // VALU partial sums of the four lanes of each Gaussian row
+    float r8[8] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2], acc.gco, acc.gga};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      r8[q] += __shfl_xor(r8[q], 16, 64);
+      r8[q] += __shfl_xor(r8[q], 32, 64);
+    }
+    wave_fence();
+    if (kg == 0 && have) {
+      if (!G.front) {
+        for (int c = 0; c < 3; ++c) {
+          dn[(size_t)c * n + g] = 0.f;
+          dalbedo[(size_t)c * n + g] = 0.f;
+        }
+        drough[g] = 0.f;
+        dtint[g] = 0.f;
+      } else {
+        const float gco = r8[6];
+        float gn3[3] = {r8[0] + gco * G.wo[0], r8[1] + gco * G.wo[1], r8[2] + gco * G.wo[2]};
+        float gw[3] = {r8[3] + gco * G.nn[0], r8[4] + gco * G.nn[1], r8[5] + gco * G.nn[2]};
+        const float pn = gn3[0] * G.nn[0] + gn3[1] * G.nn[1] + gn3[2] * G.nn[2];
+        const float pw = gw[0] * G.wo[0] + gw[1] * G.wo[1] + gw[2] * G.wo[2];
+        float ts = 0.f;
+        for (int c = 0; c < 3; ++c) {
+          const float sd = stage[row * 16 + c] + stage[row * 16 + 3 + c];
+          const float ss = stage[256 + row * 16 + c] + stage[256 + row * 16 + 3 + c];
+          dn[(size_t)c * n + g] = (gn3[c] - G.nn[c] * pn) * G.inn;
+          dx[(size_t)c * n + g] += -(gw[c] - G.wo[c] * pw) * G.iwo;
+          dalbedo[(size_t)c * n + g] = dLo[c] * sd * (1.f / kPi);
+          ts = fmaf(dLo[c], ss, ts);
+        }
+        drough[g] = r8[7];
+        dtint[g] = ts;
+      }
+    }
+    wave_fence();
+  }
+  __syncthreads();
+  float* out = denv_part + (size_t)blockIdx.x * 3 * K;
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) out[i] = denv_lds[i];
 }
 
 template <int NQ>
@@ -596,10 +953,35 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
   if (rc) return rc;
   if (n == 0) return RGA_OK;
   if (!color || !front) return rga::fail(RGA_EINVAL, "shade_gaussians: null output");
-  if (precision == RGA_BF16X3)
-    return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 form not built yet");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
+  if (precision == RGA_BF16X3) {
+    if (a.K % 32 != 0)
+      return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 needs a multiple of 32 directions");
+    const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
+    const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)16 * a.K * 2 + kMWaves * 512 * 4;
+    static bool mattr = false;
+    if (!mattr) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(shade_fwd_mfma_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      mattr = true;
+    }
+    if (lds > 150 * 1024) return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: too many directions");
+    int ncu = 0, dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+      ncu = 256;
+    const int per_cu = lds <= 40 * 1024 ? 4 : (lds <= 76 * 1024 ? 2 : 1);
+    const int tiles = (int)rga::ceil_div(n, 16);
+    int grid = ncu * per_cu;
+    const int need = (int)rga::ceil_div(tiles, kMWaves);
+    if (grid > need) grid = need;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RGA_LAUNCH("shade_fwd_bf16x3", shade_fwd_mfma_kernel, dim3(grid), dim3(kMThreads), lds, s, a,
+               ratio, color, front);
+    RGA_CHECK_LAUNCH("shade_gaussians");
+    return RGA_OK;
+  }
   const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nq = (int)rga::ceil_div(3 * a.V, 1024);
@@ -637,10 +1019,43 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
   if (!denv) return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null denv");
   if (n > 0 && (!color || !dcolor || !dx || !dn || !dalbedo || !drough || !dtint))
     return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null pointer");
-  if (precision == RGA_BF16X3)
-    return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 form not built yet");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
+  if (precision == RGA_BF16X3) {
+    if (a.K % 32 != 0)
+      return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
+    const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
+    const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)16 * a.K * 2 +
+                       (size_t)kMWaves * (4096 + 384 + 2048);
+    if (lds > 150 * 1024)
+      return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: too many directions");
+    static bool mattr = false;
+    if (!mattr) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(shade_bwd_mfma_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+      mattr = true;
+    }
+    int ncu = 0, dev = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+      ncu = 256;
+    const int per_cu = lds <= 40 * 1024 ? 4 : (lds <= 76 * 1024 ? 2 : 1);
+    int grid = ncu * per_cu;
+    const int need = (int)rga::ceil_div(rga::ceil_div(n, 16), kMWaves);
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
+      return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* part = static_cast<float*>(ws);
+    if (n > 0)
+      RGA_LAUNCH("shade_bwd_bf16x3", shade_bwd_mfma_kernel, dim3(grid), dim3(kMThreads), lds, s, a,
+                 ratio, color, dcolor, dx, dn, dalbedo, drough, dtint, part);
+    RGA_LAUNCH("shade_denv", denv_reduce_kernel, dim3(rga::ceil_div(3 * a.K, 64)), dim3(1024), 0, s,
+               a.K, he, we, n > 0 ? grid : 0, part, denv);
+    RGA_CHECK_LAUNCH("shade_gaussians_backward");
+    return RGA_OK;
+  }
   const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
   const int grid = grid_for(n, lds);
   if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))

@@ -735,18 +735,6 @@ blend_combine_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 // Per-splat sums over the tile's pixels: DPP wave reduction, the four waves'
 // partials are added in LDS, then one set of atomics per (item, splat).
 
-// Sum over the 64 lanes with DPP row shifts and row broadcasts; the total is
-// returned in every lane.
-__device__ inline float wave_sum_dpp(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                  const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
@@ -836,7 +824,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
       const bool any = __ballot(contrib) != 0ull;
       if (any) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) v[q] = wave_sum_dpp(v[q]);
+        for (int q = 0; q < 9; ++q) v[q] = rga::wave_sum(v[q]);
       }
       if (lane == 0) {
 #pragma unroll

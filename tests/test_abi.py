@@ -1,0 +1,68 @@
+"""The C ABI library loads and exports every entry point include/rga.h
+declares; host-only behaviour (workspace sizing, argument validation before
+any launch) is checked without a GPU."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2407_10707_amd import rga
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "rga.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+([a-z_][a-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported():
+    names = _declared()
+    assert len(names) >= 18, names
+    L = rga.lib()
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in rga.h but not exported"
+    for name in names:
+        assert name in rga._SIGS, f"{name} has no ctypes signature in the binding"
+
+
+def test_abi_version_and_error_string():
+    L = rga.lib()
+    assert L.rga_abi_version() == 1
+    assert isinstance(L.rga_last_error(), bytes)
+
+
+def test_workspace_sizes_are_monotone():
+    L = rga.lib()
+    a = L.splat_workspace_size(100000, 512, 512, 1 << 20)
+    b = L.splat_workspace_size(100000, 512, 512, 1 << 21)
+    assert 0 < a < b
+    assert L.splat_workspace_size(-1, 512, 512, 10) == 0
+    assert L.mesh_visibility_workspace(6840, 512) > 6840 * 512 // 8
+    assert L.shade_gaussians_workspace(100000, 16, 32) > 0
+    assert L.l1_loss_workspace(3 * 512 * 512) > 0
+
+
+def test_argument_errors_are_reported_before_any_launch():
+    L = rga.lib()
+    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None) == -1
+    assert "n_joints" in rga.last_error()
+    assert L.lbs_skin(None, 0, 24, None, None, None, None, None, None, None, None) == 0
+    assert L.mesh_visibility(None, 10, 10, None, None, 8, None, 256, None, 19, None, None, None, 0) == -4
+    assert "res" in rga.last_error()
+    assert L.mesh_visibility(None, 10, 10, None, None, 8, None, 64, None, 18, None, None, None, 0) == -1
+    cam = rga.Camera()
+    cam.width, cam.height = 0, 10
+    assert L.splat_forward(None, 10, C.byref(cam), None, None, None, None, None, None, None, None,
+                           0, 100, None, None) == -1
+    assert "image size" in rga.last_error()
+    cp = (C.c_float * 3)(0, 0, 3)
+    assert L.shade_gaussians(None, 10, None, None, None, None, None, None, None, None, 7000, 19,
+                             16, 32, 5, 32, None, C.cast(cp, C.c_void_p), 0, None, None) == -1
+    assert "divide" in rga.last_error()
+    assert L.l1_loss(None, 0, None, None, None, None, None, 0) == -1

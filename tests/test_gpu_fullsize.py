@@ -1,0 +1,159 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py
+uses (Renderer: skin mesh -> visibility -> skin -> shade -> splat, and the
+adjoint), on outputs the oracle can compute:
+
+* bit-exact: skinned positions/normals/A (all), visibility counts (all
+  views), back-face flags (all), D, tile ranges and lists (all);
+* shaded colours of a seeded sample of 1500 Gaussians vs the FP64 oracle;
+* the whole image vs the FP32 mirror's tiled compositing of the GPU colours;
+* gradients of a loss on 32 sampled pixels of one tile vs the FP64 oracle's autograd,
+  restricted to the Gaussians those pixels can see.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cpu, ref64
+from paper_2407_10707_amd import render, rga, synth
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+_CASES = {
+    # config id, overrides (pose / env index), precision
+    "avatar_512": (2, {}, "fp32"),
+    "train_1024": (3, {}, "fp32"),
+    "precision_200k_bf16x3": (4, {}, "bf16x3"),
+    "anim_300k_1080_pose7_env2": (5, {"pose_index": 7, "env_index": 2}, "bf16x3"),
+}
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module", params=list(_CASES))
+def case(request):
+    cfg, kw, precision = _CASES[request.param]
+    print(f"[fullsize] {request.param}: building scene", flush=True)
+    s = synth.make_scene(cfg, **kw)
+    d = render.upload(s)
+    R = render.Renderer(s, d, precision=precision)
+    p = {k: d[k] for k in render.TRAINABLE}
+    count = R.visibility()
+    image, T, ctx = R.forward(p, count)
+    if R.ensure_capacity():
+        image, T, ctx = R.forward(p, count)
+    torch.cuda.synchronize()
+    return dict(name=request.param, s=s, d=d, R=R, p=p, count=count, image=image, T=T, ctx=ctx,
+                precision=precision)
+
+
+def test_skinning_visibility_and_flags_bit_exact(case):
+    s = case["s"]
+    print(f"[fullsize] {case['name']}: skinning/visibility", flush=True)
+    xo, no, Ao = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    assert np.array_equal(_host(case["ctx"]["xo"]), xo)
+    assert np.array_equal(_host(case["ctx"]["no"]), no)
+    assert np.array_equal(_host(case["ctx"]["A"]), Ao)
+    _, _, cnt = helpers.oracle_visibility(s)
+    assert np.array_equal(_host(case["count"]), cnt)
+    front = cpu.front_f32(xo, no, s["cam"].centre.astype(np.float32))
+    assert np.array_equal(_host(case["ctx"]["front"]), front)
+
+
+def test_sampled_colours_match_fp64(case):
+    s = case["s"]
+    print(f"[fullsize] {case['name']}: sampled shading", flush=True)
+    col = _host(case["ctx"]["color"])
+    xo = _host(case["ctx"]["xo"])
+    no = _host(case["ctx"]["no"])
+    front = _host(case["ctx"]["front"])
+    cnt = _host(case["count"])
+    idx = np.sort(np.random.default_rng(7).choice(s["n"], 1500, replace=False))
+    ecol, _ = ref64.shade(ref64.t64(xo[:, idx]), ref64.t64(no[:, idx]), s["albedo"][:, idx],
+                          s["rough"][idx], s["tint"][idx], s["vidx"][:, idx], s["vw"][:, idx], cnt,
+                          s["kv"], s["he"], s["we"], s["hv"], s["wv"], s["env"],
+                          s["cam"].centre.astype(np.float32).astype(np.float64), front[idx])
+    ecol = ecol.numpy()
+    rtol = 1e-5 if case["precision"] == "fp32" else 1e-4
+    err = np.abs(col[:, idx] - ecol)
+    print(f"  max rel {np.max(err / (np.abs(ecol) + 1e-30)):.2e}", flush=True)
+    assert np.all(err <= rtol * np.abs(ecol) + (1e-7 if case["precision"] == "fp32" else 1e-6))
+
+
+def test_lists_and_image_match_fp32_mirror(case):
+    s, R = case["s"], case["R"]
+    print(f"[fullsize] {case['name']}: lists and image", flush=True)
+    cam = s["cam"]
+    col = _host(case["ctx"]["color"])
+    xo = _host(case["ctx"]["xo"])
+    Ao = _host(case["ctx"]["A"])
+    front = _host(case["ctx"]["front"])
+    pre = cpu.splat_preprocess(cam, xo, Ao, s["quat"], s["log_s"], s["opac"], front)
+    keys, vals, ranges = cpu.splat_bin(cam, pre)
+    D = R.ws.count()
+    assert D == len(keys) and D <= R.ws.capacity
+    st = R.ws.state()
+    tiles = st.tiles_x * st.tiles_y
+    gr = _host(R.ws.view(st.ranges, (tiles, 2), torch.int32))
+    ne = ranges[:, 1] > ranges[:, 0]
+    assert np.array_equal(gr[ne], ranges[ne])
+    assert np.array_equal(_host(R.ws.view(st.sorted, (D,), torch.int32)), vals)
+    eimg, eT, margin = cpu.composite_tiles(cam, ranges, vals, pre, s["opac"], col)
+    gi = _host(case["image"])
+    ok = margin > 1e-4
+    tol = 1e-5 * np.abs(eimg) + 1e-6
+    bad = (np.abs(gi - eimg) > tol) & ok[None]
+    print(f"  D={D} exempt={int((~ok).sum())}/{ok.size} max err "
+          f"{np.abs(gi - eimg)[:, ok].max():.2e}", flush=True)
+    assert not bad.any()
+
+
+def test_sampled_pixel_gradients_match_fp64(case):
+    """L = sum over 32 sampled pixels of w . image; the GPU adjoint (dimage = w
+    on those pixels, 0 elsewhere) against autograd of the FP64 oracle for
+    the Gaussians whose tile lists cover the sampled pixels."""
+    s, R, p = case["s"], case["R"], case["p"]
+    print(f"[fullsize] {case['name']}: sampled gradients", flush=True)
+    H, W = s["height"], s["width"]
+    rng = np.random.default_rng(11)
+    img = _host(case["image"])
+    lit = np.nonzero(img.sum(0).reshape(-1) > 0.05)[0]
+    # 32 lit pixels of one tile (keeps the FP64 oracle's share small)
+    t0 = rng.choice(lit)
+    ty, tx = (t0 // W) // 16, (t0 % W) // 16
+    in_tile = lit[((lit // W) // 16 == ty) & ((lit % W) // 16 == tx)]
+    pix = np.sort(rng.choice(in_tile, min(32, len(in_tile)), replace=False))
+    w = np.zeros((3, H * W), np.float32)
+    w[:, pix] = rng.uniform(0.5, 1.5, size=(3, len(pix)))
+    g = R.backward(p, case["ctx"], torch.as_tensor(w.reshape(3, H, W)).cuda())
+    # Gaussians that can reach the sampled pixels: their tiles' lists
+    st = R.ws.state()
+    D = R.ws.count()
+    ranges = _host(R.ws.view(st.ranges, (st.tiles_x * st.tiles_y, 2), torch.int32))
+    vals = _host(R.ws.view(st.sorted, (D,), torch.int32))
+    tiles = np.unique((pix // W) // 16 * st.tiles_x + (pix % W) // 16)
+    sub = np.unique(np.concatenate([vals[ranges[t, 0]:ranges[t, 1]] for t in tiles]))
+    print(f"  {len(sub)} Gaussians reach the {len(pix)} pixels", flush=True)
+    sub_s = dict(s)
+    for k in ("pos", "nrm", "quat", "log_s", "albedo", "jidx", "jw", "vidx", "vw"):
+        sub_s[k] = np.ascontiguousarray(s[k][:, sub])
+    for k in ("opac", "rough", "tint"):
+        sub_s[k] = np.ascontiguousarray(s[k][sub])
+    sub_s["n"] = len(sub)
+    cnt = _host(case["count"])
+    front = _host(case["ctx"]["front"])[sub]
+    p64 = helpers.params64(sub_s, requires_grad=True)
+    img64, _ = helpers.render64(sub_s, p64, cnt, front, pixels=pix)
+    (img64 * torch.tensor(w[:, pix].astype(np.float64))).sum().backward()
+    tol = 2e-3 if case["precision"] == "fp32" else 1e-2
+    for k in render.TRAINABLE:
+        ref = p64[k].grad.numpy()
+        got = _host(g[k])
+        got = got if k == "env" else got[..., sub]
+        rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
+        print(f"  {k:7s} relL2={rel:.2e}", flush=True)
+        assert rel < tol, (k, rel)

@@ -133,6 +133,31 @@ def test_shading_matches_fp64(name):
     assert np.all(err <= 1e-5 * np.abs(ecol) + 1e-7), err.max()
 
 
+@pytest.mark.parametrize("name", ["cfg1", "micro_odd"])
+def test_shading_bf16x3_matches_fp64(name):
+    """BF16 operands (hi + lo split) on MFMA with FP32 accumulation: colours
+    within 1e-4 relative of the FP64 oracle; back-face flags bit-exact."""
+    print(f"[shade bf16x3] {name}", flush=True)
+    s = _scenes()[name]()
+    xo, no, _ = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    _, _, cnt = helpers.oracle_visibility(s)
+    campos = s["cam"].centre.astype(np.float32)
+    col, front = rga.shade_gaussians(dev(xo), dev(no), dev(s["albedo"]), dev(s["rough"]),
+                                     dev(s["tint"]), dev(s["vidx"]), dev(s["vw"]), dev(cnt),
+                                     s["kv"], s["he"], s["we"], s["hv"], s["wv"], dev(s["env"]),
+                                     campos, precision="bf16x3")
+    efront = cpu.front_f32(xo, no, campos)
+    assert np.array_equal(host(front), efront)
+    ecol, _ = ref64.shade(ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"],
+                          s["vidx"], s["vw"], cnt, s["kv"], s["he"], s["we"], s["hv"], s["wv"],
+                          s["env"], campos.astype(np.float64), efront)
+    ecol = ecol.numpy()
+    got = host(col)
+    rel = np.abs(got - ecol) / (np.abs(ecol) + 1e-30)
+    print(f"  max rel {rel[ecol > 1e-3].max():.2e}", flush=True)
+    assert np.all(np.abs(got - ecol) <= 1e-4 * np.abs(ecol) + 1e-6)
+
+
 # ------------------------------------------------------------------ splatting
 def _splat_case(s, color):
     xo, no, Ao = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
@@ -239,22 +264,24 @@ def _grad_case(seed=5):
     return s, cnt, front, w
 
 
-def test_gradients_match_fp64_oracle():
-    print("[grad] micro", flush=True)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_gradients_match_fp64_oracle(precision):
+    print(f"[grad] micro {precision}", flush=True)
     s, cnt, front, w = _grad_case()
     p = helpers.params64(s, requires_grad=True)
     img, _ = helpers.render64(s, p, cnt, front)
     (img * torch.tensor(w.reshape(3, -1))).sum().backward()
     d = render.upload(s)
-    R = render.Renderer(s, d)
+    R = render.Renderer(s, d, precision=precision)
     pd = {k: d[k] for k in render.TRAINABLE}
     image, T, ctx = R.forward(pd, dev(cnt))
     g = R.backward(pd, ctx, dev(w.astype(np.float32)))
     # forward image against the FP64 oracle as a sanity check of the chain
-    assert np.abs(host(image).reshape(3, -1) - img.detach().numpy()).max() < 2e-5
+    tol_img, tol_g = (2e-5, 2e-3) if precision == "fp32" else (2e-4, 1e-2)
+    assert np.abs(host(image).reshape(3, -1) - img.detach().numpy()).max() < tol_img
     for k in render.TRAINABLE:
         ref = p[k].grad.numpy()
         got = host(g[k])
         rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
         print(f"  {k:7s} relL2={rel:.2e}", flush=True)
-        assert rel < 2e-3, (k, rel)
+        assert rel < tol_g, (k, rel)

@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--kernel", default=None, help="kernel timed for the roofline entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--all-kernels", action="store_true", help="time every kernel (diagnostic)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step in a HIP graph and replay it (no host launch cost)")
     return ap.parse_args()
@@ -193,6 +195,16 @@ def main():
         image, _, _ = R.forward(p, count)
         return image
 
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the counters of the path's kernels
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # first frame: size the splat workspace to the real duplicate count
     step()
     while R.ensure_capacity():
@@ -245,7 +257,7 @@ def main():
                      "vis_count", "shade_fwd", "splat_fill", "splat_preprocess", "radix_upsweep",
                      "radix_binscan", "radix_downsweep", "touched_blocksum", "touched_blockscan",
                      "splat_duplicate", "tile_ranges", "chunk_index", "blend_chunk",
-                     "blend_combine", "l1_partial", "l1_final",
+                     "blend_prefix", "blend_restart", "l1_partial", "l1_final",
                      "splat_zero", "blend_bwd", "preprocess_bwd", "shade_bwd", "shade_denv",
                      "lbs_bwd"):
             ms, cnt = rga.timing_read(name)

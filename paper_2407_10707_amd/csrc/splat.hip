@@ -27,8 +27,10 @@ namespace {
 
 constexpr int kTile = 16;
 constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;  // per thread
-constexpr int kRadixBlock = kRadixThreads * kRadixItems;
+constexpr int kItemsD = 16;      // per thread, passes over the duplicates
+constexpr int kItemsN = 4;       // per thread, passes over the splats
+constexpr int kBlockD = kRadixThreads * kItemsD;
+constexpr int kBlockN = kRadixThreads * kItemsN;
 constexpr int kChunk = 256;      // splats per blend work item
 
 struct Layout {
@@ -44,8 +46,8 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.tiles_x = (width + kTile - 1) / kTile;
   L.tiles_y = (height + kTile - 1) / kTile;
   const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
-  L.nb_n = (int)rga::ceil_div(n > 0 ? n : 1, kRadixBlock);
-  L.nb_cap = (int)rga::ceil_div(cap > 0 ? cap : 1, kRadixBlock);
+  L.nb_n = (int)rga::ceil_div(n > 0 ? n : 1, kBlockN);
+  L.nb_cap = (int)rga::ceil_div(cap > 0 ? cap : 1, kBlockD);
   L.nb_max = L.nb_n > L.nb_cap ? L.nb_n : L.nb_cap;
   int bits = 0;
   while ((1ll << bits) < tiles) ++bits;
@@ -317,6 +319,7 @@ __device__ inline int64_t live_count(const int64_t* cnt_ptr, int64_t fixed, int6
   return c < cap ? c : cap;
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t fixed,
               int64_t cap, int shift, uint32_t* __restrict__ hist) {
@@ -324,8 +327,8 @@ radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t count = live_count(cnt_ptr, fixed, cap);
-  const int64_t base = (int64_t)blockIdx.x * kRadixBlock;
-  for (int r = 0; r < kRadixItems; ++r) {
+  const int64_t base = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = base + (int64_t)r * kRadixThreads + threadIdx.x;
     if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
   }
@@ -362,6 +365,7 @@ radix_binscan(const uint32_t* __restrict__ hist, int nb, uint32_t* __restrict__ 
   if (threadIdx.x == 255) bintot[bin] = part[255];
 }
 
+template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -383,9 +387,9 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
   __syncthreads();
   base[tid] = excl;
   const int64_t count = live_count(cnt_ptr, fixed, cap);
-  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
+  const int64_t blk = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kRadixItems; ++r) {
+  for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = blk + (int64_t)r * kRadixThreads + tid;
     const bool ok = i < count;
     const uint32_t key = ok ? kin[i] : 0u;
@@ -430,9 +434,9 @@ __global__ void __launch_bounds__(kRadixThreads)
 touched_blocksum(int n, const uint32_t* __restrict__ order, const int32_t* __restrict__ touched,
                  uint32_t* __restrict__ bsum) {
   __shared__ uint32_t red[kRadixThreads];
-  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
+  const int64_t blk = (int64_t)blockIdx.x * kBlockN;
   uint32_t s = 0;
-  for (int r = 0; r < kRadixItems; ++r) {
+  for (int r = 0; r < kItemsN; ++r) {
     const int64_t i = blk + (int64_t)r * kRadixThreads + threadIdx.x;
     if (i < n) s += (uint32_t)touched[order[i]];
   }
@@ -477,12 +481,12 @@ duplicate_kernel(int n, int TX, int64_t cap, const uint32_t* __restrict__ order,
   // in-block exclusive scan of tiles-touched, then emission
   __shared__ uint32_t sc[kRadixThreads];
   const int tid = threadIdx.x;
-  const int64_t blk = (int64_t)blockIdx.x * kRadixBlock;
-  uint32_t loc[kRadixItems];
+  const int64_t blk = (int64_t)blockIdx.x * kBlockN;
+  uint32_t loc[kItemsN];
   uint32_t s = 0;
-  // thread tid owns items blk + tid*kRadixItems + r (contiguous run)
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t i = blk + (int64_t)tid * kRadixItems + r;
+  // thread tid owns items blk + tid*kItemsN + r (contiguous run)
+  for (int r = 0; r < kItemsN; ++r) {
+    const int64_t i = blk + (int64_t)tid * kItemsN + r;
     loc[r] = i < n ? (uint32_t)touched[order[i]] : 0u;
     s += loc[r];
   }
@@ -495,8 +499,8 @@ duplicate_kernel(int n, int TX, int64_t cap, const uint32_t* __restrict__ order,
     __syncthreads();
   }
   uint64_t off = (uint64_t)boff[blockIdx.x] + (tid ? sc[tid - 1] : 0u);
-  for (int r = 0; r < kRadixItems; ++r) {
-    const int64_t i = blk + (int64_t)tid * kRadixItems + r;
+  for (int r = 0; r < kItemsN; ++r) {
+    const int64_t i = blk + (int64_t)tid * kItemsN + r;
     if (i >= n || loc[r] == 0) continue;
     const uint32_t g = order[i];
     const int x0 = rect[g], y0 = rect[n + g], x1 = rect[2 * n + g], y1 = rect[3 * n + g];
@@ -641,88 +645,109 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   st[768 + threadIdx.x] = sat ? -1.f : T;
 }
 
+// Prefix pass, one workgroup per tile, no splat is touched: per pixel, walk
+// the tile's chunk results front to back, leave for every chunk the colour
+// before it and its incoming transmittance, find the chunk that may contain
+// the stop (saturated, or T_in * T_chunk < 1e-4) and mark it; chunks past it
+// are marked -1.  Pixels that never stop get their final colour here.
+// State code per (chunk, pixel) in the fourth plane: T_in >= 0 (whole chunk
+// used), -1 (past the stop), -(T_in + 2) (the chunk where the walk stops).
 __global__ void __launch_bounds__(256)
-blend_combine_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
-                     const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
-                     const uint32_t* __restrict__ item_off, float* __restrict__ cstate,
-                     int64_t max_items, float* __restrict__ image, float* __restrict__ Tfinal) {
-  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
+                    float* __restrict__ cstate, int64_t max_items, float* __restrict__ image,
+                    float* __restrict__ Tfinal) {
   const int t = blockIdx.x;
   const int tx = t % TX, ty = t / TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
-  const int64_t i0 = item_off[t];
-  const int nch = (int)min((int64_t)item_off[t + 1], max_items) - (int)min(i0, max_items);
-  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  const int64_t i0 = min((int64_t)item_off[t], max_items);
+  const int nch = (int)(min((int64_t)item_off[t + 1], max_items) - i0);
   float Tin = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool active = inside;
   for (int j = 0; j < nch; ++j) {
     float* st = cstate + (size_t)(i0 + j) * 1024;
-    float Cj0 = 0.f, Cj1 = 0.f, Cj2 = 0.f, Tj = 1.f;
-    if (active) {
-      Cj0 = st[threadIdx.x];
-      Cj1 = st[256 + threadIdx.x];
-      Cj2 = st[512 + threadIdx.x];
-      Tj = st[768 + threadIdx.x];
-    }
-    const bool need = active && (Tj < 0.f || Tin * Tj < 1e-4f);
-    // state for the adjoint: colour before this chunk and its incoming T
+    const float Cj0 = st[threadIdx.x], Cj1 = st[256 + threadIdx.x], Cj2 = st[512 + threadIdx.x];
+    const float Tj = st[768 + threadIdx.x];
     st[threadIdx.x] = C0;
     st[256 + threadIdx.x] = C1;
     st[512 + threadIdx.x] = C2;
-    st[768 + threadIdx.x] = active ? Tin : -1.f;
-    if (__syncthreads_or(need)) {
-      const int e0 = ranges[2 * t] + j * kChunk;
-      const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
-      if ((int)threadIdx.x < cnt) {
-        const uint32_t g = sorted[e0 + threadIdx.x];
-        s0[threadIdx.x] = rec[3 * g];
-        s1[threadIdx.x] = rec[3 * g + 1];
-        s2[threadIdx.x] = rec[3 * g + 2];
-      }
-      __syncthreads();
-      if (need) {
-        float T = Tin;
-        bool stopped = false;
-        for (int k = 0; k < cnt; ++k) {
-          const float4 a = s0[k], c1 = s1[k];
-          float dx, dy, G, araw;
-          const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
-          if (alpha < 0.f) continue;
-          const float Tn = T * (1.f - alpha);
-          if (Tn < 1e-4f) {
-            stopped = true;
-            break;
-          }
-          const float w = alpha * T;
-          C0 = fmaf(c1.z, w, C0);
-          C1 = fmaf(c1.w, w, C1);
-          C2 = fmaf(s2[k].x, w, C2);
-          T = Tn;
-        }
-        Tin = T;
-        active = !stopped;
-      } else if (active) {
-        C0 = fmaf(Tin, Cj0, C0);
-        C1 = fmaf(Tin, Cj1, C1);
-        C2 = fmaf(Tin, Cj2, C2);
-        Tin *= Tj;
-      }
-      __syncthreads();
-    } else if (active) {
-      C0 = fmaf(Tin, Cj0, C0);
-      C1 = fmaf(Tin, Cj1, C1);
-      C2 = fmaf(Tin, Cj2, C2);
-      Tin *= Tj;
+    if (!active) {
+      st[768 + threadIdx.x] = -1.f;
+      continue;
     }
+    if (Tj < 0.f || Tin * Tj < 1e-4f) {
+      st[768 + threadIdx.x] = -(Tin + 2.f);
+      active = false;          // the restart pass finishes this pixel
+      continue;
+    }
+    st[768 + threadIdx.x] = Tin;
+    C0 = fmaf(Tin, Cj0, C0);
+    C1 = fmaf(Tin, Cj1, C1);
+    C2 = fmaf(Tin, Cj2, C2);
+    Tin *= Tj;
   }
-  if (inside) {
+  if (inside && active) {
     const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
     image[p] = C0;
     image[HW + p] = C1;
     image[2 * HW + p] = C2;
     Tfinal[p] = Tin;
   }
+}
+
+// Restart pass, one workgroup per work item, in parallel: pixels whose walk
+// stops in this chunk re-walk it from T_in with the exact stop rule and
+// write their final colour and transmittance.  (A pixel whose stop test
+// does not fire here because of rounding keeps the chunk's end state.)
+__global__ void __launch_bounds__(256)
+blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+                     const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                     const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
+                     const int64_t* __restrict__ counters, int64_t max_items,
+                     const float* __restrict__ cstate, float* __restrict__ image,
+                     float* __restrict__ Tfinal) {
+  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  const int64_t nitems = min(counters[1], max_items);
+  const int b = blockIdx.x;
+  if (b >= nitems) return;
+  const float* st = cstate + (size_t)b * 1024;
+  const float code = st[768 + threadIdx.x];
+  const bool mine = code <= -2.f;
+  if (!__syncthreads_or(mine)) return;
+  const int t = item_tile[b], j = item_chunk[b];
+  const int tx = t % TX, ty = t / TX;
+  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  const int e0 = ranges[2 * t] + j * kChunk;
+  const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+  if ((int)threadIdx.x < cnt) {
+    const uint32_t g = sorted[e0 + threadIdx.x];
+    s0[threadIdx.x] = rec[3 * g];
+    s1[threadIdx.x] = rec[3 * g + 1];
+    s2[threadIdx.x] = rec[3 * g + 2];
+  }
+  __syncthreads();
+  if (!mine || !(px < W && py < H)) return;
+  const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
+  float T = -code - 2.f;
+  float C0 = st[threadIdx.x], C1 = st[256 + threadIdx.x], C2 = st[512 + threadIdx.x];
+  for (int k = 0; k < cnt; ++k) {
+    const float4 a = s0[k], c1 = s1[k];
+    float dx, dy, G, araw;
+    const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
+    if (alpha < 0.f) continue;
+    const float Tn = T * (1.f - alpha);
+    if (Tn < 1e-4f) break;
+    const float w = alpha * T;
+    C0 = fmaf(c1.z, w, C0);
+    C1 = fmaf(c1.w, w, C1);
+    C2 = fmaf(s2[k].x, w, C2);
+    T = Tn;
+  }
+  const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
+  image[p] = C0;
+  image[HW + p] = C1;
+  image[2 * HW + p] = C2;
+  Tfinal[p] = T;
 }
 
 // ---- adjoint: blend ----------------------------------------------------------
@@ -764,11 +789,12 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     s2[threadIdx.x] = rec[3 * g + 2];
   }
   const float* st = cstate + (size_t)b * 1024;
-  float T = st[768 + threadIdx.x];
+  const float code = st[768 + threadIdx.x];
+  float T = code <= -2.f ? -code - 2.f : code;
   float A0 = st[threadIdx.x], A1 = st[256 + threadIdx.x], A2 = st[512 + threadIdx.x];
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  bool done = !inside || T < 0.f;
+  bool done = !inside || code == -1.f;
   if (!done) {
     const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
     Cf0 = image[p];
@@ -1085,11 +1111,11 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     // depth sort: 4 passes of 8 bits over n keys
     for (int pass = 0; pass < 4; ++pass) {
       const int shift = 8 * pass;
-      RGA_LAUNCH("radix_upsweep", radix_upsweep, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+      RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
       RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_n, binoff,
                  bintot);
-      RGA_LAUNCH("radix_downsweep", radix_downsweep, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+      RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot);
       uint32_t* t = k0; k0 = k1; k1 = t;
       t = v0; v0 = v1; v1 = t;
@@ -1110,11 +1136,11 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                tk0, tv0);
     for (int pass = 0; pass < L.tile_passes; ++pass) {
       const int shift = 8 * pass;
-      RGA_LAUNCH("radix_upsweep", radix_upsweep, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+      RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);
       RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_cap, binoff,
                  bintot);
-      RGA_LAUNCH("radix_downsweep", radix_downsweep, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+      RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot);
       uint32_t* t = tk0; tk0 = tk1; tk1 = t;
       t = tv0; tv0 = tv1; tv1 = t;
@@ -1130,9 +1156,12 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(L.max_items), dim3(256), 0, s, W, H, L.tiles_x,
              ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate));
-  RGA_LAUNCH("blend_combine", blend_combine_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
-             ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_off),
-             at<float>(ws, L.cstate), L.max_items, image, T_final);
+  RGA_LAUNCH("blend_prefix", blend_prefix_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
+             at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final);
+  RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(L.max_items), dim3(256), 0, s, W, H,
+             L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
+             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate), image,
+             T_final);
   RGA_CHECK_LAUNCH("splat_forward");
   return RGA_OK;
 }

@@ -47,6 +47,9 @@ def parse():
                     help="also run a 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--graph", action="store_true",
                     help="capture one step in a HIP graph and replay it (no host launch cost)")
+    ap.add_argument("--sequence", action="store_true",
+                    help="animation x relighting sequence: step i renders frame i mod "
+                         "(poses x maps), pose-major; visibility once per pose")
     return ap.parse_args()
 
 
@@ -184,16 +187,33 @@ def main():
     p = {k: d[k] for k in render.TRAINABLE}
     target = d["target"]
 
+    frames = cfg.n_pose * cfg.n_env if args.sequence else 1
+    if args.sequence:
+        skins = [torch.as_tensor(synth.pose_skin(args.config, k).reshape(-1, 12)
+                                 .astype(np.float32)).cuda() for k in range(cfg.n_pose)]
+        envs = [torch.as_tensor(synth.env_map(args.config, e).astype(np.float32)).cuda()
+                for e in range(cfg.n_env)]
+    seq = {"frame": 0, "count": None}
+
     def step():
-        count = R.visibility()
-        loss, grads = R.train_step(p, count, target)
+        if not args.sequence:
+            count = R.visibility()
+            loss, grads = R.train_step(p, count, target)
+            return loss
+        k, e = divmod(seq["frame"] % frames, cfg.n_env)
+        seq["frame"] += 1
+        if e == 0 or seq["count"] is None:
+            R.d["skin"] = skins[k]
+            seq["count"] = R.visibility()
+        p["env"] = envs[e]
+        loss, grads = R.train_step(p, seq["count"], target)
         return loss
 
     def fwd(with_vis, count=None):
         if with_vis:
             count = R.visibility()
         image, _, _ = R.forward(p, count)
-        return image
+        return count
 
     if args.copy_calibration:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
@@ -205,11 +225,17 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # first frame: size the splat workspace to the real duplicate count
-    step()
-    while R.ensure_capacity():
+    # size the splat workspace to the real duplicate count (every pose of a
+    # sequence), then start the sequence again at frame 0
+    Ds = []
+    for _ in range(frames):
         step()
-    D = R.ws.count()
+        while R.ensure_capacity():
+            seq["frame"] -= 1
+            step()
+        Ds.append(R.ws.count())
+    D = max(Ds)
+    seq["frame"] = 0
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -265,14 +291,29 @@ def main():
                 per_kernel[name] = round(ms / args.steps, 4)
         per_kernel["sum_of_kernels"] = round(sum(per_kernel.values()), 4)
 
-    # forward-only frame rates (visibility per frame, and cached per pose)
+    # forward-only frame rates (visibility per frame, and cached per pose;
+    # a sequence recomputes visibility once per pose)
+    seq["frame"] = 0
+    if args.sequence:
+        R.d["skin"] = skins[0]
+        p["env"] = envs[0]
     count = R.visibility()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd(True)
+    for i in range(args.steps):
+        if args.sequence:
+            k, e = divmod(i % frames, cfg.n_env)
+            R.d["skin"] = skins[k]
+            p["env"] = envs[e]
+            count = fwd(e == 0, count)
+        else:
+            fwd(True)
     torch.cuda.synchronize()
     fps = args.steps / (time.perf_counter() - t0)
+    if args.sequence:
+        R.d["skin"] = skins[0]
+        p["env"] = envs[0]
+        count = R.visibility()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         fwd(False, count)
@@ -316,6 +357,7 @@ def main():
         "render_fps": round(fps, 2),
         "render_fps_no_vis": round(fps_nv, 2),
         "duplicates": D,
+        "sequence_frames": frames if args.sequence else None,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -281,6 +281,18 @@ def _i32(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
 
 
+def pose_skin(cfg_id: int, pose_index: int = 0) -> np.ndarray:
+    """Skinning matrices [24][3][4] of pose `pose_index` of a configuration."""
+    return skinning_matrices(random_pose(rng_for(cfg_id, 1, pose_index)))
+
+
+def env_map(cfg_id: int, env_index: int = 0) -> np.ndarray:
+    """Environment radiance [He*We][3]: log-normal per texel and channel."""
+    cfg = CONFIGS[cfg_id]
+    re = rng_for(cfg_id, 4, env_index)
+    return np.exp(re.normal(-1.0, 1.0, size=(cfg.he * cfg.we, 3)))
+
+
 def make_scene(cfg_id: int, n_gauss: Optional[int] = None, pose_index: int = 0,
                env_index: int = 0, identity_pose: bool = False,
                height: Optional[int] = None, width: Optional[int] = None) -> dict:
@@ -307,10 +319,7 @@ def make_scene(cfg_id: int, n_gauss: Optional[int] = None, pose_index: int = 0,
     w4 /= w4.sum(axis=1, keepdims=True)
 
     # pose
-    if identity_pose:
-        skin = identity_skinning()
-    else:
-        skin = skinning_matrices(random_pose(rng_for(cfg_id, 1, pose_index)))
+    skin = identity_skinning() if identity_pose else pose_skin(cfg_id, pose_index)
 
     # Gaussians: area-weighted triangle, uniform barycentric point, face normal
     rs = rng_for(cfg_id, 2)
@@ -342,9 +351,7 @@ def make_scene(cfg_id: int, n_gauss: Optional[int] = None, pose_index: int = 0,
     u = 1.0 / np.maximum(gd, 1e-12)
     u /= u.sum(axis=1, keepdims=True)
 
-    # environment radiance, log-normal per texel and channel
-    re = rng_for(cfg_id, 4, env_index)
-    env = np.exp(re.normal(-1.0, 1.0, size=(cfg.he * cfg.we, 3)))
+    env = env_map(cfg_id, env_index)
 
     cam = default_camera(W, H)
     target = rng_for(cfg_id, 5).random((3, H, W))

@@ -157,3 +157,65 @@ def test_sampled_pixel_gradients_match_fp64(case):
         rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
         print(f"  {k:7s} relL2={rel:.2e}", flush=True)
         assert rel < tol, (k, rel)
+
+
+def _subscene(s, sub):
+    sub_s = dict(s)
+    for k in ("pos", "nrm", "quat", "log_s", "albedo", "jidx", "jw", "vidx", "vw"):
+        sub_s[k] = np.ascontiguousarray(s[k][:, sub])
+    for k in ("opac", "rough", "tint"):
+        sub_s[k] = np.ascontiguousarray(s[k][sub])
+    sub_s["n"] = len(sub)
+    return sub_s
+
+
+def test_image_error_vs_fp64_on_sampled_tiles(case):
+    """Image error of the whole GPU path against the FP64 oracle's whole chain
+    (skinning, shading, projection, compositing) on every pixel of 8 sampled
+    lit tiles, as PSNR (peak 1), relative L2 and max abs.  For the workloads
+    that use the BF16X3 shading the plain FP32 form is measured beside it."""
+    s, R, d, p = case["s"], case["R"], case["d"], case["p"]
+    H, W = s["height"], s["width"]
+    st = R.ws.state()
+    TX, TY = st.tiles_x, st.tiles_y
+    img = _host(case["image"])
+    tmean = np.zeros(TX * TY)
+    for t in range(TX * TY):
+        ty, tx = divmod(t, TX)
+        tmean[t] = img[:, ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16].mean()
+    rng = np.random.default_rng(13)
+    tiles = np.sort(rng.choice(np.nonzero(tmean > 0.05)[0], 8, replace=False))
+    pix = []
+    for t in tiles:
+        ty, tx = divmod(int(t), TX)
+        yy, xx = np.meshgrid(np.arange(ty * 16, min(H, ty * 16 + 16)),
+                             np.arange(tx * 16, min(W, tx * 16 + 16)), indexing="ij")
+        pix.append((yy * W + xx).reshape(-1))
+    pix = np.sort(np.concatenate(pix))
+    D = R.ws.count()
+    ranges = _host(R.ws.view(st.ranges, (TX * TY, 2), torch.int32))
+    vals = _host(R.ws.view(st.sorted, (D,), torch.int32))
+    sub = np.unique(np.concatenate([vals[ranges[t, 0]:ranges[t, 1]] for t in tiles]))
+    print(f"[fullsize] {case['name']}: image error, {len(pix)} pixels, {len(sub)} Gaussians",
+          flush=True)
+    cnt = _host(case["count"])
+    front = _host(case["ctx"]["front"])[sub]
+    sub_s = _subscene(s, sub)
+    with torch.no_grad():
+        ref, _ = helpers.render64(sub_s, helpers.params64(sub_s), cnt, front, pixels=pix)
+    ref = ref.numpy()
+    forms = [case["precision"]] + (["fp32"] if case["precision"] == "bf16x3" else [])
+    for form in forms:
+        if form == case["precision"]:
+            got = img.reshape(3, -1)[:, pix]
+        else:
+            R2 = render.Renderer(s, d, capacity=R.ws.capacity, precision=form)
+            got = _host(R2.forward(p, case["count"])[0]).reshape(3, -1)[:, pix]
+            del R2
+        err = got - ref
+        mse = float(np.mean(err ** 2))
+        psnr = 10 * np.log10(1.0 / max(mse, 1e-300))
+        rel = float(np.linalg.norm(err) / np.linalg.norm(ref))
+        print(f"[report] {case['name']} {form}: PSNR {psnr:.1f} dB, relL2 {rel:.2e}, "
+              f"max abs {np.abs(err).max():.2e}", flush=True)
+        assert psnr > 60.0 and rel < 1e-4, (form, psnr, rel)

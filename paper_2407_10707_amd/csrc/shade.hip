@@ -102,8 +102,15 @@ __device__ inline void wait_all() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Reciprocal and reciprocal square root on the transcendental unit (about
+// 1 ulp).  The shading sums are compared with the FP64 oracle under a
+// relative tolerance, never bit for bit, so the correctly rounded
+// division sequence buys nothing here.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 struct GaussCtx {
-  float nn[3], wo[3], co, a2, kG, Go, inn, iwo, alpha, gamma;
+  float nn[3], wo[3], co, a2, kG, Go, inn, iwo, alpha, ialpha, gamma;
   float u0, u1, u2;
   const uint8_t* rows;   // LDS copy of the three count rows
   bool front;
@@ -127,6 +134,7 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
   G.co = fmaf(G.nn[2], G.wo[2], fmaf(G.nn[1], G.wo[1], G.nn[0] * G.wo[0]));
   G.gamma = A.rough;
   G.alpha = G.gamma * G.gamma;
+  G.ialpha = 1.f / G.alpha;
   G.a2 = G.alpha * G.alpha;
   G.kG = (G.gamma + 1.f) * (G.gamma + 1.f) * 0.125f;
   G.Go = 1.f / fmaf(G.co, 1.f - G.kG, G.kG);
@@ -149,7 +157,8 @@ __device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int
 }
 
 struct Pair {
-  float d[3], E[3], ci, ok, hh, nht, s2, den, invh, nh, oh, e2, F, D, G1i, deni, W0, Ws, Wd;
+  float d[3], E[3], ci, ok, hh, nht, s2, den, invh, nh, oh, e2, F, hd, D, G1i, deni, ideni, W0, Ws,
+      Wd;
 };
 
 // BRDF weights of one live (Gaussian, direction) pair.  The GGX denominator
@@ -173,15 +182,16 @@ __device__ inline void pair_eval(const GaussCtx& G, const float* tab, int K, int
   const float s2 = G.nn[0] * h1 - G.nn[1] * h0;
   P.s2 = fmaf(s2, s2, fmaf(s1, s1, s0 * s0));
   P.den = fmaf(P.nht * P.nht, G.a2, P.s2);           // (1 - nh^2 (1 - a^2)) |h~|^2
-  P.invh = 1.f / sqrtf(P.hh);
+  P.invh = rsq(P.hh);
   P.nh = P.nht * P.invh;
   P.oh = (1.f + P.ok) * P.invh;
   P.e2 = exp2f((-5.55473f * P.oh - 6.98316f) * P.oh);
   P.F = 0.04f + 0.96f * P.e2;
-  const float hd = P.hh / P.den;
-  P.D = G.a2 * hd * hd * (1.f / kPi);
+  P.hd = P.hh * rcp(P.den);                         // 1 / (1 - nh^2 (1 - a^2))
+  P.D = G.a2 * P.hd * P.hd * (1.f / kPi);
   P.deni = fmaf(P.ci, 1.f - G.kG, G.kG);
-  P.G1i = P.ci / P.deni;
+  P.ideni = rcp(P.deni);
+  P.G1i = P.ci * P.ideni;
   P.W0 = v * P.D * P.F * G.Go * 0.25f;
   P.Ws = P.W0 * P.G1i;
   P.Wd = v * P.ci;
@@ -440,6 +450,34 @@ struct BwdAcc {
   float gn[3], gw[3], gco, gga, sd[3], ts;
 };
 
+// Chain rule through one live pair's weights: upstream gWd = dL/dW_d and
+// gWs = dL/dW_s give the pair's share of dL/dn^, dL/dw_o, dL/d(n.w_o) and
+// dL/dgamma.  Uses the logarithmic derivatives of D (in n.h and alpha), F
+// (in o.h) and G1.
+__device__ inline void pair_grads(const GaussCtx& G, const Pair& P, float v, float gWd, float gWs,
+                                  BwdAcc& acc) {
+  const float one_m_a2 = 1.f - G.a2;
+  const float dlnD_dnh = 4.f * P.nh * one_m_a2 * P.hd;
+  const float dlnD_da = 2.f * G.ialpha - 4.f * G.alpha * P.nh * P.nh * P.hd;
+  const float dlnF_doh =
+      0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) * rcp(P.F);
+  const float gs = gWs * P.Ws;
+  const float ih3 = P.invh * P.invh * P.invh;
+  const float gci = gWd * v + gWs * P.W0 * G.kG * (P.ideni * P.ideni) + gs * dlnD_dnh * P.invh;
+  const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
+  const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
+  const float dlnG_dk = -(1.f - P.ci) * P.ideni - (1.f - G.co) * G.Go;
+  const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
+  acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
+  acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
+  acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
+  acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
+  acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
+  acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
+  acc.gco += gco;
+  acc.gga += gga;
+}
+
 __device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv_lds, int K, int k,
                                 float v, const float* qd, const float* dLo, float tint,
                                 const float* aop, BwdAcc& acc) {
@@ -458,27 +496,7 @@ __device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv
   atomicAdd(&denv_lds[3 * k + 0], dLo[0] * fmaf(aop[0], P.Wd, tint * P.Ws));
   atomicAdd(&denv_lds[3 * k + 1], dLo[1] * fmaf(aop[1], P.Wd, tint * P.Ws));
   atomicAdd(&denv_lds[3 * k + 2], dLo[2] * fmaf(aop[2], P.Wd, tint * P.Ws));
-  // logarithmic derivatives of D (in nh and alpha), F (in oh), G1
-  const float one_m_a2 = 1.f - G.a2;
-  const float dn = P.den / P.hh;                     // 1 - nh^2 (1 - a^2)
-  const float dlnD_dnh = 4.f * P.nh * one_m_a2 / dn;
-  const float dlnD_da = 2.f / G.alpha - 4.f * G.alpha * P.nh * P.nh / dn;
-  const float dlnF_doh = 0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) / P.F;
-  const float gs = gWs * P.Ws;
-  const float ih3 = P.invh * P.invh * P.invh;
-  const float gci = gWd * v + gWs * P.W0 * G.kG / (P.deni * P.deni) + gs * dlnD_dnh * P.invh;
-  const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
-  const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
-  const float dlnG_dk = -(1.f - P.ci) / P.deni - (1.f - G.co) * G.Go;
-  const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
-  acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
-  acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
-  acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
-  acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
-  acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
-  acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
-  acc.gco += gco;
-  acc.gga += gga;
+  pair_grads(G, P, v, gWd, gWs, acc);
 }
 
 // BF16X3 adjoint.  Same tiling (16 Gaussians x 32 directions per step).  On
@@ -591,27 +609,7 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
           const float gWd = fmaf(qd[2], P.E[2], fmaf(qd[1], P.E[1], qd[0] * P.E[0]));
           const float sE = fmaf(dLo[2], P.E[2], fmaf(dLo[1], P.E[1], dLo[0] * P.E[0]));
           const float gWs = tint * sE;
-          const float one_m_a2 = 1.f - G.a2;
-          const float dnn = P.den / P.hh;
-          const float dlnD_dnh = 4.f * P.nh * one_m_a2 / dnn;
-          const float dlnD_da = 2.f / G.alpha - 4.f * G.alpha * P.nh * P.nh / dnn;
-          const float dlnF_doh =
-              0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) / P.F;
-          const float gs = gWs * P.Ws;
-          const float ih3 = P.invh * P.invh * P.invh;
-          const float gci = gWd * v + gWs * P.W0 * G.kG / (P.deni * P.deni) + gs * dlnD_dnh * P.invh;
-          const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
-          const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
-          const float dlnG_dk = -(1.f - P.ci) / P.deni - (1.f - G.co) * G.Go;
-          const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
-          acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
-          acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
-          acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
-          acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
-          acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
-          acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
-          acc.gco += gco;
-          acc.gga += gga;
+          pair_grads(G, P, v, gWd, gWs, acc);
         }
         const __bf16 hd = (__bf16)Wd, hs = (__bf16)Ws;
         dh[i] = hd;

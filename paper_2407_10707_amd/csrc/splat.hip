@@ -543,18 +543,30 @@ tile_ranges_kernel(const uint32_t* __restrict__ tkeys, const int64_t* cnt_ptr, i
 // combine leaves (C before the chunk, T_in) per (chunk, pixel) for the
 // adjoint, and T_in = -1 for chunks past the stop.
 
-// alpha of one entry for the pixel centre (px, py): returns < 0 if skipped
-__device__ inline float entry_alpha(const float4& a, const float4& c1, float px, float py,
-                                    float& dx, float& dy, float& G, float& araw) {
+// One front-to-back compositing step for the pixel centre (px, py), written
+// with selects instead of divergent branches: an entry is skipped when its
+// exponent is positive or its alpha is below 1/255, and the walk stops at
+// the first entry that would take T below 1e-4.  Returns the weight
+// alpha * T (0 if the entry is skipped or the walk has stopped); `applied`
+// tells whether the entry contributed.
+__device__ inline float blend_step(const float4& a, const float4& c1, float px, float py, float& T,
+                                   bool& stopped, bool& applied, float& alpha, float& dx,
+                                   float& dy, float& G, float& araw) {
   dx = a.x - px;
   dy = a.y - py;
   const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
   const float power = -0.5f * qf;
-  if (power > 0.f) return -1.f;
   G = expf(power);
   araw = c1.y * G;
-  const float alpha = fminf(0.99f, araw);
-  return alpha < 1.f / 255.f ? -1.f : alpha;
+  alpha = fminf(0.99f, araw);
+  const bool use = !stopped && power <= 0.f && alpha >= 1.f / 255.f;
+  const float Tn = T * (1.f - alpha);
+  const bool stop = use && Tn < 1e-4f;
+  stopped = stopped || stop;
+  applied = use && !stop;
+  const float w = applied ? alpha * T : 0.f;
+  T = applied ? Tn : T;
+  return w;
 }
 
 __global__ void __launch_bounds__(1024)
@@ -619,25 +631,22 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   __syncthreads();
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
-  bool sat = false;
-  if (px < W && py < H) {
-    for (int k = 0; k < cnt; ++k) {
+  bool sat = !(px < W && py < H);
+  const bool outside = sat;
+  for (int k0 = 0; k0 < cnt; k0 += 32) {
+    if (__ballot(!sat) == 0ull) break;     // every pixel of this wave saturated
+    const int k1 = min(cnt, k0 + 32);
+    for (int k = k0; k < k1; ++k) {
       const float4 a = s0[k], c1 = s1[k];
-      float dx, dy, G, araw;
-      const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
-      if (alpha < 0.f) continue;
-      const float Tn = T * (1.f - alpha);
-      if (Tn < 1e-4f) {
-        sat = true;
-        break;
-      }
-      const float w = alpha * T;
+      bool applied;
+      float alpha, dx, dy, G, araw;
+      const float w = blend_step(a, c1, fpx, fpy, T, sat, applied, alpha, dx, dy, G, araw);
       C0 = fmaf(c1.z, w, C0);
       C1 = fmaf(c1.w, w, C1);
       C2 = fmaf(s2[k].x, w, C2);
-      T = Tn;
     }
   }
+  sat = sat && !outside;
   float* st = cstate + (size_t)b * 1024;
   st[threadIdx.x] = C0;
   st[256 + threadIdx.x] = C1;
@@ -730,18 +739,18 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float T = -code - 2.f;
   float C0 = st[threadIdx.x], C1 = st[256 + threadIdx.x], C2 = st[512 + threadIdx.x];
-  for (int k = 0; k < cnt; ++k) {
-    const float4 a = s0[k], c1 = s1[k];
-    float dx, dy, G, araw;
-    const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
-    if (alpha < 0.f) continue;
-    const float Tn = T * (1.f - alpha);
-    if (Tn < 1e-4f) break;
-    const float w = alpha * T;
-    C0 = fmaf(c1.z, w, C0);
-    C1 = fmaf(c1.w, w, C1);
-    C2 = fmaf(s2[k].x, w, C2);
-    T = Tn;
+  bool stopped = false;
+  for (int k0 = 0; k0 < cnt && !stopped; k0 += 32) {
+    const int k1 = min(cnt, k0 + 32);
+    for (int k = k0; k < k1; ++k) {
+      const float4 a = s0[k], c1 = s1[k];
+      bool applied;
+      float alpha, dx, dy, G, araw;
+      const float w = blend_step(a, c1, fpx, fpy, T, stopped, applied, alpha, dx, dy, G, araw);
+      C0 = fmaf(c1.z, w, C0);
+      C1 = fmaf(c1.w, w, C1);
+      C2 = fmaf(s2[k].x, w, C2);
+    }
   }
   const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
   image[p] = C0;
@@ -770,13 +779,13 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
                  float* __restrict__ dopac, float* __restrict__ dcolor) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   __shared__ uint32_t sg[kChunk];
-  __shared__ float part[4][9][64];
+  __shared__ float acc[9][kChunk];
   const int64_t nitems = min(counters[1], max_items);
   const int b = blockIdx.x;
   if (b >= nitems) return;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
   const int e0 = ranges[2 * t] + j * kChunk;
@@ -788,6 +797,8 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     s1[threadIdx.x] = rec[3 * g + 1];
     s2[threadIdx.x] = rec[3 * g + 2];
   }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q][threadIdx.x] = 0.f;
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
   float T = code <= -2.f ? -code - 2.f : code;
@@ -805,76 +816,62 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     g2 = dimage[2 * HW + p];
   }
   __syncthreads();
-  for (int j0 = 0; j0 < cnt; j0 += 64) {
-    if (__syncthreads_count(done) == 256) break;
-    const int jn = min(64, cnt - j0);
-    for (int jj = 0; jj < jn; ++jj) {
-      const int k = j0 + jj;
-      float v[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool contrib = false;
-      if (!done) {
-        const float4 a = s0[k], c1 = s1[k];
-        float dx, dy, G, araw;
-        const float alpha = entry_alpha(a, c1, fpx, fpy, dx, dy, G, araw);
-        if (alpha >= 0.f) {
-          const float Tn = T * (1.f - alpha);
-          if (Tn < 1e-4f) {
-            done = true;
-          } else {
-            contrib = true;
-            const float col0 = c1.z, col1 = c1.w, col2 = s2[k].x;
-            const float w = alpha * T;
-            A0 = fmaf(col0, w, A0);
-            A1 = fmaf(col1, w, A1);
-            A2 = fmaf(col2, w, A2);
-            v[6] = w * g0;
-            v[7] = w * g1;
-            v[8] = w * g2;
-            const float inv1m = 1.f / (1.f - alpha);
-            const float dal = g0 * (col0 * T - (Cf0 - A0) * inv1m) +
-                              g1 * (col1 * T - (Cf1 - A1) * inv1m) +
-                              g2 * (col2 * T - (Cf2 - A2) * inv1m);
-            if (araw <= 0.99f) {
-              v[5] = dal * G;                       // d/d opacity
-              const float dp = dal * alpha;         // d/d power
-              v[0] = -dp * (a.z * dx + a.w * dy);   // d/d mean x
-              v[1] = -dp * (a.w * dx + c1.x * dy);  // d/d mean y
-              v[2] = -0.5f * dp * dx * dx;          // d/d conic A
-              v[3] = -dp * dx * dy;                 // d/d conic B
-              v[4] = -0.5f * dp * dy * dy;          // d/d conic C
-            }
-            T = Tn;
-          }
-        }
-      }
-      const bool any = __ballot(contrib) != 0ull;
-      if (any) {
+  for (int k0 = 0; k0 < cnt; k0 += 32) {
+    if (__ballot(!done) == 0ull) break;    // every pixel of this wave finished
+    const int k1 = min(cnt, k0 + 32);
+    for (int k = k0; k < k1; ++k) {
+      const float4 a = s0[k], c1 = s1[k];
+      const float col2 = s2[k].x;
+      const float Tb = T;
+      bool applied;
+      float alpha, dx, dy, G, araw;
+      const float w = blend_step(a, c1, fpx, fpy, T, done, applied, alpha, dx, dy, G, araw);
+      if (__ballot(applied) == 0ull) continue;
+      A0 = fmaf(c1.z, w, A0);
+      A1 = fmaf(c1.w, w, A1);
+      A2 = fmaf(col2, w, A2);
+      const float inv1m = 1.f / (1.f - alpha);
+      const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
+                        g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
+                        g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
+      const bool lin = applied && araw <= 0.99f;   // alpha not clamped
+      const float dp = lin ? dal * alpha : 0.f;     // d/d power
+      float v[9];
+      v[0] = -dp * (a.z * dx + a.w * dy);           // d/d mean x
+      v[1] = -dp * (a.w * dx + c1.x * dy);          // d/d mean y
+      v[2] = -0.5f * dp * dx * dx;                  // d/d conic A
+      v[3] = -dp * dx * dy;                         // d/d conic B
+      v[4] = -0.5f * dp * dy * dy;                  // d/d conic C
+      v[5] = lin ? dal * G : 0.f;                   // d/d opacity
+      v[6] = w * g0;                                // d/d colour
+      v[7] = w * g1;
+      v[8] = w * g2;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) v[q] = rga::wave_sum(v[q]);
-      }
+      for (int q = 0; q < 9; ++q) v[q] = rga::wave_sum(v[q]);
       if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) part[wave][q][jj] = any ? v[q] : 0.f;
+        for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], v[q]);
       }
     }
-    __syncthreads();
-    if ((int)threadIdx.x < jn) {
-      const int jj = threadIdx.x;
-      const uint32_t g = sg[j0 + jj];
-      float sum[9];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt) {
+    const int k = threadIdx.x;
+    const uint32_t g = sg[k];
+    float sum[9];
+    bool nz = false;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) sum[q] = part[0][q][jj] + part[1][q][jj] + part[2][q][jj] + part[3][q][jj];
-      bool nz = false;
+    for (int q = 0; q < 9; ++q) {
+      sum[q] = acc[q][k];
+      nz |= sum[q] != 0.f;
+    }
+    if (nz) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) nz |= sum[q] != 0.f;
-      if (nz) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) atomicAdd(&gmean_conic[(size_t)q * n + g], sum[q]);
-        atomicAdd(&dopac[g], sum[5]);
-        atomicAdd(&dcolor[g], sum[6]);
-        atomicAdd(&dcolor[(size_t)n + g], sum[7]);
-        atomicAdd(&dcolor[(size_t)2 * n + g], sum[8]);
-      }
+      for (int q = 0; q < 5; ++q) atomicAdd(&gmean_conic[(size_t)q * n + g], sum[q]);
+      atomicAdd(&dopac[g], sum[5]);
+      atomicAdd(&dcolor[g], sum[6]);
+      atomicAdd(&dcolor[(size_t)n + g], sum[7]);
+      atomicAdd(&dcolor[(size_t)2 * n + g], sum[8]);
     }
   }
 }

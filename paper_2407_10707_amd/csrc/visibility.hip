@@ -52,16 +52,118 @@ struct Proj {
 };
 
 __device__ inline void project(const Proj& P, const float* __restrict__ v, int nv, int i,
-                               int64_t& U, int64_t& V, float& z) {
+                               int32_t& U, int32_t& V, float& z) {
   const float q0 = v[i] - P.c[0], q1 = v[nv + i] - P.c[1], q2 = v[2 * nv + i] - P.c[2];
   const float pu = fmaf(P.t[2], q2, fmaf(P.t[1], q1, P.t[0] * q0));
   const float pv = fmaf(P.b[2], q2, fmaf(P.b[1], q1, P.b[0] * q0));
   const float pd = fmaf(P.d[2], q2, fmaf(P.d[1], q1, P.d[0] * q0));
   const float u = (pu / P.rho + 1.f) * P.scale;
   const float w = (pv / P.rho + 1.f) * P.scale;
-  U = (int64_t)(int32_t)rintf(u * 256.f);
-  V = (int64_t)(int32_t)rintf(w * 256.f);
+  U = (int32_t)rintf(u * 256.f);
+  V = (int32_t)rintf(w * 256.f);
   z = P.rho - pd;
+}
+
+__device__ inline unsigned long long depth_key(float bz, int f) {
+  return ((unsigned long long)__float_as_uint(bz) << 32) | (unsigned long long)(uint32_t)f;
+}
+
+// General triangle (any extent): edge functions in 64-bit integers.
+__device__ void raster_tri_wide(unsigned long long* zb, int res, int f, int64_t x0, int64_t y0,
+                                float z0, int64_t x1, int64_t y1, float z1, int64_t x2,
+                                int64_t y2, float z2) {
+  int64_t area = edge(x0, y0, x1, y1, x2, y2);
+  if (area == 0) return;
+  if (area < 0) {
+    int64_t tx = x1, ty = y1;
+    x1 = x2; y1 = y2; x2 = tx; y2 = ty;
+    float tz = z1; z1 = z2; z2 = tz;
+    area = -area;
+  }
+  int64_t mnx = min(x0, min(x1, x2)), mxx = max(x0, max(x1, x2));
+  int64_t mny = min(y0, min(y1, y2)), mxy = max(y0, max(y1, y2));
+  int64_t i_lo = -fdiv(-(mnx - 128), 256), i_hi = fdiv(mxx - 128, 256);
+  int64_t j_lo = -fdiv(-(mny - 128), 256), j_hi = fdiv(mxy - 128, 256);
+  if (i_lo < 0) i_lo = 0;
+  if (j_lo < 0) j_lo = 0;
+  if (i_hi > res - 1) i_hi = res - 1;
+  if (j_hi > res - 1) j_hi = res - 1;
+  const bool o12 = owns(x1, y1, x2, y2), o20 = owns(x2, y2, x0, y0), o01 = owns(x0, y0, x1, y1);
+  const float fa = (float)area;
+  for (int64_t j = j_lo; j <= j_hi; ++j) {
+    const int64_t sy = 256 * j + 128;
+    for (int64_t i = i_lo; i <= i_hi; ++i) {
+      const int64_t sx = 256 * i + 128;
+      const int64_t w0 = edge(x1, y1, x2, y2, sx, sy);
+      const int64_t w1 = edge(x2, y2, x0, y0, sx, sy);
+      const int64_t w2 = edge(x0, y0, x1, y1, sx, sy);
+      const bool in0 = w0 > 0 || (w0 == 0 && o12);
+      const bool in1 = w1 > 0 || (w1 == 0 && o20);
+      const bool in2 = w2 > 0 || (w2 == 0 && o01);
+      if (!(in0 && in1 && in2)) continue;
+      const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) / fa;
+      atomicMin(&zb[j * res + i], depth_key(bz, f));
+    }
+  }
+}
+
+// Triangle whose bounding box spans fewer than 2^14 fixed-point units on
+// both axes (64 pixels): every coordinate difference inside the box (and
+// one sample step past it) is below 2^14 + 256, so each edge-function
+// product is below 2^29 and the edge functions are exact in 32-bit
+// integers.  They are stepped incrementally
+// along a row (exact integer updates), and the top-left rule becomes a
+// sign test after subtracting 1 from the edges a sample on them does not
+// belong to.  Same integers, same depth arithmetic as the wide form.
+__device__ inline void raster_tri(unsigned long long* zb, int res, int f, int32_t x0, int32_t y0,
+                                  float z0, int32_t x1, int32_t y1, float z1, int32_t x2,
+                                  int32_t y2, float z2) {
+  const int32_t mnx = min(x0, min(x1, x2)), mxx = max(x0, max(x1, x2));
+  const int32_t mny = min(y0, min(y1, y2)), mxy = max(y0, max(y1, y2));
+  if ((uint32_t)mxx - (uint32_t)mnx >= 16384u || (uint32_t)mxy - (uint32_t)mny >= 16384u) {
+    raster_tri_wide(zb, res, f, x0, y0, z0, x1, y1, z1, x2, y2, z2);
+    return;
+  }
+  int32_t area = (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0);
+  if (area == 0) return;
+  if (area < 0) {
+    int32_t tx = x1, ty = y1;
+    x1 = x2; y1 = y2; x2 = tx; y2 = ty;
+    float tz = z1; z1 = z2; z2 = tz;
+    area = -area;
+  }
+  // sample columns i with mnx <= 256 i + 128 <= mxx (arithmetic shifts floor)
+  const int i_lo = max(0, -((128 - mnx) >> 8)), i_hi = min(res - 1, (mxx - 128) >> 8);
+  const int j_lo = max(0, -((128 - mny) >> 8)), j_hi = min(res - 1, (mxy - 128) >> 8);
+  if (i_lo > i_hi || j_lo > j_hi) return;
+  // w_e(s) = a_e (sx - x_e) + b_e (sy - y_e) for the edge opposite vertex e
+  const int32_t a0 = y1 - y2, b0 = x2 - x1;
+  const int32_t a1 = y2 - y0, b1 = x0 - x2;
+  const int32_t a2 = y0 - y1, b2 = x1 - x0;
+  // 0 if a sample on the edge belongs to the triangle, else 1
+  // (edge A -> B owns its samples iff B.y > A.y, or B.y == A.y and B.x < A.x)
+  const int32_t c0 = (a0 < 0 || (a0 == 0 && b0 < 0)) ? 0 : 1;   // edge v1 -> v2
+  const int32_t c1 = (a1 < 0 || (a1 == 0 && b1 < 0)) ? 0 : 1;   // edge v2 -> v0
+  const int32_t c2 = (a2 < 0 || (a2 == 0 && b2 < 0)) ? 0 : 1;   // edge v0 -> v1
+  const float fa = (float)area;
+  const int32_t sx0 = 256 * i_lo + 128;
+  for (int j = j_lo; j <= j_hi; ++j) {
+    const int32_t sy = 256 * j + 128;
+    int32_t w0 = a0 * (sx0 - x1) + b0 * (sy - y1) - c0;
+    int32_t w1 = a1 * (sx0 - x2) + b1 * (sy - y2) - c1;
+    int32_t w2 = a2 * (sx0 - x0) + b2 * (sy - y0) - c2;
+    unsigned long long* row = zb + j * res;
+    for (int i = i_lo; i <= i_hi; ++i) {
+      if ((w0 | w1 | w2) >= 0) {
+        const float bz = fmaf((float)(w2 + c2), z2, fmaf((float)(w1 + c1), z1,
+                                                        (float)(w0 + c0) * z0)) / fa;
+        atomicMin(&row[i], depth_key(bz, f));
+      }
+      w0 += 256 * a0;
+      w1 += 256 * a1;
+      w2 += 256 * a2;
+    }
+  }
 }
 
 // frame[0..2] = centre, frame[3] = rho of the posed mesh's bounding box
@@ -123,46 +225,12 @@ raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __
     const int i0 = rga::clampi(faces[3 * f], 0, nv - 1);
     const int i1 = rga::clampi(faces[3 * f + 1], 0, nv - 1);
     const int i2 = rga::clampi(faces[3 * f + 2], 0, nv - 1);
-    int64_t x0, y0, x1, y1, x2, y2;
+    int32_t x0, y0, x1, y1, x2, y2;
     float z0, z1, z2;
     project(P, verts, nv, i0, x0, y0, z0);
     project(P, verts, nv, i1, x1, y1, z1);
     project(P, verts, nv, i2, x2, y2, z2);
-    int64_t area = edge(x0, y0, x1, y1, x2, y2);
-    if (area == 0) continue;
-    if (area < 0) {
-      int64_t tx = x1, ty = y1;
-      x1 = x2; y1 = y2; x2 = tx; y2 = ty;
-      float tz = z1; z1 = z2; z2 = tz;
-      area = -area;
-    }
-    int64_t mnx = min(x0, min(x1, x2)), mxx = max(x0, max(x1, x2));
-    int64_t mny = min(y0, min(y1, y2)), mxy = max(y0, max(y1, y2));
-    int64_t i_lo = -fdiv(-(mnx - 128), 256), i_hi = fdiv(mxx - 128, 256);
-    int64_t j_lo = -fdiv(-(mny - 128), 256), j_hi = fdiv(mxy - 128, 256);
-    if (i_lo < 0) i_lo = 0;
-    if (j_lo < 0) j_lo = 0;
-    if (i_hi > res - 1) i_hi = res - 1;
-    if (j_hi > res - 1) j_hi = res - 1;
-    const bool o12 = owns(x1, y1, x2, y2), o20 = owns(x2, y2, x0, y0), o01 = owns(x0, y0, x1, y1);
-    const float fa = (float)area;
-    for (int64_t j = j_lo; j <= j_hi; ++j) {
-      const int64_t sy = 256 * j + 128;
-      for (int64_t i = i_lo; i <= i_hi; ++i) {
-        const int64_t sx = 256 * i + 128;
-        const int64_t w0 = edge(x1, y1, x2, y2, sx, sy);
-        const int64_t w1 = edge(x2, y2, x0, y0, sx, sy);
-        const int64_t w2 = edge(x0, y0, x1, y1, sx, sy);
-        const bool in0 = w0 > 0 || (w0 == 0 && o12);
-        const bool in1 = w1 > 0 || (w1 == 0 && o20);
-        const bool in2 = w2 > 0 || (w2 == 0 && o01);
-        if (!(in0 && in1 && in2)) continue;
-        const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) / fa;
-        const unsigned long long key =
-            ((unsigned long long)__float_as_uint(bz) << 32) | (unsigned long long)(uint32_t)f;
-        atomicMin(&zb[j * res + i], key);
-      }
-    }
+    raster_tri(zb, res, f, x0, y0, z0, x1, y1, z1, x2, y2, z2);
   }
   __syncthreads();
   for (int p = threadIdx.x; p < res * res; p += blockDim.x) {

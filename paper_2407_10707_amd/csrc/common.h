@@ -60,6 +60,26 @@ __device__ inline float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Sums of N values over each row of 16 lanes, in place: DPP row shifts
+// build per-row prefix sums, so lane 15 of each row ends with that row's
+// totals.  The N chains are interleaved step by step so that no DPP read
+// has to wait for the write just before it.  All 64 lanes must be active.
+template <int N>
+__device__ inline void row_sums(float (&v)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x111, 0xf, 0xf, true));
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x112, 0xf, 0xf, true));
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x114, 0xf, 0xf, true));
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x118, 0xf, 0xf, true));
+}
+
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 }  // namespace rga

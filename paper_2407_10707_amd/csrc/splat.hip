@@ -779,7 +779,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
                  float* __restrict__ dopac, float* __restrict__ dcolor) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   __shared__ uint32_t sg[kChunk];
-  __shared__ float acc[9][kChunk];
+  __shared__ float acc[4][9][kChunk];   // per lane row (16 pixels) of every wave
   const int64_t nitems = min(counters[1], max_items);
   const int b = blockIdx.x;
   if (b >= nitems) return;
@@ -798,7 +798,9 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     s2[threadIdx.x] = rec[3 * g + 2];
   }
 #pragma unroll
-  for (int q = 0; q < 9; ++q) acc[q][threadIdx.x] = 0.f;
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[r][q][threadIdx.x] = 0.f;
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
   float T = code <= -2.f ? -code - 2.f : code;
@@ -830,7 +832,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
       A0 = fmaf(c1.z, w, A0);
       A1 = fmaf(c1.w, w, A1);
       A2 = fmaf(col2, w, A2);
-      const float inv1m = 1.f / (1.f - alpha);
+      const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
       const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
                         g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
                         g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
@@ -846,11 +848,11 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
       v[6] = w * g0;                                // d/d colour
       v[7] = w * g1;
       v[8] = w * g2;
+      rga::row_sums(v);
+      if ((lane & 15) == 15) {
+        float* dst = &acc[lane >> 4][0][k];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) v[q] = rga::wave_sum(v[q]);
-      if (lane == 0) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) atomicAdd(&acc[q][k], v[q]);
+        for (int q = 0; q < 9; ++q) atomicAdd(dst + q * kChunk, v[q]);
       }
     }
   }
@@ -862,7 +864,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     bool nz = false;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      sum[q] = acc[q][k];
+      sum[q] = (acc[0][q][k] + acc[1][q][k]) + (acc[2][q][k] + acc[3][q][k]);
       nz |= sum[q] != 0.f;
     }
     if (nz) {

@@ -21,6 +21,8 @@
 // lanes that share a digit) and mbcnt-style lane masks.
 #include "common.h"
 
+#include <algorithm>
+
 #include <math.h>
 
 namespace {
@@ -35,7 +37,7 @@ constexpr int kChunk = 256;      // splats per blend work item
 
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
-  size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, grad;
+  size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, queue, grad;
   size_t item_off, item_tile, item_chunk, cstate, total;
   int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
   int64_t max_items;
@@ -82,7 +84,8 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.bintot = take(256 * 4);
   L.bsum = take((size_t)L.nb_n * 4);
   L.boff = take((size_t)L.nb_n * 4);
-  L.count = take(16);
+  L.count = take(16);   // int64 [0] = D, [1] = work items
+  L.queue = take(4);    // item queue of the blend adjoint (a line of its own)
   L.grad = take(N * 5 * 4);
   L.max_items = rga::ceil_div(cap > 0 ? cap : 1, kChunk) + tiles;
   L.item_off = take(((size_t)tiles + 1) * 4);
@@ -607,6 +610,20 @@ chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __re
   }
 }
 
+// The blend passes run a grid of as many workgroups as fit on the device at
+// once (the item count lives on the device, so the grid cannot be sized to
+// it without a host sync).  The forward passes take items i, i + grid, ...;
+// the adjoint, whose items vary more in cost and which fits fewer
+// workgroups per CU, takes the next item from a queue with one atomic
+// (no workgroup ever waits for another).  The queue counter is zeroed on
+// the stream before the launch.
+__device__ inline int next_item(uint32_t* queue, int* slot) {
+  __syncthreads();                // every thread is done with the last item
+  if (threadIdx.x == 0) *slot = (int)atomicAdd(queue, 1u);
+  __syncthreads();
+  return *slot;
+}
+
 __global__ void __launch_bounds__(256)
 blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                    const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
@@ -615,8 +632,8 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                    float* __restrict__ cstate) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   const int64_t nitems = min(counters[1], max_items);
-  const int b = blockIdx.x;
-  if (b >= nitems) return;
+  for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
+  __syncthreads();                        // the previous item's records are done
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
@@ -651,14 +668,18 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   st[threadIdx.x] = C0;
   st[256 + threadIdx.x] = C1;
   st[512 + threadIdx.x] = C2;
-  st[768 + threadIdx.x] = sat ? -1.f : T;
+  st[768 + threadIdx.x] = sat ? -(T + 2.f) : T;   // T >= 1e-4 at a stop
+  }
 }
 
 // Prefix pass, one workgroup per tile, no splat is touched: per pixel, walk
 // the tile's chunk results front to back, leave for every chunk the colour
 // before it and its incoming transmittance, find the chunk that may contain
 // the stop (saturated, or T_in * T_chunk < 1e-4) and mark it; chunks past it
-// are marked -1.  Pixels that never stop get their final colour here.
+// are marked -1.  Pixels that never stop get their final colour here, and
+// so do pixels that stop in the tile's first chunk: that chunk was walked
+// from the true incoming T = 1, so its result is already exact.  The chunk
+// pass leaves T (>= 0) or, where it stopped, -(T at the stop + 2).
 // State code per (chunk, pixel) in the fourth plane: T_in >= 0 (whole chunk
 // used), -1 (past the stop), -(T_in + 2) (the chunk where the walk stops).
 __global__ void __launch_bounds__(256)
@@ -686,7 +707,14 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
     }
     if (Tj < 0.f || Tin * Tj < 1e-4f) {
       st[768 + threadIdx.x] = -(Tin + 2.f);
-      active = false;          // the restart pass finishes this pixel
+      active = false;
+      if (j == 0 && Tj < 0.f && inside) {   // exact already; else the restart pass
+        const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
+        image[p] = Cj0;
+        image[HW + p] = Cj1;
+        image[2 * HW + p] = Cj2;
+        Tfinal[p] = -Tj - 2.f;
+      }
       continue;
     }
     st[768 + threadIdx.x] = Tin;
@@ -704,9 +732,9 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
   }
 }
 
-// Restart pass, one workgroup per work item, in parallel: pixels whose walk
-// stops in this chunk re-walk it from T_in with the exact stop rule and
-// write their final colour and transmittance.  (A pixel whose stop test
+// Restart pass, one workgroup per work item after a tile's first, in
+// parallel: pixels whose walk stops in this chunk re-walk it from T_in with
+// the exact stop rule and write their final colour and transmittance.  (A pixel whose stop test
 // does not fire here because of rounding keeps the chunk's end state.)
 __global__ void __launch_bounds__(256)
 blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
@@ -717,12 +745,13 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                      float* __restrict__ Tfinal) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   const int64_t nitems = min(counters[1], max_items);
-  const int b = blockIdx.x;
-  if (b >= nitems) return;
+  for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
+  __syncthreads();                        // the previous item's records are done
+  if (item_chunk[b] == 0) continue;        // finished by the prefix pass
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
   const bool mine = code <= -2.f;
-  if (!__syncthreads_or(mine)) return;
+  if (!__syncthreads_or(mine)) continue;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
@@ -735,7 +764,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
     s2[threadIdx.x] = rec[3 * g + 2];
   }
   __syncthreads();
-  if (!mine || !(px < W && py < H)) return;
+  if (!mine || !(px < W && py < H)) continue;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float T = -code - 2.f;
   float C0 = st[threadIdx.x], C1 = st[256 + threadIdx.x], C2 = st[512 + threadIdx.x];
@@ -757,6 +786,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   image[HW + p] = C1;
   image[2 * HW + p] = C2;
   Tfinal[p] = T;
+  }
 }
 
 // ---- adjoint: blend ----------------------------------------------------------
@@ -774,15 +804,18 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
                  const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
                  const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                  const int64_t* __restrict__ counters, int64_t max_items,
-                 const float* __restrict__ cstate, const float* __restrict__ image,
-                 const float* __restrict__ dimage, float* __restrict__ gmean_conic /*[5][n]*/,
-                 float* __restrict__ dopac, float* __restrict__ dcolor) {
+                 uint32_t* __restrict__ queue, const float* __restrict__ cstate,
+                 const float* __restrict__ image, const float* __restrict__ dimage,
+                 float* __restrict__ gmean_conic /*[5][n]*/, float* __restrict__ dopac,
+                 float* __restrict__ dcolor) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   __shared__ uint32_t sg[kChunk];
   __shared__ float acc[4][9][kChunk];   // per lane row (16 pixels) of every wave
+  __shared__ int slot;
   const int64_t nitems = min(counters[1], max_items);
-  const int b = blockIdx.x;
-  if (b >= nitems) return;
+  for (;;) {
+  const int b = next_item(queue, &slot);
+  if (b >= nitems) break;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int lane = threadIdx.x & 63;
@@ -875,6 +908,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
       atomicAdd(&dcolor[(size_t)n + g], sum[7]);
       atomicAdd(&dcolor[(size_t)2 * n + g], sum[8]);
     }
+  }
   }
 }
 
@@ -1007,11 +1041,31 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
 
 __global__ void __launch_bounds__(256)
 zero_f32(float* __restrict__ a, int64_t na, float* __restrict__ b, int64_t nb,
-         float* __restrict__ c, int64_t nc) {
+         float* __restrict__ c, int64_t nc, uint32_t* __restrict__ queue) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *queue = 0u;
   if (i < na) a[i] = 0.f;
   if (i < nb) b[i] = 0.f;
   if (i < nc) c[i] = 0.f;
+}
+
+// Workgroups of a 256-thread blend kernel that fit on the current device at
+// once (the grid of the grid-stride blend passes), cached per device.
+template <int K>
+int resident_groups(const void* kernel) {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0) != hipSuccess ||
+        per < 1)
+      per = 1;
+    cache[dev] = (cus > 0 ? cus : 1) * per;
+  }
+  return cache[dev];
 }
 
 int check_common(const char* fn, int n, const rga_camera* cam, const void* ws, size_t ws_bytes,
@@ -1152,12 +1206,16 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
              at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), L.max_items, cnt);
-  RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(L.max_items), dim3(256), 0, s, W, H, L.tiles_x,
+  const int64_t g_chunk =
+      std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
+  const int64_t g_restart =
+      std::min<int64_t>(L.max_items, resident_groups<1>((const void*)blend_restart_kernel));
+  RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(g_chunk), dim3(256), 0, s, W, H, L.tiles_x,
              ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate));
   RGA_LAUNCH("blend_prefix", blend_prefix_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
              at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final);
-  RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(L.max_items), dim3(256), 0, s, W, H,
+  RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(g_restart), dim3(256), 0, s, W, H,
              L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate), image,
              T_final);
@@ -1183,14 +1241,17 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
   const CamDev cd = to_dev(cam);
   float* gmc = at<float>(ws, L.grad);
   const int64_t nz = 5 * (int64_t)n;
+  uint32_t* queue = at<uint32_t>(ws, L.queue);
   RGA_LAUNCH("splat_zero", zero_f32, dim3(rga::ceil_div(nz, 256)), dim3(256), 0, s, gmc, nz, dopac,
-             (int64_t)n, dcolor, 3 * (int64_t)n);
+             (int64_t)n, dcolor, 3 * (int64_t)n, queue);
+  const int64_t g_bwd =
+      std::min<int64_t>(L.max_items, resident_groups<2>((const void*)blend_bwd_kernel));
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
-  RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(L.max_items), dim3(256), 0, s, cam->width,
+  RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(g_bwd), dim3(256), 0, s, cam->width,
              cam->height, L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec),
              at<uint32_t>(ws, L.item_tile), at<uint32_t>(ws, L.item_chunk),
-             at<int64_t>(ws, L.count), L.max_items, at<float>(ws, L.cstate), image, dimage, gmc,
-             dopac, dcolor);
+             at<int64_t>(ws, L.count), L.max_items, queue, at<float>(ws, L.cstate), image,
+             dimage, gmc, dopac, dcolor);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
              n, cd, x, A, quat, log_s, opac, front, gmc, dx, dquat, dlog_s);
   RGA_CHECK_LAUNCH("splat_backward");

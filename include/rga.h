@@ -125,7 +125,11 @@ int mesh_visibility(void* stream, int nv, int nf, const float* verts, const int3
  *            (r, c) uses view (r*hv/he)*wv + c*wv/we
  * cam_pos    host float[3], camera centre in world space
  * precision  RGA_FP32 or RGA_BF16X3
- * color      [3][n] out;  front [n] uint8 out                               */
+ * color      [3][n] out;  front [n] uint8 out
+ * Limits (RGA_EUNSUPPORTED otherwise): V % 16 == 0 and V <= 2048; hv | he
+ * and wv | we; he*we <= 3584 directions.  RGA_BF16X3 also needs he*we % 32
+ * == 0, one or two texels per view (hv == he, we == wv or we == 2 wv), and
+ * at most 2432 directions in the adjoint (its LDS tables).                  */
 int shade_gaussians(void* stream, int n, const float* x, const float* nrm, const float* albedo,
                     const float* rough, const float* tint, const int32_t* vidx, const float* vw,
                     const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,

@@ -165,17 +165,24 @@ def splat_bin(cam, pre):
     return keys[:D], vals[:D], ranges
 
 
-def composite_tiles(cam, ranges, values, pre, opac, color):
+def composite_tiles(cam, ranges, values, pre, opac, color, with_applied=False):
+    """Tiled FP32-mirror compositing: image [3][H][W], T_final, the smallest
+    relative decision margin per pixel and, if asked, the number of splats
+    composited into each pixel."""
     H, W = cam.height, cam.width
     tx, _ = tiles_of(cam)
     n = pre["mean2d"].shape[1]
     img = np.empty((3, H, W), np.float32)
     T = np.empty((H, W), np.float32)
     margin = np.empty((H, W), np.float32)
+    applied = np.empty((H, W), np.int32)
     vals = _i(values) if len(values) else np.zeros(1, np.int32)
     lib().oracle_composite_tiles_f32(C.c_int(H), C.c_int(W), C.c_int(tx), _p(_i(ranges)),
                                      _p(vals), C.c_int(n), _p(pre["mean2d"]), _p(pre["conic"]),
-                                     _p(_f(opac)), _p(_f(color)), _p(img), _p(T), _p(margin))
+                                     _p(_f(opac)), _p(_f(color)), _p(img), _p(T), _p(margin),
+                                     _p(applied))
+    if with_applied:
+        return img, T, margin, applied
     return img, T, margin
 
 

@@ -599,8 +599,9 @@ int64_t oracle_splat_bin(int n, int tiles_x, int tiles_y, const int32_t* rect,
 static void composite_pixel(float px, float py, const int32_t* list, int64_t len,
                             const float* mean2d, const float* conic, const float* opac,
                             const float* color, int n, float* out_c, float* out_T,
-                            float* out_margin) {
+                            float* out_margin, int32_t* out_applied) {
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, margin = INFINITY;
+  int32_t applied = 0;
   for (int64_t e = 0; e < len; ++e) {
     const int g = list[e];
     const float dx = mean2d[g] - px, dy = mean2d[n + g] - py;
@@ -627,6 +628,7 @@ static void composite_pixel(float px, float py, const int32_t* list, int64_t len
     C0 = fmaf(color[g], w, C0);
     C1 = fmaf(color[n + g], w, C1);
     C2 = fmaf(color[2 * n + g], w, C2);
+    ++applied;
     T = Tn;
   }
   out_c[0] = C0;
@@ -634,25 +636,29 @@ static void composite_pixel(float px, float py, const int32_t* list, int64_t len
   out_c[2] = C2;
   *out_T = T;
   if (out_margin) *out_margin = margin;
+  if (out_applied) *out_applied = applied;
 }
 
 /* Tiled compositing: each pixel walks the sorted list of its 16x16 tile.
- * image [3][H][W], T_final [H][W], margin [H][W] (may be NULL).           */
+ * image [3][H][W], T_final [H][W], margin [H][W] and applied [H][W] (the
+ * number of splats composited into the pixel) may be NULL.                */
 void oracle_composite_tiles_f32(int H, int W, int tiles_x, const int32_t* ranges,
                                 const int32_t* values, int n, const float* mean2d,
                                 const float* conic, const float* opac, const float* color,
-                                float* image, float* T_final, float* margin) {
+                                float* image, float* T_final, float* margin, int32_t* applied) {
 #pragma omp parallel for schedule(dynamic, 4)
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
       const int t = (y / 16) * tiles_x + (x / 16);
       float c[3], T, m;
+      int32_t na;
       composite_pixel((float)x + 0.5f, (float)y + 0.5f, values + ranges[2 * t],
                       (int64_t)ranges[2 * t + 1] - ranges[2 * t], mean2d, conic, opac, color, n,
-                      c, &T, &m);
+                      c, &T, &m, &na);
       for (int ch = 0; ch < 3; ++ch) image[(size_t)ch * H * W + (size_t)y * W + x] = c[ch];
       T_final[(size_t)y * W + x] = T;
       if (margin) margin[(size_t)y * W + x] = m;
+      if (applied) applied[(size_t)y * W + x] = na;
     }
 }
 
@@ -689,7 +695,7 @@ void oracle_composite_brute_f32(int H, int W, int n, const uint8_t* valid, const
     for (int x = 0; x < W; ++x) {
       float c[3], T;
       composite_pixel((float)x + 0.5f, (float)y + 0.5f, list, m, mean2d, conic, opac, color, n,
-                      c, &T, NULL);
+                      c, &T, NULL, NULL);
       for (int ch = 0; ch < 3; ++ch) image[(size_t)ch * H * W + (size_t)y * W + x] = c[ch];
       T_final[(size_t)y * W + x] = T;
     }

@@ -325,18 +325,28 @@ constexpr int kMWaves = 4;
 constexpr int kMThreads = kMWaves * 64;
 
 // LDS: dir x,y,z | E r,g,b | view (int) [K each], then B [16 cols][K] bf16
+// B operand of the shading contraction in LDS, [6 columns][K] bf16:
+// columns 0-2 the high parts of E (r, g, b), 3-5 the low parts.  The other
+// ten columns of the 16-wide MFMA operand are zero and never stored.
 __device__ inline void build_btab(const float* tab, int K, __bf16* bt) {
-  for (int i = threadIdx.x; i < 16 * K; i += blockDim.x) {
+  for (int i = threadIdx.x; i < 6 * K; i += blockDim.x) {
     const int col = i / K, k = i - col * K;
     float v = 0.f;
     if (col < 3) {
       v = (float)(__bf16)tab[(3 + col) * K + k];
-    } else if (col < 6) {
+    } else {
       const float e = tab[(3 + col - 3) * K + k];
       v = e - (float)(__bf16)e;
     }
     bt[i] = (__bf16)v;
   }
+}
+
+// 8 consecutive k of column `col` of the B operand (zero for col >= 6).
+__device__ inline bf16x8 btab_load(const __bf16* bt, int K, int col, int kb) {
+  const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (size_t)min(col, 5) * K + kb);
+  const bf16x8 z = {};
+  return col < 6 ? b : z;
 }
 
 // visibility bytes of 8 consecutive directions k..k+7 (k % 8 == 0, same
@@ -365,7 +375,7 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
   extern __shared__ __align__(16) float tab[];
   const int K = a.K, n = a.n, V = a.V;
   __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
-  float* stage = reinterpret_cast<float*>(bt + 16 * K) + (threadIdx.x >> 6) * 512;
+  float* stage = reinterpret_cast<float*>(bt + 6 * K) + (threadIdx.x >> 6) * 512;
   build_table(a, tab, 0);
   __syncthreads();
   build_btab(tab, K, bt);
@@ -411,7 +421,7 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
         sh[i] = hs;
         sl[i] = (__bf16)(Ws - (float)hs);
       }
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (size_t)row * K + kb);
+      const bf16x8 b = btab_load(bt, K, row, kb);
       accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, b, accD, 0, 0, 0);
       accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl, b, accD, 0, 0, 0);
       accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, b, accS, 0, 0, 0);
@@ -518,7 +528,7 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
   extern __shared__ __align__(16) float tab[];
   const int K = a.K, n = a.n, V = a.V;
   __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
-  float* denv_lds = reinterpret_cast<float*>(bt + 16 * K);
+  float* denv_lds = reinterpret_cast<float*>(bt + 6 * K);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // per-wave scratch: W^T stage (4 x [32 k][16 g] bf16 = 4 KB), Q (16 x 6 f32),
   // per-Gaussian sums (2 x 256 f32)
@@ -623,7 +633,7 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
         wt[2 * 512 + kl * 16 + row] = sh[i];
         wt[3 * 512 + kl * 16 + row] = sl[i];
       }
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (size_t)row * K + kb);
+      const bf16x8 b = btab_load(bt, K, row, kb);
       accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, b, accD, 0, 0, 0);
       accD = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl, b, accD, 0, 0, 0);
       accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, b, accS, 0, 0, 0);
@@ -957,7 +967,7 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
-    const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)16 * a.K * 2 + kMWaves * 512 * 4;
+    const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)6 * a.K * 2 + kMWaves * 512 * 4;
     static bool mattr = false;
     if (!mattr) {
       hipFuncSetAttribute(reinterpret_cast<const void*>(shade_fwd_mfma_kernel),
@@ -1023,7 +1033,7 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
-    const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)16 * a.K * 2 +
+    const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)6 * a.K * 2 +
                        (size_t)kMWaves * (4096 + 384 + 2048);
     if (lds > 150 * 1024)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: too many directions");

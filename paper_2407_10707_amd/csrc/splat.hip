@@ -543,8 +543,12 @@ tile_ranges_kernel(const uint32_t* __restrict__ tkeys, const int64_t* cnt_ptr, i
 // keeps T_in * T_chunk >= 1e-4 cannot contain the stop (T is monotone), so
 // it contributes T_in * C_chunk; the first chunk that may contain the stop
 // is re-walked sequentially from T_in with the exact stop rule.  The
-// combine leaves (C before the chunk, T_in) per (chunk, pixel) for the
-// adjoint, and T_in = -1 for chunks past the stop.
+// combine leaves (C before the chunk, a code for T_in) per (chunk, pixel)
+// for the adjoint.  The codes only flip signs, so T_in comes back exactly:
+//   code >= 0          whole chunk used, T_in = code
+//   -1 <= code < 0     the chunk where the walk stops, T_in = -code
+//   code = kPastStop   chunk past the stop
+constexpr float kPastStop = -2.f;
 
 // One front-to-back compositing step for the pixel centre (px, py), written
 // with selects instead of divergent branches: an entry is skipped when its
@@ -668,7 +672,7 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   st[threadIdx.x] = C0;
   st[256 + threadIdx.x] = C1;
   st[512 + threadIdx.x] = C2;
-  st[768 + threadIdx.x] = sat ? -(T + 2.f) : T;   // T >= 1e-4 at a stop
+  st[768 + threadIdx.x] = sat ? -T : T;   // T >= 1e-4 > 0 at a stop
   }
 }
 
@@ -676,12 +680,11 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 // the tile's chunk results front to back, leave for every chunk the colour
 // before it and its incoming transmittance, find the chunk that may contain
 // the stop (saturated, or T_in * T_chunk < 1e-4) and mark it; chunks past it
-// are marked -1.  Pixels that never stop get their final colour here, and
-// so do pixels that stop in the tile's first chunk: that chunk was walked
-// from the true incoming T = 1, so its result is already exact.  The chunk
-// pass leaves T (>= 0) or, where it stopped, -(T at the stop + 2).
-// State code per (chunk, pixel) in the fourth plane: T_in >= 0 (whole chunk
-// used), -1 (past the stop), -(T_in + 2) (the chunk where the walk stops).
+// are marked past the stop.  Pixels that never stop get their final colour
+// here, and so do pixels that stop in the tile's first chunk: that chunk
+// was walked from the true incoming T = 1, so its result is already exact.
+// The chunk pass leaves T (>= 0) or, where it stopped, -(T at the stop).
+// The state codes it leaves are those described above.
 __global__ void __launch_bounds__(256)
 blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
                     float* __restrict__ cstate, int64_t max_items, float* __restrict__ image,
@@ -702,18 +705,18 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
     st[256 + threadIdx.x] = C1;
     st[512 + threadIdx.x] = C2;
     if (!active) {
-      st[768 + threadIdx.x] = -1.f;
+      st[768 + threadIdx.x] = kPastStop;
       continue;
     }
     if (Tj < 0.f || Tin * Tj < 1e-4f) {
-      st[768 + threadIdx.x] = -(Tin + 2.f);
+      st[768 + threadIdx.x] = -Tin;
       active = false;
       if (j == 0 && Tj < 0.f && inside) {   // exact already; else the restart pass
         const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
         image[p] = Cj0;
         image[HW + p] = Cj1;
         image[2 * HW + p] = Cj2;
-        Tfinal[p] = -Tj - 2.f;
+        Tfinal[p] = -Tj;
       }
       continue;
     }
@@ -750,7 +753,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   if (item_chunk[b] == 0) continue;        // finished by the prefix pass
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
-  const bool mine = code <= -2.f;
+  const bool mine = code < 0.f && code >= -1.f;
   if (!__syncthreads_or(mine)) continue;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
@@ -766,7 +769,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   __syncthreads();
   if (!mine || !(px < W && py < H)) continue;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-  float T = -code - 2.f;
+  float T = -code;
   float C0 = st[threadIdx.x], C1 = st[256 + threadIdx.x], C2 = st[512 + threadIdx.x];
   bool stopped = false;
   for (int k0 = 0; k0 < cnt && !stopped; k0 += 32) {
@@ -836,11 +839,11 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     for (int q = 0; q < 9; ++q) acc[r][q][threadIdx.x] = 0.f;
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
-  float T = code <= -2.f ? -code - 2.f : code;
+  float T = fabsf(code);
   float A0 = st[threadIdx.x], A1 = st[256 + threadIdx.x], A2 = st[512 + threadIdx.x];
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  bool done = !inside || code == -1.f;
+  bool done = !inside || code < -1.f;
   if (!done) {
     const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
     Cf0 = image[p];

@@ -223,6 +223,50 @@ def test_splat_forward_parity(name):
     print(f"  D={D} exempt={int((~ok).sum())}/{ok.size}", flush=True)
 
 
+def test_splat_deep_tiles_parity():
+    """Thousands of faint splats over a few tiles: lists span many 256-entry
+    chunks and most pixels stop in a later chunk with an incoming
+    transmittance near the 1e-4 stop, where the chunk combine and the
+    restart must carry T exactly.  Image and T_final against the FP32
+    mirror, with the tolerance and the decision exemption scaled by the
+    number of splats composited per pixel (chunked vs sequential rounding)."""
+    print("[splat] deep tiles", flush=True)
+    rng = np.random.default_rng(5)
+    cam = synth.default_camera(48, 32)
+    n = 4000
+    x = np.stack([rng.uniform(-1.7, 0.6, n), rng.uniform(-0.3, 1.2, n),
+                  rng.uniform(-0.2, 0.2, n)]).astype(np.float32)
+    A = np.tile(np.eye(3, dtype=np.float32).reshape(9, 1), (1, n))
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    log_s = rng.normal(-1.0, 0.2, (3, n)).astype(np.float32)
+    opac = rng.uniform(0.005, 0.03, n).astype(np.float32)
+    col = rng.random((3, n)).astype(np.float32)
+    front = np.ones(n, np.uint8)
+    ws = rga.SplatWorkspace(n, cam.width, cam.height, 8 * n, "cuda")
+    img, T = rga.splat_forward(cam, dev(x), dev(A), dev(q), dev(log_s), dev(opac), dev(col),
+                               dev(front), ws)
+    pre = cpu.splat_preprocess(cam, x, A, q, log_s, opac, front)
+    keys, vals, ranges = cpu.splat_bin(cam, pre)
+    eimg, eT, margin, napp = cpu.composite_tiles(cam, ranges, vals, pre, opac, col,
+                                                 with_applied=True)
+    assert ws.count() == len(keys)
+    st = ws.state()
+    assert np.array_equal(host(ws.view(st.sorted, (len(keys),), torch.int32)), vals)
+    lens = ranges[:, 1] - ranges[:, 0]
+    deep = int((napp > 300).sum())
+    print(f"  D={len(keys)} longest list {lens.max()} pixels past 300 splats {deep}", flush=True)
+    assert lens.max() > 4 * 256 and deep > 100
+    u = 2.0 ** -24
+    rel = 1e-5 + 8.0 * (napp + 2) * u
+    ok = margin > np.maximum(1e-4, rel)
+    gi, gT = host(img), host(T)
+    bad = (np.abs(gi - eimg) > rel[None] * np.abs(eimg) + 1e-6) & ok[None]
+    assert not bad.any(), int(bad.sum())
+    # T_final >= 1e-4 everywhere a walk stopped: compare relatively
+    badT = (np.abs(gT - eT) > rel * eT) & ok
+    assert not badT.any(), (int(badT.sum()), float(np.max(np.abs(gT - eT)[ok] / eT[ok])))
+
+
 def test_splat_empty_and_all_culled():
     cam = synth.default_camera(40, 24)
     ws = rga.SplatWorkspace(0, 40, 24, 16, "cuda")

@@ -62,18 +62,35 @@ struct Attr {
   int vidx[3];
 };
 
+// In the wave-per-Gaussian forward (UNI = true) one Gaussian's attributes
+// and derived constants are the same in every lane: they are pinned to
+// scalar registers, which lowers the vector register count enough for one
+// more wave per SIMD.  (The adjoint gains no occupancy from it and pays
+// the extra scalar-to-vector moves, so it keeps them in vector registers;
+// the MFMA kernels hold a different Gaussian per lane row.)
+__device__ inline float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <bool UNI, typename T>
+__device__ inline T pin(T v) {
+  if constexpr (UNI) return uni(v);
+  return v;
+}
+
+template <bool UNI>
 __device__ inline void attr_load(const ShadeArgs& a, int g, Attr& A) {
   const int n = a.n, nvm = a.nv - 1;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    A.x[c] = a.x[(size_t)c * n + g];
-    A.m[c] = a.nrm[(size_t)c * n + g];
-    A.alb[c] = a.albedo[(size_t)c * n + g];
-    A.vw[c] = a.vw[(size_t)c * n + g];
-    A.vidx[c] = rga::clampi(a.vidx[(size_t)c * n + g], 0, nvm);
+    A.x[c] = pin<UNI>(a.x[(size_t)c * n + g]);
+    A.m[c] = pin<UNI>(a.nrm[(size_t)c * n + g]);
+    A.alb[c] = pin<UNI>(a.albedo[(size_t)c * n + g]);
+    A.vw[c] = pin<UNI>(a.vw[(size_t)c * n + g]);
+    A.vidx[c] = pin<UNI>(rga::clampi(a.vidx[(size_t)c * n + g], 0, nvm));
   }
-  A.rough = a.rough[g];
-  A.tint = a.tint[g];
+  A.rough = pin<UNI>(a.rough[g]);
+  A.tint = pin<UNI>(a.tint[g]);
 }
 
 // The three visibility-count rows of a Gaussian (3 V bytes, V % 16 == 0) are
@@ -116,6 +133,7 @@ struct GaussCtx {
   bool front;
 };
 
+template <bool UNI>
 __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint8_t* rows,
                                    GaussCtx& G) {
   const float m0 = A.m[0], m1 = A.m[1], m2 = A.m[2];
@@ -143,6 +161,24 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
   G.u1 = A.vw[1] * ikv;
   G.u2 = A.vw[2] * ikv;
   G.rows = rows;
+  if constexpr (UNI) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      G.nn[c] = uni(G.nn[c]);
+      G.wo[c] = uni(G.wo[c]);
+    }
+    G.co = uni(G.co);
+    G.a2 = uni(G.a2);
+    G.kG = uni(G.kG);
+    G.Go = uni(G.Go);
+    G.inn = uni(G.inn);
+    G.iwo = uni(G.iwo);
+    G.alpha = uni(G.alpha);
+    G.gamma = uni(G.gamma);
+    G.u0 = uni(G.u0);
+    G.u1 = uni(G.u1);
+    G.u2 = uni(G.u2);
+  }
 }
 
 // Live-direction test for direction k; returns the visibility (0 if dead).
@@ -197,8 +233,24 @@ __device__ inline void pair_eval(const GaussCtx& G, const float* tab, int K, int
   P.Wd = v * P.ci;
 }
 
+// x^p for x > 0 (normal) as 2^(p log2 x) on the transcendental unit: a
+// few ulp, where the library powf spends ~180 instructions on special
+// cases that cannot occur here.
+__device__ inline float pos_pow(float x, float p) {
+  return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x));
+}
+
+// sRGB transfer curve (gamma correction of L_o)
 __device__ inline float srgb(float L) {
-  return L <= 0.0031308f ? 12.92f * L : 1.055f * powf(L, 1.f / 2.4f) - 0.055f;
+  return L <= 0.0031308f ? 12.92f * L : 1.055f * pos_pow(L, 1.f / 2.4f) - 0.055f;
+}
+
+// dL/dL_o from dL/dcolour, with L_o recovered from the colour by inverting
+// the transfer curve
+__device__ inline float srgb_adjoint(float col, float dc) {
+  if (col <= 0.04045f) return dc * 12.92f;
+  const float Lo = pos_pow((col + 0.055f) / 1.055f, 2.4f);
+  return dc * (col + 0.055f) / (2.4f * Lo);
 }
 
 __device__ inline void wave_fence() {
@@ -224,7 +276,7 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   Attr A;
   int cur = 0;
   if (g < n) {
-    attr_load(a, g, A);
+    attr_load<true>(a, g, A);
     rows_dma<NQ>(a, A, rows0, lane);
   }
   wait_all();
@@ -235,11 +287,11 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
     // fetch the next Gaussian's inputs while this one is shaded
     Attr An;
     if (gn < n) {
-      attr_load(a, gn, An);
+      attr_load<true>(a, gn, An);
       rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
     }
     GaussCtx G;
-    gauss_setup(a, A, rows, G);
+    gauss_setup<true>(a, A, rows, G);
     if (!G.front) {
       if (lane < 3) color[(size_t)lane * n + g] = 0.f;
       if (lane == 0) front[g] = 0;
@@ -388,9 +440,9 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
     const int g = tile * 16 + row;
     const bool have = g < n;
     Attr A;
-    attr_load(a, have ? g : n - 1, A);
+    attr_load<false>(a, have ? g : n - 1, A);
     GaussCtx G;
-    gauss_setup(a, A, nullptr, G);
+    gauss_setup<false>(a, A, nullptr, G);
     const bool on = have && G.front;
     const uint8_t* r0 = a.count + (size_t)A.vidx[0] * V;
     const uint8_t* r1 = a.count + (size_t)A.vidx[1] * V;
@@ -549,21 +601,16 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
     const bool have = g < n;
     const int gc = have ? g : n - 1;
     Attr A;
-    attr_load(a, gc, A);
+    attr_load<false>(a, gc, A);
     GaussCtx G;
-    gauss_setup(a, A, nullptr, G);
+    gauss_setup<false>(a, A, nullptr, G);
     const bool on = have && G.front;
     float dLo[3], aop[3], qd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float col = color[(size_t)c * n + gc];
       const float dc = on ? dcolor[(size_t)c * n + gc] : 0.f;
-      if (col <= 0.04045f) {
-        dLo[c] = dc * 12.92f;
-      } else {
-        const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
-        dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
-      }
+      dLo[c] = srgb_adjoint(col, dc);
       aop[c] = A.alb[c] * (1.f / kPi);
       qd[c] = dLo[c] * aop[c];
     }
@@ -733,7 +780,7 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   Attr A;
   int cur = 0;
   if (g < n) {
-    attr_load(a, g, A);
+    attr_load<false>(a, g, A);
     rows_dma<NQ>(a, A, rows0, lane);
   }
   wait_all();
@@ -744,11 +791,11 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
     // fetch the next Gaussian's inputs while this one is shaded
     Attr An;
     if (gn < n) {
-      attr_load(a, gn, An);
+      attr_load<false>(a, gn, An);
       rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
     }
     GaussCtx G;
-    gauss_setup(a, A, rows, G);
+    gauss_setup<false>(a, A, rows, G);
     if (!G.front) {
       if (lane < 3) {
         dn[(size_t)lane * n + g] = 0.f;
@@ -759,18 +806,17 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
         dtint[g] = 0.f;
       }
     } else {
-      // recover L_o from the colour and form dL/dL_o
+      // dL/dL_o: lane c < 3 takes channel c, every lane reads the three
       float dLo[3], aop[3], qd[3];
+      {
+        const int c = min(lane, 2);
+        const float d = srgb_adjoint(color[(size_t)c * n + g], dcolor[(size_t)c * n + g]);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          dLo[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), q));
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float col = color[(size_t)c * n + g];
-        const float dc = dcolor[(size_t)c * n + g];
-        if (col <= 0.04045f) {
-          dLo[c] = dc * 12.92f;
-        } else {
-          const float Lo = powf((col + 0.055f) / 1.055f, 2.4f);
-          dLo[c] = dc * (col + 0.055f) / (2.4f * Lo);
-        }
         aop[c] = A.alb[c] * (1.f / kPi);
         qd[c] = dLo[c] * aop[c];
       }

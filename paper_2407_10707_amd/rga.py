@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librga.so")
+# RGA_LIBRARY may name another build of the same library (same ABI)
+LIB_PATH = os.environ.get("RGA_LIBRARY") or os.path.join(_HERE, "librga.so")
 _lib = None
 
 RGA_FP32 = 0

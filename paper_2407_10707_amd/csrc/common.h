@@ -80,6 +80,23 @@ __device__ inline void row_sums(float (&v)[N]) {
     v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x118, 0xf, 0xf, true));
 }
 
+// Float add into LDS through an integer compare-and-swap loop.  On gfx950
+// the LDS float atomic add is several times slower than the integer atomic
+// path when a whole wave adds to distinct addresses; a compare-and-swap then
+// almost always succeeds at once.  (Where only a few lanes add and the
+// result is needed soon, the returned-value latency makes it the slower
+// choice.)  A failed swap means another lane's add landed first, so the
+// loop always finishes.
+__device__ inline void lds_add(float* p, float x) {
+  unsigned* u = reinterpret_cast<unsigned*>(p);
+  unsigned old = *u;
+  for (;;) {
+    const unsigned seen = old;
+    old = atomicCAS(u, seen, __float_as_uint(__uint_as_float(seen) + x));
+    if (old == seen) break;
+  }
+}
+
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 }  // namespace rga

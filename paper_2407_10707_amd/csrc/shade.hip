@@ -33,8 +33,11 @@ struct ShadeArgs {
   const uint8_t* count;
 };
 
-// Table layout in LDS: dir x,y,z | E r,g,b | view (int) | area, each [K].
-__device__ inline void build_table(const ShadeArgs& a, float* tab, int with_area) {
+// Table in LDS, two float4 per direction k: [k] = (direction x, y, z,
+// view index as int bits), [K + k] = (E = radiance x texel solid angle, r,
+// g, b, and the solid angle).  One 16-byte LDS read fetches either half.
+__device__ inline void build_table(const ShadeArgs& a, float* tab) {
+  float4* t4 = reinterpret_cast<float4*>(tab);
   const int K = a.K;
   const float dth = kPi / (float)a.he, dph = 2.f * kPi / (float)a.we;
   // exact solid angle of a texel row: (2 pi / we) * 2 sin(theta_r) sin(pi / (2 he))
@@ -45,18 +48,20 @@ __device__ inline void build_table(const ShadeArgs& a, float* tab, int with_area
     sincosf(((float)r + 0.5f) * dth, &st, &ct);
     sincosf(((float)c + 0.5f) * dph, &sp, &cp);
     const float area = band * st;
-    tab[k] = st * sp;
-    tab[K + k] = ct;
-    tab[2 * K + k] = st * cp;
-    tab[3 * K + k] = a.env[3 * k] * area;
-    tab[4 * K + k] = a.env[3 * k + 1] * area;
-    tab[5 * K + k] = a.env[3 * k + 2] * area;
-    reinterpret_cast<int*>(tab)[6 * K + k] = ((r * a.hv) / a.he) * a.wv + (c * a.wv) / a.we;
-    if (with_area) tab[7 * K + k] = area;
+    const int view = ((r * a.hv) / a.he) * a.wv + (c * a.wv) / a.we;
+    t4[k] = make_float4(st * sp, ct, st * cp, __int_as_float(view));
+    t4[K + k] = make_float4(a.env[3 * k] * area, a.env[3 * k + 1] * area,
+                            a.env[3 * k + 2] * area, area);
   }
 }
 
-// Per-Gaussian inputs, loaded one Gaussian ahead of its use.
+__device__ inline float4 dir_of(const float* tab, int k) {
+  return reinterpret_cast<const float4*>(tab)[k];
+}
+__device__ inline float4 rad_of(const float* tab, int K, int k) {
+  return reinterpret_cast<const float4*>(tab)[K + k];
+}
+
 struct Attr {
   float x[3], m[3], alb[3], rough, tint, vw[3];
   int vidx[3];
@@ -141,21 +146,21 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
   // back-face decision in FP32 with a fixed operation order
   const float dotf = fmaf(m2, w2, fmaf(m1, w1, m0 * w0));
   G.front = dotf > 0.f;
-  G.inn = 1.f / sqrtf(fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));
+  G.inn = rsq(fmaf(m2, m2, fmaf(m1, m1, m0 * m0)));
   G.nn[0] = m0 * G.inn;
   G.nn[1] = m1 * G.inn;
   G.nn[2] = m2 * G.inn;
-  G.iwo = 1.f / sqrtf(fmaf(w2, w2, fmaf(w1, w1, w0 * w0)));
+  G.iwo = rsq(fmaf(w2, w2, fmaf(w1, w1, w0 * w0)));
   G.wo[0] = w0 * G.iwo;
   G.wo[1] = w1 * G.iwo;
   G.wo[2] = w2 * G.iwo;
   G.co = fmaf(G.nn[2], G.wo[2], fmaf(G.nn[1], G.wo[1], G.nn[0] * G.wo[0]));
   G.gamma = A.rough;
   G.alpha = G.gamma * G.gamma;
-  G.ialpha = 1.f / G.alpha;
+  G.ialpha = rcp(G.alpha);
   G.a2 = G.alpha * G.alpha;
   G.kG = (G.gamma + 1.f) * (G.gamma + 1.f) * 0.125f;
-  G.Go = 1.f / fmaf(G.co, 1.f - G.kG, G.kG);
+  G.Go = rcp(fmaf(G.co, 1.f - G.kG, G.kG));
   const float ikv = 1.f / (float)a.kv;
   G.u0 = A.vw[0] * ikv;
   G.u1 = A.vw[1] * ikv;
@@ -183,10 +188,10 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
 
 // Live-direction test for direction k; returns the visibility (0 if dead).
 __device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int V, int k) {
-  const float d0 = tab[k], d1 = tab[K + k], d2 = tab[2 * K + k];
-  const float ci = fmaf(G.nn[2], d2, fmaf(G.nn[1], d1, G.nn[0] * d0));
+  const float4 dv = dir_of(tab, k);
+  const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
   if (!(ci > 0.f)) return 0.f;
-  const int view = reinterpret_cast<const int*>(tab)[6 * K + k];
+  const int view = __float_as_int(dv.w);
   const float c0 = (float)G.rows[view], c1 = (float)G.rows[V + view],
               c2 = (float)G.rows[2 * V + view];
   return fmaf(G.u2, c2, fmaf(G.u1, c1, G.u0 * c0));
@@ -202,12 +207,13 @@ struct Pair {
 // with h~ = w_k + w_o, which keeps its relative accuracy when nh -> 1.
 __device__ inline void pair_eval(const GaussCtx& G, const float* tab, int K, int k, float v,
                                  Pair& P) {
-  P.d[0] = tab[k];
-  P.d[1] = tab[K + k];
-  P.d[2] = tab[2 * K + k];
-  P.E[0] = tab[3 * K + k];
-  P.E[1] = tab[4 * K + k];
-  P.E[2] = tab[5 * K + k];
+  const float4 dv = dir_of(tab, k), er = rad_of(tab, K, k);
+  P.d[0] = dv.x;
+  P.d[1] = dv.y;
+  P.d[2] = dv.z;
+  P.E[0] = er.x;
+  P.E[1] = er.y;
+  P.E[2] = er.z;
   P.ci = fmaf(G.nn[2], P.d[2], fmaf(G.nn[1], P.d[1], G.nn[0] * P.d[0]));
   P.ok = fmaf(G.wo[2], P.d[2], fmaf(G.wo[1], P.d[1], G.wo[0] * P.d[0]));
   const float h0 = P.d[0] + G.wo[0], h1 = P.d[1] + G.wo[1], h2 = P.d[2] + G.wo[2];
@@ -265,11 +271,11 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   extern __shared__ __align__(16) float tab[];
   __shared__ int qk[kWaves][kRing];
   __shared__ float qv[kWaves][kRing];
-  build_table(a, tab, 0);
+  build_table(a, tab);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int K = a.K, n = a.n, V = a.V;
-  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 7 * K) + (size_t)wave * 6 * V;
+  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 8 * K) + (size_t)wave * 6 * V;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int stride = gridDim.x * kWaves;
   int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
@@ -281,9 +287,19 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   }
   wait_all();
   __syncthreads();
+  // each Gaussian's outputs are stored when the next one starts, so the
+  // wait for the next row copies at the end of an iteration never waits on
+  // a store issued just before
+  int og = -1;
+  float o_col = 0.f;
+  uint8_t o_front = 0;
   while (g < n) {
     const int gn = g + stride;
     uint8_t* rows = rows0 + cur * 3 * V;
+    if (og >= 0) {
+      if (lane < 3) color[(size_t)lane * n + og] = o_col;
+      if (lane == 0) front[og] = o_front;
+    }
     // fetch the next Gaussian's inputs while this one is shaded
     Attr An;
     if (gn < n) {
@@ -292,9 +308,10 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
     }
     GaussCtx G;
     gauss_setup<true>(a, A, rows, G);
+    og = g;
     if (!G.front) {
-      if (lane < 3) color[(size_t)lane * n + g] = 0.f;
-      if (lane == 0) front[g] = 0;
+      o_col = 0.f;
+      o_front = 0;
     } else {
       float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
       int head = 0, tail = 0;
@@ -350,15 +367,19 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
         const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
         const float alb = lane == 0 ? A.alb[0] : (lane == 1 ? A.alb[1] : A.alb[2]);
         const float Lo = alb * (1.f / kPi) * sd + A.tint * ss;
-        color[(size_t)lane * n + g] = srgb(Lo);
+        o_col = srgb(Lo);
       }
-      if (lane == 0) front[g] = 1;
+      o_front = 1;
     }
     wait_all();
     wave_fence();
     if (gn < n) A = An;
     cur ^= 1;
     g = gn;
+  }
+  if (og >= 0) {
+    if (lane < 3) color[(size_t)lane * n + og] = o_col;
+    if (lane == 0) front[og] = o_front;
   }
 }
 
@@ -384,12 +405,10 @@ __device__ inline void build_btab(const float* tab, int K, __bf16* bt) {
   for (int i = threadIdx.x; i < 6 * K; i += blockDim.x) {
     const int col = i / K, k = i - col * K;
     float v = 0.f;
-    if (col < 3) {
-      v = (float)(__bf16)tab[(3 + col) * K + k];
-    } else {
-      const float e = tab[(3 + col - 3) * K + k];
-      v = e - (float)(__bf16)e;
-    }
+    const float4 er = rad_of(tab, K, k);
+    const int cc = col < 3 ? col : col - 3;
+    const float e = cc == 0 ? er.x : (cc == 1 ? er.y : er.z);
+    v = col < 3 ? (float)(__bf16)e : e - (float)(__bf16)e;
     bt[i] = (__bf16)v;
   }
 }
@@ -402,22 +421,23 @@ __device__ inline bf16x8 btab_load(const __bf16* bt, int K, int col, int kb) {
 }
 
 // visibility bytes of 8 consecutive directions k..k+7 (k % 8 == 0, same
-// texel row) for one count row: identity view map or two texels per view
-__device__ inline void vis8(const uint8_t* row, const int* view, int k, int ratio, float* c) {
+// texel row) for one count row: identity view map (view = k), two texels
+// per view (view = k / 2), or the table's view indices
+__device__ inline void vis8(const uint8_t* row, const float* tab, int k, int ratio, float* c) {
   if (ratio == 1) {
-    const uint2 w = *reinterpret_cast<const uint2*>(row + view[k]);
+    const uint2 w = *reinterpret_cast<const uint2*>(row + k);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       c[i] = (float)((w.x >> (8 * i)) & 0xFFu);
       c[4 + i] = (float)((w.y >> (8 * i)) & 0xFFu);
     }
   } else if (ratio == 2) {
-    const uint32_t w = *reinterpret_cast<const uint32_t*>(row + view[k]);
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(row + (k >> 1));
 #pragma unroll
     for (int i = 0; i < 8; ++i) c[i] = (float)((w >> (8 * (i >> 1))) & 0xFFu);
   } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) c[i] = (float)row[view[k + i]];
+    for (int i = 0; i < 8; ++i) c[i] = (float)row[__float_as_int(dir_of(tab, k + i).w)];
   }
 }
 
@@ -426,15 +446,14 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
                       uint8_t* __restrict__ front) {
   extern __shared__ __align__(16) float tab[];
   const int K = a.K, n = a.n, V = a.V;
-  __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
+  __bf16* bt = reinterpret_cast<__bf16*>(tab + 8 * K);
   float* stage = reinterpret_cast<float*>(bt + 6 * K) + (threadIdx.x >> 6) * 512;
-  build_table(a, tab, 0);
+  build_table(a, tab);
   __syncthreads();
   build_btab(tab, K, bt);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, kg = lane >> 4;
-  const int* view = reinterpret_cast<const int*>(tab) + 6 * K;
   const int ntiles = (n + 15) / 16;
   for (int tile = blockIdx.x * kMWaves + wave; tile < ntiles; tile += gridDim.x * kMWaves) {
     const int g = tile * 16 + row;
@@ -451,15 +470,16 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kb = k0 + 8 * kg;
       float c0[8], c1[8], c2[8];
-      vis8(r0, view, kb, ratio, c0);
-      vis8(r1, view, kb, ratio, c1);
-      vis8(r2, view, kb, ratio, c2);
+      vis8(r0, tab, kb, ratio, c0);
+      vis8(r1, tab, kb, ratio, c1);
+      vis8(r2, tab, kb, ratio, c2);
       bf16x8 dh, dl, sh, sl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = kb + i;
         float Wd = 0.f, Ws = 0.f;
-        const float ci = fmaf(G.nn[2], tab[2 * K + k], fmaf(G.nn[1], tab[K + k], G.nn[0] * tab[k]));
+        const float4 dv = dir_of(tab, k);
+        const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
         const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
         if (on && ci > 0.f && v > 0.f) {
           Pair P;
@@ -555,9 +575,9 @@ __device__ inline void pair_bwd(const GaussCtx& G, const float* tab, float* denv
   acc.ts = fmaf(P.Ws, sE, acc.ts);
   // environment: dL/d(L_k,c A_k) = dLo_c (a_c/pi W_d + p W_s); the area
   // factor is applied when the per-workgroup sums are reduced
-  atomicAdd(&denv_lds[3 * k + 0], dLo[0] * fmaf(aop[0], P.Wd, tint * P.Ws));
-  atomicAdd(&denv_lds[3 * k + 1], dLo[1] * fmaf(aop[1], P.Wd, tint * P.Ws));
-  atomicAdd(&denv_lds[3 * k + 2], dLo[2] * fmaf(aop[2], P.Wd, tint * P.Ws));
+  rga::lds_add(&denv_lds[3 * k + 0], dLo[0] * fmaf(aop[0], P.Wd, tint * P.Ws));
+  rga::lds_add(&denv_lds[3 * k + 1], dLo[1] * fmaf(aop[1], P.Wd, tint * P.Ws));
+  rga::lds_add(&denv_lds[3 * k + 2], dLo[2] * fmaf(aop[2], P.Wd, tint * P.Ws));
   pair_grads(G, P, v, gWd, gWs, acc);
 }
 
@@ -579,7 +599,7 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
                       float* __restrict__ denv_part) {
   extern __shared__ __align__(16) float tab[];
   const int K = a.K, n = a.n, V = a.V;
-  __bf16* bt = reinterpret_cast<__bf16*>(tab + 7 * K);
+  __bf16* bt = reinterpret_cast<__bf16*>(tab + 8 * K);
   float* denv_lds = reinterpret_cast<float*>(bt + 6 * K);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   // per-wave scratch: W^T stage (4 x [32 k][16 g] bf16 = 4 KB), Q (16 x 6 f32),
@@ -588,13 +608,12 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
   __bf16* wt = reinterpret_cast<__bf16*>(wbase);
   float* qst = reinterpret_cast<float*>(wbase + 4096);
   float* stage = reinterpret_cast<float*>(wbase + 4096 + 384);
-  build_table(a, tab, 0);
+  build_table(a, tab);
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
   __syncthreads();
   build_btab(tab, K, bt);
   __syncthreads();
   const int row = lane & 15, kg = lane >> 4;
-  const int* view = reinterpret_cast<const int*>(tab) + 6 * K;
   const int ntiles = (n + 15) / 16;
   for (int tile = blockIdx.x * kMWaves + wave; tile < ntiles; tile += gridDim.x * kMWaves) {
     const int g = tile * 16 + row;
@@ -648,15 +667,16 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kb = k0 + 8 * kg;
       float c0[8], c1[8], c2[8];
-      vis8(r0, view, kb, ratio, c0);
-      vis8(r1, view, kb, ratio, c1);
-      vis8(r2, view, kb, ratio, c2);
+      vis8(r0, tab, kb, ratio, c0);
+      vis8(r1, tab, kb, ratio, c1);
+      vis8(r2, tab, kb, ratio, c2);
       bf16x8 dh, dl, sh, sl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = kb + i;
         float Wd = 0.f, Ws = 0.f;
-        const float ci = fmaf(G.nn[2], tab[2 * K + k], fmaf(G.nn[1], tab[K + k], G.nn[0] * tab[k]));
+        const float4 dv = dir_of(tab, k);
+        const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
         const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
         if (on && ci > 0.f && v > 0.f) {
           Pair P;
@@ -768,49 +788,74 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   __shared__ int qk[kWaves][kRing];
   __shared__ float qv[kWaves][kRing];
   const int K = a.K, n = a.n, V = a.V;
-  float* denv_lds = tab + 7 * K;
+  float* denv_lds = tab + 8 * K;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 10 * K) + (size_t)wave * 6 * V;
-  build_table(a, tab, 0);
+  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 11 * K) + (size_t)wave * 6 * V;
+  float* red = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(tab + 11 * K) +
+                                        (size_t)kWaves * 6 * V) + wave * 48;
+  build_table(a, tab);
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   const int stride = gridDim.x * kWaves;
   int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
+  // Lane c < 3 handles channel c of the per-Gaussian inputs and outputs.
+  // The colour and its gradient are fetched one Gaussian ahead, dx when the
+  // Gaussian starts, and each Gaussian's outputs are stored when the next
+  // one starts, so that the wait for the next Gaussian's row copies at the
+  // end of an iteration never waits on a load or store issued just before.
+  const int ch = min(lane, 2);
   Attr A;
   int cur = 0;
+  float pcol = 0.f, pdc = 0.f;
   if (g < n) {
     attr_load<false>(a, g, A);
     rows_dma<NQ>(a, A, rows0, lane);
+    pcol = color[(size_t)ch * n + g];
+    pdc = dcolor[(size_t)ch * n + g];
   }
   wait_all();
   __syncthreads();
+  int og = -1;                                  // Gaussian whose outputs are pending
+  float o_dn = 0.f, o_dalb = 0.f, o_dx = 0.f, o_rough = 0.f, o_tint = 0.f;
   while (g < n) {
     const int gn = g + stride;
     uint8_t* rows = rows0 + cur * 3 * V;
+    if (og >= 0) {
+      if (lane < 3) {
+        dn[(size_t)lane * n + og] = o_dn;
+        dalbedo[(size_t)lane * n + og] = o_dalb;
+        dx[(size_t)lane * n + og] = o_dx;
+      }
+      if (lane == 0) {
+        drough[og] = o_rough;
+        dtint[og] = o_tint;
+      }
+    }
+    const float col = pcol, dcol = pdc;
+    const float dx_in = dx[(size_t)ch * n + g];
     // fetch the next Gaussian's inputs while this one is shaded
     Attr An;
     if (gn < n) {
       attr_load<false>(a, gn, An);
       rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
+      pcol = color[(size_t)ch * n + gn];
+      pdc = dcolor[(size_t)ch * n + gn];
     }
     GaussCtx G;
     gauss_setup<false>(a, A, rows, G);
+    og = g;
     if (!G.front) {
-      if (lane < 3) {
-        dn[(size_t)lane * n + g] = 0.f;
-        dalbedo[(size_t)lane * n + g] = 0.f;
-      }
-      if (lane == 0) {
-        drough[g] = 0.f;
-        dtint[g] = 0.f;
-      }
+      o_dn = 0.f;
+      o_dalb = 0.f;
+      o_dx = dx_in;
+      o_rough = 0.f;
+      o_tint = 0.f;
     } else {
       // dL/dL_o: lane c < 3 takes channel c, every lane reads the three
       float dLo[3], aop[3], qd[3];
       {
-        const int c = min(lane, 2);
-        const float d = srgb_adjoint(color[(size_t)c * n + g], dcolor[(size_t)c * n + g]);
+        const float d = srgb_adjoint(col, dcol);
 #pragma unroll
         for (int q = 0; q < 3; ++q)
           dLo[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), q));
@@ -850,24 +895,41 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
         }
         wave_fence();
       }
+      // per-Gaussian sums: DPP row sums (lane 15 of each row), the four row
+      // totals through the wave's LDS slot, then every lane reads the twelve
       float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
                      acc.gco, acc.gga, acc.sd[0], acc.sd[1], acc.sd[2], acc.ts};
+      rga::row_sums(r);
+      if ((lane & 15) == 15) {
 #pragma unroll
-      for (int i = 0; i < 12; ++i) r[i] = rga::wave_sum(r[i]);
-      if (lane == 0) {
+        for (int q = 0; q < 12; ++q) red[(lane >> 4) * 12 + q] = r[q];
+      }
+      wave_fence();
+      const float tot = lane < 12 ? (red[lane] + red[12 + lane]) + (red[24 + lane] + red[36 + lane])
+                                  : 0.f;
+#pragma unroll
+      for (int q = 0; q < 12; ++q)
+        r[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), q));
+      wave_fence();
+      {
         const float gco = r[6];
         float gn3[3] = {r[0] + gco * G.wo[0], r[1] + gco * G.wo[1], r[2] + gco * G.wo[2]};
         float gw[3] = {r[3] + gco * G.nn[0], r[4] + gco * G.nn[1], r[5] + gco * G.nn[2]};
         const float pn = gn3[0] * G.nn[0] + gn3[1] * G.nn[1] + gn3[2] * G.nn[2];
         const float pw = gw[0] * G.wo[0] + gw[1] * G.wo[1] + gw[2] * G.wo[2];
-        for (int c = 0; c < 3; ++c) {
-          dn[(size_t)c * n + g] = (gn3[c] - G.nn[c] * pn) * G.inn;
-          // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
-          dx[(size_t)c * n + g] += -(gw[c] - G.wo[c] * pw) * G.iwo;
-          dalbedo[(size_t)c * n + g] = dLo[c] * r[8 + c] * (1.f / kPi);
-        }
-        drough[g] = r[7];
-        dtint[g] = r[11];
+        const int c = ch;
+        const float gnc = c == 0 ? gn3[0] : (c == 1 ? gn3[1] : gn3[2]);
+        const float gwc = c == 0 ? gw[0] : (c == 1 ? gw[1] : gw[2]);
+        const float nnc = c == 0 ? G.nn[0] : (c == 1 ? G.nn[1] : G.nn[2]);
+        const float woc = c == 0 ? G.wo[0] : (c == 1 ? G.wo[1] : G.wo[2]);
+        const float dlc = c == 0 ? dLo[0] : (c == 1 ? dLo[1] : dLo[2]);
+        const float sdc = c == 0 ? r[8] : (c == 1 ? r[9] : r[10]);
+        o_dn = (gnc - nnc * pn) * G.inn;
+        // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
+        o_dx = dx_in - (gwc - woc * pw) * G.iwo;
+        o_dalb = dlc * sdc * (1.f / kPi);
+        o_rough = r[7];
+        o_tint = r[11];
       }
     }
     wait_all();
@@ -875,6 +937,17 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
     if (gn < n) A = An;
     cur ^= 1;
     g = gn;
+  }
+  if (og >= 0) {
+    if (lane < 3) {
+      dn[(size_t)lane * n + og] = o_dn;
+      dalbedo[(size_t)lane * n + og] = o_dalb;
+      dx[(size_t)lane * n + og] = o_dx;
+    }
+    if (lane == 0) {
+      drough[og] = o_rough;
+      dtint[og] = o_tint;
+    }
   }
   __syncthreads();
   float* out = denv_part + (size_t)blockIdx.x * 3 * K;
@@ -1013,7 +1086,7 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
-    const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)6 * a.K * 2 + kMWaves * 512 * 4;
+    const size_t lds = (size_t)8 * a.K * sizeof(float) + (size_t)6 * a.K * 2 + kMWaves * 512 * 4;
     static bool mattr = false;
     if (!mattr) {
       hipFuncSetAttribute(reinterpret_cast<const void*>(shade_fwd_mfma_kernel),
@@ -1036,7 +1109,10 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     RGA_CHECK_LAUNCH("shade_gaussians");
     return RGA_OK;
   }
-  const size_t lds = (size_t)7 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
+  const size_t lds = (size_t)8 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
+  if (lds > 160 * 1024)
+    return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: %d directions and %d views need %zu B of LDS",
+                     a.K, a.V, lds);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nq = (int)rga::ceil_div(3 * a.V, 1024);
   const dim3 grid(grid_for(n, lds));
@@ -1079,7 +1155,7 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
-    const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)6 * a.K * 2 +
+    const size_t lds = (size_t)11 * a.K * sizeof(float) + (size_t)6 * a.K * 2 +
                        (size_t)kMWaves * (4096 + 384 + 2048);
     if (lds > 150 * 1024)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: too many directions");
@@ -1110,7 +1186,11 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     RGA_CHECK_LAUNCH("shade_gaussians_backward");
     return RGA_OK;
   }
-  const size_t lds = (size_t)10 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
+  const size_t lds = (size_t)11 * a.K * sizeof(float) + (size_t)kWaves * (6 * a.V + 48 * 4);
+  if (lds > 160 * 1024)
+    return rga::fail(RGA_EUNSUPPORTED,
+                     "shade_gaussians_backward: %d directions and %d views need %zu B of LDS", a.K,
+                     a.V, lds);
   const int grid = grid_for(n, lds);
   if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
     return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");

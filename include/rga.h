@@ -127,9 +127,12 @@ int mesh_visibility(void* stream, int nv, int nf, const float* verts, const int3
  * precision  RGA_FP32 or RGA_BF16X3
  * color      [3][n] out;  front [n] uint8 out
  * Limits (RGA_EUNSUPPORTED otherwise): V % 16 == 0 and V <= 2048; hv | he
- * and wv | we; he*we <= 3584 directions.  RGA_BF16X3 also needs he*we % 32
- * == 0, one or two texels per view (hv == he, we == wv or we == 2 wv), and
- * at most 2432 directions in the adjoint (its LDS tables).                  */
+ * and wv | we; he*we <= 3584 directions; the LDS tables must fit 160 KB:
+ * 32 K + 48 V bytes (forward) and 44 K + 48 V + 1536 bytes (adjoint) for
+ * K = he*we directions and V views (e.g. 2048 directions with 1024 views).
+ * RGA_BF16X3 also needs K % 32 == 0, one or two texels per view (hv == he,
+ * we == wv or we == 2 wv), and at most 3296 directions in the forward and
+ * 2272 in the adjoint.                                                      */
 int shade_gaussians(void* stream, int n, const float* x, const float* nrm, const float* albedo,
                     const float* rough, const float* tint, const int32_t* vidx, const float* vw,
                     const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,

@@ -609,7 +609,9 @@ static void composite_pixel(float px, float py, const int32_t* list, int64_t len
     const float qf = fmaf(ca * dx, dx, fmaf(cc * dy, dy, 2.f * ((cb * dx) * dy)));
     const float power = -0.5f * qf;
     if (power > 0.f) continue;
-    const float araw = opac[g] * expf(power);
+    /* exp(power) evaluated as 2^(power log2 e), the product in FP32: the
+     * GPU takes the same skip / clamp / stop decisions from the same value */
+    const float araw = opac[g] * exp2f(power * 1.44269504f);
     const float alpha = fminf(0.99f, araw);
     {
       const float m1 = fabsf(araw - 1.f / 255.f) * 255.f;

@@ -563,7 +563,7 @@ __device__ inline float blend_step(const float4& a, const float4& c1, float px, 
   dy = a.y - py;
   const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
   const float power = -0.5f * qf;
-  G = expf(power);
+  G = __builtin_amdgcn_exp2f(power * 1.44269504f);   // exp(power) as 2^(power log2 e)
   araw = c1.y * G;
   alpha = fminf(0.99f, araw);
   const bool use = !stopped && power <= 0.f && alpha >= 1.f / 255.f;
@@ -799,8 +799,10 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 //   dL/dc_i     = alpha_i T_i g
 //   dL/dalpha_i = sum_c g_c (c_ic T_i - (C_c - C_<=i,c) / (1 - alpha_i))
 // with C the forward colour, then alpha = o exp(power) (unless clamped).
-// Per-splat sums over the tile's pixels: DPP wave reduction, the four waves'
-// partials are added in LDS, then one set of atomics per (item, splat).
+// Per-splat sums over the tile's pixels: DPP sums over each row of 16
+// lanes, added into the row's LDS slice by the row's last lane; after the
+// chunk the four slices are added and each splat gets one set of global
+// atomics per item.
 
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,

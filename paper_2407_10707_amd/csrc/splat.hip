@@ -34,6 +34,8 @@ constexpr int kItemsN = 4;       // per thread, passes over the splats
 constexpr int kBlockD = kRadixThreads * kItemsD;
 constexpr int kBlockN = kRadixThreads * kItemsN;
 constexpr int kChunk = 256;      // splats per blend work item
+constexpr int kDigitBits = 11;   // radix digit width: 2048 bins
+constexpr int kRadix = 1 << kDigitBits;
 
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
@@ -53,7 +55,7 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.nb_max = L.nb_n > L.nb_cap ? L.nb_n : L.nb_cap;
   int bits = 0;
   while ((1ll << bits) < tiles) ++bits;
-  L.tile_passes = bits <= 8 ? 1 : (bits <= 16 ? 2 : 3);
+  L.tile_passes = bits <= kDigitBits ? 1 : (bits <= 2 * kDigitBits ? 2 : 3);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -79,9 +81,9 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.tk1 = take(C * 4);
   L.tv1 = take(C * 4);
   L.ranges = take((size_t)tiles * 8);
-  L.hist = take((size_t)L.nb_max * 256 * 4);
-  L.binoff = take((size_t)L.nb_max * 256 * 4);
-  L.bintot = take(256 * 4);
+  L.hist = take((size_t)L.nb_max * kRadix * 4);
+  L.binoff = take((size_t)L.nb_max * kRadix * 4);
+  L.bintot = take(kRadix * 4);
   L.bsum = take((size_t)L.nb_n * 4);
   L.boff = take((size_t)L.nb_n * 4);
   L.count = take(16);   // int64 [0] = D, [1] = work items
@@ -322,111 +324,140 @@ __device__ inline int64_t live_count(const int64_t* cnt_ptr, int64_t fixed, int6
   return c < cap ? c : cap;
 }
 
+// Digits of kDigitBits bits (2048 bins): 32-bit depth keys take 3 passes,
+// tile keys of up to 2048 tiles 1 pass.
+
+// Per-block digit histogram (LDS integer atomics).
 template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t fixed,
               int64_t cap, int shift, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
+  __shared__ uint32_t h[kRadix];
   const int64_t count = live_count(cnt_ptr, fixed, cap);
   const int64_t base = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
+  if (base >= count) return;              // no items: the scan skips this block
+  for (int d = threadIdx.x; d < kRadix; d += kRadixThreads) h[d] = 0;
+  __syncthreads();
   for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = base + (int64_t)r * kRadixThreads + threadIdx.x;
-    if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < count) atomicAdd(&h[(keys[i] >> shift) & (kRadix - 1)], 1u);
   }
   __syncthreads();
-  hist[(size_t)blockIdx.x * 256 + threadIdx.x] = h[threadIdx.x];
+  for (int d = threadIdx.x; d < kRadix; d += kRadixThreads)
+    hist[(size_t)blockIdx.x * kRadix + d] = h[d];
 }
 
-// One workgroup per digit: exclusive scan of that digit's counts over blocks.
+// Exclusive scan of each digit's counts over the blocks that hold items
+// (the rest of a capacity-sized grid is skipped): 8 digits per workgroup,
+// 32 threads per digit each summing a run of blocks.
 __global__ void __launch_bounds__(256)
-radix_binscan(const uint32_t* __restrict__ hist, int nb, uint32_t* __restrict__ binoff,
+radix_binscan(const uint32_t* __restrict__ hist, int nb, const int64_t* cnt_ptr, int64_t fixed,
+              int64_t cap, int block_items, uint32_t* __restrict__ binoff,
               uint32_t* __restrict__ bintot) {
-  __shared__ uint32_t part[256];
-  const int bin = blockIdx.x;
-  const int chunk = (nb + 255) / 256;
-  const int j0 = threadIdx.x * chunk;
-  const int j1 = min(nb, j0 + chunk);
+  __shared__ uint32_t part[8][33];
+  const int dl = threadIdx.x & 7, c = threadIdx.x >> 3;
+  const int d = blockIdx.x * 8 + dl;
+  const int64_t count = live_count(cnt_ptr, fixed, cap);
+  const int nbl = (int)min((int64_t)nb, (count + block_items - 1) / block_items);
+  const int chunk = (nbl + 31) / 32;
+  const int j0 = c * chunk, j1 = min(nbl, j0 + chunk);
   uint32_t s = 0;
-  for (int j = j0; j < j1; ++j) s += hist[(size_t)j * 256 + bin];
-  part[threadIdx.x] = s;
+  for (int j = j0; j < j1; ++j) s += hist[(size_t)j * kRadix + d];
+  part[dl][c] = s;
   __syncthreads();
-  // Hillis-Steele inclusive scan over 256 partial sums
-  for (int o = 1; o < 256; o <<= 1) {
-    uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  if (threadIdx.x < 8) {
+    uint32_t run = 0;
+    for (int q = 0; q < 32; ++q) {
+      const uint32_t v = part[threadIdx.x][q];
+      part[threadIdx.x][q] = run;
+      run += v;
+    }
+    bintot[blockIdx.x * 8 + threadIdx.x] = run;
   }
-  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  __syncthreads();
+  uint32_t run = part[dl][c];
   for (int j = j0; j < j1; ++j) {
-    const uint32_t c = hist[(size_t)j * 256 + bin];
-    binoff[(size_t)j * 256 + bin] = run;
-    run += c;
+    const uint32_t v = hist[(size_t)j * kRadix + d];
+    binoff[(size_t)j * kRadix + d] = run;
+    run += v;
   }
-  if (threadIdx.x == 255) bintot[bin] = part[255];
 }
 
+// Stable scatter of one block.  Per round of 256 items: within a wave,
+// items with the same digit are matched with one ballot per digit bit (the
+// rank is the number of lower lanes with that digit); across the four waves
+// the lowest lane of each digit group publishes the group's size in
+// wcnt[wave][digit], items add the sizes of the earlier waves' groups, and
+// the same lanes then advance base[digit] and clear their wcnt entry (so
+// only the entries used in a round are ever touched).
 template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
                 const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[4][256];
+  constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the initial scan
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wcnt[4][kRadix];
+  __shared__ uint32_t part[kRadixThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // global exclusive offset of each digit + this block's offset inside it
-  base[tid] = bintot[tid];
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    uint32_t v = tid >= o ? base[tid - o] : 0u;
-    __syncthreads();
-    base[tid] += v;
-    __syncthreads();
-  }
-  uint32_t excl = (tid ? base[tid - 1] : 0u) + binoff[(size_t)blockIdx.x * 256 + tid];
-  __syncthreads();
-  base[tid] = excl;
   const int64_t count = live_count(cnt_ptr, fixed, cap);
   const int64_t blk = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
+  if (blk >= count) return;
+  // base[d] = sum of bintot over digits < d (all blocks) + this block's offset in d
+  uint32_t loc[kPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    loc[i] = sum;
+    sum += bintot[tid * kPer + i];
+  }
+  part[tid] = sum;
+  for (int d = tid; d < 4 * kRadix; d += kRadixThreads) (&wcnt[0][0])[d] = 0u;
+  __syncthreads();
+  for (int o = 1; o < kRadixThreads; o <<= 1) {
+    const uint32_t v = tid >= o ? part[tid - o] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  const uint32_t excl = tid ? part[tid - 1] : 0u;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int d = tid * kPer + i;
+    base[d] = excl + loc[i] + binoff[(size_t)blockIdx.x * kRadix + d];
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = blk + (int64_t)r * kRadixThreads + tid;
     const bool ok = i < count;
     const uint32_t key = ok ? kin[i] : 0u;
     const uint32_t val = ok ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t d = (key >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(ok);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kDigitBits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = __popcll(peers & lt);
-    wcnt[0][tid] = 0;
-    wcnt[1][tid] = 0;
-    wcnt[2][tid] = 0;
-    wcnt[3][tid] = 0;
-    __syncthreads();
-    if (ok && rank == 0) wcnt[wave][d] = __popcll(peers);
-    __syncthreads();
-    {
-      const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-      const uint32_t b0 = base[tid];
-      wcnt[0][tid] = b0;
-      wcnt[1][tid] = b0 + c0;
-      wcnt[2][tid] = b0 + c0 + c1;
-      wcnt[3][tid] = b0 + c0 + c1 + c2;
-      base[tid] = b0 + c0 + c1 + c2 + c3;
-    }
+    const uint32_t group = __popcll(peers);
+    const bool leader = ok && rank == 0;
+    if (leader) wcnt[wave][d] = group;
     __syncthreads();
     if (ok) {
-      const uint32_t pos = wcnt[wave][d] + rank;
+      uint32_t before = 0;
+      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
+      const uint32_t pos = base[d] + before + rank;
       kout[pos] = key;
       vout[pos] = val;
+    }
+    __syncthreads();
+    if (leader) {
+      atomicAdd(&base[d], group);
+      wcnt[wave][d] = 0u;
     }
     __syncthreads();
   }
@@ -1166,19 +1197,19 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
                at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
                at<uint8_t>(ws, L.fp64), k0, v0);
-    // depth sort: 4 passes of 8 bits over n keys
-    for (int pass = 0; pass < 4; ++pass) {
-      const int shift = 8 * pass;
+    // depth sort: 3 passes of 11 bits over n 32-bit keys
+    for (int pass = 0; pass < 3; ++pass) {
+      const int shift = kDigitBits * pass;
       RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
-      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_n, binoff,
-                 bintot);
+      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_n,
+                 (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot);
       uint32_t* t = k0; k0 = k1; k1 = t;
       t = v0; v0 = v1; v1 = t;
     }
-    // after 4 passes the (depth, index)-ordered splat indices are in v0 (= vals0)
+    // v0 now holds the splat indices in (depth, index) order
     uint32_t* bsum = at<uint32_t>(ws, L.bsum);
     uint32_t* boff = at<uint32_t>(ws, L.boff);
     RGA_LAUNCH("touched_blocksum", touched_blocksum, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n, v0,
@@ -1193,11 +1224,11 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                L.tiles_x, capacity, v0, at<int32_t>(ws, L.touched), at<int32_t>(ws, L.rect), boff,
                tk0, tv0);
     for (int pass = 0; pass < L.tile_passes; ++pass) {
-      const int shift = 8 * pass;
+      const int shift = kDigitBits * pass;
       RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);
-      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(256), dim3(256), 0, s, hist, L.nb_cap, binoff,
-                 bintot);
+      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_cap,
+                 (const int64_t*)cnt, (int64_t)0, capacity, kBlockD, binoff, bintot);
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot);
       uint32_t* t = tk0; tk0 = tk1; tk1 = t;

@@ -144,13 +144,14 @@ static void project_view(int nv, const float* v, const float* c, float rho, cons
   float t[3], b[3];
   basis_f32(d, t, b);
   const float scale = 0.5f * (float)res;
+  const float irho = 1.f / rho;   /* u = (t.(x - c) (1/rho) + 1) res / 2 */
   for (int i = 0; i < nv; ++i) {
     const float q0 = v[i] - c[0], q1 = v[nv + i] - c[1], q2 = v[2 * nv + i] - c[2];
     const float pu = fmaf(t[2], q2, fmaf(t[1], q1, t[0] * q0));
     const float pv = fmaf(b[2], q2, fmaf(b[1], q1, b[0] * q0));
     const float pd = fmaf(d[2], q2, fmaf(d[1], q1, d[0] * q0));
-    const float u = (pu / rho + 1.f) * scale;
-    const float w = (pv / rho + 1.f) * scale;
+    const float u = (pu * irho + 1.f) * scale;
+    const float w = (pv * irho + 1.f) * scale;
     U[i] = (int32_t)rintf(u * 256.f);
     V[i] = (int32_t)rintf(w * 256.f);
     z[i] = rho - pd;
@@ -199,6 +200,7 @@ static void raster_fixed(int nt, const int64_t* X, const int64_t* Y, const float
       float tz = z1; z1 = z2; z2 = tz;
       area = -area;
     }
+    const float ia = 1.f / (float)area;
     int64_t i_lo = 0, i_hi = res - 1, j_lo = 0, j_hi = res - 1;
     if (!brute) {
       int64_t mnx = x0, mxx = x0, mny = y0, mxy = y0;
@@ -227,7 +229,8 @@ static void raster_fixed(int nt, const int64_t* X, const int64_t* Y, const float
         const int in1 = w1 > 0 || (w1 == 0 && o20);
         const int in2 = w2 > 0 || (w2 == 0 && o01);
         if (!(in0 && in1 && in2)) continue;
-        const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) / (float)area;
+        /* depth: barycentric weights w_e / area through the reciprocal */
+        const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) * ia;
         uint32_t zb;
         memcpy(&zb, &bz, 4);
         const uint64_t key = ((uint64_t)zb << 32) | (uint32_t)ids[f];

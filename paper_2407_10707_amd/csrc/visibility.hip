@@ -48,7 +48,7 @@ __device__ inline int64_t fdiv(int64_t a, int64_t b) {
 }
 
 struct Proj {
-  float c[3], rho, t[3], b[3], d[3], scale;
+  float c[3], rho, irho, t[3], b[3], d[3], scale;
 };
 
 __device__ inline void project(const Proj& P, const float* __restrict__ v, int nv, int i,
@@ -57,8 +57,9 @@ __device__ inline void project(const Proj& P, const float* __restrict__ v, int n
   const float pu = fmaf(P.t[2], q2, fmaf(P.t[1], q1, P.t[0] * q0));
   const float pv = fmaf(P.b[2], q2, fmaf(P.b[1], q1, P.b[0] * q0));
   const float pd = fmaf(P.d[2], q2, fmaf(P.d[1], q1, P.d[0] * q0));
-  const float u = (pu / P.rho + 1.f) * P.scale;
-  const float w = (pv / P.rho + 1.f) * P.scale;
+  // u = (t.(x - c) (1/rho) + 1) res / 2
+  const float u = (pu * P.irho + 1.f) * P.scale;
+  const float w = (pv * P.irho + 1.f) * P.scale;
   U = (int32_t)rintf(u * 256.f);
   V = (int32_t)rintf(w * 256.f);
   z = P.rho - pd;
@@ -89,7 +90,7 @@ __device__ void raster_tri_wide(unsigned long long* zb, int res, int f, int64_t 
   if (i_hi > res - 1) i_hi = res - 1;
   if (j_hi > res - 1) j_hi = res - 1;
   const bool o12 = owns(x1, y1, x2, y2), o20 = owns(x2, y2, x0, y0), o01 = owns(x0, y0, x1, y1);
-  const float fa = (float)area;
+  const float ia = 1.f / (float)area;   // barycentric weights w_e / area
   for (int64_t j = j_lo; j <= j_hi; ++j) {
     const int64_t sy = 256 * j + 128;
     for (int64_t i = i_lo; i <= i_hi; ++i) {
@@ -101,7 +102,7 @@ __device__ void raster_tri_wide(unsigned long long* zb, int res, int f, int64_t 
       const bool in1 = w1 > 0 || (w1 == 0 && o20);
       const bool in2 = w2 > 0 || (w2 == 0 && o01);
       if (!(in0 && in1 && in2)) continue;
-      const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) / fa;
+      const float bz = fmaf((float)w2, z2, fmaf((float)w1, z1, (float)w0 * z0)) * ia;
       atomicMin(&zb[j * res + i], depth_key(bz, f));
     }
   }
@@ -145,7 +146,7 @@ __device__ inline void raster_tri(unsigned long long* zb, int res, int f, int32_
   const int32_t c0 = (a0 < 0 || (a0 == 0 && b0 < 0)) ? 0 : 1;   // edge v1 -> v2
   const int32_t c1 = (a1 < 0 || (a1 == 0 && b1 < 0)) ? 0 : 1;   // edge v2 -> v0
   const int32_t c2 = (a2 < 0 || (a2 == 0 && b2 < 0)) ? 0 : 1;   // edge v0 -> v1
-  const float fa = (float)area;
+  const float ia = 1.f / (float)area;   // barycentric weights w_e / area
   const int32_t sx0 = 256 * i_lo + 128;
   for (int j = j_lo; j <= j_hi; ++j) {
     const int32_t sy = 256 * j + 128;
@@ -156,7 +157,7 @@ __device__ inline void raster_tri(unsigned long long* zb, int res, int f, int32_
     for (int i = i_lo; i <= i_hi; ++i) {
       if ((w0 | w1 | w2) >= 0) {
         const float bz = fmaf((float)(w2 + c2), z2, fmaf((float)(w1 + c1), z1,
-                                                        (float)(w0 + c0) * z0)) / fa;
+                                                        (float)(w0 + c0) * z0)) * ia;
         atomicMin(&row[i], depth_key(bz, f));
       }
       w0 += 256 * a0;
@@ -213,6 +214,7 @@ raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __
   P.c[1] = frame[1];
   P.c[2] = frame[2];
   P.rho = frame[3];
+  P.irho = 1.f / P.rho;
   P.d[0] = dirs[3 * view];
   P.d[1] = dirs[3 * view + 1];
   P.d[2] = dirs[3 * view + 2];

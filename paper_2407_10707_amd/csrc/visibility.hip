@@ -167,37 +167,66 @@ __device__ inline void raster_tri(unsigned long long* zb, int res, int f, int32_
   }
 }
 
+// min / max over the 64 lanes of a wave (DPP row shifts, then the two row
+// broadcasts; a lane with no source keeps its own value), result in lane 63
+template <int CTRL, int ROWS>
+__device__ inline float dpp_same(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+
+template <bool MAX>
+__device__ inline float wave_extreme(float v) {
+  auto op = [](float a, float b) { return MAX ? fmaxf(a, b) : fminf(a, b); };
+  v = op(v, dpp_same<0x111, 0xf>(v));
+  v = op(v, dpp_same<0x112, 0xf>(v));
+  v = op(v, dpp_same<0x114, 0xf>(v));
+  v = op(v, dpp_same<0x118, 0xf>(v));
+  v = op(v, dpp_same<0x142, 0xa>(v));
+  v = op(v, dpp_same<0x143, 0xc>(v));
+  return v;
+}
+
 // frame[0..2] = centre, frame[3] = rho of the posed mesh's bounding box
+// (min and max are exact and independent of the reduction order)
 __global__ void __launch_bounds__(1024)
 frame_kernel(int nv, const float* __restrict__ v, float* __restrict__ frame) {
-  __shared__ float lo[3][1024], hi[3][1024];
+  __shared__ float ext[6][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float r[6];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     float l = v[a * nv], h = v[a * nv];
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
       l = fminf(l, v[a * nv + i]);
       h = fmaxf(h, v[a * nv + i]);
     }
-    lo[a][threadIdx.x] = l;
-    hi[a][threadIdx.x] = h;
+    r[a] = wave_extreme<false>(l);
+    r[3 + a] = wave_extreme<true>(h);
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) ext[q][wave] = r[q];
   }
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (threadIdx.x < o)
-      for (int a = 0; a < 3; ++a) {
-        lo[a][threadIdx.x] = fminf(lo[a][threadIdx.x], lo[a][threadIdx.x + o]);
-        hi[a][threadIdx.x] = fmaxf(hi[a][threadIdx.x], hi[a][threadIdx.x + o]);
-      }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = ext[a][0];
+      hi[a] = ext[3 + a][0];
+      for (int w = 1; w < 16; ++w) {
+        lo[a] = fminf(lo[a], ext[a][w]);
+        hi[a] = fmaxf(hi[a], ext[3 + a][w]);
+      }
+    }
     float e[3];
     for (int a = 0; a < 3; ++a) {
-      frame[a] = (lo[a][0] + hi[a][0]) * 0.5f;
-      e[a] = hi[a][0] - lo[a][0];
+      frame[a] = (lo[a] + hi[a]) * 0.5f;
+      e[a] = hi[a] - lo[a];
     }
-    float r = 1.01f * (0.5f * sqrtf(fmaf(e[2], e[2], fmaf(e[1], e[1], e[0] * e[0]))));
-    if (!(r > 0.f)) r = 1.f;
-    frame[3] = r;
+    float rr = 1.01f * (0.5f * sqrtf(fmaf(e[2], e[2], fmaf(e[1], e[1], e[0] * e[0]))));
+    if (!(rr > 0.f)) rr = 1.f;
+    frame[3] = rr;
   }
 }
 

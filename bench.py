@@ -314,7 +314,7 @@ def main():
         for name in ("lbs_fwd", "vis_frame", "vis_raster", "vis_transpose", "vis_majority",
                      "vis_count", "shade_fwd", "shade_fwd_bf16x3", "splat_fill",
                      "splat_preprocess", "radix_upsweep", "radix_binscan", "radix_downsweep",
-                     "touched_blocksum", "touched_blockscan", "splat_duplicate", "tile_ranges",
+                     "touched_scan", "splat_duplicate", "tile_ranges",
                      "chunk_index", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
                      "l1_final", "splat_zero", "blend_bwd", "preprocess_bwd", "shade_bwd",
                      "shade_bwd_bf16x3", "shade_denv", "lbs_bwd"):

@@ -86,7 +86,7 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.bintot = take(kRadix * 4);
   L.bsum = take((size_t)L.nb_n * 4);
   L.boff = take((size_t)L.nb_n * 4);
-  L.count = take(16);   // int64 [0] = D, [1] = work items
+  L.count = take(32);   // int64 [0] = D, [1] = work items; uint32 [4] = scan ticket
   L.queue = take(4);    // item queue of the blend adjoint (a line of its own)
   L.grad = take(N * 5 * 4);
   L.max_items = rga::ceil_div(cap > 0 ? cap : 1, kChunk) + tiles;
@@ -248,8 +248,12 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
                   float4* __restrict__ rec, float* __restrict__ mean2d, float* __restrict__ conic,
                   float* __restrict__ depth, int32_t* __restrict__ rect,
                   int32_t* __restrict__ touched, uint8_t* __restrict__ fp64,
-                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                  uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                  uint32_t* __restrict__ ranges_u32, int64_t nranges, uint32_t* __restrict__ cnt4) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  // the frame's tile ranges start empty and its counters at zero
+  if (g < nranges) ranges_u32[g] = 0u;
+  if (g < 8) cnt4[g] = 0u;
   if (g >= n) return;
   Geo G;
   bool okq;
@@ -464,10 +468,18 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 }
 
 // ---- exclusive scan of tiles-touched in depth order -> offsets, D ---------
+// Exclusive scan of tiles-touched in depth order, in one launch: every block
+// sums its items, publishes the sum and takes a ticket; the block that takes
+// the last ticket scans the block sums in a fixed order (deterministic) and
+// writes the offsets and D.  No block waits for another.  `done` is zeroed
+// on the stream before the launch.
 __global__ void __launch_bounds__(kRadixThreads)
-touched_blocksum(int n, const uint32_t* __restrict__ order, const int32_t* __restrict__ touched,
-                 uint32_t* __restrict__ bsum) {
+touched_scan_kernel(int n, const uint32_t* __restrict__ order, const int32_t* __restrict__ touched,
+                    uint32_t* __restrict__ bsum, uint32_t* __restrict__ boff,
+                    int64_t* __restrict__ count, uint32_t* __restrict__ done) {
   __shared__ uint32_t red[kRadixThreads];
+  __shared__ uint64_t part[kRadixThreads];
+  __shared__ bool last;
   const int64_t blk = (int64_t)blockIdx.x * kBlockN;
   uint32_t s = 0;
   for (int r = 0; r < kItemsN; ++r) {
@@ -480,21 +492,23 @@ touched_blocksum(int n, const uint32_t* __restrict__ order, const int32_t* __res
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
-}
-
-__global__ void __launch_bounds__(256)
-touched_blockscan(int nb, const uint32_t* __restrict__ bsum, uint32_t* __restrict__ boff,
-                  int64_t* __restrict__ count) {
-  __shared__ uint64_t part[256];
-  const int chunk = (nb + 255) / 256;
-  const int j0 = threadIdx.x * chunk, j1 = min(nb, j0 + chunk);
-  uint64_t s = 0;
-  for (int j = j0; j < j1; ++j) s += bsum[j];
-  part[threadIdx.x] = s;
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = red[0];
+    __threadfence();                                   // publish before the ticket
+    last = atomicAdd(done, 1u) == gridDim.x - 1;
+  }
   __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
+  if (!last) return;
+  __threadfence();                                     // see every block's sum
+  const int nb = gridDim.x;
+  const int chunk = (nb + kRadixThreads - 1) / kRadixThreads;
+  const int j0 = threadIdx.x * chunk, j1 = min(nb, j0 + chunk);
+  uint64_t t = 0;
+  for (int j = j0; j < j1; ++j) t += bsum[j];
+  part[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 1; o < kRadixThreads; o <<= 1) {
+    const uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
     __syncthreads();
     part[threadIdx.x] += v;
     __syncthreads();
@@ -504,7 +518,7 @@ touched_blockscan(int nb, const uint32_t* __restrict__ bsum, uint32_t* __restric
     boff[j] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
     run += bsum[j];
   }
-  if (threadIdx.x == 255) count[0] = (int64_t)part[255];
+  if (threadIdx.x == kRadixThreads - 1) count[0] = (int64_t)part[kRadixThreads - 1];
 }
 
 __global__ void __launch_bounds__(kRadixThreads)
@@ -1186,17 +1200,21 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   uint32_t* binoff = at<uint32_t>(ws, L.binoff);
   uint32_t* bintot = at<uint32_t>(ws, L.bintot);
   int32_t* ranges = at<int32_t>(ws, L.ranges);
-  // ranges := empty; count := 0 (for n == 0)
-  RGA_LAUNCH("splat_fill", fill_u32, dim3(rga::ceil_div(2 * tiles + 4, 256)), dim3(256), 0, s,
-             reinterpret_cast<uint32_t*>(ranges), 2 * tiles, 0u);
-  RGA_LAUNCH("splat_fill", fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt),
-             (int64_t)4, 0u);
-  if (n > 0) {
-    RGA_LAUNCH("splat_preprocess", preprocess_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
-               n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, color, front,
-               at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
+  if (n == 0) {
+    // ranges := empty; count := 0
+    RGA_LAUNCH("splat_fill", fill_u32, dim3(rga::ceil_div(2 * tiles + 4, 256)), dim3(256), 0, s,
+               reinterpret_cast<uint32_t*>(ranges), 2 * tiles, 0u);
+    RGA_LAUNCH("splat_fill", fill_u32, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(cnt),
+               (int64_t)8, 0u);
+  } else {
+    // the projection also clears the tile ranges and the counters
+    const int64_t pre_threads = std::max<int64_t>(std::max<int64_t>(n, 2 * tiles), 8);
+    RGA_LAUNCH("splat_preprocess", preprocess_kernel, dim3(rga::ceil_div(pre_threads, 256)),
+               dim3(256), 0, s, n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, color,
+               front, at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
                at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
-               at<uint8_t>(ws, L.fp64), k0, v0);
+               at<uint8_t>(ws, L.fp64), k0, v0, reinterpret_cast<uint32_t*>(ranges), 2 * tiles,
+               reinterpret_cast<uint32_t*>(cnt));
     // depth sort: 3 passes of 11 bits over n 32-bit keys
     for (int pass = 0; pass < 3; ++pass) {
       const int shift = kDigitBits * pass;
@@ -1212,10 +1230,9 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     // v0 now holds the splat indices in (depth, index) order
     uint32_t* bsum = at<uint32_t>(ws, L.bsum);
     uint32_t* boff = at<uint32_t>(ws, L.boff);
-    RGA_LAUNCH("touched_blocksum", touched_blocksum, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n, v0,
-               at<int32_t>(ws, L.touched), bsum);
-    RGA_LAUNCH("touched_blockscan", touched_blockscan, dim3(1), dim3(256), 0, s, L.nb_n, bsum, boff,
-               cnt);
+    RGA_LAUNCH("touched_scan", touched_scan_kernel, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n, v0,
+               at<int32_t>(ws, L.touched), bsum, boff, cnt,
+               reinterpret_cast<uint32_t*>(cnt) + 4);
     uint32_t* tk0 = at<uint32_t>(ws, L.tk0);
     uint32_t* tv0 = at<uint32_t>(ws, L.tv0);
     uint32_t* tk1 = at<uint32_t>(ws, L.tk1);

@@ -170,9 +170,10 @@ int shade_gaussians_backward(void* stream, int n, const float* x, const float* n
  * log_s [3][n], opac [n], color [3][n], front [n].
  * capacity   maximum number of (splat, tile) duplicates D the workspace holds
  * ws         splat_workspace_size(n, width, height, capacity) bytes; holds the
- *            per-splat records, sorted lists and tile ranges that
- *            splat_backward and splat_state read.  Keep it alive and
- *            unmodified until the backward pass.
+ *            per-splat records, sorted lists, tile ranges and, per pixel,
+ *            the (colour, transmittance) state at every 64th entry of each
+ *            tile list that splat_backward and splat_state read.  Keep it
+ *            alive and unmodified until the backward pass.
  * image [3][H][W], T_final [H][W] out.
  * No host synchronisation: if D exceeds capacity the lists are truncated, the
  * image is wrong, and splat_read_count reports D > capacity (retry larger). */

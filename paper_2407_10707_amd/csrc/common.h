@@ -80,6 +80,94 @@ __device__ inline void row_sums(float (&v)[N]) {
     v[q] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[q]), 0x118, 0xf, 0xf, true));
 }
 
+// Lane exchanges of gfx950: swap_halves exchanges the upper half-wave of
+// `a` with the lower half-wave of `b` (v_permlane32_swap); swap_rows
+// exchanges the odd rows of `a` with the even rows of `b`
+// (v_permlane16_swap).
+__device__ inline void swap_halves(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+
+__device__ inline void swap_rows(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ inline float dpp_add(float v) {
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
+// Sums over all 64 lanes of a wave for four slots of N values each; slot s
+// ends, fully summed, in every lane of row s (lanes 16s .. 16s+15) of
+// `out`.  Two halving steps each hand half of the slots to the partner lane
+// and keep the other half (half-wave swap, then odd/even row swap); four
+// butterflies inside the row (lane xor 15, 7, 2, 1: row mirror, half-row
+// mirror, two quad permutations) finish the sums.  10 instructions per
+// value for four slots, against 4 DPP adds per value and slot for a row
+// sum alone.  All 64 lanes must be active.
+template <int N>
+__device__ inline void slot_sums4(float (&v)[4][N], float (&out)[N]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {   // lanes 0-31 keep slots 0-1, lanes 32-63 slots 2-3
+      swap_halves(v[s][q], v[s + 2][q]);
+      v[s][q] += v[s + 2][q];
+    }
+#pragma unroll
+  for (int q = 0; q < N; ++q) {     // row s keeps slot s
+    swap_rows(v[0][q], v[1][q]);
+    out[q] = v[0][q] + v[1][q];
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0x140>(out[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0x141>(out[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0x4E>(out[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0xB1>(out[q]);
+}
+
+// The same for eight slots: slot s ends, fully summed, in lanes 8s .. 8s+7.
+// Three halving steps (half-wave swap, odd/even row swap, row mirror with a
+// select), then three butterflies over the eight lanes of a slot (lane xor
+// 7, 2, 1).  18 instructions per value for eight slots.
+template <int N>
+__device__ inline void slot_sums8(float (&v)[8][N], float (&out)[N]) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {   // lanes 0-31 keep slots 0-3, lanes 32-63 slots 4-7
+      swap_halves(v[s][q], v[s + 4][q]);
+      v[s][q] += v[s + 4][q];
+    }
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {   // rows 0 and 2 keep v[0], v[1]; rows 1 and 3 v[2], v[3]
+      swap_rows(v[s][q], v[s + 2][q]);
+      v[s][q] += v[s + 2][q];
+    }
+  const bool low = (__lane_id() & 8) == 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {     // lanes 0-7 of a row keep v[0], lanes 8-15 v[1]
+    const float a = dpp_add<0x140>(v[0][q]);
+    const float b = dpp_add<0x140>(v[1][q]);
+    out[q] = low ? a : b;
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0x141>(out[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0x4E>(out[q]);
+#pragma unroll
+  for (int q = 0; q < N; ++q) out[q] = dpp_add<0xB1>(out[q]);
+}
+
 // Float add into LDS through an integer compare-and-swap loop.  On gfx950
 // the LDS float atomic add is several times slower than the integer atomic
 // path when a whole wave adds to distinct addresses; a compare-and-swap then

@@ -34,15 +34,17 @@ constexpr int kItemsN = 4;       // per thread, passes over the splats
 constexpr int kBlockD = kRadixThreads * kItemsD;
 constexpr int kBlockN = kRadixThreads * kItemsN;
 constexpr int kChunk = 256;      // splats per blend work item
+constexpr int kSub = 64;         // splats per work item of the blend adjoint
+constexpr int kSubs = kChunk / kSub;
 constexpr int kDigitBits = 11;   // radix digit width: 2048 bins
 constexpr int kRadix = 1 << kDigitBits;
 
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
   size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, queue, grad;
-  size_t item_off, item_tile, item_chunk, cstate, total;
+  size_t item_off, item_tile, item_chunk, cstate, sstate, sub_item, total;
   int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
-  int64_t max_items;
+  int64_t max_items, max_subs;
 };
 
 Layout make_layout(int n, int width, int height, int64_t cap) {
@@ -86,7 +88,7 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.bintot = take(kRadix * 4);
   L.bsum = take((size_t)L.nb_n * 4);
   L.boff = take((size_t)L.nb_n * 4);
-  L.count = take(32);   // int64 [0] = D, [1] = work items; uint32 [4] = scan ticket
+  L.count = take(32);   // int64 [0] = D, [1] = work items, [3] = adjoint items; uint32 [4] = scan ticket
   L.queue = take(4);    // item queue of the blend adjoint (a line of its own)
   L.grad = take(N * 5 * 4);
   L.max_items = rga::ceil_div(cap > 0 ? cap : 1, kChunk) + tiles;
@@ -94,6 +96,9 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.item_tile = take((size_t)L.max_items * 4);
   L.item_chunk = take((size_t)L.max_items * 4);
   L.cstate = take((size_t)L.max_items * 4 * 256 * 4);
+  L.sstate = take((size_t)L.max_items * (kSubs - 1) * 4 * 256 * 4);
+  L.max_subs = rga::ceil_div(cap > 0 ? cap : 1, kSub) + tiles;
+  L.sub_item = take((size_t)L.max_subs * 4);
   L.total = o;
   return L;
 }
@@ -593,6 +598,13 @@ tile_ranges_kernel(const uint32_t* __restrict__ tkeys, const int64_t* cnt_ptr, i
 //   code >= 0          whole chunk used, T_in = code
 //   -1 <= code < 0     the chunk where the walk stops, T_in = -code
 //   code = kPastStop   chunk past the stop
+// For the adjoint, which works on sub-chunks of kSub entries so that no
+// workgroup walks a long chunk alone, the chunk pass also leaves each
+// pixel's (C, T) at the sub-chunk boundaries, measured from the chunk's
+// start (T = 1, C = 0), with T negated once the walk has stopped; the
+// restart pass overwrites them, for the pixels it re-walks, with absolute
+// states: T_in * T_local and C_before + T_in * C_local up to the sub-chunk
+// it starts in, then those of its sequential walk.
 constexpr float kPastStop = -2.f;
 
 // One front-to-back compositing step for the pixel centre (px, py), written
@@ -621,42 +633,62 @@ __device__ inline float blend_step(const float4& a, const float4& c1, float px, 
   return w;
 }
 
+// Work items: (tile, chunk of kChunk entries) for the forward passes, and
+// (item, sub-chunk of kSub entries) for the adjoint, listed tile by tile
+// with one scan over the tiles (the two counts packed in one 64-bit sum).
 __global__ void __launch_bounds__(1024)
 chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __restrict__ item_off,
                    uint32_t* __restrict__ item_tile, uint32_t* __restrict__ item_chunk,
-                   int64_t max_items, int64_t* __restrict__ counters) {
-  __shared__ uint32_t part[1024];
+                   int64_t max_items, uint32_t* __restrict__ sub_item, int64_t max_subs,
+                   int64_t* __restrict__ counters) {
+  __shared__ uint64_t part[1024];
   const int per = (tiles + 1023) / 1024;
   const int t0 = threadIdx.x * per, t1 = min(tiles, t0 + per);
-  uint32_t s = 0;
+  uint64_t s = 0;
   for (int t = t0; t < t1; ++t) {
     const int len = ranges[2 * t + 1] - ranges[2 * t];
-    s += (uint32_t)((len + kChunk - 1) / kChunk);
+    s += (uint64_t)((len + kChunk - 1) / kChunk) | ((uint64_t)((len + kSub - 1) / kSub) << 32);
   }
   part[threadIdx.x] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
-    uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
     __syncthreads();
     part[threadIdx.x] += v;
     __syncthreads();
   }
-  uint32_t off = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  const uint64_t before = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+  uint32_t off = (uint32_t)before, soff = (uint32_t)(before >> 32);
   for (int t = t0; t < t1; ++t) {
     item_off[t] = off;
     const int len = ranges[2 * t + 1] - ranges[2 * t];
     const int nch = (len + kChunk - 1) / kChunk;
-    for (int j = 0; j < nch; ++j)
-      if ((int64_t)(off + j) < max_items) {
+    for (int j = 0; j < nch; ++j) {
+      const bool ok = (int64_t)(off + j) < max_items;
+      if (ok) {
         item_tile[off + j] = (uint32_t)t;
         item_chunk[off + j] = (uint32_t)j;
       }
+      const int nsub = min(kSubs, (len - j * kChunk + kSub - 1) / kSub);
+      for (int m = 0; m < nsub; ++m, ++soff)
+        if ((int64_t)soff < max_subs) sub_item[soff] = ok ? ((off + j) << 2) | (uint32_t)m : ~0u;
+    }
     off += nch;
   }
   if (threadIdx.x == 1023) {
-    item_off[tiles] = part[1023];
-    counters[1] = (int64_t)part[1023];
+    item_off[tiles] = (uint32_t)part[1023];
+    counters[1] = (int64_t)(uint32_t)part[1023];
+    counters[3] = (int64_t)(part[1023] >> 32);
   }
+}
+
+// One pixel's (C, T code) into a 1024-float state block: C0, C1, C2, code,
+// each 256 floats in pixel order.
+__device__ inline void put_state(float* q, float C0, float C1, float C2, float code) {
+  q[threadIdx.x] = C0;
+  q[256 + threadIdx.x] = C1;
+  q[512 + threadIdx.x] = C2;
+  q[768 + threadIdx.x] = code;
 }
 
 // The blend passes run a grid of as many workgroups as fit on the device at
@@ -678,7 +710,7 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                    const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
                    const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                    const int64_t* __restrict__ counters, int64_t max_items,
-                   float* __restrict__ cstate) {
+                   float* __restrict__ cstate, float* __restrict__ sstate) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
@@ -699,7 +731,10 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   bool sat = !(px < W && py < H);
   const bool outside = sat;
+  float* sub = sstate + (size_t)b * (kSubs - 1) * 1024;
+  int m = 1;                              // next sub-chunk boundary to record
   for (int k0 = 0; k0 < cnt; k0 += 32) {
+    if (k0 == m * kSub) put_state(sub + (m++ - 1) * 1024, C0, C1, C2, sat ? -T : T);
     if (__ballot(!sat) == 0ull) break;     // every pixel of this wave saturated
     const int k1 = min(cnt, k0 + 32);
     for (int k = k0; k < k1; ++k) {
@@ -712,12 +747,9 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
       C2 = fmaf(s2[k].x, w, C2);
     }
   }
+  for (; m < kSubs && m * kSub < cnt; ++m) put_state(sub + (m - 1) * 1024, C0, C1, C2, sat ? -T : T);
   sat = sat && !outside;
-  float* st = cstate + (size_t)b * 1024;
-  st[threadIdx.x] = C0;
-  st[256 + threadIdx.x] = C1;
-  st[512 + threadIdx.x] = C2;
-  st[768 + threadIdx.x] = sat ? -T : T;   // T >= 1e-4 > 0 at a stop
+  put_state(cstate + (size_t)b * 1024, C0, C1, C2, sat ? -T : T);   // T >= 1e-4 > 0 at a stop
   }
 }
 
@@ -782,15 +814,16 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
 
 // Restart pass, one workgroup per work item after a tile's first, in
 // parallel: pixels whose walk stops in this chunk re-walk it from T_in with
-// the exact stop rule and write their final colour and transmittance.  (A pixel whose stop test
+// the exact stop rule, starting at the sub-chunk that may hold the stop, and
+// write their final colour and transmittance.  (A pixel whose stop test
 // does not fire here because of rounding keeps the chunk's end state.)
 __global__ void __launch_bounds__(256)
 blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                      const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
                      const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                      const int64_t* __restrict__ counters, int64_t max_items,
-                     const float* __restrict__ cstate, float* __restrict__ image,
-                     float* __restrict__ Tfinal) {
+                     const float* __restrict__ cstate, float* __restrict__ sstate,
+                     float* __restrict__ image, float* __restrict__ Tfinal) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
@@ -814,10 +847,28 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   __syncthreads();
   if (!mine || !(px < W && py < H)) continue;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
-  float T = -code;
-  float C0 = st[threadIdx.x], C1 = st[256 + threadIdx.x], C2 = st[512 + threadIdx.x];
+  const float Tin = -code;
+  const float B0 = st[threadIdx.x], B1 = st[256 + threadIdx.x], B2 = st[512 + threadIdx.x];
+  float T = Tin, C0 = B0, C1 = B1, C2 = B2;
   bool stopped = false;
-  for (int k0 = 0; k0 < cnt && !stopped; k0 += 32) {
+  // Skip the sub-chunks that cannot hold the stop (chunk pass not
+  // saturated there and T_in * T_local >= 1e-4; T is monotone): start from
+  // the product state at the last such boundary, and leave the absolute
+  // states for the adjoint.
+  float* sub = sstate + (size_t)b * (kSubs - 1) * 1024;
+  int m = 1;                              // next sub-chunk boundary to record
+  for (; m < kSubs && m * kSub < cnt; ++m) {
+    float* q = sub + (m - 1) * 1024;
+    const float Tr = q[768 + threadIdx.x];
+    if (Tr < 0.f || Tin * Tr < 1e-4f) break;
+    T = Tin * Tr;
+    C0 = fmaf(Tin, q[threadIdx.x], B0);
+    C1 = fmaf(Tin, q[256 + threadIdx.x], B1);
+    C2 = fmaf(Tin, q[512 + threadIdx.x], B2);
+    put_state(q, C0, C1, C2, T);
+  }
+  for (int k0 = (m - 1) * kSub; k0 < cnt && !stopped; k0 += 32) {
+    if (k0 == m * kSub) put_state(sub + (m++ - 1) * 1024, C0, C1, C2, T);
     const int k1 = min(cnt, k0 + 32);
     for (int k = k0; k < k1; ++k) {
       const float4 a = s0[k], c1 = s1[k];
@@ -829,6 +880,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
       C2 = fmaf(s2[k].x, w, C2);
     }
   }
+  for (; m < kSubs && m * kSub < cnt; ++m) put_state(sub + (m - 1) * 1024, C0, C1, C2, stopped ? -T : T);
   const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
   image[p] = C0;
   image[HW + p] = C1;
@@ -838,59 +890,86 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 }
 
 // ---- adjoint: blend ----------------------------------------------------------
-// Per work item (tile, chunk) and pixel, starting from the chunk's incoming
-// transmittance T_in and colour C_before left by the combine pass, the
-// entries are re-walked front to back with the same decisions:
+// Per work item (chunk, sub-chunk of kSub entries) and pixel, starting from
+// the sub-chunk's incoming state (the chunk's T_in and colour before it for
+// the first sub-chunk; for later ones T_in * T_local and C_before +
+// T_in * C_local inside a whole chunk, the restart's exact state inside the
+// stop chunk), the entries are re-walked front to back with the same
+// decisions:
 //   dL/dc_i     = alpha_i T_i g
 //   dL/dalpha_i = sum_c g_c (c_ic T_i - (C_c - C_<=i,c) / (1 - alpha_i))
 // with C the forward colour, then alpha = o exp(power) (unless clamped).
-// Per-splat sums over the tile's pixels: DPP sums over each row of 16
-// lanes, added into the row's LDS slice by the row's last lane; after the
-// chunk the four slices are added and each splat gets one set of global
-// atomics per item.
-
+// Per-splat sums over the tile's pixels: the partials of eight entries that
+// touch a wave's pixels are summed over the wave together (lane swaps and
+// DPP) and stored into the wave's LDS slice; after the sub-chunk the four
+// slices are added and each splat gets one set of global atomics per item.
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                  const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
                  const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
-                 const int64_t* __restrict__ counters, int64_t max_items,
-                 uint32_t* __restrict__ queue, const float* __restrict__ cstate,
+                 const uint32_t* __restrict__ sub_item, const int64_t* __restrict__ counters,
+                 int64_t max_items, int64_t max_subs, uint32_t* __restrict__ queue,
+                 const float* __restrict__ cstate, const float* __restrict__ sstate,
                  const float* __restrict__ image, const float* __restrict__ dimage,
                  float* __restrict__ gmean_conic /*[5][n]*/, float* __restrict__ dopac,
                  float* __restrict__ dcolor) {
-  __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
-  __shared__ uint32_t sg[kChunk];
-  __shared__ float acc[4][9][kChunk];   // per lane row (16 pixels) of every wave
+  __shared__ float4 s0[kSub], s1[kSub], s2[kSub];
+  __shared__ uint32_t sg[kSub];
+  __shared__ float acc[4][9][kSub];       // per wave: entry sums over its 64 pixels
   __shared__ int slot;
   const int64_t nitems = min(counters[1], max_items);
+  const int64_t nsubs = min(counters[3], max_subs);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, myslot = lane >> 3;
   for (;;) {
-  const int b = next_item(queue, &slot);
-  if (b >= nitems) break;
+  const int u = next_item(queue, &slot);
+  if (u >= nsubs) break;
+  const uint32_t su = sub_item[u];
+  const int b = (int)(su >> 2), m = (int)(su & 3u);
+  if (su == ~0u || b >= nitems) continue;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
-  const int lane = threadIdx.x & 63;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const bool inside = px < W && py < H;
-  const int e0 = ranges[2 * t] + j * kChunk;
-  const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
-  if ((int)threadIdx.x < cnt) {
-    const uint32_t g = sorted[e0 + threadIdx.x];
-    sg[threadIdx.x] = g;
-    s0[threadIdx.x] = rec[3 * g];
-    s1[threadIdx.x] = rec[3 * g + 1];
-    s2[threadIdx.x] = rec[3 * g + 2];
+  const int e0 = ranges[2 * t] + j * kChunk + m * kSub;
+  const int cnt = min(kSub, ranges[2 * t + 1] - e0);
+  {
+    const int r = threadIdx.x & (kSub - 1), part = threadIdx.x / kSub;
+    if (r < cnt) {
+      const uint32_t g = sorted[e0 + r];
+      if (part < 3) {
+        float4* dst = part == 0 ? s0 : (part == 1 ? s1 : s2);
+        dst[r] = rec[3 * g + part];
+      } else {
+        sg[r] = g;
+      }
+    }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 9; ++q) acc[r][q][threadIdx.x] = 0.f;
+  for (int q = 0; q < 9; ++q) (&acc[0][0][0])[q * 256 + threadIdx.x] = 0.f;
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
+  bool done = !inside || code < -1.f;
   float T = fabsf(code);
   float A0 = st[threadIdx.x], A1 = st[256 + threadIdx.x], A2 = st[512 + threadIdx.x];
+  if (m > 0 && !done) {
+    const float* q = sstate + ((size_t)b * (kSubs - 1) + (m - 1)) * 1024;
+    const float Tr = q[768 + threadIdx.x];
+    const float R0 = q[threadIdx.x], R1 = q[256 + threadIdx.x], R2 = q[512 + threadIdx.x];
+    if (code >= 0.f) {                    // whole chunk: local state from the chunk start
+      A0 = fmaf(code, R0, A0);
+      A1 = fmaf(code, R1, A1);
+      A2 = fmaf(code, R2, A2);
+      T = code * Tr;
+    } else {                              // stop chunk: the exact walk's state
+      done = Tr < 0.f;
+      T = Tr;
+      A0 = R0;
+      A1 = R1;
+      A2 = R2;
+    }
+  }
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   float Cf0 = 0.f, Cf1 = 0.f, Cf2 = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f;
-  bool done = !inside || code < -1.f;
   if (!done) {
     const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
     Cf0 = image[p];
@@ -901,53 +980,77 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     g2 = dimage[2 * HW + p];
   }
   __syncthreads();
-  for (int k0 = 0; k0 < cnt; k0 += 32) {
-    if (__ballot(!done) == 0ull) break;    // every pixel of this wave finished
-    const int k1 = min(cnt, k0 + 32);
-    for (int k = k0; k < k1; ++k) {
-      const float4 a = s0[k], c1 = s1[k];
-      const float col2 = s2[k].x;
-      const float Tb = T;
-      bool applied;
-      float alpha, dx, dy, G, araw;
-      const float w = blend_step(a, c1, fpx, fpy, T, done, applied, alpha, dx, dy, G, araw);
-      if (__ballot(applied) == 0ull) continue;
-      A0 = fmaf(c1.z, w, A0);
-      A1 = fmaf(c1.w, w, A1);
-      A2 = fmaf(col2, w, A2);
-      const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
-      const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
-                        g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
-                        g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
-      const bool lin = applied && araw <= 0.99f;   // alpha not clamped
-      const float dp = lin ? dal * alpha : 0.f;     // d/d power
-      float v[9];
-      v[0] = -dp * (a.z * dx + a.w * dy);           // d/d mean x
-      v[1] = -dp * (a.w * dx + c1.x * dy);          // d/d mean y
-      v[2] = -0.5f * dp * dx * dx;                  // d/d conic A
-      v[3] = -dp * dx * dy;                         // d/d conic B
-      v[4] = -0.5f * dp * dy * dy;                  // d/d conic C
-      v[5] = lin ? dal * G : 0.f;                   // d/d opacity
-      v[6] = w * g0;                                // d/d colour
-      v[7] = w * g1;
-      v[8] = w * g2;
-      rga::row_sums(v);
-      if ((lane & 15) == 15) {
-        float* dst = &acc[lane >> 4][0][k];
+  // Entries that touch a pixel of this wave fill eight slots of partials,
+  // which are then summed over the wave in one go (slot s ends in lanes
+  // 8s .. 8s+7) and stored into this wave's LDS slice.  The next entry's
+  // record is read from LDS one step ahead.
+  float4 na = s0[0], nc = s1[0];
+  float ncol = s2[0].x;
+  int k = 0;
+  while (k < cnt && __ballot(!done) != 0ull) {
+    float v[8][9];
+    int kv = 0;                             // entry of this lane's slot
+    int ns = 0;                             // slots filled
 #pragma unroll
-        for (int q = 0; q < 9; ++q) atomicAdd(dst + q * kChunk, v[q]);
+    for (int s = 0; s < 8; ++s) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[s][q] = 0.f;
+      bool got = false;
+      while (!got && k < cnt) {
+        const float4 a = na, c1 = nc;
+        const float col2 = ncol;
+        {
+          const int kn = min(k + 1, cnt - 1);
+          na = s0[kn];
+          nc = s1[kn];
+          ncol = s2[kn].x;
+        }
+        const float Tb = T;
+        bool applied;
+        float alpha, dx, dy, G, araw;
+        const float w = blend_step(a, c1, fpx, fpy, T, done, applied, alpha, dx, dy, G, araw);
+        got = __ballot(applied) != 0ull;
+        if (got) {
+          A0 = fmaf(c1.z, w, A0);
+          A1 = fmaf(c1.w, w, A1);
+          A2 = fmaf(col2, w, A2);
+          const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
+          const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
+                            g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
+                            g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
+          const bool lin = applied && araw <= 0.99f;   // alpha not clamped
+          const float dp = lin ? dal * alpha : 0.f;     // d/d power
+          v[s][0] = -dp * (a.z * dx + a.w * dy);        // d/d mean x
+          v[s][1] = -dp * (a.w * dx + c1.x * dy);       // d/d mean y
+          v[s][2] = -0.5f * dp * dx * dx;               // d/d conic A
+          v[s][3] = -dp * dx * dy;                      // d/d conic B
+          v[s][4] = -0.5f * dp * dy * dy;               // d/d conic C
+          v[s][5] = lin ? dal * G : 0.f;                // d/d opacity
+          v[s][6] = w * g0;                             // d/d colour
+          v[s][7] = w * g1;
+          v[s][8] = w * g2;
+          kv = myslot == s ? k : kv;
+          ++ns;
+        }
+        ++k;
       }
+    }
+    float r[9];
+    rga::slot_sums8(v, r);
+    if ((lane & 7) == 0 && myslot < ns) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) acc[wave][q][kv] = r[q];
     }
   }
   __syncthreads();
   if ((int)threadIdx.x < cnt) {
-    const int k = threadIdx.x;
-    const uint32_t g = sg[k];
+    const int e = threadIdx.x;
+    const uint32_t g = sg[e];
     float sum[9];
     bool nz = false;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      sum[q] = (acc[0][q][k] + acc[1][q][k]) + (acc[2][q][k] + acc[3][q][k]);
+      sum[q] = (acc[0][q][e] + acc[1][q][e]) + (acc[2][q][e] + acc[3][q][e]);
       nz |= sum[q] != 0.f;
     }
     if (nz) {
@@ -1258,20 +1361,22 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
              at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), L.max_items, cnt);
+             at<uint32_t>(ws, L.item_chunk), L.max_items, at<uint32_t>(ws, L.sub_item),
+             L.max_subs, cnt);
   const int64_t g_chunk =
       std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
   const int64_t g_restart =
       std::min<int64_t>(L.max_items, resident_groups<1>((const void*)blend_restart_kernel));
   RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(g_chunk), dim3(256), 0, s, W, H, L.tiles_x,
              ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate));
+             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
+             at<float>(ws, L.sstate));
   RGA_LAUNCH("blend_prefix", blend_prefix_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
              at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final);
   RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(g_restart), dim3(256), 0, s, W, H,
              L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate), image,
-             T_final);
+             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
+             at<float>(ws, L.sstate), image, T_final);
   RGA_CHECK_LAUNCH("splat_forward");
   return RGA_OK;
 }
@@ -1298,13 +1403,14 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
   RGA_LAUNCH("splat_zero", zero_f32, dim3(rga::ceil_div(nz, 256)), dim3(256), 0, s, gmc, nz, dopac,
              (int64_t)n, dcolor, 3 * (int64_t)n, queue);
   const int64_t g_bwd =
-      std::min<int64_t>(L.max_items, resident_groups<2>((const void*)blend_bwd_kernel));
+      std::min<int64_t>(L.max_subs, resident_groups<2>((const void*)blend_bwd_kernel));
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(g_bwd), dim3(256), 0, s, cam->width,
              cam->height, L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec),
              at<uint32_t>(ws, L.item_tile), at<uint32_t>(ws, L.item_chunk),
-             at<int64_t>(ws, L.count), L.max_items, queue, at<float>(ws, L.cstate), image,
-             dimage, gmc, dopac, dcolor);
+             at<uint32_t>(ws, L.sub_item), at<int64_t>(ws, L.count), L.max_items, L.max_subs,
+             queue, at<float>(ws, L.cstate), at<float>(ws, L.sstate), image, dimage, gmc, dopac,
+             dcolor);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
              n, cd, x, A, quat, log_s, opac, front, gmc, dx, dquat, dlog_s);
   RGA_CHECK_LAUNCH("splat_backward");

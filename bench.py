@@ -316,7 +316,7 @@ def main():
                      "splat_preprocess", "radix_upsweep", "radix_binscan", "radix_downsweep",
                      "touched_scan", "splat_duplicate", "tile_ranges",
                      "chunk_index", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
-                     "l1_final", "splat_zero", "blend_bwd", "preprocess_bwd", "shade_bwd",
+                     "l1_final", "blend_bwd", "preprocess_bwd", "shade_bwd",
                      "shade_bwd_bf16x3", "shade_denv", "lbs_bwd"):
             ms, cnt = rga.timing_read(name)
             if cnt:

@@ -42,7 +42,7 @@ constexpr int kRadix = 1 << kDigitBits;
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
   size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, queue, grad;
-  size_t item_off, item_tile, item_chunk, cstate, sstate, sub_item, total;
+  size_t item_off, item_tile, item_chunk, item_sub, cstate, sstate, sub_item, total;
   int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
   int64_t max_items, max_subs;
 };
@@ -90,11 +90,12 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.boff = take((size_t)L.nb_n * 4);
   L.count = take(32);   // int64 [0] = D, [1] = work items, [3] = adjoint items; uint32 [4] = scan ticket
   L.queue = take(4);    // item queue of the blend adjoint (a line of its own)
-  L.grad = take(N * 5 * 4);
+  L.grad = take(N * 9 * 4);   // adjoint sums: mean2d, conic [5][n], opacity [n], colour [3][n]
   L.max_items = rga::ceil_div(cap > 0 ? cap : 1, kChunk) + tiles;
   L.item_off = take(((size_t)tiles + 1) * 4);
   L.item_tile = take((size_t)L.max_items * 4);
   L.item_chunk = take((size_t)L.max_items * 4);
+  L.item_sub = take((size_t)L.max_items * 4);
   L.cstate = take((size_t)L.max_items * 4 * 256 * 4);
   L.sstate = take((size_t)L.max_items * (kSubs - 1) * 4 * 256 * 4);
   L.max_subs = rga::ceil_div(cap > 0 ? cap : 1, kSub) + tiles;
@@ -254,12 +255,17 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
                   float* __restrict__ depth, int32_t* __restrict__ rect,
                   int32_t* __restrict__ touched, uint8_t* __restrict__ fp64,
                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                  uint32_t* __restrict__ ranges_u32, int64_t nranges, uint32_t* __restrict__ cnt4) {
+                  uint32_t* __restrict__ ranges_u32, int64_t nranges, uint32_t* __restrict__ cnt4,
+                  float* __restrict__ grad9, uint32_t* __restrict__ queue) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  // the frame's tile ranges start empty and its counters at zero
+  // the frame's tile ranges start empty, its counters at zero, and so do the
+  // adjoint's per-splat sums and item queue
   if (g < nranges) ranges_u32[g] = 0u;
   if (g < 8) cnt4[g] = 0u;
+  if (g == 0) *queue = 0u;
   if (g >= n) return;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) grad9[(size_t)q * n + g] = 0.f;
   Geo G;
   bool okq;
   geo_forward(cam, x, A, quat, log_s, n, g, G, okq);
@@ -634,12 +640,14 @@ __device__ inline float blend_step(const float4& a, const float4& c1, float px, 
 }
 
 // Work items: (tile, chunk of kChunk entries) for the forward passes, and
-// (item, sub-chunk of kSub entries) for the adjoint, listed tile by tile
+// (item, sub-chunk of kSub entries) for the adjoint, numbered tile by tile
 // with one scan over the tiles (the two counts packed in one 64-bit sum).
+// Here each item gets its tile, chunk index and first sub-item; the chunk
+// pass lists the sub-items.
 __global__ void __launch_bounds__(1024)
 chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __restrict__ item_off,
                    uint32_t* __restrict__ item_tile, uint32_t* __restrict__ item_chunk,
-                   int64_t max_items, uint32_t* __restrict__ sub_item, int64_t max_subs,
+                   uint32_t* __restrict__ item_sub, int64_t max_items,
                    int64_t* __restrict__ counters) {
   __shared__ uint64_t part[1024];
   const int per = (tiles + 1023) / 1024;
@@ -664,21 +672,21 @@ chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __re
     const int len = ranges[2 * t + 1] - ranges[2 * t];
     const int nch = (len + kChunk - 1) / kChunk;
     for (int j = 0; j < nch; ++j) {
-      const bool ok = (int64_t)(off + j) < max_items;
-      if (ok) {
-        item_tile[off + j] = (uint32_t)t;
-        item_chunk[off + j] = (uint32_t)j;
+      const int64_t b = (int64_t)off + j;
+      if (b == max_items) counters[3] = (int64_t)soff;   // lists truncated: existing items' only
+      if (b < max_items) {
+        item_tile[b] = (uint32_t)t;
+        item_chunk[b] = (uint32_t)j;
+        item_sub[b] = soff;
       }
-      const int nsub = min(kSubs, (len - j * kChunk + kSub - 1) / kSub);
-      for (int m = 0; m < nsub; ++m, ++soff)
-        if ((int64_t)soff < max_subs) sub_item[soff] = ok ? ((off + j) << 2) | (uint32_t)m : ~0u;
+      soff += (uint32_t)min(kSubs, (len - j * kChunk + kSub - 1) / kSub);
     }
     off += nch;
   }
   if (threadIdx.x == 1023) {
     item_off[tiles] = (uint32_t)part[1023];
     counters[1] = (int64_t)(uint32_t)part[1023];
-    counters[3] = (int64_t)(part[1023] >> 32);
+    if ((int64_t)(uint32_t)part[1023] <= max_items) counters[3] = (int64_t)(part[1023] >> 32);
   }
 }
 
@@ -710,7 +718,8 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                    const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
                    const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                    const int64_t* __restrict__ counters, int64_t max_items,
-                   float* __restrict__ cstate, float* __restrict__ sstate) {
+                   const uint32_t* __restrict__ item_sub, uint32_t* __restrict__ sub_item,
+                   int64_t max_subs, float* __restrict__ cstate, float* __restrict__ sstate) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
@@ -720,6 +729,10 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
   const int e0 = ranges[2 * t] + j * kChunk;
   const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+  if ((int)threadIdx.x * kSub < cnt) {    // the adjoint's sub-items of this chunk
+    const int64_t u = (int64_t)item_sub[b] + threadIdx.x;
+    if (u < max_subs) sub_item[u] = ((uint32_t)b << 2) | threadIdx.x;
+  }
   if ((int)threadIdx.x < cnt) {
     const uint32_t g = sorted[e0 + threadIdx.x];
     s0[threadIdx.x] = rec[3 * g];
@@ -925,7 +938,7 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
   if (u >= nsubs) break;
   const uint32_t su = sub_item[u];
   const int b = (int)(su >> 2), m = (int)(su & 3u);
-  if (su == ~0u || b >= nitems) continue;
+  if (b >= nitems) continue;
   const int t = item_tile[b], j = item_chunk[b];
   const int tx = t % TX, ty = t / TX;
   const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
@@ -1117,18 +1130,29 @@ __global__ void __launch_bounds__(256)
 preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const float* __restrict__ A,
                       const float* __restrict__ quat, const float* __restrict__ log_s,
                       const float* __restrict__ opac, const uint8_t* __restrict__ front,
-                      const float* __restrict__ gmc, float* __restrict__ dx,
-                      float* __restrict__ dquat, float* __restrict__ dlog_s) {
+                      float* __restrict__ grad9, uint32_t* __restrict__ queue,
+                      float* __restrict__ dx, float* __restrict__ dquat,
+                      float* __restrict__ dlog_s, float* __restrict__ dopac,
+                      float* __restrict__ dcolor) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) *queue = 0u;
   if (g >= n) return;
+  // take the blend adjoint's sums and leave them zero for another backward
+  float gs[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    gs[q] = grad9[(size_t)q * n + g];
+    grad9[(size_t)q * n + g] = 0.f;
+  }
+  dopac[g] = gs[5];
+  for (int k = 0; k < 3; ++k) dcolor[(size_t)k * n + g] = gs[6 + k];
   Geo G;
   bool okq;
   geo_forward(cam, x, A, quat, log_s, n, g, G, okq);
   bool valid = (G.Z > 0.2f) && front[g] && (opac[g] >= 1.f / 255.f) && okq;
   float gM[9], gXYZ[3];
   if (valid) {
-    const float du = gmc[g], dv = gmc[(size_t)n + g];
-    const float dca = gmc[(size_t)2 * n + g], dcb = gmc[(size_t)3 * n + g], dcc = gmc[(size_t)4 * n + g];
+    const float du = gs[0], dv = gs[1], dca = gs[2], dcb = gs[3], dcc = gs[4];
     const float det = fmaf(G.a, G.c, -(G.b * G.b));
     if (det <= (G.a * G.c) * 0x1p-12f) {
       Geo64 D;
@@ -1190,16 +1214,6 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
   dquat[(size_t)n + g] = (gx - qx * dot) * G.inv;
   dquat[(size_t)2 * n + g] = (gy - qy * dot) * G.inv;
   dquat[(size_t)3 * n + g] = (gz - qz * dot) * G.inv;
-}
-
-__global__ void __launch_bounds__(256)
-zero_f32(float* __restrict__ a, int64_t na, float* __restrict__ b, int64_t nb,
-         float* __restrict__ c, int64_t nc, uint32_t* __restrict__ queue) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *queue = 0u;
-  if (i < na) a[i] = 0.f;
-  if (i < nb) b[i] = 0.f;
-  if (i < nc) c[i] = 0.f;
 }
 
 // Workgroups of a 256-thread blend kernel that fit on the current device at
@@ -1317,7 +1331,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                front, at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
                at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
                at<uint8_t>(ws, L.fp64), k0, v0, reinterpret_cast<uint32_t*>(ranges), 2 * tiles,
-               reinterpret_cast<uint32_t*>(cnt));
+               reinterpret_cast<uint32_t*>(cnt), at<float>(ws, L.grad), at<uint32_t>(ws, L.queue));
     // depth sort: 3 passes of 11 bits over n 32-bit keys
     for (int pass = 0; pass < 3; ++pass) {
       const int shift = kDigitBits * pass;
@@ -1361,15 +1375,15 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
              at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), L.max_items, at<uint32_t>(ws, L.sub_item),
-             L.max_subs, cnt);
+             at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items, cnt);
   const int64_t g_chunk =
       std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
   const int64_t g_restart =
       std::min<int64_t>(L.max_items, resident_groups<1>((const void*)blend_restart_kernel));
   RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(g_chunk), dim3(256), 0, s, W, H, L.tiles_x,
              ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
+             at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<uint32_t>(ws, L.item_sub),
+             at<uint32_t>(ws, L.sub_item), L.max_subs, at<float>(ws, L.cstate),
              at<float>(ws, L.sstate));
   RGA_LAUNCH("blend_prefix", blend_prefix_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
              at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final);
@@ -1397,11 +1411,10 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
     return rga::fail(RGA_EINVAL, "splat_backward: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const CamDev cd = to_dev(cam);
-  float* gmc = at<float>(ws, L.grad);
-  const int64_t nz = 5 * (int64_t)n;
+  // The per-splat sums and the item queue were zeroed by splat_forward's
+  // projection, and the projection adjoint zeroes them again after use.
+  float* grad9 = at<float>(ws, L.grad);
   uint32_t* queue = at<uint32_t>(ws, L.queue);
-  RGA_LAUNCH("splat_zero", zero_f32, dim3(rga::ceil_div(nz, 256)), dim3(256), 0, s, gmc, nz, dopac,
-             (int64_t)n, dcolor, 3 * (int64_t)n, queue);
   const int64_t g_bwd =
       std::min<int64_t>(L.max_subs, resident_groups<2>((const void*)blend_bwd_kernel));
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
@@ -1409,10 +1422,10 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
              cam->height, L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec),
              at<uint32_t>(ws, L.item_tile), at<uint32_t>(ws, L.item_chunk),
              at<uint32_t>(ws, L.sub_item), at<int64_t>(ws, L.count), L.max_items, L.max_subs,
-             queue, at<float>(ws, L.cstate), at<float>(ws, L.sstate), image, dimage, gmc, dopac,
-             dcolor);
+             queue, at<float>(ws, L.cstate), at<float>(ws, L.sstate), image, dimage, grad9,
+             grad9 + (size_t)5 * n, grad9 + (size_t)6 * n);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
-             n, cd, x, A, quat, log_s, opac, front, gmc, dx, dquat, dlog_s);
+             n, cd, x, A, quat, log_s, opac, front, grad9, queue, dx, dquat, dlog_s, dopac, dcolor);
   RGA_CHECK_LAUNCH("splat_backward");
   return RGA_OK;
 }

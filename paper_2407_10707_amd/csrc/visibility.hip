@@ -6,7 +6,7 @@
 //              (128 KB at 128^2, within gfx950's 160 KB), filled with LDS
 //              64-bit atomic-min; winning triangles mark their three
 //              vertices in an LDS bitmask that is written out view-major
-//   transpose  32x32 bit-matrix transposes -> vertex-major words
+//   transpose  32x32 bit-matrix transposes by wave ballots -> vertex-major words
 //              raw[v][w] whose bit b is view 32w + b
 //   filter     bit-sliced: one 32-bit word carries 32 views, so the median
 //              of kv neighbours is a bitwise majority vote computed with a
@@ -277,43 +277,31 @@ raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __
   for (int w = threadIdx.x; w < nwv; w += blockDim.x) bits_vm[(size_t)view * nwv + w] = mark[w];
 }
 
-// 32x32 bit-matrix transpose (in registers).
-__device__ inline void transpose32(uint32_t* a) {
-  uint32_t m = 0x0000FFFFu;
-  for (int j = 16; j != 0; j >>= 1, m ^= (m << j)) {
-    for (int k = 0; k < 32; k = ((k | j) + 1) & ~j) {
-      const uint32_t t = (a[k] ^ (a[k | j] >> j)) & m;
-      a[k] ^= t;
-      a[k | j] ^= (t << j);
-    }
-  }
-}
-
 // view-major [V][nwv] (bit i&31 of word i>>5 = vertex i) -> vertex-major
-// [nv][nwV] (bit k&31 of word k>>5 = view k)
+// [nv][nwV] (bit k&31 of word k>>5 = view k).  Each half-wave transposes one
+// 32 x 32 bit block: lane r holds the row of view 32 kw + r, and the ballot
+// of bit c over the half-wave is the column of vertex 32 vw + c, which
+// lane c keeps and writes.
 __global__ void __launch_bounds__(256)
 transpose_kernel(int nv, int V, int nwv, int nwV, const uint32_t* __restrict__ vm,
                  uint32_t* __restrict__ out) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t blk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
   const int64_t total = (int64_t)nwv * nwV;
-  if (id >= total) return;
-  const int vw = (int)(id / nwV);  // word of vertices
-  const int kw = (int)(id % nwV);  // word of views
-  uint32_t a[32];
-  // row r of the block = view 32 kw + r; bit c = vertex 32 vw + c
-  for (int r = 0; r < 32; ++r) {
-    const int k = 32 * kw + r;
-    a[r] = k < V ? vm[(size_t)k * nwv + vw] : 0u;
-  }
-  // transpose32 treats a[r] bit (31 - c) as column c; reverse bits so that
-  // column c maps to bit c, transpose, then reverse back.
-  for (int r = 0; r < 32; ++r) a[r] = __brev(a[r]);
-  transpose32(a);
-  for (int r = 0; r < 32; ++r) a[r] = __brev(a[r]);
+  const int lane = threadIdx.x & 63, r = lane & 31;
+  const bool live = blk < total;            // both halves of a wave run the ballots
+  const int vw = live ? (int)(blk / nwV) : 0;  // word of vertices
+  const int kw = live ? (int)(blk % nwV) : 0;  // word of views
+  const int k = 32 * kw + r;
+  const uint32_t a = live && k < V ? vm[(size_t)k * nwv + vw] : 0u;
+  uint32_t col = 0u;
+#pragma unroll
   for (int c = 0; c < 32; ++c) {
-    const int i = 32 * vw + c;
-    if (i < nv) out[(size_t)i * nwV + kw] = a[c];
+    const uint64_t m = __ballot((a >> c) & 1u);
+    const uint32_t half = lane < 32 ? (uint32_t)m : (uint32_t)(m >> 32);
+    col = r == c ? half : col;
   }
+  const int i = 32 * vw + r;
+  if (live && i < nv) out[(size_t)i * nwV + kw] = col;
 }
 
 struct Planes {
@@ -344,17 +332,32 @@ __device__ inline uint32_t at_least(const Planes& s, int thr) {
   return ge | eq;
 }
 
+// Bit planes of the number of neighbours (kv <= 31) whose word has each bit
+// set.  All neighbour indices are read first and then all words, so the
+// loads overlap instead of forming a chain of dependent round trips.
+__device__ inline Planes neighbour_planes(const int32_t* __restrict__ knn, int i, int kv, int nv,
+                                          const uint32_t* __restrict__ src, int nwV, int w) {
+  const int32_t* row = knn + (size_t)i * kv;
+  int idx[31];
+#pragma unroll
+  for (int j = 0; j < 31; ++j) idx[j] = j < kv ? rga::clampi(row[j], 0, nv - 1) : 0;
+  uint32_t x[31];
+#pragma unroll
+  for (int j = 0; j < 31; ++j) x[j] = j < kv ? src[(size_t)idx[j] * nwV + w] : 0u;
+  Planes s = {{0u, 0u, 0u, 0u, 0u}};
+#pragma unroll
+  for (int j = 0; j < 31; ++j)
+    if (j < kv) add_word(s, x[j]);
+  return s;
+}
+
 __global__ void __launch_bounds__(256)
 majority_kernel(int nv, int nwV, const int32_t* __restrict__ knn, int kv,
                 const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)nv * nwV) return;
   const int i = (int)(id / nwV), w = (int)(id % nwV);
-  Planes s = {{0u, 0u, 0u, 0u, 0u}};
-  for (int j = 0; j < kv; ++j) {
-    const int nb = rga::clampi(knn[(size_t)i * kv + j], 0, nv - 1);
-    add_word(s, src[(size_t)nb * nwV + w]);
-  }
+  const Planes s = neighbour_planes(knn, i, kv, nv, src, nwV, w);
   dst[id] = at_least(s, (kv + 1) / 2);
 }
 
@@ -364,11 +367,7 @@ count_kernel(int nv, int V, int nwV, const int32_t* __restrict__ knn, int kv,
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)nv * nwV) return;
   const int i = (int)(id / nwV), w = (int)(id % nwV);
-  Planes s = {{0u, 0u, 0u, 0u, 0u}};
-  for (int j = 0; j < kv; ++j) {
-    const int nb = rga::clampi(knn[(size_t)i * kv + j], 0, nv - 1);
-    add_word(s, src[(size_t)nb * nwV + w]);
-  }
+  const Planes s = neighbour_planes(knn, i, kv, nv, src, nwV, w);
   uint32_t words[8];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -461,7 +460,7 @@ extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
   RGA_LAUNCH("vis_raster", raster_kernel, dim3(V), dim3(kRasterThreads), lds, s, nv, nf, verts,
              faces, view_dirs, res, frame, vm, L.nwv);
   const int64_t tw = (int64_t)L.nwv * L.nwV;
-  RGA_LAUNCH("vis_transpose", transpose_kernel, dim3(rga::ceil_div(tw, 256)), dim3(256), 0, s, nv,
+  RGA_LAUNCH("vis_transpose", transpose_kernel, dim3(rga::ceil_div(tw * 32, 256)), dim3(256), 0, s, nv,
              V, L.nwv, L.nwV, vm, raw);
   const int64_t nw = (int64_t)nv * L.nwV;
   RGA_LAUNCH("vis_majority", majority_kernel, dim3(rga::ceil_div(nw, 256)), dim3(256), 0, s, nv,

@@ -4,21 +4,24 @@
 //
 // Pipeline on one stream, no host synchronisation:
 //   preprocess        1 thread / splat: camera transform, covariance, conic,
-//                     opacity-aware tile rectangle, packed 48-byte record
-//   depth sort        stable LSD radix sort of (depth bits, index) over n
-//                     (4 passes x [upsweep histogram, per-bin scan, ranked
-//                     scatter]); culled splats carry key 0xFFFFFFFF
+//                     opacity-aware tile rectangle, packed 48-byte record;
+//                     also clears the frame's ranges, counters and sums
+//   depth sort        stable LSD radix sort of (depth bits, index) over n:
+//                     3 passes of 11-bit digits, each [upsweep of per-block
+//                     digit counts, per-digit scan, ranked scatter]; culled
+//                     splats carry key 0xFFFFFFFF
 //   offsets           exclusive scan of tiles-touched in depth order -> D
 //   duplicate         one (tile, splat) entry per touched tile, emitted in
 //                     depth order
-//   tile sort         stable LSD radix sort of the entries by tile id
-//                     (ceil(log2 tiles / 8) passes) -> per tile, entries in
+//   tile sort         stable LSD radix sort of the entries by tile id (one
+//                     pass up to 2048 tiles) -> per tile, entries in
 //                     (depth bits, index) order
 //   ranges            tile boundaries in the sorted entries
-//   blend             1 workgroup of 256 threads per 16x16 tile; splat
-//                     records staged through LDS in batches of 256
-// Stable ranking inside a radix pass uses wave64 ballots (8 ballots give the
-// lanes that share a digit) and mbcnt-style lane masks.
+//   blend             (tile, 256-entry chunk) work items over a resident
+//                     grid; chunk composites, per-tile combine, restart of
+//                     the stop chunk; the adjoint over 64-entry sub-chunks
+// Stable ranking inside a radix pass uses wave64 ballots (11 ballots give
+// the lanes that share a digit) and mbcnt-style lane masks.
 #include "common.h"
 
 #include <algorithm>

@@ -60,6 +60,20 @@ __device__ inline float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave (integers): row shifts
+// by 1, 2, 4, 8 (lanes past the row start read 0), then the last lane of
+// rows 0 and 2 is added to rows 1 and 3, and lane 31 to rows 2 and 3.
+// All 64 lanes must be active.
+__device__ inline uint32_t wave_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
 // Sums of N values over each row of 16 lanes, in place: DPP row shifts
 // build per-row prefix sums, so lane 15 of each row ends with that row's
 // totals.  The N chains are interleaved step by step so that no DPP read

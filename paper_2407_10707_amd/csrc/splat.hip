@@ -535,46 +535,38 @@ touched_scan_kernel(int n, const uint32_t* __restrict__ order, const int32_t* __
   if (threadIdx.x == kRadixThreads - 1) count[0] = (int64_t)part[kRadixThreads - 1];
 }
 
-__global__ void __launch_bounds__(kRadixThreads)
+// One thread per splat in depth order (blocks of kBlockN, as in the
+// offsets scan): a workgroup scan of tiles-touched (wave scans, then the
+// sixteen wave totals) gives each splat its first entry.
+__global__ void __launch_bounds__(kBlockN)
 duplicate_kernel(int n, int TX, int64_t cap, const uint32_t* __restrict__ order,
                  const int32_t* __restrict__ touched, const int32_t* __restrict__ rect,
                  const uint32_t* __restrict__ boff, uint32_t* __restrict__ tkeys,
                  uint32_t* __restrict__ tvals) {
-  // in-block exclusive scan of tiles-touched, then emission
-  __shared__ uint32_t sc[kRadixThreads];
-  const int tid = threadIdx.x;
-  const int64_t blk = (int64_t)blockIdx.x * kBlockN;
-  uint32_t loc[kItemsN];
-  uint32_t s = 0;
-  // thread tid owns items blk + tid*kItemsN + r (contiguous run)
-  for (int r = 0; r < kItemsN; ++r) {
-    const int64_t i = blk + (int64_t)tid * kItemsN + r;
-    loc[r] = i < n ? (uint32_t)touched[order[i]] : 0u;
-    s += loc[r];
+  __shared__ uint32_t wt[kBlockN / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kBlockN + tid;
+  uint32_t g = 0u, cnt = 0u;
+  if (i < n) {
+    g = order[i];
+    cnt = (uint32_t)touched[g];
   }
-  sc[tid] = s;
+  const uint32_t incl = rga::wave_scan(cnt);
+  if (lane == 63) wt[wave] = incl;
   __syncthreads();
-  for (int o = 1; o < kRadixThreads; o <<= 1) {
-    uint32_t v = tid >= o ? sc[tid - o] : 0u;
-    __syncthreads();
-    sc[tid] += v;
-    __syncthreads();
-  }
-  uint64_t off = (uint64_t)boff[blockIdx.x] + (tid ? sc[tid - 1] : 0u);
-  for (int r = 0; r < kItemsN; ++r) {
-    const int64_t i = blk + (int64_t)tid * kItemsN + r;
-    if (i >= n || loc[r] == 0) continue;
-    const uint32_t g = order[i];
-    const int x0 = rect[g], y0 = rect[n + g], x1 = rect[2 * n + g], y1 = rect[3 * n + g];
-    for (int ty = y0; ty <= y1; ++ty)
-      for (int tx = x0; tx <= x1; ++tx) {
-        if ((int64_t)off < cap) {
-          tkeys[off] = (uint32_t)(ty * TX + tx);
-          tvals[off] = g;
-        }
-        ++off;
+  uint32_t before = 0u;
+  for (int w = 0; w < wave; ++w) before += wt[w];
+  if (cnt == 0u) return;
+  uint64_t off = (uint64_t)boff[blockIdx.x] + before + (incl - cnt);
+  const int x0 = rect[g], y0 = rect[n + g], x1 = rect[2 * n + g], y1 = rect[3 * n + g];
+  for (int ty = y0; ty <= y1; ++ty)
+    for (int tx = x0; tx <= x1; ++tx) {
+      if ((int64_t)off < cap) {
+        tkeys[off] = (uint32_t)(ty * TX + tx);
+        tvals[off] = g;
       }
-  }
+      ++off;
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -1357,7 +1349,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     uint32_t* tv0 = at<uint32_t>(ws, L.tv0);
     uint32_t* tk1 = at<uint32_t>(ws, L.tk1);
     uint32_t* tv1 = at<uint32_t>(ws, L.tv1);
-    RGA_LAUNCH("splat_duplicate", duplicate_kernel, dim3(L.nb_n), dim3(kRadixThreads), 0, s, n,
+    RGA_LAUNCH("splat_duplicate", duplicate_kernel, dim3(L.nb_n), dim3(kBlockN), 0, s, n,
                L.tiles_x, capacity, v0, at<int32_t>(ws, L.touched), at<int32_t>(ws, L.rect), boff,
                tk0, tv0);
     for (int pass = 0; pass < L.tile_passes; ++pass) {

@@ -39,6 +39,8 @@ constexpr int kBlockN = kRadixThreads * kItemsN;
 constexpr int kChunk = 256;      // splats per blend work item
 constexpr int kSub = 64;         // splats per work item of the blend adjoint
 constexpr int kSubs = kChunk / kSub;
+constexpr float kHalfNegLog2e = -0.72134752f;   // -log2(e) / 2
+constexpr float kInvHalfLog2e = 1.38629436f;    // 2 / log2(e) = 2 ln 2
 constexpr int kDigitBits = 11;   // radix digit width: 2048 bins
 constexpr int kRadix = 1 << kDigitBits;
 
@@ -317,8 +319,10 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
       cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     }
   }
-  rec[3 * g + 0] = make_float4(u, v, ca, cb);
-  rec[3 * g + 1] = make_float4(cc, o, color[g], color[n + g]);
+  // the blend evaluates the exponent of alpha in base 2: the record holds
+  // the conic scaled by -log2(e) / 2 (cross term by -log2(e))
+  rec[3 * g + 0] = make_float4(u, v, ca * kHalfNegLog2e, cb * (2.f * kHalfNegLog2e));
+  rec[3 * g + 1] = make_float4(cc * kHalfNegLog2e, o, color[g], color[n + g]);
   rec[3 * g + 2] = make_float4(color[2 * n + g], 0.f, 0.f, 0.f);
   mean2d[g] = valid ? u : 0.f;
   mean2d[n + g] = valid ? v : 0.f;
@@ -619,12 +623,13 @@ __device__ inline float blend_step(const float4& a, const float4& c1, float px, 
                                    float& dy, float& G, float& araw) {
   dx = a.x - px;
   dy = a.y - py;
-  const float qf = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, 2.f * ((a.w * dx) * dy)));
-  const float power = -0.5f * qf;
-  G = __builtin_amdgcn_exp2f(power * 1.44269504f);   // exp(power) as 2^(power log2 e)
+  // power log2(e) = -(A dx^2 + 2 B dx dy + C dy^2) log2(e) / 2 from the
+  // scaled conic; exp(power) = 2^(power log2 e)
+  const float e2 = fmaf(a.z * dx, dx, fmaf(c1.x * dy, dy, (a.w * dx) * dy));
+  G = __builtin_amdgcn_exp2f(e2);
   araw = c1.y * G;
   alpha = fminf(0.99f, araw);
-  const bool use = !stopped && power <= 0.f && alpha >= 1.f / 255.f;
+  const bool use = !stopped && e2 <= 0.f && alpha >= 1.f / 255.f;
   const float Tn = T * (1.f - alpha);
   const bool stop = use && Tn < 1e-4f;
   stopped = stopped || stop;
@@ -745,6 +750,7 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
     if (k0 == m * kSub) put_state(sub + (m++ - 1) * 1024, C0, C1, C2, sat ? -T : T);
     if (__ballot(!sat) == 0ull) break;     // every pixel of this wave saturated
     const int k1 = min(cnt, k0 + 32);
+#pragma unroll 4
     for (int k = k0; k < k1; ++k) {
       const float4 a = s0[k], c1 = s1[k];
       bool applied;
@@ -1028,8 +1034,9 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
                             g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
           const bool lin = applied && araw <= 0.99f;   // alpha not clamped
           const float dp = lin ? dal * alpha : 0.f;     // d/d power
-          v[s][0] = -dp * (a.z * dx + a.w * dy);        // d/d mean x
-          v[s][1] = -dp * (a.w * dx + c1.x * dy);       // d/d mean y
+          const float q = dp * kInvHalfLog2e;           // unscale the record's conic
+          v[s][0] = q * fmaf(0.5f * a.w, dy, a.z * dx);  // d/d mean x
+          v[s][1] = q * fmaf(0.5f * a.w, dx, c1.x * dy); // d/d mean y
           v[s][2] = -0.5f * dp * dx * dx;               // d/d conic A
           v[s][3] = -dp * dx * dy;                      // d/d conic B
           v[s][4] = -0.5f * dp * dy * dy;               // d/d conic C

@@ -300,8 +300,10 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
   const float u = fmaf(cam.fx, G.xzr, cam.cx);
   const float v = fmaf(cam.fy, G.yzr, cam.cy);
   int tx0 = 0, ty0 = 0, tx1 = -1, ty1 = -1, cnt = 0;
+  float r2_cull = 0.f;
   if (valid) {
     const float r2 = 2.f * ln_upper(255.f * o);
+    r2_cull = r2;
     const float hx = sqrtf(r2 * G.a) * 1.001f + 1e-3f;
     const float hy = sqrtf(r2 * G.c) * 1.001f + 1e-3f;
     float fx0 = floorf((u - hx) * 0.0625f), fx1 = floorf((u + hx) * 0.0625f);
@@ -323,7 +325,12 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
   // the conic scaled by -log2(e) / 2 (cross term by -log2(e))
   rec[3 * g + 0] = make_float4(u, v, ca * kHalfNegLog2e, cb * (2.f * kHalfNegLog2e));
   rec[3 * g + 1] = make_float4(cc * kHalfNegLog2e, o, color[g], color[n + g]);
-  rec[3 * g + 2] = make_float4(color[2 * n + g], 0.f, 0.f, 0.f);
+  // for the blend's per-wave culling: the slopes of the exponent's maxima
+  // along vertical and horizontal lines, and a lower bound of the exponent
+  // any pixel with alpha >= 1/255 can have (r2 bounds 2 ln(255 o) from
+  // above; the margin covers the rounding of both evaluations)
+  const float thr = valid ? (r2_cull * kHalfNegLog2e) * 1.01f - 0.01f : 0.f;
+  rec[3 * g + 2] = make_float4(color[2 * n + g], valid ? -cb / cc : 0.f, valid ? -cb / ca : 0.f, thr);
   mean2d[g] = valid ? u : 0.f;
   mean2d[n + g] = valid ? v : 0.f;
   conic[g] = ca;
@@ -639,6 +646,49 @@ __device__ inline float blend_step(const float4& a, const float4& c1, float px, 
   return w;
 }
 
+// The pixels of a tile in the blend passes: wave w covers the 8 x 8 block
+// (w & 1, w >> 1) of the 16 x 16 tile, lane l its pixel (l & 7, l >> 3).
+__device__ inline void tile_pixel(int t, int TX, int& px, int& py) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  px = (t % TX) * kTile + 8 * (w & 1) + (l & 7);
+  py = (t / TX) * kTile + 8 * (w >> 1) + (l >> 3);
+}
+
+// Whether a splat record can give alpha >= 1/255 at any pixel centre of
+// the rectangle [x0, x1] x [y0, y1]: the base-2 exponent is a concave
+// quadratic, so its largest value there is 0 when the mean is inside, else
+// the best of the four edges, each maximised along its line in closed form
+// (slopes in the record) and clamped to the edge.  The record's threshold
+// is a lower bound with a margin, so the test never drops an entry that a
+// pixel would use.
+__device__ inline bool reaches(const float4& r0, const float4& r1, const float4& r2, float x0,
+                               float x1, float y0, float y1) {
+  const float A = r0.z, B = r0.w, C = r1.x;
+  const float lx = x0 - r0.x, hx = x1 - r0.x, ly = y0 - r0.y, hy = y1 - r0.y;
+  auto ex = [&](float dx, float dy) { return fmaf(A * dx, dx, fmaf(C * dy, dy, (B * dx) * dy)); };
+  const float e0 = ex(lx, fminf(fmaxf(r2.y * lx, ly), hy));
+  const float e1 = ex(hx, fminf(fmaxf(r2.y * hx, ly), hy));
+  const float e2 = ex(fminf(fmaxf(r2.z * ly, lx), hx), ly);
+  const float e3 = ex(fminf(fmaxf(r2.z * hy, lx), hx), hy);
+  const bool inside = lx <= 0.f && hx >= 0.f && ly <= 0.f && hy >= 0.f;
+  return inside || !(fmaxf(fmaxf(e0, e1), fmaxf(e2, e3)) < r2.w);
+}
+
+// Staging-time culling: the calling thread holds the record of entry
+// 64 * qw + lane (valid if `ok`) and tests it against the 8 x 8 pixel block
+// of each of the four waves; one ballot per wave gives that wave's mask for
+// this quarter, stored in wmask[wave][qw].  All 64 lanes must be active.
+__device__ inline void cull_entry(const float4& r0, const float4& r1, const float4& r2, bool ok,
+                                  int t, int TX, int qw, uint64_t (*wmask)[kSubs]) {
+  const float bx = (float)((t % TX) * kTile) + 0.5f, by = (float)((t / TX) * kTile) + 0.5f;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float x0 = bx + 8.f * (w & 1), y0 = by + 8.f * (w >> 1);
+    const uint64_t m = __ballot(ok && reaches(r0, r1, r2, x0, x0 + 7.f, y0, y0 + 7.f));
+    if ((threadIdx.x & 63) == 0) wmask[w][qw] = m;
+  }
+}
+
 // Work items: (tile, chunk of kChunk entries) for the forward passes, and
 // (item, sub-chunk of kSub entries) for the adjoint, numbered tile by tile
 // with one scan over the tiles (the two counts packed in one 64-bit sum).
@@ -721,23 +771,33 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                    const uint32_t* __restrict__ item_sub, uint32_t* __restrict__ sub_item,
                    int64_t max_subs, float* __restrict__ cstate, float* __restrict__ sstate) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  __shared__ uint64_t wmask[4][kSubs];    // per wave and quarter: entries that can reach its pixels
+  __shared__ uint32_t lists[4][kChunk];   // the same, as a list per wave
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
   __syncthreads();                        // the previous item's records are done
   const int t = item_tile[b], j = item_chunk[b];
-  const int tx = t % TX, ty = t / TX;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  int px, py;
+  tile_pixel(t, TX, px, py);
   const int e0 = ranges[2 * t] + j * kChunk;
   const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
   if ((int)threadIdx.x * kSub < cnt) {    // the adjoint's sub-items of this chunk
     const int64_t u = (int64_t)item_sub[b] + threadIdx.x;
     if (u < max_subs) sub_item[u] = ((uint32_t)b << 2) | threadIdx.x;
   }
-  if ((int)threadIdx.x < cnt) {
-    const uint32_t g = sorted[e0 + threadIdx.x];
-    s0[threadIdx.x] = rec[3 * g];
-    s1[threadIdx.x] = rec[3 * g + 1];
-    s2[threadIdx.x] = rec[3 * g + 2];
+  {
+    const bool ok = (int)threadIdx.x < cnt;
+    float4 r0 = {}, r1 = {}, r2 = {};
+    if (ok) {
+      const uint32_t g = sorted[e0 + threadIdx.x];
+      r0 = rec[3 * g];
+      r1 = rec[3 * g + 1];
+      r2 = rec[3 * g + 2];
+      s0[threadIdx.x] = r0;
+      s1[threadIdx.x] = r1;
+      s2[threadIdx.x] = r2;
+    }
+    cull_entry(r0, r1, r2, ok, t, TX, threadIdx.x >> 6, wmask);
   }
   __syncthreads();
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
@@ -745,13 +805,35 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   bool sat = !(px < W && py < H);
   const bool outside = sat;
   float* sub = sstate + (size_t)b * (kSubs - 1) * 1024;
-  int m = 1;                              // next sub-chunk boundary to record
-  for (int k0 = 0; k0 < cnt; k0 += 32) {
-    if (k0 == m * kSub) put_state(sub + (m++ - 1) * 1024, C0, C1, C2, sat ? -T : T);
-    if (__ballot(!sat) == 0ull) break;     // every pixel of this wave saturated
-    const int k1 = min(cnt, k0 + 32);
+  // this wave's entries as a list (quarter after quarter), nq[q] per quarter
+  uint32_t* lst = lists[threadIdx.x >> 6];
+  int nq[kSubs];
+  {
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int base = 0;
+#pragma unroll
+    for (int q = 0; q < kSubs; ++q) {
+      const uint64_t m = wmask[threadIdx.x >> 6][q];
+      if ((m >> lane) & 1ull) lst[base + __popcll(m & below)] = (uint32_t)(q * kSub + lane);
+      nq[q] = __popcll(m);
+      base += nq[q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the wave reads what its lanes wrote
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  bool live = true;                       // some pixel of this wave not saturated
+  int pos = 0;
+#pragma unroll
+  for (int q = 0; q < kSubs; ++q) {
+    if (q * kSub >= cnt) break;
+    if (q > 0) put_state(sub + (q - 1) * 1024, C0, C1, C2, sat ? -T : T);
+    if (live && __ballot(!sat) == 0ull) live = false;
+    const int end = live ? pos + nq[q] : pos;
 #pragma unroll 4
-    for (int k = k0; k < k1; ++k) {
+    for (int i = pos; i < end; ++i) {
+      const int k = (int)lst[i];
       const float4 a = s0[k], c1 = s1[k];
       bool applied;
       float alpha, dx, dy, G, araw;
@@ -760,8 +842,8 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
       C1 = fmaf(c1.w, w, C1);
       C2 = fmaf(s2[k].x, w, C2);
     }
+    pos += nq[q];
   }
-  for (; m < kSubs && m * kSub < cnt; ++m) put_state(sub + (m - 1) * 1024, C0, C1, C2, sat ? -T : T);
   sat = sat && !outside;
   put_state(cstate + (size_t)b * 1024, C0, C1, C2, sat ? -T : T);   // T >= 1e-4 > 0 at a stop
   }
@@ -781,8 +863,8 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
                     float* __restrict__ cstate, int64_t max_items, float* __restrict__ image,
                     float* __restrict__ Tfinal) {
   const int t = blockIdx.x;
-  const int tx = t % TX, ty = t / TX;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  int px, py;
+  tile_pixel(t, TX, px, py);
   const bool inside = px < W && py < H;
   const int64_t i0 = min((int64_t)item_off[t], max_items);
   const int nch = (int)(min((int64_t)item_off[t + 1], max_items) - i0);
@@ -848,8 +930,8 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   const bool mine = code < 0.f && code >= -1.f;
   if (!__syncthreads_or(mine)) continue;
   const int t = item_tile[b], j = item_chunk[b];
-  const int tx = t % TX, ty = t / TX;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  int px, py;
+  tile_pixel(t, TX, px, py);
   const int e0 = ranges[2 * t] + j * kChunk;
   const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
   if ((int)threadIdx.x < cnt) {
@@ -941,8 +1023,8 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
   const int b = (int)(su >> 2), m = (int)(su & 3u);
   if (b >= nitems) continue;
   const int t = item_tile[b], j = item_chunk[b];
-  const int tx = t % TX, ty = t / TX;
-  const int px = tx * kTile + (threadIdx.x & 15), py = ty * kTile + (threadIdx.x >> 4);
+  int px, py;
+  tile_pixel(t, TX, px, py);
   const bool inside = px < W && py < H;
   const int e0 = ranges[2 * t] + j * kChunk + m * kSub;
   const int cnt = min(kSub, ranges[2 * t + 1] - e0);

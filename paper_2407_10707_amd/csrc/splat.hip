@@ -1028,17 +1028,27 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
   const bool inside = px < W && py < H;
   const int e0 = ranges[2 * t] + j * kChunk + m * kSub;
   const int cnt = min(kSub, ranges[2 * t + 1] - e0);
+  // Every wave reads the sub-chunk's records (lane = entry) and keeps a mask
+  // of the entries that can reach its 8 x 8 block; wave 0 stages them.
+  uint64_t mm;
   {
-    const int r = threadIdx.x & (kSub - 1), part = threadIdx.x / kSub;
-    if (r < cnt) {
-      const uint32_t g = sorted[e0 + r];
-      if (part < 3) {
-        float4* dst = part == 0 ? s0 : (part == 1 ? s1 : s2);
-        dst[r] = rec[3 * g + part];
-      } else {
-        sg[r] = g;
+    const bool ok = lane < cnt;
+    float4 r0 = {}, r1 = {}, r2 = {};
+    if (ok) {
+      const uint32_t g = sorted[e0 + lane];
+      r0 = rec[3 * g];
+      r1 = rec[3 * g + 1];
+      r2 = rec[3 * g + 2];
+      if (wave == 0) {
+        s0[lane] = r0;
+        s1[lane] = r1;
+        s2[lane] = r2;
+        sg[lane] = g;
       }
     }
+    const float x0 = (float)((t % TX) * kTile + 8 * (wave & 1)) + 0.5f;
+    const float y0 = (float)((t / TX) * kTile + 8 * (wave >> 1)) + 0.5f;
+    mm = __ballot(ok && reaches(r0, r1, r2, x0, x0 + 7.f, y0, y0 + 7.f));
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) (&acc[0][0][0])[q * 256 + threadIdx.x] = 0.f;
@@ -1076,14 +1086,11 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     g2 = dimage[2 * HW + p];
   }
   __syncthreads();
-  // Entries that touch a pixel of this wave fill eight slots of partials,
-  // which are then summed over the wave in one go (slot s ends in lanes
-  // 8s .. 8s+7) and stored into this wave's LDS slice.  The next entry's
-  // record is read from LDS one step ahead.
-  float4 na = s0[0], nc = s1[0];
-  float ncol = s2[0].x;
-  int k = 0;
-  while (k < cnt && __ballot(!done) != 0ull) {
+  // The listed entries, eight at a time and without branching on whether
+  // any pixel uses them, fill eight slots of partials, which are then summed
+  // over the wave in one go (slot s ends in lanes 8s .. 8s+7) and stored
+  // into this wave's LDS slice.
+  while (mm && __ballot(!done) != 0ull) {
     float v[8][9];
     int kv = 0;                             // entry of this lane's slot
     int ns = 0;                             // slots filled
@@ -1091,45 +1098,36 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
     for (int s = 0; s < 8; ++s) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) v[s][q] = 0.f;
-      bool got = false;
-      while (!got && k < cnt) {
-        const float4 a = na, c1 = nc;
-        const float col2 = ncol;
-        {
-          const int kn = min(k + 1, cnt - 1);
-          na = s0[kn];
-          nc = s1[kn];
-          ncol = s2[kn].x;
-        }
+      if (mm) {
+        const int k = (int)__builtin_ctzll(mm);
+        mm &= mm - 1;
+        const float4 a = s0[k], c1 = s1[k];
+        const float col2 = s2[k].x;
         const float Tb = T;
         bool applied;
         float alpha, dx, dy, G, araw;
         const float w = blend_step(a, c1, fpx, fpy, T, done, applied, alpha, dx, dy, G, araw);
-        got = __ballot(applied) != 0ull;
-        if (got) {
-          A0 = fmaf(c1.z, w, A0);
-          A1 = fmaf(c1.w, w, A1);
-          A2 = fmaf(col2, w, A2);
-          const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
-          const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
-                            g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
-                            g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
-          const bool lin = applied && araw <= 0.99f;   // alpha not clamped
-          const float dp = lin ? dal * alpha : 0.f;     // d/d power
-          const float q = dp * kInvHalfLog2e;           // unscale the record's conic
-          v[s][0] = q * fmaf(0.5f * a.w, dy, a.z * dx);  // d/d mean x
-          v[s][1] = q * fmaf(0.5f * a.w, dx, c1.x * dy); // d/d mean y
-          v[s][2] = -0.5f * dp * dx * dx;               // d/d conic A
-          v[s][3] = -dp * dx * dy;                      // d/d conic B
-          v[s][4] = -0.5f * dp * dy * dy;               // d/d conic C
-          v[s][5] = lin ? dal * G : 0.f;                // d/d opacity
-          v[s][6] = w * g0;                             // d/d colour
-          v[s][7] = w * g1;
-          v[s][8] = w * g2;
-          kv = myslot == s ? k : kv;
-          ++ns;
-        }
-        ++k;
+        A0 = fmaf(c1.z, w, A0);
+        A1 = fmaf(c1.w, w, A1);
+        A2 = fmaf(col2, w, A2);
+        const float inv1m = __builtin_amdgcn_rcpf(1.f - alpha);   // alpha <= 0.99
+        const float dal = g0 * (c1.z * Tb - (Cf0 - A0) * inv1m) +
+                          g1 * (c1.w * Tb - (Cf1 - A1) * inv1m) +
+                          g2 * (col2 * Tb - (Cf2 - A2) * inv1m);
+        const bool lin = applied && araw <= 0.99f;   // alpha not clamped
+        const float dp = lin ? dal * alpha : 0.f;     // d/d power
+        const float q = dp * kInvHalfLog2e;           // unscale the record's conic
+        v[s][0] = q * fmaf(0.5f * a.w, dy, a.z * dx);  // d/d mean x
+        v[s][1] = q * fmaf(0.5f * a.w, dx, c1.x * dy); // d/d mean y
+        v[s][2] = -0.5f * dp * dx * dx;               // d/d conic A
+        v[s][3] = -dp * dx * dy;                      // d/d conic B
+        v[s][4] = -0.5f * dp * dy * dy;               // d/d conic C
+        v[s][5] = lin ? dal * G : 0.f;                // d/d opacity
+        v[s][6] = w * g0;                             // d/d colour
+        v[s][7] = w * g1;
+        v[s][8] = w * g2;
+        kv = myslot == s ? k : kv;
+        ++ns;
       }
     }
     float r[9];

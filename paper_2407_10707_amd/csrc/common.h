@@ -199,6 +199,20 @@ __device__ inline void lds_add(float* p, float x) {
   }
 }
 
+// Three such adds to consecutive floats: one compare-and-swap attempt for
+// each, all three issued before waiting (one LDS round trip when no other
+// lane interferes); a failed attempt falls back to the loop above.
+__device__ inline void lds_add3(float* p, float x0, float x1, float x2) {
+  unsigned* u = reinterpret_cast<unsigned*>(p);
+  const unsigned o0 = u[0], o1 = u[1], o2 = u[2];
+  const unsigned r0 = atomicCAS(u, o0, __float_as_uint(__uint_as_float(o0) + x0));
+  const unsigned r1 = atomicCAS(u + 1, o1, __float_as_uint(__uint_as_float(o1) + x1));
+  const unsigned r2 = atomicCAS(u + 2, o2, __float_as_uint(__uint_as_float(o2) + x2));
+  if (r0 != o0) lds_add(p, x0);
+  if (r1 != o1) lds_add(p + 1, x1);
+  if (r2 != o2) lds_add(p + 2, x2);
+}
+
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 }  // namespace rga

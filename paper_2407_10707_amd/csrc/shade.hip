@@ -132,7 +132,7 @@ __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 struct GaussCtx {
-  float nn[3], wo[3], co, a2, kG, Go, inn, iwo, alpha, ialpha, gamma;
+  float nn[3], wo[3], co, a2, kG, Go, Gq, inn, iwo, alpha, ialpha, gamma;
   float u0, u1, u2;
   const uint8_t* rows;   // LDS copy of the three count rows
   bool front;
@@ -161,6 +161,7 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
   G.a2 = G.alpha * G.alpha;
   G.kG = (G.gamma + 1.f) * (G.gamma + 1.f) * 0.125f;
   G.Go = rcp(fmaf(G.co, 1.f - G.kG, G.kG));
+  G.Gq = G.Go * (0.25f / kPi);                      // the constant factors of W0
   const float ikv = 1.f / (float)a.kv;
   G.u0 = A.vw[0] * ikv;
   G.u1 = A.vw[1] * ikv;
@@ -176,6 +177,7 @@ __device__ inline void gauss_setup(const ShadeArgs& a, const Attr& A, const uint
     G.a2 = uni(G.a2);
     G.kG = uni(G.kG);
     G.Go = uni(G.Go);
+    G.Gq = uni(G.Gq);
     G.inn = uni(G.inn);
     G.iwo = uni(G.iwo);
     G.alpha = uni(G.alpha);
@@ -198,7 +200,7 @@ __device__ inline float live_vis(const GaussCtx& G, const float* tab, int K, int
 }
 
 struct Pair {
-  float d[3], E[3], ci, ok, hh, nht, s2, den, invh, nh, oh, e2, F, hd, D, G1i, deni, ideni, W0, Ws,
+  float d[3], E[3], ci, ok, hh, nht, s2, den, invh, nh, oh, e2, F, hd, D, G1i, deni, ideni, W0F, W0, Ws,
       Wd;
 };
 
@@ -231,11 +233,12 @@ __device__ inline void pair_eval(const GaussCtx& G, const float* tab, int K, int
   P.e2 = __builtin_amdgcn_exp2f((-5.55473f * P.oh - 6.98316f) * P.oh);
   P.F = 0.04f + 0.96f * P.e2;
   P.hd = P.hh * rcp(P.den);                         // 1 / (1 - nh^2 (1 - a^2))
-  P.D = G.a2 * P.hd * P.hd * (1.f / kPi);
+  P.D = G.a2 * P.hd * P.hd;                         // pi D
   P.deni = fmaf(P.ci, 1.f - G.kG, G.kG);
   P.ideni = rcp(P.deni);
   P.G1i = P.ci * P.ideni;
-  P.W0 = v * P.D * P.F * G.Go * 0.25f;
+  P.W0F = v * P.D * G.Gq;                          // W0 / F
+  P.W0 = P.W0F * P.F;
   P.Ws = P.W0 * P.G1i;
   P.Wd = v * P.ci;
 }
@@ -536,19 +539,20 @@ struct BwdAcc {
 // Chain rule through one live pair's weights: upstream gWd = dL/dW_d and
 // gWs = dL/dW_s give the pair's share of dL/dn^, dL/dw_o, dL/d(n.w_o) and
 // dL/dgamma.  Uses the logarithmic derivatives of D (in n.h and alpha), F
-// (in o.h) and G1.
+// (through dF/d(o.h)) and G1.
 __device__ inline void pair_grads(const GaussCtx& G, const Pair& P, float v, float gWd, float gWs,
                                   BwdAcc& acc) {
   const float one_m_a2 = 1.f - G.a2;
   const float dlnD_dnh = 4.f * P.nh * one_m_a2 * P.hd;
   const float dlnD_da = 2.f * G.ialpha - 4.f * G.alpha * P.nh * P.nh * P.hd;
-  const float dlnF_doh =
-      0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f) * rcp(P.F);
+  // dF/d(o.h); gs dlnF/d(o.h) = gWs (W_s / F) dF/d(o.h) needs no 1/F
+  const float dF_doh = 0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f);
   const float gs = gWs * P.Ws;
+  const float gsF = gWs * P.W0F * P.G1i * dF_doh;
   const float ih3 = P.invh * P.invh * P.invh;
   const float gci = gWd * v + gWs * P.W0 * G.kG * (P.ideni * P.ideni) + gs * dlnD_dnh * P.invh;
   const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
-  const float gok = gs * (-dlnD_dnh * P.nht * ih3 + dlnF_doh * 0.5f * P.invh);
+  const float gok = fmaf(gsF, 0.5f * P.invh, gs * (-dlnD_dnh * P.nht * ih3));
   const float dlnG_dk = -(1.f - P.ci) * P.ideni - (1.f - G.co) * G.Go;
   const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
   acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);

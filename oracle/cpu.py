@@ -217,3 +217,15 @@ def project_view(verts, d, res):
     z = np.empty(nv, np.float32)
     lib().oracle_project_view(C.c_int(nv), _p(v), _p(_f(d)), C.c_int(res), _p(U), _p(V), _p(z))
     return U, V, z
+
+
+def knn(q, ref, k):
+    """k nearest rows of ref [3,nr] for every query [3,n], ordered by (distance^2,
+    index), distance^2 in FP32 (rga_oracle.c) -> idx [k,n] int32, d2 [k,n] f32."""
+    q = _f(q)
+    ref = _f(ref)
+    n, nr = q.shape[1], ref.shape[1]
+    idx = np.empty((k, n), np.int32)
+    d2 = np.empty((k, n), np.float32)
+    lib().oracle_knn(C.c_int(n), _p(q), C.c_int(nr), _p(ref), C.c_int(k), _p(idx), _p(d2))
+    return idx, d2

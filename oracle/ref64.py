@@ -325,3 +325,35 @@ def composite(cam, proj, opac, color, pixels: Optional[np.ndarray] = None):
 def l1_loss(image, target):
     """Mean absolute error over all 3HW values (the L1 term of the image loss)."""
     return (image - t64(target)).abs().mean()
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1, interpolation equation: a Gaussian's attribute is the average of
+# its K_g nearest canonical vertices' attributes weighted by
+# u_j = 1 / ||x_g - x_j||.  The neighbour set comes from the FP32 mirror
+# (`cpu.knn`, an integer decision); the weights and the average are taken
+# here in FP64 from the same squared distances.  A query that coincides with
+# a vertex (distance 0) takes that vertex's attribute (the limit of the
+# weights); among several such vertices, the first in (distance, index) order.
+# ---------------------------------------------------------------------------
+def knn_weights(d2):
+    """d2 [k,n] squared distances in (distance, index) order -> w [k,n]."""
+    d2 = t64(d2)
+    k = d2.shape[0]
+    zero = d2[0] == 0
+    u = 1.0 / torch.sqrt(torch.where(zero[None].expand(k, -1), torch.ones_like(d2), d2))
+    w = u / u.sum(dim=0, keepdim=True)
+    first = torch.zeros_like(d2)
+    first[0] = 1.0
+    return torch.where(zero[None].expand(k, -1), first, w)
+
+
+def interpolate(idx, w, attr):
+    """idx [k,n] vertex indices, w [k,n], attr [C,nv] -> [C,n]: sum_t w_t attr[:, idx_t]."""
+    idx = torch.as_tensor(np.asarray(idx), dtype=torch.long)
+    w = t64(w)
+    attr = t64(attr)
+    out = torch.zeros(attr.shape[0], idx.shape[1], dtype=f64)
+    for t in range(idx.shape[0]):
+        out = out + w[t][None] * attr[:, idx[t]]
+    return out

@@ -24,6 +24,8 @@
  *     camera get zero opacity (back-face flag).
  *   - Sec. 3.1, last paragraph: the 3DGS tile rasterizer (projection, tile
  *     binning, depth sort, front-to-back alpha compositing).
+ *   - Sec. 3.1, interpolation equation: the K_g (K_v) nearest canonical
+ *     vertices of each Gaussian (vertex), brute force.
  */
 #include <math.h>
 #include <stdint.h>
@@ -706,4 +708,46 @@ void oracle_composite_brute_f32(int H, int W, int n, const uint8_t* valid, const
     }
   free(list);
   free(items);
+}
+
+/* ---- Sec. 3.1, interpolation equation: the K nearest canonical vertices ----
+ * For every query point (a Gaussian's canonical position) the k reference
+ * points (canonical mesh vertices) with the smallest squared distance,
+ * ordered by (distance^2, index).  distance^2 in FP32 with d = ref - query,
+ * evaluated as fmaf(dz, dz, fmaf(dy, dy, dx * dx)); the order on equal
+ * distances is the lower index first.  Plain brute force over all pairs,
+ * keeping the k best in a sorted array.  k <= nr.                        */
+void oracle_knn(int n, const float* q, int nr, const float* ref, int k, int32_t* idx, float* d2) {
+#pragma omp parallel
+  {
+    float* bd = (float*)malloc(sizeof(float) * (size_t)(k > 0 ? k : 1));
+    int32_t* bi = (int32_t*)malloc(sizeof(int32_t) * (size_t)(k > 0 ? k : 1));
+#pragma omp for schedule(static)
+    for (int i = 0; i < n; ++i) {
+      const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
+      int m = 0;
+      for (int j = 0; j < nr; ++j) {
+        const float dx = ref[j] - qx, dy = ref[nr + j] - qy, dz = ref[2 * nr + j] - qz;
+        const float dd = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        /* j is larger than every index already kept, so on equal distance it
+         * goes after them */
+        if (m == k && !(dd < bd[k - 1])) continue;
+        int p = m < k ? m : k - 1;
+        while (p > 0 && dd < bd[p - 1]) {
+          bd[p] = bd[p - 1];
+          bi[p] = bi[p - 1];
+          --p;
+        }
+        bd[p] = dd;
+        bi[p] = j;
+        if (m < k) ++m;
+      }
+      for (int t = 0; t < k; ++t) {
+        idx[(size_t)t * n + i] = bi[t];
+        d2[(size_t)t * n + i] = bd[t];
+      }
+    }
+    free(bd);
+    free(bi);
+  }
 }

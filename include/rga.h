@@ -227,6 +227,38 @@ int l1_loss(void* stream, int64_t count, const float* image, const float* target
             float* dimage, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
+ * Sec. 3.1, interpolation equation: the K_g (or K_v) nearest canonical mesh
+ * vertices of each Gaussian (or vertex), and the attribute average
+ *   *_g = sum_{j in S_g} u_j *^j / sum_{j in S_g} u_j,  u_j = 1 / |x_g - x_j|.
+ * Neighbours are ordered by (squared distance, vertex index); the squared
+ * distance is computed in FP32 as fmaf(dz, dz, fmaf(dy, dy, dx * dx)) with
+ * d = x_j - x_g, so the sets and their order are exact (ties: lower index
+ * first).  w_t = u_t / sum u (normalised, FP32); a query at distance 0 from
+ * its nearest vertex gets w = (1, 0, ...).  No gradient flows through the
+ * choice of neighbours or the weights (decisions of the method).
+ *
+ * knn_build: ref [3][nr] reference points (e.g. the canonical vertices); ws
+ *   is knn_workspace(nr) bytes of device memory owned by the caller, filled
+ *   with a uniform grid over ref; keep it unmodified while querying.
+ * knn_query: q [3][n] query points; k in 1..min(32, nr); idx [k][n] int32 and
+ *   w [k][n] out (t-th nearest in row t).  Queries may lie outside ref's box.
+ * knn_interpolate: attr [C][nr] vertex attributes -> out [C][n] =
+ *   sum_t w[t][i] attr[c][idx[t][i]] (t in order, FP32).
+ * knn_interpolate_backward: dout [C][n] -> dattr [C][nr] (overwritten) =
+ *   sum over (i, t) with idx[t][i] = j of w[t][i] dout[c][i] (float atomics:
+ *   the summation order varies between runs).
+ * Errors: RGA_EINVAL for bad sizes or NULL pointers, RGA_ECAPACITY for a
+ * short workspace; all calls are asynchronous on `stream`.                  */
+size_t knn_workspace(int nr);
+int knn_build(void* stream, int nr, const float* ref, void* ws, size_t ws_bytes);
+int knn_query(void* stream, int n, const float* q, int nr, int k, int32_t* idx, float* w,
+              const void* ws, size_t ws_bytes);
+int knn_interpolate(void* stream, int n, int k, const int32_t* idx, const float* w, int C, int nr,
+                    const float* attr, float* out);
+int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx, const float* w,
+                             int C, int nr, const float* dout, float* dattr);
+
+/* ------------------------------------------------------------------------
  * Kernel timing with HIP events, for measurement.  While enabled, every
  * kernel launch is bracketed by events on its stream; rga_timing_read
  * synchronises and returns the summed milliseconds and launch count of the

@@ -1,0 +1,391 @@
+// K nearest canonical vertices and the interpolation equation (Sec. 3.1):
+// a Gaussian's attributes are the inverse-distance weighted average of the
+// attributes of its K_g nearest mesh vertices (K_v nearest for the
+// vertex-to-vertex neighbourhood of the visibility filters).
+//
+//   build   (once per reference set, e.g. the canonical mesh) uniform grid of
+//           G^3 cells over the points' bounding box, G ~ (n_ref / 2)^(1/3):
+//           bounds, per-cell counts (atomics), one-workgroup scan, fill of
+//           (x, y, z, index) records in cell order
+//   query   one thread per query point: cells are visited in shells of
+//           growing Chebyshev radius r around the query's cell (the cells
+//           of one row of a shell are contiguous, so their records are one
+//           run); the best k by (distance^2, index) are kept sorted in
+//           registers; the search stops once the k-th distance is below the
+//           distance to any unvisited cell (r cell widths, with a margin for
+//           rounding) or every cell has been visited.  Then the normalised
+//           inverse-distance weights.
+//   interpolate / adjoint   gathers by (query, neighbour) / scatter-adds of
+//           the weighted upstream gradient into the vertex attributes.
+#include "common.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int kMaxK = 32;
+constexpr int kMaxGrid = 64;
+constexpr int kBlock = 256;
+
+int grid_dim(int nr) {
+  int g = (int)ceil(cbrt((double)(nr > 0 ? nr : 1) / 2.0));
+  return g < 1 ? 1 : (g > kMaxGrid ? kMaxGrid : g);
+}
+
+struct KnnLayout {
+  size_t bounds, count, start, cell, rank, recs, total;
+  int G;
+};
+
+KnnLayout knn_layout(int nr) {
+  KnnLayout L{};
+  L.G = grid_dim(nr);
+  const size_t cells = (size_t)L.G * L.G * L.G;
+  const size_t R = (size_t)(nr > 0 ? nr : 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t a = o;
+    o = rga::align_up(o + bytes, 256);
+    return a;
+  };
+  L.bounds = take(16 * 4);
+  L.count = take(cells * 4);
+  L.start = take((cells + 1) * 4);
+  L.cell = take(R * 4);
+  L.rank = take(R * 4);
+  L.recs = take(R * 16);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+// bounds[0..2] origin, [3] G, [4..6] cell size, [8..10] 1 / cell size,
+// [11] smallest cell size; cell counts cleared
+__global__ void __launch_bounds__(1024)
+knn_bounds_kernel(int nr, const float* __restrict__ ref, int G, float* __restrict__ bounds,
+                  uint32_t* __restrict__ count) {
+  __shared__ float ext[6][1024];
+  float lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = ref[a * nr];
+    hi[a] = lo[a];
+  }
+  for (int i = threadIdx.x; i < nr; i += blockDim.x)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float v = ref[a * nr + i];
+      lo[a] = fminf(lo[a], v);
+      hi[a] = fmaxf(hi[a], v);
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ext[a][threadIdx.x] = lo[a];
+    ext[3 + a][threadIdx.x] = hi[a];
+  }
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        ext[a][threadIdx.x] = fminf(ext[a][threadIdx.x], ext[a][threadIdx.x + o]);
+        ext[3 + a][threadIdx.x] = fmaxf(ext[3 + a][threadIdx.x], ext[3 + a][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    float hmin = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float e = ext[3 + a][0] - ext[a][0];
+      const float h = e > 0.f ? e / (float)G : 1.f;
+      bounds[a] = ext[a][0];
+      bounds[4 + a] = h;
+      bounds[8 + a] = 1.f / h;
+      hmin = fminf(hmin, h);
+    }
+    bounds[3] = (float)G;
+    bounds[11] = hmin;
+  }
+  const int cells = G * G * G;
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) count[c] = 0u;
+}
+
+__device__ inline int cell_of(float v, float origin, float inv, int G) {
+  return rga::clampi((int)floorf((v - origin) * inv), 0, G - 1);
+}
+
+__global__ void __launch_bounds__(kBlock)
+knn_count_kernel(int nr, const float* __restrict__ ref, int G, const float* __restrict__ bounds,
+                 uint32_t* __restrict__ count, uint32_t* __restrict__ cell,
+                 uint32_t* __restrict__ rank) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  const int cx = cell_of(ref[i], bounds[0], bounds[8], G);
+  const int cy = cell_of(ref[nr + i], bounds[1], bounds[9], G);
+  const int cz = cell_of(ref[2 * nr + i], bounds[2], bounds[10], G);
+  const uint32_t c = (uint32_t)((cz * G + cy) * G + cx);
+  cell[i] = c;
+  rank[i] = atomicAdd(&count[c], 1u);
+}
+
+// exclusive scan of the cell counts, one workgroup
+__global__ void __launch_bounds__(1024)
+knn_scan_kernel(int cells, const uint32_t* __restrict__ count, uint32_t* __restrict__ start) {
+  __shared__ uint32_t part[1024];
+  const int per = (cells + 1023) / 1024;
+  const int c0 = threadIdx.x * per, c1 = min(cells, c0 + per);
+  uint32_t s = 0;
+  for (int c = c0; c < c1; ++c) s += count[c];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const uint32_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
+  for (int c = c0; c < c1; ++c) {
+    start[c] = run;
+    run += count[c];
+  }
+  if (threadIdx.x == 1023) start[cells] = part[1023];
+}
+
+__global__ void __launch_bounds__(kBlock)
+knn_fill_kernel(int nr, const float* __restrict__ ref, const uint32_t* __restrict__ start,
+                const uint32_t* __restrict__ cell, const uint32_t* __restrict__ rank,
+                float4* __restrict__ recs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nr) return;
+  recs[start[cell[i]] + rank[i]] = make_float4(ref[i], ref[nr + i], ref[2 * nr + i], __int_as_float(i));
+}
+
+// (d, j) before (e, l) in (distance^2, index) order
+__device__ inline bool before(float d, int j, float e, int l) { return d < e || (d == e && j < l); }
+
+// The best k are kept in the last k of KMAX register slots, sorted; the
+// slots before them hold -inf sentinels that nothing is ever placed before,
+// so the worst kept entry is always slot KMAX - 1 (no dynamic register
+// indexing).
+template <int KMAX>
+__global__ void __launch_bounds__(kBlock)
+knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
+                 const uint32_t* __restrict__ start, const float4* __restrict__ recs,
+                 int32_t* __restrict__ idx, float* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int G = (int)bounds[3];
+  const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
+  const int cx = cell_of(qx, bounds[0], bounds[8], G);
+  const int cy = cell_of(qy, bounds[1], bounds[9], G);
+  const int cz = cell_of(qz, bounds[2], bounds[10], G);
+  const float hmin = bounds[11];
+  const int first = KMAX - k;             // slot of the nearest
+  float bd[KMAX];
+  int bi[KMAX];
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    bd[t] = t < first ? -INFINITY : INFINITY;
+    bi[t] = t < first ? -1 : 0x7fffffff;
+  }
+  for (int r = 0; r <= G; ++r) {
+    const int z0 = max(cz - r, 0), z1 = min(cz + r, G - 1);
+    const int y0 = max(cy - r, 0), y1 = min(cy + r, G - 1);
+    for (int z = z0; z <= z1; ++z)
+      for (int y = y0; y <= y1; ++y) {
+        const bool face = abs(z - cz) == r || abs(y - cy) == r;
+        const int row = (z * G + y) * G;
+        // a shell row is either the whole x range (on a z or y face) or
+        // its two end cells
+        for (int side = 0; side < (face ? 1 : 2); ++side) {
+          int x0, x1;
+          if (face) {
+            x0 = max(cx - r, 0);
+            x1 = min(cx + r, G - 1);
+          } else {
+            x0 = x1 = side == 0 ? cx - r : cx + r;
+            if (x0 < 0 || x0 > G - 1) continue;
+          }
+          const uint32_t e0 = start[row + x0], e1 = start[row + x1 + 1];
+          for (uint32_t e = e0; e < e1; ++e) {
+            const float4 p = recs[e];
+            const int j = __float_as_int(p.w);
+            const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+            const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            if (!before(d, j, bd[KMAX - 1], bi[KMAX - 1])) continue;
+            // insert, keeping the slots sorted; the last entry drops out
+            bool placed = false;
+#pragma unroll
+            for (int t = KMAX - 1; t >= 0; --t) {
+              if (placed) continue;
+              if (t > 0 && before(d, j, bd[t - 1], bi[t - 1])) {
+                bd[t] = bd[t - 1];
+                bi[t] = bi[t - 1];
+              } else {
+                bd[t] = d;
+                bi[t] = j;
+                placed = true;
+              }
+            }
+          }
+        }
+      }
+    // unvisited cells are at least r cell widths away (less a margin for
+    // the rounding of cell assignment and distances)
+    const float reach = (float)r * hmin;
+    if (bd[KMAX - 1] < reach * reach * 0.9999f) break;
+  }
+  // normalised inverse-distance weights; a query on a vertex takes it alone
+  bool on_vertex = false;
+  float u[KMAX], s = 0.f;
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    if (t == first) on_vertex = bd[t] == 0.f;
+    u[t] = t >= first ? __builtin_amdgcn_rcpf(__builtin_sqrtf(bd[t])) : 0.f;
+    s += u[t];
+  }
+  const float is = 1.f / s;
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    if (t < first) continue;
+    const size_t o = (size_t)(t - first) * n + i;
+    idx[o] = bi[t];
+    w[o] = on_vertex ? (t == first ? 1.f : 0.f) : u[t] * is;
+  }
+}
+
+template <int KMAX>
+__global__ void __launch_bounds__(kBlock)
+knn_interp_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __restrict__ w,
+                  int C, int nr, const float* __restrict__ attr, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j[KMAX];
+  float wt[KMAX];
+#pragma unroll
+  for (int t = 0; t < KMAX; ++t) {
+    j[t] = t < k ? rga::clampi(idx[(size_t)t * n + i], 0, nr - 1) : 0;
+    wt[t] = t < k ? w[(size_t)t * n + i] : 0.f;
+  }
+  for (int c = 0; c < C; ++c) {
+    const float* a = attr + (size_t)c * nr;
+    float v = 0.f;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t)
+      if (t < k) v = fmaf(wt[t], a[j[t]], v);
+    out[(size_t)c * n + i] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+knn_zero_kernel(float* __restrict__ p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.f;
+}
+
+// one thread per (query, channel): dattr[c][idx_t] += w_t dout[c][i]
+__global__ void __launch_bounds__(kBlock)
+knn_interp_bwd_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __restrict__ w,
+                      int C, int nr, const float* __restrict__ dout, float* __restrict__ dattr) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)n * C) return;
+  const int c = (int)(id / n), i = (int)(id % n);
+  const float g = dout[(size_t)c * n + i];
+  if (g == 0.f) return;
+  for (int t = 0; t < k; ++t) {
+    const int j = rga::clampi(idx[(size_t)t * n + i], 0, nr - 1);
+    atomicAdd(&dattr[(size_t)c * nr + j], w[(size_t)t * n + i] * g);
+  }
+}
+
+}  // namespace
+
+extern "C" size_t knn_workspace(int nr) { return knn_layout(nr).total; }
+
+extern "C" int knn_build(void* stream, int nr, const float* ref, void* ws, size_t ws_bytes) {
+  if (nr < 1) return rga::fail(RGA_EINVAL, "knn_build: nr >= 1");
+  if (!ref || !ws) return rga::fail(RGA_EINVAL, "knn_build: null pointer");
+  const KnnLayout L = knn_layout(nr);
+  if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "knn_build: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int G = L.G, cells = G * G * G;
+  RGA_LAUNCH("knn_bounds", knn_bounds_kernel, dim3(1), dim3(1024), 0, s, nr, ref, G,
+             at<float>(ws, L.bounds), at<uint32_t>(ws, L.count));
+  RGA_LAUNCH("knn_count", knn_count_kernel, dim3(rga::ceil_div(nr, kBlock)), dim3(kBlock), 0, s,
+             nr, ref, G, at<float>(ws, L.bounds), at<uint32_t>(ws, L.count),
+             at<uint32_t>(ws, L.cell), at<uint32_t>(ws, L.rank));
+  RGA_LAUNCH("knn_scan", knn_scan_kernel, dim3(1), dim3(1024), 0, s, cells,
+             at<uint32_t>(ws, L.count), at<uint32_t>(ws, L.start));
+  RGA_LAUNCH("knn_fill", knn_fill_kernel, dim3(rga::ceil_div(nr, kBlock)), dim3(kBlock), 0, s, nr,
+             ref, at<uint32_t>(ws, L.start), at<uint32_t>(ws, L.cell), at<uint32_t>(ws, L.rank),
+             at<float4>(ws, L.recs));
+  RGA_CHECK_LAUNCH("knn_build");
+  return RGA_OK;
+}
+
+extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int32_t* idx,
+                         float* w, const void* ws, size_t ws_bytes) {
+  if (n < 0 || nr < 1) return rga::fail(RGA_EINVAL, "knn_query: n >= 0 and nr >= 1");
+  if (k < 1 || k > kMaxK || k > nr)
+    return rga::fail(RGA_EINVAL, "knn_query: k must be in 1..min(%d, nr)", kMaxK);
+  if (n == 0) return RGA_OK;
+  if (!q || !idx || !w || !ws) return rga::fail(RGA_EINVAL, "knn_query: null pointer");
+  const KnnLayout L = knn_layout(nr);
+  if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "knn_query: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void* W = const_cast<void*>(ws);
+  const dim3 grid(rga::ceil_div(n, kBlock));
+  if (k <= 4)
+    RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
+               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
+  else
+    RGA_LAUNCH("knn_query", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
+               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
+  RGA_CHECK_LAUNCH("knn_query");
+  return RGA_OK;
+}
+
+extern "C" int knn_interpolate(void* stream, int n, int k, const int32_t* idx, const float* w,
+                               int C, int nr, const float* attr, float* out) {
+  if (n < 0 || C < 0 || nr < 1 || k < 1 || k > kMaxK)
+    return rga::fail(RGA_EINVAL, "knn_interpolate: bad size");
+  if (n == 0 || C == 0) return RGA_OK;
+  if (!idx || !w || !attr || !out) return rga::fail(RGA_EINVAL, "knn_interpolate: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(rga::ceil_div(n, kBlock));
+  if (k <= 4)
+    RGA_LAUNCH("knn_interp", knn_interp_kernel<4>, grid, dim3(kBlock), 0, s, n, k, idx, w, C, nr,
+               attr, out);
+  else
+    RGA_LAUNCH("knn_interp", knn_interp_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, k, idx, w, C,
+               nr, attr, out);
+  RGA_CHECK_LAUNCH("knn_interpolate");
+  return RGA_OK;
+}
+
+extern "C" int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx,
+                                        const float* w, int C, int nr, const float* dout,
+                                        float* dattr) {
+  if (n < 0 || C < 0 || nr < 1 || k < 1 || k > kMaxK)
+    return rga::fail(RGA_EINVAL, "knn_interpolate_backward: bad size");
+  if (C == 0) return RGA_OK;
+  if (!dattr || (n > 0 && (!idx || !w || !dout)))
+    return rga::fail(RGA_EINVAL, "knn_interpolate_backward: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t za = (int64_t)C * nr;
+  RGA_LAUNCH("knn_interp_zero", knn_zero_kernel, dim3(rga::ceil_div(za, kBlock)), dim3(kBlock), 0,
+             s, dattr, za);
+  if (n > 0) {
+    const int64_t t = (int64_t)n * C;
+    RGA_LAUNCH("knn_interp_bwd", knn_interp_bwd_kernel, dim3(rga::ceil_div(t, kBlock)),
+               dim3(kBlock), 0, s, n, k, idx, w, C, nr, dout, dattr);
+  }
+  RGA_CHECK_LAUNCH("knn_interpolate_backward");
+  return RGA_OK;
+}

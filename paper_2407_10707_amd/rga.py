@@ -51,6 +51,11 @@ _SIGS = {
                             _VP, _VP, _VP, _VP, _VP, _VP]),
     "l1_loss_workspace": (_SZ, [_I64]),
     "l1_loss": (_I, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _SZ]),
+    "knn_workspace": (_SZ, [_I]),
+    "knn_build": (_I, [_VP, _I, _VP, _VP, _SZ]),
+    "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ]),
+    "knn_interpolate": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
+    "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "rga_timing_enable": (_I, [_I]),
     "rga_timing_reset": (_I, []),
     "rga_timing_filter": (_I, [C.c_char_p]),
@@ -325,6 +330,58 @@ def l1_loss(image, target, want_grad: bool = True, ws=None):
 
 
 # ----------------------------------------------------------------------------- timing
+class KnnIndex:
+    """Uniform grid over a reference point set (e.g. the canonical mesh
+    vertices), built on the device; query it with `knn`."""
+
+    def __init__(self, ref):
+        ref = _f32(ref, "ref")
+        if ref.dim() != 2 or ref.shape[0] != 3:
+            raise RgaError("ref must be [3, nr]")
+        self.ref = ref
+        self.nr = int(ref.shape[1])
+        self.bytes = int(lib().knn_workspace(self.nr))
+        self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=ref.device)
+        _check(lib().knn_build(_stream(), self.nr, _p(ref), _p(self.buf), self.bytes), "knn_build")
+
+
+def knn(index: KnnIndex, q, k: int):
+    """(idx [k,n] int32, w [k,n]) of the k nearest reference points of q [3,n]."""
+    q = _f32(q, "q")
+    n = int(q.shape[1])
+    idx = torch.empty((k, n), dtype=torch.int32, device=q.device)
+    w = torch.empty((k, n), dtype=torch.float32, device=q.device)
+    _check(lib().knn_query(_stream(), n, _p(q), index.nr, int(k), _p(idx), _p(w), _p(index.buf),
+                           index.bytes), "knn_query")
+    return idx, w
+
+
+def knn_interpolate(idx, w, attr):
+    """attr [C, nr] -> [C, n] with the weights of `knn`."""
+    idx = _i32(idx, "idx")
+    w = _f32(w, "w")
+    attr = _f32(attr, "attr")
+    k, n = int(idx.shape[0]), int(idx.shape[1])
+    C_, nr = int(attr.shape[0]), int(attr.shape[1])
+    out = torch.empty((C_, n), dtype=torch.float32, device=attr.device)
+    _check(lib().knn_interpolate(_stream(), n, k, _p(idx), _p(w), C_, nr, _p(attr), _p(out)),
+           "knn_interpolate")
+    return out
+
+
+def knn_interpolate_backward(idx, w, dout, nr: int):
+    """dout [C, n] -> dattr [C, nr]."""
+    idx = _i32(idx, "idx")
+    w = _f32(w, "w")
+    dout = _f32(dout, "dout")
+    k, n = int(idx.shape[0]), int(idx.shape[1])
+    C_ = int(dout.shape[0])
+    dattr = torch.empty((C_, nr), dtype=torch.float32, device=dout.device)
+    _check(lib().knn_interpolate_backward(_stream(), n, k, _p(idx), _p(w), C_, int(nr), _p(dout),
+                                          _p(dattr)), "knn_interpolate_backward")
+    return dattr
+
+
 def timing_enable(on: bool = True):
     _check(lib().rga_timing_enable(int(on)), "rga_timing_enable")
 

@@ -46,6 +46,7 @@ def test_workspace_sizes_are_monotone():
     assert L.mesh_visibility_workspace(6840, 512) > 6840 * 512 // 8
     assert L.shade_gaussians_workspace(100000, 16, 32) > 0
     assert L.l1_loss_workspace(3 * 512 * 512) > 0
+    assert L.knn_workspace(6840) > 6840 * 16
 
 
 def test_argument_errors_are_reported_before_any_launch():
@@ -66,3 +67,8 @@ def test_argument_errors_are_reported_before_any_launch():
                              16, 32, 5, 32, None, C.cast(cp, C.c_void_p), 0, None, None) == -1
     assert "divide" in rga.last_error()
     assert L.l1_loss(None, 0, None, None, None, None, None, 0) == -1
+    assert L.knn_query(None, 10, None, 5, 6, None, None, None, 0) == -1
+    assert "k must be" in rga.last_error()
+    assert L.knn_query(None, 10, None, 5, 0, None, None, None, 0) == -1
+    assert L.knn_build(None, 0, None, None, 0) == -1
+    assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1

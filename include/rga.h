@@ -245,8 +245,9 @@ int l1_loss(void* stream, int64_t count, const float* image, const float* target
  * knn_interpolate: attr [C][nr] vertex attributes -> out [C][n] =
  *   sum_t w[t][i] attr[c][idx[t][i]] (t in order, FP32).
  * knn_interpolate_backward: dout [C][n] -> dattr [C][nr] (overwritten) =
- *   sum over (i, t) with idx[t][i] = j of w[t][i] dout[c][i] (float atomics:
- *   the summation order varies between runs).
+ *   sum over (i, t) with idx[t][i] = j of w[t][i] dout[c][i] (partial sums
+ *   per workgroup, added with float atomics: the rounding of the sum may
+ *   vary between runs).  C <= 65535.
  * Errors: RGA_EINVAL for bad sizes or NULL pointers, RGA_ECAPACITY for a
  * short workspace; all calls are asynchronous on `stream`.                  */
 size_t knn_workspace(int nr);

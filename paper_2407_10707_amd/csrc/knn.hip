@@ -4,43 +4,40 @@
 // vertex-to-vertex neighbourhood of the visibility filters).
 //
 //   build   (once per reference set, e.g. the canonical mesh) uniform grid of
-//           G^3 cells over the points' bounding box, G ~ (n_ref / 2)^(1/3):
-//           bounds, per-cell counts (atomics), one-workgroup scan, fill of
-//           (x, y, z, index) records in cell order
-//   query   one thread per query point: cells are visited in shells of
-//           growing Chebyshev radius r around the query's cell (the cells
-//           of one row of a shell are contiguous, so their records are one
-//           run); the best k by (distance^2, index) are kept sorted in
-//           registers; the search stops once the k-th distance is below the
-//           distance to any unvisited cell (r cell widths, with a margin for
-//           rounding) or every cell has been visited.  Then the normalised
+//           cubic cells over the points' bounding box, about two points per
+//           cell and at most kMaxCells cells: bounds and cell size, per-cell
+//           counts (atomics), one-workgroup scan, fill of (x, y, z, index)
+//           records in cell order
+//   query   one thread per query point, the cell-start table staged in LDS
+//           per workgroup: cells are visited in shells of growing Chebyshev
+//           radius r around the query's cell (the cells of one row of a
+//           shell are contiguous, so their records are one run); the best k
+//           by (distance^2, index) are kept sorted in registers; the search
+//           stops once the k-th distance is below the distance to any
+//           unvisited cell (r cell widths, with a margin for rounding) or
+//           every cell has been visited.  Then the normalised
 //           inverse-distance weights.
-//   interpolate / adjoint   gathers by (query, neighbour) / scatter-adds of
-//           the weighted upstream gradient into the vertex attributes.
+//   interpolate   gathers by (query, neighbour)
+//   adjoint  per (query chunk, channel, vertex range) workgroup: LDS sums,
+//           then coalesced atomic adds into the vertex attributes
 #include "common.h"
 
+#include <algorithm>
 #include <math.h>
 
 namespace {
 
 constexpr int kMaxK = 32;
-constexpr int kMaxGrid = 64;
+constexpr int kMaxCells = 8192;          // cell-start table of 32 KB in LDS
 constexpr int kBlock = 256;
-
-int grid_dim(int nr) {
-  int g = (int)ceil(cbrt((double)(nr > 0 ? nr : 1) / 2.0));
-  return g < 1 ? 1 : (g > kMaxGrid ? kMaxGrid : g);
-}
+constexpr int kBatch = 8;                // candidate records loaded together
 
 struct KnnLayout {
   size_t bounds, count, start, cell, rank, recs, total;
-  int G;
 };
 
 KnnLayout knn_layout(int nr) {
   KnnLayout L{};
-  L.G = grid_dim(nr);
-  const size_t cells = (size_t)L.G * L.G * L.G;
   const size_t R = (size_t)(nr > 0 ? nr : 1);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -49,8 +46,8 @@ KnnLayout knn_layout(int nr) {
     return a;
   };
   L.bounds = take(16 * 4);
-  L.count = take(cells * 4);
-  L.start = take((cells + 1) * 4);
+  L.count = take((size_t)kMaxCells * 4);
+  L.start = take(((size_t)kMaxCells + 1) * 4);
   L.cell = take(R * 4);
   L.rank = take(R * 4);
   L.recs = take(R * 16);
@@ -63,12 +60,13 @@ T* at(void* ws, size_t off) {
   return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
-// bounds[0..2] origin, [3] G, [4..6] cell size, [8..10] 1 / cell size,
-// [11] smallest cell size; cell counts cleared
+// bounds[0..2] origin, [3] 1 / cell size, [4] cell size, [5..7] cells per
+// axis (as floats), [8] cell count; cell counts cleared
 __global__ void __launch_bounds__(1024)
-knn_bounds_kernel(int nr, const float* __restrict__ ref, int G, float* __restrict__ bounds,
+knn_bounds_kernel(int nr, const float* __restrict__ ref, float* __restrict__ bounds,
                   uint32_t* __restrict__ count) {
   __shared__ float ext[6][1024];
+  __shared__ int ncells;
   float lo[3], hi[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -98,21 +96,46 @@ knn_bounds_kernel(int nr, const float* __restrict__ ref, int G, float* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    float hmin = INFINITY;
+    // cubic cells holding about two points each (the box's volume with each
+    // side at least 1e-3 of the longest), enlarged until the grid fits
+    float e[3], emax = 0.f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float e = ext[3 + a][0] - ext[a][0];
-      const float h = e > 0.f ? e / (float)G : 1.f;
-      bounds[a] = ext[a][0];
-      bounds[4 + a] = h;
-      bounds[8 + a] = 1.f / h;
-      hmin = fminf(hmin, h);
+      e[a] = ext[3 + a][0] - ext[a][0];
+      emax = fmaxf(emax, e[a]);
     }
-    bounds[3] = (float)G;
-    bounds[11] = hmin;
+    if (!(emax > 0.f)) emax = 1.f;
+    const float floor_e = 1e-3f * emax;
+    const float vol = fmaxf(e[0], floor_e) * fmaxf(e[1], floor_e) * fmaxf(e[2], floor_e);
+    float h = cbrtf(vol / fminf(fmaxf(0.5f * (float)nr, 1.f), (float)kMaxCells));
+    int g[3], cells = 0;
+    for (int it = 0; it < 64; ++it) {
+      cells = 1;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        g[a] = max(1, min(1024, (int)ceilf(e[a] / h)));
+        cells *= g[a];
+      }
+      if (cells <= kMaxCells) break;
+      h *= 1.1f;
+    }
+    if (cells > kMaxCells) {   // unreachable for finite inputs; one cell then
+      g[0] = g[1] = g[2] = 1;
+      cells = 1;
+      h = emax;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bounds[a] = ext[a][0];
+      bounds[5 + a] = (float)g[a];
+    }
+    bounds[3] = 1.f / h;
+    bounds[4] = h;
+    bounds[8] = (float)cells;
+    ncells = cells;
   }
-  const int cells = G * G * G;
-  for (int c = threadIdx.x; c < cells; c += blockDim.x) count[c] = 0u;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncells; c += blockDim.x) count[c] = 0u;
 }
 
 __device__ inline int cell_of(float v, float origin, float inv, int G) {
@@ -120,23 +143,26 @@ __device__ inline int cell_of(float v, float origin, float inv, int G) {
 }
 
 __global__ void __launch_bounds__(kBlock)
-knn_count_kernel(int nr, const float* __restrict__ ref, int G, const float* __restrict__ bounds,
+knn_count_kernel(int nr, const float* __restrict__ ref, const float* __restrict__ bounds,
                  uint32_t* __restrict__ count, uint32_t* __restrict__ cell,
                  uint32_t* __restrict__ rank) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nr) return;
-  const int cx = cell_of(ref[i], bounds[0], bounds[8], G);
-  const int cy = cell_of(ref[nr + i], bounds[1], bounds[9], G);
-  const int cz = cell_of(ref[2 * nr + i], bounds[2], bounds[10], G);
-  const uint32_t c = (uint32_t)((cz * G + cy) * G + cx);
+  const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
+  const int cx = cell_of(ref[i], bounds[0], bounds[3], gx);
+  const int cy = cell_of(ref[nr + i], bounds[1], bounds[3], gy);
+  const int cz = cell_of(ref[2 * nr + i], bounds[2], bounds[3], gz);
+  const uint32_t c = (uint32_t)((cz * gy + cy) * gx + cx);
   cell[i] = c;
   rank[i] = atomicAdd(&count[c], 1u);
 }
 
 // exclusive scan of the cell counts, one workgroup
 __global__ void __launch_bounds__(1024)
-knn_scan_kernel(int cells, const uint32_t* __restrict__ count, uint32_t* __restrict__ start) {
+knn_scan_kernel(const float* __restrict__ bounds, const uint32_t* __restrict__ count,
+                uint32_t* __restrict__ start) {
   __shared__ uint32_t part[1024];
+  const int cells = (int)bounds[8];
   const int per = (cells + 1023) / 1024;
   const int c0 = threadIdx.x * per, c1 = min(cells, c0 + per);
   uint32_t s = 0;
@@ -178,14 +204,19 @@ __global__ void __launch_bounds__(kBlock)
 knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
                  const uint32_t* __restrict__ start, const float4* __restrict__ recs,
                  int32_t* __restrict__ idx, float* __restrict__ w) {
+  __shared__ uint32_t st[kMaxCells + 1];
+  const int cells = (int)bounds[8];
+  for (int c = threadIdx.x; c <= cells; c += blockDim.x) st[c] = start[c];
+  __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int G = (int)bounds[3];
+  const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
   const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
-  const int cx = cell_of(qx, bounds[0], bounds[8], G);
-  const int cy = cell_of(qy, bounds[1], bounds[9], G);
-  const int cz = cell_of(qz, bounds[2], bounds[10], G);
-  const float hmin = bounds[11];
+  const int cx = cell_of(qx, bounds[0], bounds[3], gx);
+  const int cy = cell_of(qy, bounds[1], bounds[3], gy);
+  const int cz = cell_of(qz, bounds[2], bounds[3], gz);
+  const float h = bounds[4];
+  const int rmax = max(gx, max(gy, gz));
   const int first = KMAX - k;             // slot of the nearest
   float bd[KMAX];
   int bi[KMAX];
@@ -194,43 +225,52 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
     bd[t] = t < first ? -INFINITY : INFINITY;
     bi[t] = t < first ? -1 : 0x7fffffff;
   }
-  for (int r = 0; r <= G; ++r) {
-    const int z0 = max(cz - r, 0), z1 = min(cz + r, G - 1);
-    const int y0 = max(cy - r, 0), y1 = min(cy + r, G - 1);
+  for (int r = 0; r <= rmax; ++r) {
+    const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
+    const int y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
     for (int z = z0; z <= z1; ++z)
       for (int y = y0; y <= y1; ++y) {
         const bool face = abs(z - cz) == r || abs(y - cy) == r;
-        const int row = (z * G + y) * G;
+        const int row = (z * gy + y) * gx;
         // a shell row is either the whole x range (on a z or y face) or
         // its two end cells
         for (int side = 0; side < (face ? 1 : 2); ++side) {
           int x0, x1;
           if (face) {
             x0 = max(cx - r, 0);
-            x1 = min(cx + r, G - 1);
+            x1 = min(cx + r, gx - 1);
           } else {
             x0 = x1 = side == 0 ? cx - r : cx + r;
-            if (x0 < 0 || x0 > G - 1) continue;
+            if (x0 < 0 || x0 > gx - 1) continue;
           }
-          const uint32_t e0 = start[row + x0], e1 = start[row + x1 + 1];
-          for (uint32_t e = e0; e < e1; ++e) {
-            const float4 p = recs[e];
-            const int j = __float_as_int(p.w);
-            const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
-            const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            if (!before(d, j, bd[KMAX - 1], bi[KMAX - 1])) continue;
-            // insert, keeping the slots sorted; the last entry drops out
-            bool placed = false;
+          const uint32_t e0 = st[row + x0], e1 = st[row + x1 + 1];
+          // records in batches of kBatch, loaded together
+          for (uint32_t e = e0; e < e1; e += kBatch) {
+            float4 pb[kBatch];
 #pragma unroll
-            for (int t = KMAX - 1; t >= 0; --t) {
-              if (placed) continue;
-              if (t > 0 && before(d, j, bd[t - 1], bi[t - 1])) {
-                bd[t] = bd[t - 1];
-                bi[t] = bi[t - 1];
-              } else {
-                bd[t] = d;
-                bi[t] = j;
-                placed = true;
+            for (int u = 0; u < kBatch; ++u)
+              pb[u] = e + u < e1 ? recs[e + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+              if (e + u >= e1) continue;
+              const float4 p = pb[u];
+              const int j = __float_as_int(p.w);
+              const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
+              const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              if (!before(d, j, bd[KMAX - 1], bi[KMAX - 1])) continue;
+              // insert, keeping the slots sorted; the last entry drops out
+              bool placed = false;
+#pragma unroll
+              for (int t = KMAX - 1; t >= 0; --t) {
+                if (placed) continue;
+                if (t > 0 && before(d, j, bd[t - 1], bi[t - 1])) {
+                  bd[t] = bd[t - 1];
+                  bi[t] = bi[t - 1];
+                } else {
+                  bd[t] = d;
+                  bi[t] = j;
+                  placed = true;
+                }
               }
             }
           }
@@ -238,7 +278,7 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
       }
     // unvisited cells are at least r cell widths away (less a margin for
     // the rounding of cell assignment and distances)
-    const float reach = (float)r * hmin;
+    const float reach = (float)r * h;
     if (bd[KMAX - 1] < reach * reach * 0.9999f) break;
   }
   // normalised inverse-distance weights; a query on a vertex takes it alone
@@ -273,13 +313,20 @@ knn_interp_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __
     j[t] = t < k ? rga::clampi(idx[(size_t)t * n + i], 0, nr - 1) : 0;
     wt[t] = t < k ? w[(size_t)t * n + i] : 0.f;
   }
-  for (int c = 0; c < C; ++c) {
-    const float* a = attr + (size_t)c * nr;
-    float v = 0.f;
+  // four channels per step, so that their gathers are in flight together
+  for (int c0 = 0; c0 < C; c0 += 4) {
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < KMAX; ++t)
-      if (t < k) v = fmaf(wt[t], a[j[t]], v);
-    out[(size_t)c * n + i] = v;
+    for (int u = 0; u < 4; ++u) {
+      if (c0 + u >= C) continue;
+      const float* a = attr + (size_t)(c0 + u) * nr;
+#pragma unroll
+      for (int t = 0; t < KMAX; ++t)
+        if (t < k) v[u] = fmaf(wt[t], a[j[t]], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (c0 + u < C) out[(size_t)(c0 + u) * n + i] = v[u];
   }
 }
 
@@ -289,18 +336,36 @@ knn_zero_kernel(float* __restrict__ p, int64_t count) {
   if (i < count) p[i] = 0.f;
 }
 
-// one thread per (query, channel): dattr[c][idx_t] += w_t dout[c][i]
+// Adjoint of the average, one workgroup per (chunk of queries, channel,
+// range of kVRange vertices): the chunk's w dout terms for vertices in the
+// range are summed in LDS (integer compare-and-swap adds), then added to
+// dattr with coalesced atomics, one per vertex of the range.  (Global float
+// atomics at scattered addresses are far slower on this part.)
+constexpr int kVRange = 16384;           // 64 KB of LDS
 __global__ void __launch_bounds__(kBlock)
 knn_interp_bwd_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __restrict__ w,
-                      int C, int nr, const float* __restrict__ dout, float* __restrict__ dattr) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= (int64_t)n * C) return;
-  const int c = (int)(id / n), i = (int)(id % n);
-  const float g = dout[(size_t)c * n + i];
-  if (g == 0.f) return;
-  for (int t = 0; t < k; ++t) {
-    const int j = rga::clampi(idx[(size_t)t * n + i], 0, nr - 1);
-    atomicAdd(&dattr[(size_t)c * nr + j], w[(size_t)t * n + i] * g);
+                      int nr, const float* __restrict__ dout, float* __restrict__ dattr,
+                      int chunk) {
+  __shared__ float acc[kVRange];
+  const int c = blockIdx.y;
+  const int v0 = blockIdx.z * kVRange, vn = min(kVRange, nr - v0);
+  const int q0 = blockIdx.x * chunk, q1 = min(n, q0 + chunk);
+  for (int j = threadIdx.x; j < vn; j += blockDim.x) acc[j] = 0.f;
+  __syncthreads();
+  const float* g = dout + (size_t)c * n;
+  for (int i = q0 + threadIdx.x; i < q1; i += blockDim.x) {
+    const float gi = g[i];
+    if (gi == 0.f) continue;
+    for (int t = 0; t < k; ++t) {
+      const int j = idx[(size_t)t * n + i] - v0;
+      if (j >= 0 && j < vn) rga::lds_add(&acc[j], w[(size_t)t * n + i] * gi);
+    }
+  }
+  __syncthreads();
+  float* out = dattr + (size_t)c * nr + v0;
+  for (int j = threadIdx.x; j < vn; j += blockDim.x) {
+    const float a = acc[j];
+    if (a != 0.f) atomicAdd(&out[j], a);
   }
 }
 
@@ -314,13 +379,12 @@ extern "C" int knn_build(void* stream, int nr, const float* ref, void* ws, size_
   const KnnLayout L = knn_layout(nr);
   if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "knn_build: workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int G = L.G, cells = G * G * G;
-  RGA_LAUNCH("knn_bounds", knn_bounds_kernel, dim3(1), dim3(1024), 0, s, nr, ref, G,
+  RGA_LAUNCH("knn_bounds", knn_bounds_kernel, dim3(1), dim3(1024), 0, s, nr, ref,
              at<float>(ws, L.bounds), at<uint32_t>(ws, L.count));
   RGA_LAUNCH("knn_count", knn_count_kernel, dim3(rga::ceil_div(nr, kBlock)), dim3(kBlock), 0, s,
-             nr, ref, G, at<float>(ws, L.bounds), at<uint32_t>(ws, L.count),
+             nr, ref, at<float>(ws, L.bounds), at<uint32_t>(ws, L.count),
              at<uint32_t>(ws, L.cell), at<uint32_t>(ws, L.rank));
-  RGA_LAUNCH("knn_scan", knn_scan_kernel, dim3(1), dim3(1024), 0, s, cells,
+  RGA_LAUNCH("knn_scan", knn_scan_kernel, dim3(1), dim3(1024), 0, s, at<float>(ws, L.bounds),
              at<uint32_t>(ws, L.count), at<uint32_t>(ws, L.start));
   RGA_LAUNCH("knn_fill", knn_fill_kernel, dim3(rga::ceil_div(nr, kBlock)), dim3(kBlock), 0, s, nr,
              ref, at<uint32_t>(ws, L.start), at<uint32_t>(ws, L.cell), at<uint32_t>(ws, L.rank),
@@ -345,7 +409,7 @@ extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int
     RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
                at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
   else
-    RGA_LAUNCH("knn_query", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
+    RGA_LAUNCH("knn_query_wide", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
                at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
   RGA_CHECK_LAUNCH("knn_query");
   return RGA_OK;
@@ -372,7 +436,7 @@ extern "C" int knn_interpolate(void* stream, int n, int k, const int32_t* idx, c
 extern "C" int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx,
                                         const float* w, int C, int nr, const float* dout,
                                         float* dattr) {
-  if (n < 0 || C < 0 || nr < 1 || k < 1 || k > kMaxK)
+  if (n < 0 || C < 0 || nr < 1 || k < 1 || k > kMaxK || C > 65535)
     return rga::fail(RGA_EINVAL, "knn_interpolate_backward: bad size");
   if (C == 0) return RGA_OK;
   if (!dattr || (n > 0 && (!idx || !w || !dout)))
@@ -382,9 +446,12 @@ extern "C" int knn_interpolate_backward(void* stream, int n, int k, const int32_
   RGA_LAUNCH("knn_interp_zero", knn_zero_kernel, dim3(rga::ceil_div(za, kBlock)), dim3(kBlock), 0,
              s, dattr, za);
   if (n > 0) {
-    const int64_t t = (int64_t)n * C;
-    RGA_LAUNCH("knn_interp_bwd", knn_interp_bwd_kernel, dim3(rga::ceil_div(t, kBlock)),
-               dim3(kBlock), 0, s, n, k, idx, w, C, nr, dout, dattr);
+    const int ranges = (int)rga::ceil_div(nr, kVRange);
+    const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(rga::ceil_div(n, kBlock),
+                                                                   512 / ((int64_t)C * ranges)));
+    const int chunk = (int)rga::ceil_div(n, chunks);
+    RGA_LAUNCH("knn_interp_bwd", knn_interp_bwd_kernel, dim3(chunks, C, ranges), dim3(kBlock), 0,
+               s, n, k, idx, w, nr, dout, dattr, chunk);
   }
   RGA_CHECK_LAUNCH("knn_interpolate_backward");
   return RGA_OK;

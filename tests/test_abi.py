@@ -72,3 +72,4 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.knn_query(None, 10, None, 5, 0, None, None, None, 0) == -1
     assert L.knn_build(None, 0, None, None, 0) == -1
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
+    assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1

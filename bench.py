@@ -199,38 +199,38 @@ def knn_measure(s, d, reps: int = 20):
     (Sec. 3.1) at the workload's sizes, outside the timed step: K_g = 3
     nearest canonical vertices of every Gaussian, K_v = 19 of every vertex,
     and the average of 42 attribute channels (r 4, s 3, n 3, a 3, gamma,
-    p, w 24, dx 3) with its adjoint.  Kernel times from HIP events."""
+    p, w 24, dx 3) with its adjoint.  Sums of kernel times from HIP events,
+    per call."""
     import torch
     from paper_2407_10707_amd import rga
     n, nv = int(s["n"]), int(s["nv"])
-    rga.timing_reset()
-    rga.timing_filter(None)
-    rga.timing_enable(True)
-    for _ in range(reps):
-        index = rga.KnnIndex(d["verts"])
-    idx, w = rga.knn(index, d["pos"], 3)
     attr = torch.rand((42, nv), device="cuda")
     dout = torch.rand((42, n), device="cuda")
-    for _ in range(reps):
-        idx, w = rga.knn(index, d["pos"], 3)
-        vi, vw = rga.knn(index, d["verts"], 19)
-        out = rga.knn_interpolate(idx, w, attr)
-        da = rga.knn_interpolate_backward(idx, w, dout, nv)
-    torch.cuda.synchronize()
-    rga.timing_enable(False)
-    t = {}
-    for name in ("knn_bounds", "knn_count", "knn_scan", "knn_fill", "knn_query", "knn_query_wide",
-                 "knn_interp", "knn_interp_zero", "knn_interp_bwd"):
-        ms, cnt = rga.timing_read(name)
-        t[name] = (ms, cnt)
-    del out, da, vi, vw
-    build = sum(t[k][0] for k in ("knn_bounds", "knn_count", "knn_scan", "knn_fill")) / reps
+    index = rga.KnnIndex(d["verts"])
+    idx, w = rga.knn(index, d["pos"], 3)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        rga.timing_reset()
+        rga.timing_filter(None)
+        rga.timing_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        rga.timing_enable(False)
+        tot = 0.0
+        for name in ("knn_bounds", "knn_count", "knn_scan", "knn_fill", "knn_qzero", "knn_qcell",
+                     "knn_qscan", "knn_qfill", "knn_query", "knn_query_wide", "knn_interp",
+                     "knn_interp_zero", "knn_interp_bwd"):
+            tot += rga.timing_read(name)[0]
+        return round(tot / reps, 4)
+
     return {"refs": nv, "queries": n, "k_g": 3, "k_v": 19, "channels": 42,
-            "build_ms": round(build, 4),
-            "gaussian_query_ms": round(t["knn_query"][0] / reps, 4),
-            "vertex_query_ms": round(t["knn_query_wide"][0] / reps, 4),
-            "interp_ms": round(t["knn_interp"][0] / reps, 4),
-            "interp_bwd_ms": round((t["knn_interp_zero"][0] + t["knn_interp_bwd"][0]) / reps, 4)}
+            "build_ms": timed(lambda: rga.KnnIndex(d["verts"])),
+            "gaussian_query_ms": timed(lambda: rga.knn(index, d["pos"], 3)),
+            "vertex_query_ms": timed(lambda: rga.knn(index, d["verts"], 19)),
+            "interp_ms": timed(lambda: rga.knn_interpolate(idx, w, attr)),
+            "interp_bwd_ms": timed(lambda: rga.knn_interpolate_backward(idx, w, dout, nv))}
 
 
 def main():

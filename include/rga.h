@@ -242,6 +242,8 @@ int l1_loss(void* stream, int64_t count, const float* image, const float* target
  *   with a uniform grid over ref; keep it unmodified while querying.
  * knn_query: q [3][n] query points; k in 1..min(32, nr); idx [k][n] int32 and
  *   w [k][n] out (t-th nearest in row t).  Queries may lie outside ref's box.
+ *   scratch: knn_query_workspace(n) bytes of device memory (the queries are
+ *   taken in grid-cell order); ws is the built grid, read only.
  * knn_interpolate: attr [C][nr] vertex attributes -> out [C][n] =
  *   sum_t w[t][i] attr[c][idx[t][i]] (t in order, FP32).
  * knn_interpolate_backward: dout [C][n] -> dattr [C][nr] (overwritten) =
@@ -252,8 +254,9 @@ int l1_loss(void* stream, int64_t count, const float* image, const float* target
  * short workspace; all calls are asynchronous on `stream`.                  */
 size_t knn_workspace(int nr);
 int knn_build(void* stream, int nr, const float* ref, void* ws, size_t ws_bytes);
+size_t knn_query_workspace(int n);
 int knn_query(void* stream, int n, const float* q, int nr, int k, int32_t* idx, float* w,
-              const void* ws, size_t ws_bytes);
+              const void* ws, size_t ws_bytes, void* scratch, size_t scratch_bytes);
 int knn_interpolate(void* stream, int n, int k, const int32_t* idx, const float* w, int C, int nr,
                     const float* attr, float* out);
 int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx, const float* w,

@@ -8,8 +8,9 @@
 //           cell and at most kMaxCells cells: bounds and cell size, per-cell
 //           counts (atomics), one-workgroup scan, fill of (x, y, z, index)
 //           records in cell order
-//   query   one thread per query point, the cell-start table staged in LDS
-//           per workgroup: cells are visited in shells of growing Chebyshev
+//   query   queries sorted by grid cell (counting sort), one thread per
+//           query point, the cell-start table staged in LDS per workgroup:
+//           cells are visited in shells of growing Chebyshev
 //           radius r around the query's cell (the cells of one row of a
 //           shell are contiguous, so their records are one run); the best k
 //           by (distance^2, index) are kept sorted in registers; the search
@@ -143,6 +144,12 @@ __device__ inline int cell_of(float v, float origin, float inv, int G) {
 }
 
 __global__ void __launch_bounds__(kBlock)
+knn_zero_u32(uint32_t* __restrict__ p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kBlock)
 knn_count_kernel(int nr, const float* __restrict__ ref, const float* __restrict__ bounds,
                  uint32_t* __restrict__ count, uint32_t* __restrict__ cell,
                  uint32_t* __restrict__ rank) {
@@ -195,6 +202,31 @@ knn_fill_kernel(int nr, const float* __restrict__ ref, const uint32_t* __restric
 // (d, j) before (e, l) in (distance^2, index) order
 __device__ inline bool before(float d, int j, float e, int l) { return d < e || (d == e && j < l); }
 
+// Queries are taken in the order of their grid cells (a counting sort:
+// per-cell counts with ranks, one-workgroup scan, fill), so that the lanes
+// of a wave search the same or neighbouring cells.
+__global__ void __launch_bounds__(kBlock)
+knn_qcell_kernel(int n, const float* __restrict__ q, const float* __restrict__ bounds,
+                 uint32_t* __restrict__ qcount, uint32_t* __restrict__ qcell,
+                 uint32_t* __restrict__ qrank) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
+  const int cx = cell_of(q[i], bounds[0], bounds[3], gx);
+  const int cy = cell_of(q[n + i], bounds[1], bounds[3], gy);
+  const int cz = cell_of(q[2 * n + i], bounds[2], bounds[3], gz);
+  const uint32_t c = (uint32_t)((cz * gy + cy) * gx + cx);
+  qcell[i] = c;
+  qrank[i] = atomicAdd(&qcount[c], 1u);
+}
+
+__global__ void __launch_bounds__(kBlock)
+knn_qfill_kernel(int n, const uint32_t* __restrict__ qstart, const uint32_t* __restrict__ qcell,
+                 const uint32_t* __restrict__ qrank, uint32_t* __restrict__ order) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) order[qstart[qcell[i]] + qrank[i]] = (uint32_t)i;
+}
+
 // The best k are kept in the last k of KMAX register slots, sorted; the
 // slots before them hold -inf sentinels that nothing is ever placed before,
 // so the worst kept entry is always slot KMAX - 1 (no dynamic register
@@ -203,13 +235,15 @@ template <int KMAX>
 __global__ void __launch_bounds__(kBlock)
 knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
                  const uint32_t* __restrict__ start, const float4* __restrict__ recs,
-                 int32_t* __restrict__ idx, float* __restrict__ w) {
+                 const uint32_t* __restrict__ order, int32_t* __restrict__ idx,
+                 float* __restrict__ w) {
   __shared__ uint32_t st[kMaxCells + 1];
   const int cells = (int)bounds[8];
   for (int c = threadIdx.x; c <= cells; c += blockDim.x) st[c] = start[c];
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  const int it = blockIdx.x * blockDim.x + threadIdx.x;
+  if (it >= n) return;
+  const int i = (int)order[it];          // queries in cell order: a wave searches nearby cells
   const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
   const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
   const int cx = cell_of(qx, bounds[0], bounds[3], gx);
@@ -393,24 +427,50 @@ extern "C" int knn_build(void* stream, int nr, const float* ref, void* ws, size_
   return RGA_OK;
 }
 
+extern "C" size_t knn_query_workspace(int n) {
+  if (n < 0) return 0;
+  const size_t N = (size_t)(n > 0 ? n : 1);
+  return rga::align_up((size_t)kMaxCells * 4, 256) + rga::align_up(((size_t)kMaxCells + 1) * 4, 256) +
+         3 * rga::align_up(N * 4, 256);
+}
+
 extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int32_t* idx,
-                         float* w, const void* ws, size_t ws_bytes) {
+                         float* w, const void* ws, size_t ws_bytes, void* scratch,
+                         size_t scratch_bytes) {
   if (n < 0 || nr < 1) return rga::fail(RGA_EINVAL, "knn_query: n >= 0 and nr >= 1");
   if (k < 1 || k > kMaxK || k > nr)
     return rga::fail(RGA_EINVAL, "knn_query: k must be in 1..min(%d, nr)", kMaxK);
   if (n == 0) return RGA_OK;
-  if (!q || !idx || !w || !ws) return rga::fail(RGA_EINVAL, "knn_query: null pointer");
+  if (!q || !idx || !w || !ws || !scratch) return rga::fail(RGA_EINVAL, "knn_query: null pointer");
   const KnnLayout L = knn_layout(nr);
   if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "knn_query: workspace too small");
+  if (scratch_bytes < knn_query_workspace(n))
+    return rga::fail(RGA_ECAPACITY, "knn_query: scratch too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   void* W = const_cast<void*>(ws);
+  const size_t N = rga::align_up((size_t)n * 4, 256);
+  uint32_t* qcount = static_cast<uint32_t*>(scratch);
+  uint32_t* qstart = qcount + rga::align_up((size_t)kMaxCells * 4, 256) / 4;
+  uint32_t* qcell = qstart + rga::align_up(((size_t)kMaxCells + 1) * 4, 256) / 4;
+  uint32_t* qrank = qcell + N / 4;
+  uint32_t* order = qrank + N / 4;
   const dim3 grid(rga::ceil_div(n, kBlock));
+  RGA_LAUNCH("knn_qzero", knn_zero_u32, dim3(rga::ceil_div(kMaxCells, kBlock)), dim3(kBlock), 0, s,
+             qcount, kMaxCells);
+  RGA_LAUNCH("knn_qcell", knn_qcell_kernel, grid, dim3(kBlock), 0, s, n, q, at<float>(W, L.bounds),
+             qcount, qcell, qrank);
+  RGA_LAUNCH("knn_qscan", knn_scan_kernel, dim3(1), dim3(1024), 0, s, at<float>(W, L.bounds),
+             qcount, qstart);
+  RGA_LAUNCH("knn_qfill", knn_qfill_kernel, grid, dim3(kBlock), 0, s, n, qstart, qcell, qrank,
+             order);
   if (k <= 4)
     RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
-               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
+               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
+               w);
   else
     RGA_LAUNCH("knn_query_wide", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
-               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), idx, w);
+               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
+               w);
   RGA_CHECK_LAUNCH("knn_query");
   return RGA_OK;
 }

@@ -53,7 +53,8 @@ _SIGS = {
     "l1_loss": (_I, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "knn_workspace": (_SZ, [_I]),
     "knn_build": (_I, [_VP, _I, _VP, _VP, _SZ]),
-    "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ]),
+    "knn_query_workspace": (_SZ, [_I]),
+    "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ, _VP, _SZ]),
     "knn_interpolate": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "rga_timing_enable": (_I, [_I]),
@@ -351,8 +352,10 @@ def knn(index: KnnIndex, q, k: int):
     n = int(q.shape[1])
     idx = torch.empty((k, n), dtype=torch.int32, device=q.device)
     w = torch.empty((k, n), dtype=torch.float32, device=q.device)
+    sb = int(lib().knn_query_workspace(n))
+    scratch = torch.empty(sb, dtype=torch.uint8, device=q.device)
     _check(lib().knn_query(_stream(), n, _p(q), index.nr, int(k), _p(idx), _p(w), _p(index.buf),
-                           index.bytes), "knn_query")
+                           index.bytes, _p(scratch), sb), "knn_query")
     return idx, w
 
 

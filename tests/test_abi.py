@@ -67,9 +67,10 @@ def test_argument_errors_are_reported_before_any_launch():
                              16, 32, 5, 32, None, C.cast(cp, C.c_void_p), 0, None, None) == -1
     assert "divide" in rga.last_error()
     assert L.l1_loss(None, 0, None, None, None, None, None, 0) == -1
-    assert L.knn_query(None, 10, None, 5, 6, None, None, None, 0) == -1
+    assert L.knn_query(None, 10, None, 5, 6, None, None, None, 0, None, 0) == -1
     assert "k must be" in rga.last_error()
-    assert L.knn_query(None, 10, None, 5, 0, None, None, None, 0) == -1
+    assert L.knn_query(None, 10, None, 5, 0, None, None, None, 0, None, 0) == -1
+    assert L.knn_query_workspace(1000) >= 3 * 4000
     assert L.knn_build(None, 0, None, None, 0) == -1
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
     assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1

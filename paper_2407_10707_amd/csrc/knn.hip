@@ -467,6 +467,10 @@ extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int
     RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
                at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
                w);
+  else if (k <= 20)
+    RGA_LAUNCH("knn_query_wide", knn_query_kernel<20>, grid, dim3(kBlock), 0, s, n, q, k,
+               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
+               w);
   else
     RGA_LAUNCH("knn_query_wide", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
                at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,

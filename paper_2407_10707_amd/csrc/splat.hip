@@ -16,7 +16,8 @@
 //   tile sort         stable LSD radix sort of the entries by tile id (one
 //                     pass up to 2048 tiles) -> per tile, entries in
 //                     (depth bits, index) order
-//   ranges            tile boundaries in the sorted entries
+//   ranges            tile boundaries in the sorted entries (written by the
+//                     tile sort's scatter when it takes one pass)
 //   blend             (tile, 256-entry chunk) work items over a resident
 //                     grid; chunk composites, per-tile combine, restart of
 //                     the stop chunk; the adjoint over 64-entry sub-chunks
@@ -424,7 +425,8 @@ __global__ void __launch_bounds__(kRadixThreads)
 radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
-                const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot) {
+                const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot,
+                int32_t* __restrict__ ranges, int nranges) {
   constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the initial scan
   __shared__ uint32_t base[kRadix];
   __shared__ uint32_t wcnt[4][kRadix];
@@ -455,6 +457,12 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
   for (int i = 0; i < kPer; ++i) {
     const int d = tid * kPer + i;
     base[d] = excl + loc[i] + binoff[(size_t)blockIdx.x * kRadix + d];
+    // a one-pass tile sort: digit d is tile d, and its entries land at
+    // [start of the digit, + its total)
+    if (ranges && blockIdx.x == 0 && d < nranges) {
+      ranges[2 * d] = (int32_t)(excl + loc[i]);
+      ranges[2 * d + 1] = (int32_t)(excl + loc[i] + bintot[d]);
+    }
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -1422,7 +1430,8 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
       RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_n,
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
-                 v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot);
+                 v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot,
+                 (int32_t*)nullptr, 0);
       uint32_t* t = k0; k0 = k1; k1 = t;
       t = v0; v0 = v1; v1 = t;
     }
@@ -1445,13 +1454,17 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                  (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);
       RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_cap,
                  (const int64_t*)cnt, (int64_t)0, capacity, kBlockD, binoff, bintot);
+      // with one tile pass its scatter also writes the tile ranges
+      const bool one = L.tile_passes == 1;
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
-                 tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot);
+                 tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot,
+                 one ? ranges : (int32_t*)nullptr, one ? (int)tiles : 0);
       uint32_t* t = tk0; tk0 = tk1; tk1 = t;
       t = tv0; tv0 = tv1; tv1 = t;
     }
-    RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
-               s, tk0, (const int64_t*)cnt, capacity, ranges);
+    if (L.tile_passes > 1)
+      RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
+                 s, tk0, (const int64_t*)cnt, capacity, ranges);
   }
   // work items (tile, chunk), chunk composites, front-to-back combine
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);

@@ -8,8 +8,9 @@
 //           cell and at most kMaxCells cells: bounds and cell size, per-cell
 //           counts (atomics), one-workgroup scan, fill of (x, y, z, index)
 //           records in cell order
-//   query   queries sorted by grid cell (counting sort), one thread per
-//           query point, the cell-start table staged in LDS per workgroup:
+//   query   queries sorted by grid cell (counting sort); for k <= 4 one
+//           thread per query point, the cell-start table staged in LDS per
+//           workgroup, for wider k one wave per query (below):
 //           cells are visited in shells of growing Chebyshev
 //           radius r around the query's cell (the cells of one row of a
 //           shell are contiguous, so their records are one run); the best k
@@ -334,6 +335,102 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
   }
 }
 
+// Wider searches (k > 4): one wave per query.  The lanes take the cells of
+// a shell (the shell's cells among the clipped cube of radius r, 64 at a
+// time) and step through their cells' records together, four records per
+// lane at a time; a candidate that beats the current k-th is inserted into
+// the sorted list held one entry per lane (lane t = the t-th nearest so
+// far): its position is the number of list entries before it (one ballot),
+// the entries from there on move up one lane.  The stop rule is the one of
+// the thread-per-query search, so both return the same neighbours.
+constexpr int kWaveBatch = 4;
+__global__ void __launch_bounds__(kBlock)
+knn_query_wave_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
+                      const uint32_t* __restrict__ start, const float4* __restrict__ recs,
+                      const uint32_t* __restrict__ order, int32_t* __restrict__ idx,
+                      float* __restrict__ w) {
+  const int lane = threadIdx.x & 63;
+  const int it = __builtin_amdgcn_readfirstlane(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+  if (it >= n) return;                   // whole waves leave
+  const int i = __builtin_amdgcn_readfirstlane((int)order[it]);
+  const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
+  const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
+  const int cx = cell_of(qx, bounds[0], bounds[3], gx);
+  const int cy = cell_of(qy, bounds[1], bounds[3], gy);
+  const int cz = cell_of(qz, bounds[2], bounds[3], gz);
+  const float h = bounds[4];
+  const int rmax = max(gx, max(gy, gz));
+  float bd = INFINITY;                   // this lane's list entry
+  int bi = 0x7fffffff;
+  float wd = INFINITY;                   // the k-th entry (wave-uniform)
+  int wj = 0x7fffffff;
+  const int up = ((lane + 63) & 63) << 2;   // ds_bpermute address of the lane below
+  for (int r = 0; r <= rmax; ++r) {
+    const int x0 = max(cx - r, 0), x1 = min(cx + r, gx - 1);
+    const int y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
+    const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
+    const int sx = x1 - x0 + 1, sy = y1 - y0 + 1;
+    const int box = sx * sy * (z1 - z0 + 1);
+    for (int c0 = 0; c0 < box; c0 += 64) {
+      const int c = c0 + lane;
+      uint32_t e0 = 0, len = 0;
+      if (c < box) {
+        const int x = x0 + c % sx, yz = c / sx;
+        const int y = y0 + yz % sy, z = z0 + yz / sy;
+        if (max(abs(x - cx), max(abs(y - cy), abs(z - cz))) == r) {
+          const int cell = (z * gy + y) * gx + x;
+          e0 = start[cell];
+          len = start[cell + 1] - e0;
+        }
+      }
+      for (uint32_t m = 0; __ballot(m < len) != 0ull; m += kWaveBatch) {
+        float4 pb[kWaveBatch];
+#pragma unroll
+        for (int u = 0; u < kWaveBatch; ++u)
+          pb[u] = m + u < len ? recs[e0 + m + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < kWaveBatch; ++u) {
+          const bool has = m + u < len;
+          const int j = __float_as_int(pb[u].w);
+          const float dx = pb[u].x - qx, dy = pb[u].y - qy, dz = pb[u].z - qz;
+          const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          uint64_t sm = __ballot(has && before(d, j, wd, wj));
+          while (sm) {
+            const int src = (int)__builtin_ctzll(sm);
+            sm &= sm - 1;
+            const float cd = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), src));
+            const int cj = __builtin_amdgcn_readlane(j, src);
+            if (!before(cd, cj, wd, wj)) continue;   // an earlier insertion raised the bar
+            const int pos = __popcll(__ballot(lane < k && before(bd, bi, cd, cj)));
+            const float ld = __int_as_float(__builtin_amdgcn_ds_bpermute(up, __float_as_int(bd)));
+            const int li = __builtin_amdgcn_ds_bpermute(up, bi);
+            if (lane == pos) {
+              bd = cd;
+              bi = cj;
+            } else if (lane > pos) {
+              bd = ld;
+              bi = li;
+            }
+            wd = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bd), k - 1));
+            wj = __builtin_amdgcn_readlane(bi, k - 1);
+          }
+        }
+      }
+    }
+    const float reach = (float)r * h;
+    if (wd < reach * reach * 0.9999f) break;
+  }
+  // normalised inverse-distance weights; a query on a vertex takes it alone
+  const bool on_vertex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bd), 0)) == 0.f;
+  const float u = lane < k ? __builtin_amdgcn_rcpf(__builtin_sqrtf(bd)) : 0.f;
+  const float is = 1.f / rga::wave_sum(u);
+  if (lane < k) {
+    const size_t o = (size_t)lane * n + i;
+    idx[o] = bi;
+    w[o] = on_vertex ? (lane == 0 ? 1.f : 0.f) : u * is;
+  }
+}
+
 template <int KMAX>
 __global__ void __launch_bounds__(kBlock)
 knn_interp_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __restrict__ w,
@@ -347,11 +444,13 @@ knn_interp_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __
     j[t] = t < k ? rga::clampi(idx[(size_t)t * n + i], 0, nr - 1) : 0;
     wt[t] = t < k ? w[(size_t)t * n + i] : 0.f;
   }
-  // four channels per step, so that their gathers are in flight together
-  for (int c0 = 0; c0 < C; c0 += 4) {
-    float v[4] = {0.f, 0.f, 0.f, 0.f};
+  // for small k four channels per step, so that their gathers are in
+  // flight together (for wide k the neighbours alone fill the registers)
+  constexpr int kStep = KMAX <= 4 ? 4 : 1;
+  for (int c0 = 0; c0 < C; c0 += kStep) {
+    float v[kStep] = {};
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kStep; ++u) {
       if (c0 + u >= C) continue;
       const float* a = attr + (size_t)(c0 + u) * nr;
 #pragma unroll
@@ -359,7 +458,7 @@ knn_interp_kernel(int n, int k, const int32_t* __restrict__ idx, const float* __
         if (t < k) v[u] = fmaf(wt[t], a[j[t]], v[u]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < kStep; ++u)
       if (c0 + u < C) out[(size_t)(c0 + u) * n + i] = v[u];
   }
 }
@@ -467,14 +566,10 @@ extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int
     RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
                at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
                w);
-  else if (k <= 20)
-    RGA_LAUNCH("knn_query_wide", knn_query_kernel<20>, grid, dim3(kBlock), 0, s, n, q, k,
-               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
-               w);
   else
-    RGA_LAUNCH("knn_query_wide", knn_query_kernel<kMaxK>, grid, dim3(kBlock), 0, s, n, q, k,
-               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
-               w);
+    RGA_LAUNCH("knn_query_wide", knn_query_wave_kernel, dim3(rga::ceil_div(n, kBlock / 64)),
+               dim3(kBlock), 0, s, n, q, k, at<float>(W, L.bounds), at<uint32_t>(W, L.start),
+               at<float4>(W, L.recs), order, idx, w);
   RGA_CHECK_LAUNCH("knn_query");
   return RGA_OK;
 }

@@ -8,9 +8,8 @@
 //           cell and at most kMaxCells cells: bounds and cell size, per-cell
 //           counts (atomics), one-workgroup scan, fill of (x, y, z, index)
 //           records in cell order
-//   query   queries sorted by grid cell (counting sort); for k <= 4 one
-//           thread per query point, the cell-start table staged in LDS per
-//           workgroup, for wider k one wave per query (below):
+//   query   queries sorted by grid cell (counting sort); for k <= 4 four
+//           lanes per query point, for wider k one wave (below):
 //           cells are visited in shells of growing Chebyshev
 //           radius r around the query's cell (the cells of one row of a
 //           shell are contiguous, so their records are one run); the best k
@@ -30,9 +29,8 @@
 namespace {
 
 constexpr int kMaxK = 32;
-constexpr int kMaxCells = 8192;          // cell-start table of 32 KB in LDS
+constexpr int kMaxCells = 8192;          // cells of the grid (its start table: 32 KB)
 constexpr int kBlock = 256;
-constexpr int kBatch = 8;                // candidate records loaded together
 
 struct KnnLayout {
   size_t bounds, count, start, cell, rank, recs, total;
@@ -228,23 +226,47 @@ knn_qfill_kernel(int n, const uint32_t* __restrict__ qstart, const uint32_t* __r
   if (i < n) order[qstart[qcell[i]] + qrank[i]] = (uint32_t)i;
 }
 
-// The best k are kept in the last k of KMAX register slots, sorted; the
-// slots before them hold -inf sentinels that nothing is ever placed before,
-// so the worst kept entry is always slot KMAX - 1 (no dynamic register
-// indexing).
-template <int KMAX>
+// Small k (<= 4): four lanes per query (a quad), so that a search of a
+// few hundred thousand queries still has several waves per SIMD to hide
+// the latency of its dependent loads.  The quad walks the shells row by
+// row as one; the records of a row are dealt out to its lanes in turn (so
+// a quad reads consecutive records), each lane keeping the best k of its
+// own records, sorted, in the last k of four register slots (the slots
+// before them hold -inf sentinels that nothing is ever placed before, so
+// the worst kept entry is always the last slot).  At the end of each shell the quad merges its four lists:
+// k rounds of a minimum over the quad (two DPP exchanges), the lane that
+// holds the minimum moving to its next entry; the k-th of the merge drives
+// the stop rule and prunes the lanes' candidates.
+constexpr int kQuadBatch = 2;            // records per lane loaded together
+
+// (d, j) <- the smallest of the quad's four in (distance^2, index) order
+__device__ inline void quad_min(float& d, int& j) {
+  float od = __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(d), __float_as_int(d), 0xB1, 0xf, 0xf, false));
+  int oj = __builtin_amdgcn_update_dpp(j, j, 0xB1, 0xf, 0xf, false);
+  if (before(od, oj, d, j)) {
+    d = od;
+    j = oj;
+  }
+  od = __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(d), __float_as_int(d), 0x4E, 0xf, 0xf, false));
+  oj = __builtin_amdgcn_update_dpp(j, j, 0x4E, 0xf, 0xf, false);
+  if (before(od, oj, d, j)) {
+    d = od;
+    j = oj;
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
-knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
-                 const uint32_t* __restrict__ start, const float4* __restrict__ recs,
-                 const uint32_t* __restrict__ order, int32_t* __restrict__ idx,
-                 float* __restrict__ w) {
-  __shared__ uint32_t st[kMaxCells + 1];
-  const int cells = (int)bounds[8];
-  for (int c = threadIdx.x; c <= cells; c += blockDim.x) st[c] = start[c];
-  __syncthreads();
-  const int it = blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= n) return;
-  const int i = (int)order[it];          // queries in cell order: a wave searches nearby cells
+knn_query_quad_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
+                      const uint32_t* __restrict__ start, const float4* __restrict__ recs,
+                      const uint32_t* __restrict__ order, int32_t* __restrict__ idx,
+                      float* __restrict__ w) {
+  constexpr int S = 4;                    // register slots = the largest k
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int it = (int)(gt >> 2), sub = (int)(gt & 3);
+  if (it >= n) return;                    // whole quads leave
+  const int i = (int)order[it];
   const int gx = (int)bounds[5], gy = (int)bounds[6], gz = (int)bounds[7];
   const float qx = q[i], qy = q[n + i], qz = q[2 * n + i];
   const int cx = cell_of(qx, bounds[0], bounds[3], gx);
@@ -252,14 +274,16 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
   const int cz = cell_of(qz, bounds[2], bounds[3], gz);
   const float h = bounds[4];
   const int rmax = max(gx, max(gy, gz));
-  const int first = KMAX - k;             // slot of the nearest
-  float bd[KMAX];
-  int bi[KMAX];
+  const int first = S - k;                // slot of the nearest
+  float bd[S];
+  int bi[S];
 #pragma unroll
-  for (int t = 0; t < KMAX; ++t) {
+  for (int t = 0; t < S; ++t) {
     bd[t] = t < first ? -INFINITY : INFINITY;
     bi[t] = t < first ? -1 : 0x7fffffff;
   }
+  float md[S], kd = INFINITY;             // the quad's merged best k; its k-th
+  int mj[S], kj = 0x7fffffff;
   for (int r = 0; r <= rmax; ++r) {
     const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
     const int y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
@@ -267,8 +291,6 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
       for (int y = y0; y <= y1; ++y) {
         const bool face = abs(z - cz) == r || abs(y - cy) == r;
         const int row = (z * gy + y) * gx;
-        // a shell row is either the whole x range (on a z or y face) or
-        // its two end cells
         for (int side = 0; side < (face ? 1 : 2); ++side) {
           int x0, x1;
           if (face) {
@@ -278,25 +300,24 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
             x0 = x1 = side == 0 ? cx - r : cx + r;
             if (x0 < 0 || x0 > gx - 1) continue;
           }
-          const uint32_t e0 = st[row + x0], e1 = st[row + x1 + 1];
-          // records in batches of kBatch, loaded together
-          for (uint32_t e = e0; e < e1; e += kBatch) {
-            float4 pb[kBatch];
+          const uint32_t e0 = start[row + x0], e1 = start[row + x1 + 1];
+          for (uint32_t b = e0; b < e1; b += 4 * kQuadBatch) {   // the same steps in the quad
+            const uint32_t e = b + sub;
+            float4 pb[kQuadBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u)
-              pb[u] = e + u < e1 ? recs[e + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int u = 0; u < kQuadBatch; ++u)
+              pb[u] = e + 4 * u < e1 ? recs[e + 4 * u] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-              if (e + u >= e1) continue;
+            for (int u = 0; u < kQuadBatch; ++u) {
+              if (e + 4 * u >= e1) continue;
               const float4 p = pb[u];
               const int j = __float_as_int(p.w);
               const float dx = p.x - qx, dy = p.y - qy, dz = p.z - qz;
               const float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-              if (!before(d, j, bd[KMAX - 1], bi[KMAX - 1])) continue;
-              // insert, keeping the slots sorted; the last entry drops out
+              if (!before(d, j, bd[S - 1], bi[S - 1]) || !before(d, j, kd, kj)) continue;
               bool placed = false;
 #pragma unroll
-              for (int t = KMAX - 1; t >= 0; --t) {
+              for (int t = S - 1; t >= 0; --t) {
                 if (placed) continue;
                 if (t > 0 && before(d, j, bd[t - 1], bi[t - 1])) {
                   bd[t] = bd[t - 1];
@@ -311,27 +332,50 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
           }
         }
       }
+    // merge the quad's lists: k rounds of a quad minimum
+    int ptr = first;
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      md[t] = INFINITY;
+      mj[t] = 0x7fffffff;
+      if (t >= k) continue;
+      float hd = INFINITY;
+      int hj = 0x7fffffff;
+#pragma unroll
+      for (int u = 0; u < S; ++u)
+        if (u == ptr) {
+          hd = bd[u];
+          hj = bi[u];
+        }
+      float d = hd;
+      int j = hj;
+      quad_min(d, j);
+      if (d == hd && j == hj) ++ptr;
+      md[t] = d;
+      mj[t] = j;
+      kd = d;
+      kj = j;
+    }
     // unvisited cells are at least r cell widths away (less a margin for
     // the rounding of cell assignment and distances)
     const float reach = (float)r * h;
-    if (bd[KMAX - 1] < reach * reach * 0.9999f) break;
+    if (kd < reach * reach * 0.9999f) break;
   }
   // normalised inverse-distance weights; a query on a vertex takes it alone
-  bool on_vertex = false;
-  float u[KMAX], s = 0.f;
+  const bool on_vertex = md[0] == 0.f;
+  float u[S], s = 0.f;
 #pragma unroll
-  for (int t = 0; t < KMAX; ++t) {
-    if (t == first) on_vertex = bd[t] == 0.f;
-    u[t] = t >= first ? __builtin_amdgcn_rcpf(__builtin_sqrtf(bd[t])) : 0.f;
+  for (int t = 0; t < S; ++t) {
+    u[t] = t < k ? __builtin_amdgcn_rcpf(__builtin_sqrtf(md[t])) : 0.f;
     s += u[t];
   }
   const float is = 1.f / s;
 #pragma unroll
-  for (int t = 0; t < KMAX; ++t) {
-    if (t < first) continue;
-    const size_t o = (size_t)(t - first) * n + i;
-    idx[o] = bi[t];
-    w[o] = on_vertex ? (t == first ? 1.f : 0.f) : u[t] * is;
+  for (int t = 0; t < S; ++t) {
+    if (t != sub || t >= k) continue;
+    const size_t o = (size_t)t * n + i;
+    idx[o] = mj[t];
+    w[o] = on_vertex ? (t == 0 ? 1.f : 0.f) : u[t] * is;
   }
 }
 
@@ -341,8 +385,8 @@ knn_query_kernel(int n, const float* __restrict__ q, int k, const float* __restr
 // lane at a time; a candidate that beats the current k-th is inserted into
 // the sorted list held one entry per lane (lane t = the t-th nearest so
 // far): its position is the number of list entries before it (one ballot),
-// the entries from there on move up one lane.  The stop rule is the one of
-// the thread-per-query search, so both return the same neighbours.
+// the entries from there on move up one lane.  The stop rule is the quad
+// search's, so both return the same neighbours.
 constexpr int kWaveBatch = 4;
 __global__ void __launch_bounds__(kBlock)
 knn_query_wave_kernel(int n, const float* __restrict__ q, int k, const float* __restrict__ bounds,
@@ -563,9 +607,9 @@ extern "C" int knn_query(void* stream, int n, const float* q, int nr, int k, int
   RGA_LAUNCH("knn_qfill", knn_qfill_kernel, grid, dim3(kBlock), 0, s, n, qstart, qcell, qrank,
              order);
   if (k <= 4)
-    RGA_LAUNCH("knn_query", knn_query_kernel<4>, grid, dim3(kBlock), 0, s, n, q, k,
-               at<float>(W, L.bounds), at<uint32_t>(W, L.start), at<float4>(W, L.recs), order, idx,
-               w);
+    RGA_LAUNCH("knn_query", knn_query_quad_kernel, dim3(rga::ceil_div((int64_t)n * 4, kBlock)),
+               dim3(kBlock), 0, s, n, q, k, at<float>(W, L.bounds), at<uint32_t>(W, L.start),
+               at<float4>(W, L.recs), order, idx, w);
   else
     RGA_LAUNCH("knn_query_wide", knn_query_wave_kernel, dim3(rga::ceil_div(n, kBlock / 64)),
                dim3(kBlock), 0, s, n, q, k, at<float>(W, L.bounds), at<uint32_t>(W, L.start),

@@ -357,3 +357,71 @@ def interpolate(idx, w, attr):
     for t in range(idx.shape[0]):
         out = out + w[t][None] * attr[:, idx[t]]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.1 (attributes) and Sec. 4 (implementation details): the pose-
+# dependent vertex displacement dx = d(x, theta), an MLP of four hidden
+# layers of width 256 with ReLU, whose coordinate input goes through random
+# Fourier features.  Readings (the paper gives neither the encoding's size
+# nor how the pose enters): gamma(x) = [sin(2 pi B x), cos(2 pi B x)] with a
+# fixed B [64, 3]; the network input is [gamma(x), theta] (128 + 72 = 200);
+# layers h_l = relu(W_l h_{l-1} + b_l), l = 1..4, and a linear output
+# dx = W_5 h_4 + b_5 (3).  Parameters are one flat vector in the order
+# W_1 [256, 200], b_1, W_2 [256, 256], b_2, W_3, b_3, W_4, b_4, W_5 [3, 256], b_5.
+# ---------------------------------------------------------------------------
+MLP_FREQS = 64
+MLP_POSE = 72
+MLP_WIDTH = 256
+MLP_SHAPES = [(MLP_WIDTH, 2 * MLP_FREQS + MLP_POSE), (MLP_WIDTH, MLP_WIDTH),
+              (MLP_WIDTH, MLP_WIDTH), (MLP_WIDTH, MLP_WIDTH), (3, MLP_WIDTH)]
+
+
+def mlp_param_count(shapes=MLP_SHAPES) -> int:
+    return sum(o * i + o for o, i in shapes)
+
+
+def mlp_unpack(params, shapes=MLP_SHAPES):
+    """Flat parameter vector -> [(W_l, b_l)] in layer order."""
+    p = t64(params)
+    out, o = [], 0
+    for n_out, n_in in shapes:
+        W = p[o:o + n_out * n_in].reshape(n_out, n_in)
+        o += n_out * n_in
+        b = p[o:o + n_out]
+        o += n_out
+        out.append((W, b))
+    assert o == p.numel()
+    return out
+
+
+def rff(x, freqs):
+    """x [3, n], freqs B [m, 3] -> gamma [2m, n] = [sin(2 pi B x); cos(2 pi B x)]."""
+    f = 2.0 * math.pi * (t64(freqs) @ t64(x))
+    return torch.cat([torch.sin(f), torch.cos(f)], dim=0)
+
+
+def mlp_layers(x, freqs, theta, layers):
+    """Pre-activations z_l [out_l, n] of every layer and the output dx [3, n].
+
+    The pose is the same for every vertex: it is appended to each column of
+    the encoded coordinates."""
+    g = rff(x, freqs)
+    th = t64(theta).reshape(-1, 1).expand(-1, g.shape[1])
+    h = torch.cat([g, th], dim=0)
+    zs = []
+    for li, (W, b) in enumerate(layers):
+        z = W @ h + b[:, None]
+        zs.append(z)
+        h = torch.relu(z) if li + 1 < len(layers) else z
+    return zs, h
+
+
+def displacement(x, freqs, theta, params):
+    """d(x, theta) for every column of x: [3, n]."""
+    return mlp_layers(x, freqs, theta, mlp_unpack(params))[1]
+
+
+def mean_displacement(x, freqs, thetas, params):
+    """Average displacement over a set of poses (used for novel poses)."""
+    return torch.stack([displacement(x, freqs, th, params) for th in thetas]).mean(dim=0)

@@ -408,3 +408,24 @@ def micro_scene(seed: int, n: int, height: int, width: int, he: int = 4, we: int
         view_dirs=_f32(latlong_centres(hv, wv)), vis_res=vis_res, cam=cam,
         target=_f32(rng.random((3, height, width))),
     )
+
+
+def mlp_inputs(seed: int, n_pose: int = 1, freqs: int = 64, pose: int = 72, width: int = 256,
+               sigma: float = 1.0) -> dict:
+    """Inputs of the displacement network: the Fourier matrix B [freqs, 3]
+    (normal, std sigma, per unit of length), poses [n_pose, pose] (axis-angle
+    components, normal with std 0.2) and a flat parameter vector drawn as a
+    freshly initialised network would be (each layer's weights and biases
+    uniform in +-1/sqrt(fan_in)), in the order W_1, b_1, ..., W_5, b_5 with
+    W_1 [width, 2 freqs + pose], W_2..W_4 [width, width], W_5 [3, width]."""
+    rng = np.random.default_rng([7, seed])
+    shapes = [(width, 2 * freqs + pose), (width, width), (width, width), (width, width),
+              (3, width)]
+    parts = []
+    for n_out, n_in in shapes:
+        bound = 1.0 / math.sqrt(n_in)
+        parts.append(rng.uniform(-bound, bound, n_out * n_in))
+        parts.append(rng.uniform(-bound, bound, n_out))
+    return dict(freqs=_f32(rng.normal(0.0, sigma, (freqs, 3))),
+                thetas=_f32(rng.normal(0.0, 0.2, (n_pose, pose))),
+                params=_f32(np.concatenate(parts)))

@@ -263,6 +263,41 @@ int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx, con
                              int C, int nr, const float* dout, float* dattr);
 
 /* ------------------------------------------------------------------------
+ * Pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1, attribute
+ * paragraph: an MLP of the canonical position and the pose; Sec. 4,
+ * implementation details: four layers of width 256 with ReLU and random
+ * Fourier features of the coordinates).  Readings: gamma(x) =
+ * [sin(2 pi B x), cos(2 pi B x)] with B [RGA_MLP_FREQS][3]; the input of
+ * the first layer is [gamma(x), theta] (128 + 72); four hidden layers
+ * h_l = relu(W_l h_{l-1} + b_l) and a linear output dx = W_5 h_4 + b_5.
+ *
+ * params: RGA_MLP_PARAMS floats, W_1 [256][200], b_1 [256], W_2 [256][256],
+ *   b_2, W_3, b_3, W_4, b_4, W_5 [3][256], b_5 [3] (row-major, out x in).
+ * x [3][nv] canonical vertex positions; freqs B [64][3]; theta [72]; all
+ *   device memory.  ws: mlp_workspace(nv) bytes of device memory owned by
+ *   the caller, 16-byte aligned: the operands packed from params, the
+ *   kept activations and the adjoint's partial sums.
+ * mlp_forward: dx [3][nv] (written).  The products run on bf16 MFMA with
+ *   FP32 accumulation, each operand split into bf16 high and low parts
+ *   (hi.hi + lo.hi + hi.lo): about FP32 accuracy.
+ * mlp_backward: the adjoint of the last mlp_forward on the same ws (same
+ *   nv, x, freqs, theta, params; it reads the packed operands and the kept
+ *   activations): ddx [3][nv] -> dparams [RGA_MLP_PARAMS] and dtheta [72]
+ *   (overwritten).  Calls on one ws must not overlap.
+ * Errors: RGA_EINVAL (nv outside 0..2^26, null pointer, unaligned ws),
+ *   RGA_ECAPACITY (ws too small); nothing is launched then.              */
+#define RGA_MLP_FREQS 64
+#define RGA_MLP_POSE 72
+#define RGA_MLP_WIDTH 256
+#define RGA_MLP_PARAMS 249603
+size_t mlp_workspace(int nv);
+int mlp_forward(void* stream, int nv, const float* x, const float* freqs, const float* theta,
+                const float* params, void* ws, size_t ws_bytes, float* dx);
+int mlp_backward(void* stream, int nv, const float* x, const float* freqs, const float* theta,
+                 const float* params, const float* ddx, void* ws, size_t ws_bytes,
+                 float* dparams, float* dtheta);
+
+/* ------------------------------------------------------------------------
  * Kernel timing with HIP events, for measurement.  While enabled, every
  * kernel launch is bracketed by events on its stream; rga_timing_read
  * synchronises and returns the summed milliseconds and launch count of the

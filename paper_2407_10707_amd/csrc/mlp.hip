@@ -1,0 +1,493 @@
+// The pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1,
+// attribute paragraph; Sec. 4, implementation details): four hidden layers
+// of width 256 with ReLU and a linear output of 3, the coordinates encoded by
+// random Fourier features gamma(x) = [sin(2 pi B x), cos(2 pi B x)] (B is
+// 64 x 3) and the pose theta (72) appended to every vertex's input.
+//
+// Every layer is a dense product over the vertices, so it runs on MFMA
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation) in a split form that keeps
+// FP32 accuracy: each operand is a bf16 high part plus a bf16 low part and
+// a product is taken as hi.hi + lo.hi + hi.lo (the lo.lo term is below FP32
+// rounding).
+//
+//   pack      weights -> bf16 hi/lo operands in the exact per-lane order of
+//             the MFMA B operand (one 16-byte load per lane and step), once
+//             in forward order and once transposed for the adjoint; the pose
+//             is folded into the first layer's bias (b_1 + W_1[:, 128:] theta)
+//   forward   one wave per 16 vertices, all layers in one kernel: the
+//             activations stay in the wave's LDS slice, the weights stream
+//             from L2; the hidden activations are kept for the adjoint
+//   backward  one wave per 16 vertices: dz_5 = ddx, dh = dz W (transposed
+//             pack), dz = dh where h > 0; every dz is kept
+//   wgrad     dW_l = sum over vertices of dz_l h_{l-1}^T: workgroups over
+//             (layer, 16-row band, chunk of vertices), each wave 64 columns,
+//             partial sums per chunk (no atomics), then a fixed-order sum
+//             over the chunks; the Fourier features of the first layer are
+//             recomputed from x; dW_1's pose columns are db_1 theta^T and
+//             dtheta = W_1[:, 128:]^T db_1
+#include "common.h"
+
+#include <algorithm>
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kFreqs = RGA_MLP_FREQS;     // 64
+constexpr int kPose = RGA_MLP_POSE;       // 72
+constexpr int kWidth = RGA_MLP_WIDTH;     // 256
+constexpr int kIn1 = 2 * kFreqs + kPose;  // 200
+constexpr int kLayers = 5;
+constexpr int kParams = RGA_MLP_PARAMS;
+constexpr int kAS = kWidth + 4;           // LDS row stride of the activations (floats)
+constexpr int kMaxChunks = 16;
+constexpr int kWaves = 4;
+
+// parameter layout: W_1 [256][200], b_1, W_2 [256][256], b_2, W_3, b_3, W_4, b_4, W_5 [3][256], b_5
+__host__ __device__ constexpr int n_out(int l) { return l < 4 ? kWidth : 3; }
+__host__ __device__ constexpr int n_in(int l) { return l == 0 ? kIn1 : kWidth; }
+__host__ __device__ constexpr int w_off(int l) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += n_out(i) * n_in(i) + n_out(i);
+  return o;
+}
+__host__ __device__ constexpr int b_off(int l) { return w_off(l) + n_out(l) * n_in(l); }
+static_assert(w_off(kLayers) == kParams, "parameter count");
+
+// forward operand of layer l: reduction over its MFMA inputs (the 128
+// Fourier features for l = 0), columns = outputs padded to 16
+__host__ __device__ constexpr int f_k(int l) { return l == 0 ? 2 * kFreqs : kWidth; }
+__host__ __device__ constexpr int f_n(int l) { return l < 4 ? kWidth : 16; }
+__host__ __device__ constexpr int f_off(int l) {
+  int o = 0;
+  for (int i = 0; i < l; ++i) o += f_k(i) * f_n(i);
+  return o;
+}
+constexpr int kFwdElems = f_off(kLayers);
+// transposed operand of layer l = 1..4: reduction over its outputs (padded
+// to 32), columns = its 256 inputs
+__host__ __device__ constexpr int t_k(int l) { return l < 4 ? kWidth : 32; }
+__host__ __device__ constexpr int t_off(int l) {
+  int o = kFwdElems;
+  for (int i = 1; i < l; ++i) o += t_k(i) * kWidth;
+  return o;
+}
+constexpr int kPackElems = t_off(kLayers);   // per hi and lo
+
+struct MlpLayout {
+  int nvp, chunks, chunk_len;
+  size_t pack, bias, h, dz, part, total;
+};
+
+MlpLayout mlp_layout(int nv) {
+  MlpLayout L{};
+  L.nvp = (int)rga::align_up((size_t)(nv > 0 ? nv : 1), 32);
+  L.chunks = std::max(1, std::min(kMaxChunks, L.nvp / 512));
+  L.chunk_len = (int)rga::align_up((size_t)rga::ceil_div(L.nvp, L.chunks), 32);
+  const size_t V = (size_t)L.nvp;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t a = o;
+    o = rga::align_up(o + bytes, 256);
+    return a;
+  };
+  L.pack = take((size_t)2 * kPackElems * 2);
+  L.bias = take((size_t)kLayers * kWidth * 4);
+  L.h = take((size_t)4 * kWidth * V * 4);
+  L.dz = take(((size_t)4 * kWidth + 16) * V * 4);
+  L.part = take((size_t)kMaxChunks * kParams * 4);
+  L.total = o;
+  return L;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 8 floats -> bf16 high parts and bf16 low parts (the remainders)
+__device__ inline void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)v[e];
+    hi[e] = h;
+    lo[e] = (__bf16)(v[e] - (float)h);
+  }
+}
+
+__device__ inline f32x4 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                              const bf16x8& bl, f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ inline void load8(const float* p, float* v) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  const float4 b = *reinterpret_cast<const float4*>(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// Fragment order of an operand with KS reduction steps of 32: element
+// ((ct * KS + ks) * 64 + lane) * 8 + e holds column ct * 16 + lane % 16 and
+// reduction index ks * 32 + 8 (lane / 16) + e.
+__global__ void __launch_bounds__(256)
+mlp_pack_kernel(const float* __restrict__ P, const float* __restrict__ theta,
+                __bf16* __restrict__ hi, __bf16* __restrict__ lo, float* __restrict__ bias) {
+  const int groups = kPackElems / 8;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < groups + kLayers * kWidth;
+       i += gridDim.x * blockDim.x) {
+    if (i < groups) {
+      const int e0 = 8 * i;
+      float v[8];
+      if (e0 < kFwdElems) {
+        int l = 0;
+        while (l + 1 < kLayers && e0 >= f_off(l + 1)) ++l;
+        const int KS = f_k(l) / 32, frag = (e0 - f_off(l)) / 8;
+        const int lane = frag & 63, t = frag >> 6, ks = t % KS, ct = t / KS;
+        const int n = ct * 16 + (lane & 15), kb = ks * 32 + 8 * (lane >> 4);
+        for (int e = 0; e < 8; ++e)
+          v[e] = n < n_out(l) ? P[w_off(l) + n * n_in(l) + kb + e] : 0.f;
+      } else {
+        int l = 1;
+        while (l + 1 < kLayers && e0 >= t_off(l + 1)) ++l;
+        const int KS = t_k(l) / 32, frag = (e0 - t_off(l)) / 8;
+        const int lane = frag & 63, t = frag >> 6, ks = t % KS, ct = t / KS;
+        const int k = ct * 16 + (lane & 15), nb = ks * 32 + 8 * (lane >> 4);
+        for (int e = 0; e < 8; ++e)
+          v[e] = nb + e < n_out(l) ? P[w_off(l) + (nb + e) * n_in(l) + k] : 0.f;
+      }
+      bf16x8 h, l8;
+      split8(v, h, l8);
+      *reinterpret_cast<bf16x8*>(hi + e0) = h;
+      *reinterpret_cast<bf16x8*>(lo + e0) = l8;
+    } else {
+      const int j = i - groups, l = j / kWidth, n = j % kWidth;
+      float b = 0.f;
+      if (l == 0) {
+        b = P[b_off(0) + n];
+        for (int t = 0; t < kPose; ++t) b = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + t], theta[t], b);
+      } else if (n < n_out(l)) {
+        b = P[b_off(l) + n];
+      }
+      bias[j] = b;
+    }
+  }
+}
+
+// gamma(x): sin and cos of 2 pi (B_j . x), with the 2 folded into the
+// argument of sinpi / cospi
+__device__ inline float fourier_arg(const float* __restrict__ freqs, int j, float x0, float x1,
+                                    float x2) {
+  const float a = fmaf(freqs[3 * j + 2], x2, fmaf(freqs[3 * j + 1], x1, freqs[3 * j] * x0));
+  return 2.f * a;
+}
+
+__global__ void __launch_bounds__(256)
+mlp_forward_kernel(int nv, int nvp, const float* __restrict__ x, const float* __restrict__ freqs,
+                   const __bf16* __restrict__ phi, const __bf16* __restrict__ plo,
+                   const float* __restrict__ bias, float* __restrict__ H, float* __restrict__ out) {
+  __shared__ __align__(16) float act[kWaves][16][kAS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * kWaves + wave) * 16;
+  if (r0 >= nvp) return;                 // whole waves; no workgroup barrier below
+  float(*A)[kAS] = act[wave];
+  // Fourier features: lane = frequency, one row per step
+  for (int r = 0; r < 16; ++r) {
+    const int v = r0 + r;
+    const bool in = v < nv;
+    const float x0 = in ? x[v] : 0.f, x1 = in ? x[nv + v] : 0.f, x2 = in ? x[2 * nv + v] : 0.f;
+    const float f = fourier_arg(freqs, lane, x0, x1, x2);
+    A[r][lane] = sinpif(f);
+    A[r][kFreqs + lane] = cospif(f);
+  }
+  wave_sync();
+  const int row = lane & 15, g = lane >> 4;
+  const bf16x8* bh = reinterpret_cast<const bf16x8*>(phi);
+  const bf16x8* bl = reinterpret_cast<const bf16x8*>(plo);
+  for (int l = 0; l < kLayers; ++l) {
+    const int KS = f_k(l) / 32, NT = f_n(l) / 16, fo = f_off(l) / 8;
+    f32x4 acc[16];
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+      float av[8];
+      load8(&A[row][ks * 32 + 8 * g], av);
+      bf16x8 ah, al;
+      split8(av, ah, al);
+#pragma unroll
+      for (int ct = 0; ct < 16; ++ct) {
+        if (ct >= NT) break;
+        const int fi = fo + (ct * KS + ks) * 64 + lane;
+        acc[ct] = mfma3(ah, al, bh[fi], bl[fi], acc[ct]);
+      }
+    }
+    wave_sync();
+    if (l < kLayers - 1) {
+#pragma unroll
+      for (int ct = 0; ct < 16; ++ct) {
+        const int n = ct * 16 + row;
+        const float bn = bias[l * kWidth + n];
+        float hv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 4 * g + i;
+          const float h = fmaxf(acc[ct][i] + bn, 0.f);
+          A[r][n] = h;
+          hv[i] = r0 + r < nv ? h : 0.f;
+        }
+        *reinterpret_cast<float4*>(H + ((size_t)l * kWidth + n) * nvp + r0 + 4 * g) =
+            make_float4(hv[0], hv[1], hv[2], hv[3]);
+      }
+      wave_sync();
+    } else if (row < 3) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int v = r0 + 4 * g + i;
+        if (v < nv) out[(size_t)row * nv + v] = acc[0][i] + bias[l * kWidth + row];
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+mlp_backward_kernel(int nv, int nvp, const float* __restrict__ ddx, const __bf16* __restrict__ phi,
+                    const __bf16* __restrict__ plo, const float* __restrict__ H,
+                    float* __restrict__ dZ) {
+  __shared__ __align__(16) float act[kWaves][16][kAS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = (blockIdx.x * kWaves + wave) * 16;
+  if (r0 >= nvp) return;
+  float(*A)[kAS] = act[wave];
+  float* dZ5 = dZ + (size_t)4 * kWidth * nvp;
+  // dz_5 = ddx, as 32 reduction columns (3 used)
+  for (int r = 0; r < 16; ++r) {
+    const int v = r0 + r;
+    if (lane < 32) {
+      const float d = (lane < 3 && v < nv) ? ddx[(size_t)lane * nv + v] : 0.f;
+      A[r][lane] = d;
+      if (lane < 16) dZ5[(size_t)lane * nvp + v] = d;
+    }
+  }
+  wave_sync();
+  const int row = lane & 15, g = lane >> 4;
+  const bf16x8* bh = reinterpret_cast<const bf16x8*>(phi);
+  const bf16x8* bl = reinterpret_cast<const bf16x8*>(plo);
+  for (int l = kLayers - 1; l >= 1; --l) {
+    const int KS = t_k(l) / 32, to = t_off(l) / 8;
+    f32x4 acc[16];
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+      float av[8];
+      load8(&A[row][ks * 32 + 8 * g], av);
+      bf16x8 ah, al;
+      split8(av, ah, al);
+#pragma unroll
+      for (int ct = 0; ct < 16; ++ct) {
+        const int fi = to + (ct * KS + ks) * 64 + lane;
+        acc[ct] = mfma3(ah, al, bh[fi], bl[fi], acc[ct]);
+      }
+    }
+    wave_sync();
+    // dz of hidden layer l - 1 (the input of layer l): dh where h > 0
+#pragma unroll
+    for (int ct = 0; ct < 16; ++ct) {
+      const int n = ct * 16 + row;
+      const size_t o = ((size_t)(l - 1) * kWidth + n) * nvp + r0 + 4 * g;
+      const float4 h = *reinterpret_cast<const float4*>(H + o);
+      const float hv[4] = {h.x, h.y, h.z, h.w};
+      float dv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dv[i] = hv[i] > 0.f ? acc[ct][i] : 0.f;
+        A[4 * g + i][n] = dv[i];
+      }
+      *reinterpret_cast<float4*>(dZ + o) = make_float4(dv[0], dv[1], dv[2], dv[3]);
+    }
+    wave_sync();
+  }
+}
+
+// dW_l[n][k] = sum_v dz_l[n][v] hin_l[k][v] over one chunk of vertices;
+// item = (layer, band of 16 rows n), blockIdx.y = chunk; wave w takes the
+// columns 64 w .. 64 w + 63.  Wave 0 also sums the band's dz rows (db).
+__global__ void __launch_bounds__(256)
+mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
+                 const float* __restrict__ freqs, const float* __restrict__ H,
+                 const float* __restrict__ dZ, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = blockIdx.x, c = blockIdx.y;
+  const int l = item < 64 ? item / 16 : 4, band = item < 64 ? item % 16 : 0;
+  const int K = f_k(l);                  // reduction inputs of the layer's weights here
+  const int col0 = 64 * wave;
+  const bool cols = col0 < K;
+  if (!cols && wave != 0) return;        // whole waves; no workgroup barrier below
+  const int row = lane & 15, g = lane >> 4;
+  const int n = band * 16 + row;
+  const float* dz = l < 4 ? dZ + ((size_t)l * kWidth + n) * nvp
+                          : dZ + ((size_t)4 * kWidth + n) * nvp;
+  const int v0 = c * chunk_len, v1 = min(nvp, v0 + chunk_len);
+  f32x4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbs = 0.f;
+  for (int vb = v0; vb < v1; vb += 32) {
+    const int va = vb + 8 * g;
+    float av[8];
+    load8(dz + va, av);
+    if (wave == 0)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dbs += av[e];
+    if (!cols) continue;
+    bf16x8 ah, al;
+    split8(av, ah, al);
+    float xs[8][3];
+    if (l == 0)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int v = va + e;
+        const bool in = v < nv;
+        xs[e][0] = in ? x[v] : 0.f;
+        xs[e][1] = in ? x[nv + v] : 0.f;
+        xs[e][2] = in ? x[2 * nv + v] : 0.f;
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = col0 + 16 * q + row;
+      float bv[8];
+      if (l == 0) {
+        const int j = k & (kFreqs - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float f = fourier_arg(freqs, j, xs[e][0], xs[e][1], xs[e][2]);
+          bv[e] = k < kFreqs ? sinpif(f) : cospif(f);
+        }
+      } else {
+        load8(H + ((size_t)(l - 1) * kWidth + k) * nvp + va, bv);
+      }
+      bf16x8 bh, bl;
+      split8(bv, bh, bl);
+      acc[q] = mfma3(ah, al, bh, bl, acc[q]);
+    }
+  }
+  float* pc = part + (size_t)c * kParams;
+  if (cols) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = col0 + 16 * q + row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int nn = band * 16 + 4 * g + i;
+        if (nn < n_out(l)) pc[w_off(l) + nn * n_in(l) + k] = acc[q][i];
+      }
+    }
+  }
+  if (wave == 0) {
+    dbs += __shfl_xor(dbs, 16);
+    dbs += __shfl_xor(dbs, 32);
+    if (g == 0 && n < n_out(l)) pc[b_off(l) + n] = dbs;
+  }
+}
+
+// dparams = sum over the chunks (fixed order); W_1's pose columns are
+// db_1 theta^T (the pose is shared by every vertex)
+__global__ void __launch_bounds__(256)
+mlp_reduce_kernel(int chunks, const float* __restrict__ theta, const float* __restrict__ part,
+                  float* __restrict__ dP) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  const int k = p % kIn1;
+  if (p < b_off(0) && k >= 2 * kFreqs) {
+    const int n = p / kIn1;
+    float db = 0.f;
+    for (int c = 0; c < chunks; ++c) db += part[(size_t)c * kParams + b_off(0) + n];
+    dP[p] = db * theta[k - 2 * kFreqs];
+  } else {
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * kParams + p];
+    dP[p] = s;
+  }
+}
+
+// dtheta = W_1[:, 128:]^T db_1
+__global__ void __launch_bounds__(128)
+mlp_dtheta_kernel(int chunks, const float* __restrict__ P, const float* __restrict__ part,
+                  float* __restrict__ dtheta) {
+  const int t = threadIdx.x;
+  if (t >= kPose) return;
+  float s = 0.f;
+  for (int n = 0; n < kWidth; ++n) {
+    float db = 0.f;
+    for (int c = 0; c < chunks; ++c) db += part[(size_t)c * kParams + b_off(0) + n];
+    s = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + t], db, s);
+  }
+  dtheta[t] = s;
+}
+
+}  // namespace
+
+extern "C" size_t mlp_workspace(int nv) {
+  if (nv < 0) return 0;
+  return mlp_layout(nv).total;
+}
+
+extern "C" int mlp_forward(void* stream, int nv, const float* x, const float* freqs,
+                           const float* theta, const float* params, void* ws, size_t ws_bytes,
+                           float* dx) {
+  if (nv < 0 || nv > (1 << 26)) return rga::fail(RGA_EINVAL, "mlp_forward: nv in 0..2^26");
+  if (!freqs || !theta || !params || !ws || (nv > 0 && (!x || !dx)))
+    return rga::fail(RGA_EINVAL, "mlp_forward: null pointer");
+  const MlpLayout L = mlp_layout(nv);
+  if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "mlp_forward: workspace too small");
+  if (!rga::aligned16(ws)) return rga::fail(RGA_EINVAL, "mlp_forward: workspace not 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  __bf16* hi = at<__bf16>(ws, L.pack);
+  __bf16* lo = hi + kPackElems;
+  RGA_LAUNCH("mlp_pack", mlp_pack_kernel, dim3(256), dim3(256), 0, s, params, theta, hi, lo,
+             at<float>(ws, L.bias));
+  // with no vertices the kernel still clears the kept activations of the
+  // padding rows, which the adjoint reads
+  RGA_LAUNCH("mlp_fwd", mlp_forward_kernel, dim3(rga::ceil_div(L.nvp / 16, kWaves)),
+               dim3(64 * kWaves), 0, s, nv, L.nvp, x, freqs, hi, lo, at<float>(ws, L.bias),
+               at<float>(ws, L.h), dx);
+  RGA_CHECK_LAUNCH("mlp_forward");
+  return RGA_OK;
+}
+
+extern "C" int mlp_backward(void* stream, int nv, const float* x, const float* freqs,
+                            const float* theta, const float* params, const float* ddx, void* ws,
+                            size_t ws_bytes, float* dparams, float* dtheta) {
+  if (nv < 0 || nv > (1 << 26)) return rga::fail(RGA_EINVAL, "mlp_backward: nv in 0..2^26");
+  if (!freqs || !theta || !params || !ws || !dparams || !dtheta || (nv > 0 && (!x || !ddx)))
+    return rga::fail(RGA_EINVAL, "mlp_backward: null pointer");
+  const MlpLayout L = mlp_layout(nv);
+  if (ws_bytes < L.total) return rga::fail(RGA_ECAPACITY, "mlp_backward: workspace too small");
+  if (!rga::aligned16(ws)) return rga::fail(RGA_EINVAL, "mlp_backward: workspace not 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const __bf16* hi = at<__bf16>(ws, L.pack);
+  const __bf16* lo = hi + kPackElems;
+  float* part = at<float>(ws, L.part);
+  // with no vertices every partial sum is zero: the backward and the
+  // weight-gradient kernels still run over the (zero) padding rows
+  RGA_LAUNCH("mlp_bwd", mlp_backward_kernel, dim3(rga::ceil_div(L.nvp / 16, kWaves)),
+             dim3(64 * kWaves), 0, s, nv, L.nvp, ddx, hi, lo, at<float>(ws, L.h),
+             at<float>(ws, L.dz));
+  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_kernel, dim3(65, L.chunks), dim3(64 * kWaves), 0, s, nv,
+             L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
+  RGA_LAUNCH("mlp_reduce", mlp_reduce_kernel, dim3(rga::ceil_div(kParams, 256)), dim3(256), 0, s,
+             L.chunks, theta, part, dparams);
+  RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(128), 0, s, L.chunks, params, part,
+             dtheta);
+  RGA_CHECK_LAUNCH("mlp_backward");
+  return RGA_OK;
+}

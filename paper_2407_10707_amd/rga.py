@@ -57,6 +57,9 @@ _SIGS = {
     "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ, _VP, _SZ]),
     "knn_interpolate": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
+    "mlp_workspace": (_SZ, [_I]),
+    "mlp_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    "mlp_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
     "rga_timing_enable": (_I, [_I]),
     "rga_timing_reset": (_I, []),
     "rga_timing_filter": (_I, [C.c_char_p]),
@@ -383,6 +386,48 @@ def knn_interpolate_backward(idx, w, dout, nr: int):
     _check(lib().knn_interpolate_backward(_stream(), n, k, _p(idx), _p(w), C_, int(nr), _p(dout),
                                           _p(dattr)), "knn_interpolate_backward")
     return dattr
+
+
+MLP_PARAMS = 249603
+
+
+class Displacement:
+    """The displacement network d(x, theta) over a fixed set of vertices:
+    holds the workspace that `forward` fills and `backward` reads."""
+
+    def __init__(self, x, freqs):
+        self.x = _f32(x, "x")
+        if self.x.dim() != 2 or self.x.shape[0] != 3:
+            raise RgaError("x must be [3, nv]")
+        self.freqs = _f32(freqs, "freqs")
+        if tuple(self.freqs.shape) != (64, 3):
+            raise RgaError("freqs must be [64, 3]")
+        self.nv = int(self.x.shape[1])
+        self.bytes = int(lib().mlp_workspace(self.nv))
+        self.ws = torch.empty(self.bytes, dtype=torch.uint8, device=self.x.device)
+
+    def forward(self, theta, params):
+        """dx [3, nv] for pose theta [72] and the flat parameters."""
+        self.theta = _f32(theta, "theta").reshape(-1)
+        self.params = _f32(params, "params").reshape(-1)
+        if self.theta.numel() != 72 or self.params.numel() != MLP_PARAMS:
+            raise RgaError("theta must hold 72 and params %d floats" % MLP_PARAMS)
+        dx = torch.empty((3, self.nv), dtype=torch.float32, device=self.x.device)
+        _check(lib().mlp_forward(_stream(), self.nv, _p(self.x), _p(self.freqs), _p(self.theta),
+                                 _p(self.params), _p(self.ws), self.bytes, _p(dx)), "mlp_forward")
+        return dx
+
+    def backward(self, ddx):
+        """(dparams, dtheta) of the last forward for ddx [3, nv]."""
+        ddx = _f32(ddx, "ddx")
+        if tuple(ddx.shape) != (3, self.nv):
+            raise RgaError("ddx must be [3, nv]")
+        dp = torch.empty(MLP_PARAMS, dtype=torch.float32, device=ddx.device)
+        dt = torch.empty(72, dtype=torch.float32, device=ddx.device)
+        _check(lib().mlp_backward(_stream(), self.nv, _p(self.x), _p(self.freqs), _p(self.theta),
+                                  _p(self.params), _p(ddx), _p(self.ws), self.bytes, _p(dp),
+                                  _p(dt)), "mlp_backward")
+        return dp, dt
 
 
 def timing_enable(on: bool = True):

@@ -47,6 +47,8 @@ def test_workspace_sizes_are_monotone():
     assert L.shade_gaussians_workspace(100000, 16, 32) > 0
     assert L.l1_loss_workspace(3 * 512 * 512) > 0
     assert L.knn_workspace(6840) > 6840 * 16
+    assert 0 < L.mlp_workspace(100) < L.mlp_workspace(10000)
+    assert L.mlp_workspace(-1) == 0
 
 
 def test_argument_errors_are_reported_before_any_launch():
@@ -74,3 +76,10 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.knn_build(None, 0, None, None, 0) == -1
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
     assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1
+    assert L.mlp_forward(None, -1, None, None, None, None, None, 0, None) == -1
+    assert L.mlp_forward(None, 10, None, None, None, None, None, 0, None) == -1
+    assert "null" in rga.last_error()
+    fake = C.c_void_p(16)   # never dereferenced: the size check fails first
+    assert L.mlp_forward(None, 10, fake, fake, fake, fake, fake, 16, fake) == -2
+    assert "workspace" in rga.last_error()
+    assert L.mlp_backward(None, 10, fake, fake, fake, fake, fake, fake, 16, fake, None) == -1

@@ -1,0 +1,151 @@
+"""The displacement network (Sec. 3.1 attributes, Sec. 4 details) on the GPU
+through the C ABI against the FP64 oracle.
+
+Tolerances, from the arithmetic: every product runs on bf16 MFMA with each
+operand split into high and low bf16 parts (hi.hi + lo.hi + hi.lo), so a
+product carries a relative error of about 2^-16 (the dropped lo.lo term and
+the rounding of the low parts), and the FP32 sums over 256 terms add
+rounding of the same order.  Over five layers this stays near 1e-5 of the
+output's scale: the bound used is max |d - d_ref| <= 2e-4 rms(d_ref).
+
+The adjoint's ReLU masks are decisions taken on the forward's FP32
+pre-activations.  A vertex with a pre-activation within 3e-4 of its layer's
+RMS of zero (30 times the forward's error) may take the other decision on
+the GPU, which is as correct; such vertices get a zero upstream gradient,
+so that they contribute nothing on either side.  The remaining gradients
+(sums over the vertices of products of the same split form) are compared
+blockwise: max |g - g_ref| <= 2e-4 max |g_ref|.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref64
+from paper_2407_10707_amd import rga, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(torch.float32).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    rga.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _inputs(nv, seed, x=None):
+    inp = synth.mlp_inputs(seed, n_pose=2)
+    if x is None:
+        x = np.random.default_rng([11, seed]).normal(0.0, 0.5, (3, nv)).astype(np.float32)
+    return x, inp
+
+
+def _forward_check(x, inp, pose=0):
+    nv = x.shape[1]
+    print(f"[mlp] forward nv={nv} pose={pose}", flush=True)
+    net = rga.Displacement(dev(x), dev(inp["freqs"]))
+    out = host(net.forward(dev(inp["thetas"][pose]), dev(inp["params"])))
+    ref = ref64.displacement(x.astype(np.float64), inp["freqs"].astype(np.float64),
+                             inp["thetas"][pose].astype(np.float64),
+                             inp["params"].astype(np.float64)).numpy()
+    if nv:
+        rms = np.sqrt(np.mean(ref ** 2))
+        err = np.abs(out - ref).max()
+        print(f"[mlp]   max err / rms = {err / rms:.3e}", flush=True)
+        assert err <= 2e-4 * rms
+    return net
+
+
+@pytest.mark.parametrize("nv", [1, 37, 300])
+def test_forward_small_and_ragged(nv):
+    x, inp = _inputs(nv, nv)
+    _forward_check(x, inp)
+
+
+def test_forward_avatar_mesh_and_two_poses():
+    verts, _ = synth.body_mesh(18, 21)
+    x = verts.T.astype(np.float32)
+    _, inp = _inputs(0, 5)
+    net = _forward_check(x, inp, pose=0)
+    del net
+    _forward_check(x, inp, pose=1)
+
+
+def _grad_ref(x, inp, ddx):
+    shapes = ref64.MLP_SHAPES
+    p = torch.tensor(inp["params"].astype(np.float64), requires_grad=True)
+    th = torch.tensor(inp["thetas"][0].astype(np.float64), requires_grad=True)
+    zs, out = ref64.mlp_layers(x.astype(np.float64), inp["freqs"].astype(np.float64), th,
+                               ref64.mlp_unpack(p, shapes))
+    gp, gt = torch.autograd.grad((out * torch.tensor(ddx)).sum(), (p, th))
+    return gp.numpy(), gt.numpy()
+
+
+def _safe_mask(x, inp):
+    """Vertices whose every hidden pre-activation is at least 3e-4 of its
+    layer's RMS away from zero (decided on the oracle's FP64 values)."""
+    zs, _ = ref64.mlp_layers(x.astype(np.float64), inp["freqs"].astype(np.float64),
+                             inp["thetas"][0].astype(np.float64),
+                             ref64.mlp_unpack(inp["params"].astype(np.float64)))
+    ok = np.ones(x.shape[1], dtype=bool)
+    for z in zs[:-1]:
+        z = z.numpy()
+        rms = np.sqrt(np.mean(z ** 2))
+        ok &= (np.abs(z) >= 3e-4 * rms).all(axis=0)
+    return ok
+
+
+def _backward_check(x, inp, seed):
+    nv = x.shape[1]
+    ddx = np.random.default_rng([13, seed]).normal(size=(3, nv))
+    ok = _safe_mask(x, inp)
+    ddx[:, ~ok] = 0.0
+    print(f"[mlp] backward nv={nv} vertices compared={ok.sum()}", flush=True)
+    net = rga.Displacement(dev(x), dev(inp["freqs"]))
+    net.forward(dev(inp["thetas"][0]), dev(inp["params"]))
+    dp, dt = net.backward(dev(ddx))
+    dp, dt = host(dp), host(dt)
+    gp, gt = _grad_ref(x, inp, ddx)
+    o = 0
+    for li, (n_out, n_in) in enumerate(ref64.MLP_SHAPES):
+        for name, size in (("W", n_out * n_in), ("b", n_out)):
+            a, r = dp[o:o + size], gp[o:o + size]
+            scale = np.abs(r).max()
+            err = np.abs(a - r).max()
+            print(f"[mlp]   {name}{li + 1}: max err / max = {err / max(scale, 1e-30):.3e}", flush=True)
+            assert err <= 2e-4 * scale + 1e-30
+            o += size
+    err = np.abs(dt - gt).max()
+    print(f"[mlp]   theta: max err / max = {err / np.abs(gt).max():.3e}", flush=True)
+    assert err <= 2e-4 * np.abs(gt).max()
+
+
+def test_backward_ragged():
+    x, inp = _inputs(300, 21)
+    _backward_check(x, inp, 1)
+
+
+def test_backward_avatar_mesh():
+    verts, _ = synth.body_mesh(18, 21)
+    _, inp = _inputs(0, 22)
+    _backward_check(verts.T.astype(np.float32), inp, 2)
+
+
+def test_no_vertices():
+    _, inp = _inputs(0, 23)
+    net = rga.Displacement(torch.zeros((3, 0), device="cuda"), dev(inp["freqs"]))
+    out = net.forward(dev(inp["thetas"][0]), dev(inp["params"]))
+    assert out.shape == (3, 0)
+    dp, dt = net.backward(torch.zeros((3, 0), device="cuda"))
+    assert not host(dp).any() and not host(dt).any()

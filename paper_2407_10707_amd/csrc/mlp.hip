@@ -14,13 +14,14 @@
 //             the MFMA B operand (one 16-byte load per lane and step), once
 //             in forward order and once transposed for the adjoint; the pose
 //             is folded into the first layer's bias (b_1 + W_1[:, 128:] theta)
-//   forward   one wave per 16 vertices, all layers in one kernel: the
-//             activations stay in the wave's LDS slice, the weights stream
-//             from L2; the hidden activations are kept for the adjoint
-//   backward  one wave per 16 vertices: dz_5 = ddx, dh = dz W (transposed
-//             pack), dz = dh where h > 0; every dz is kept
+//   forward   one workgroup per 32 vertices, all layers in one kernel: the
+//             activations stay in LDS (two buffers), each wave computes 64
+//             of a layer's columns with the weights streaming from L2; the
+//             hidden activations are kept for the adjoint
+//   backward  the same shape: dz_5 = ddx, dh = dz W (transposed pack),
+//             dz = dh where h > 0; every dz is kept
 //   wgrad     dW_l = sum over vertices of dz_l h_{l-1}^T: workgroups over
-//             (layer, 16-row band, chunk of vertices), each wave 64 columns,
+//             (layer, 64 x 128 tile, chunk of vertices),
 //             partial sums per chunk (no atomics), then a fixed-order sum
 //             over the chunks; the Fourier features of the first layer are
 //             recomputed from x; dW_1's pose columns are db_1 theta^T and
@@ -41,7 +42,7 @@ constexpr int kIn1 = 2 * kFreqs + kPose;  // 200
 constexpr int kLayers = 5;
 constexpr int kParams = RGA_MLP_PARAMS;
 constexpr int kAS = kWidth + 4;           // LDS row stride of the activations (floats)
-constexpr int kMaxChunks = 16;
+constexpr int kMaxChunks = 32;
 constexpr int kWaves = 4;
 
 // parameter layout: W_1 [256][200], b_1, W_2 [256][256], b_2, W_3, b_3, W_4, b_4, W_5 [3][256], b_5
@@ -83,7 +84,7 @@ struct MlpLayout {
 MlpLayout mlp_layout(int nv) {
   MlpLayout L{};
   L.nvp = (int)rga::align_up((size_t)(nv > 0 ? nv : 1), 32);
-  L.chunks = std::max(1, std::min(kMaxChunks, L.nvp / 512));
+  L.chunks = std::max(1, std::min(kMaxChunks, L.nvp / 256));
   L.chunk_len = (int)rga::align_up((size_t)rga::ceil_div(L.nvp, L.chunks), 32);
   const size_t V = (size_t)L.nvp;
   size_t o = 0;
@@ -192,70 +193,113 @@ __device__ inline float fourier_arg(const float* __restrict__ freqs, int j, floa
   return 2.f * a;
 }
 
+// One layer's product for a workgroup's 32 rows: wave w takes the NQ
+// column tiles from `ct0`; A comes from the LDS activations (two row tiles),
+// the operand fragments from global memory, those of the next reduction
+// step loaded before the products of the current one.
+template <int NQ>
+__device__ inline void layer_mm(const float (*Ain)[kAS], const bf16x8* __restrict__ bh,
+                                const bf16x8* __restrict__ bl, int fo, int KS, int ct0,
+                                f32x4 (&acc)[2][NQ]) {
+  const int lane = threadIdx.x & 63, row = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[rt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 ch[NQ], cl[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int fi = fo + ((ct0 + q) * KS) * 64 + lane;
+    ch[q] = bh[fi];
+    cl[q] = bl[fi];
+  }
+  for (int ks = 0; ks < KS; ++ks) {
+    bf16x8 nh[NQ], nl[NQ];
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int fi = fo + ((ct0 + q) * KS + ks + 1) * 64 + lane;
+        nh[q] = bh[fi];
+        nl[q] = bl[fi];
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      float av[8];
+      load8(&Ain[rt * 16 + row][ks * 32 + 8 * g], av);
+      bf16x8 ah, al;
+      split8(av, ah, al);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[rt][q] = mfma3(ah, al, ch[q], cl[q], acc[rt][q]);
+    }
+    if (ks + 1 < KS) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        ch[q] = nh[q];
+        cl[q] = nl[q];
+      }
+    }
+  }
+}
+
+constexpr int kRows = 32;                // vertices per workgroup
+
 __global__ void __launch_bounds__(256)
 mlp_forward_kernel(int nv, int nvp, const float* __restrict__ x, const float* __restrict__ freqs,
                    const __bf16* __restrict__ phi, const __bf16* __restrict__ plo,
                    const float* __restrict__ bias, float* __restrict__ H, float* __restrict__ out) {
-  __shared__ __align__(16) float act[kWaves][16][kAS];
+  __shared__ __align__(16) float act[2][kRows][kAS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.x * kWaves + wave) * 16;
-  if (r0 >= nvp) return;                 // whole waves; no workgroup barrier below
-  float(*A)[kAS] = act[wave];
-  // Fourier features: lane = frequency, one row per step
-  for (int r = 0; r < 16; ++r) {
+  const int row = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * kRows;     // < nvp by the grid
+  // Fourier features: lane = frequency, rows wave, wave + 4, ...
+  for (int r = wave; r < kRows; r += kWaves) {
     const int v = r0 + r;
     const bool in = v < nv;
     const float x0 = in ? x[v] : 0.f, x1 = in ? x[nv + v] : 0.f, x2 = in ? x[2 * nv + v] : 0.f;
     const float f = fourier_arg(freqs, lane, x0, x1, x2);
-    A[r][lane] = sinpif(f);
-    A[r][kFreqs + lane] = cospif(f);
+    act[0][r][lane] = sinpif(f);
+    act[0][r][kFreqs + lane] = cospif(f);
   }
-  wave_sync();
-  const int row = lane & 15, g = lane >> 4;
+  __syncthreads();
   const bf16x8* bh = reinterpret_cast<const bf16x8*>(phi);
   const bf16x8* bl = reinterpret_cast<const bf16x8*>(plo);
-  for (int l = 0; l < kLayers; ++l) {
-    const int KS = f_k(l) / 32, NT = f_n(l) / 16, fo = f_off(l) / 8;
-    f32x4 acc[16];
+  int cur = 0;
+  for (int l = 0; l < kLayers - 1; ++l) {
+    f32x4 acc[2][4];
+    layer_mm<4>(act[cur], bh, bl, f_off(l) / 8, f_k(l) / 32, 4 * wave, acc);
 #pragma unroll
-    for (int ct = 0; ct < 16; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < KS; ++ks) {
-      float av[8];
-      load8(&A[row][ks * 32 + 8 * g], av);
-      bf16x8 ah, al;
-      split8(av, ah, al);
+    for (int q = 0; q < 4; ++q) {
+      const int n = (4 * wave + q) * 16 + row;
+      const float bn = bias[l * kWidth + n];
 #pragma unroll
-      for (int ct = 0; ct < 16; ++ct) {
-        if (ct >= NT) break;
-        const int fi = fo + (ct * KS + ks) * 64 + lane;
-        acc[ct] = mfma3(ah, al, bh[fi], bl[fi], acc[ct]);
-      }
-    }
-    wave_sync();
-    if (l < kLayers - 1) {
-#pragma unroll
-      for (int ct = 0; ct < 16; ++ct) {
-        const int n = ct * 16 + row;
-        const float bn = bias[l * kWidth + n];
+      for (int rt = 0; rt < 2; ++rt) {
         float hv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int r = 4 * g + i;
-          const float h = fmaxf(acc[ct][i] + bn, 0.f);
-          A[r][n] = h;
+          const int r = rt * 16 + 4 * g + i;
+          const float h = fmaxf(acc[rt][q][i] + bn, 0.f);
+          act[cur ^ 1][r][n] = h;
           hv[i] = r0 + r < nv ? h : 0.f;
         }
-        *reinterpret_cast<float4*>(H + ((size_t)l * kWidth + n) * nvp + r0 + 4 * g) =
+        *reinterpret_cast<float4*>(H + ((size_t)l * kWidth + n) * nvp + r0 + rt * 16 + 4 * g) =
             make_float4(hv[0], hv[1], hv[2], hv[3]);
       }
-      wave_sync();
-    } else if (row < 3) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int v = r0 + 4 * g + i;
-        if (v < nv) out[(size_t)row * nv + v] = acc[0][i] + bias[l * kWidth + row];
-      }
     }
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (wave == 0) {                       // the output layer: one 16-column tile
+    f32x4 acc[2][1];
+    layer_mm<1>(act[cur], bh, bl, f_off(kLayers - 1) / 8, f_k(kLayers - 1) / 32, 0, acc);
+    if (row < 3)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int v = r0 + rt * 16 + 4 * g + i;
+          if (v < nv) out[(size_t)row * nv + v] = acc[rt][0][i] + bias[(kLayers - 1) * kWidth + row];
+        }
   }
 }
 
@@ -263,139 +307,178 @@ __global__ void __launch_bounds__(256)
 mlp_backward_kernel(int nv, int nvp, const float* __restrict__ ddx, const __bf16* __restrict__ phi,
                     const __bf16* __restrict__ plo, const float* __restrict__ H,
                     float* __restrict__ dZ) {
-  __shared__ __align__(16) float act[kWaves][16][kAS];
+  __shared__ __align__(16) float act[2][kRows][kAS];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r0 = (blockIdx.x * kWaves + wave) * 16;
-  if (r0 >= nvp) return;
-  float(*A)[kAS] = act[wave];
+  const int row = lane & 15, g = lane >> 4;
+  const int r0 = blockIdx.x * kRows;
   float* dZ5 = dZ + (size_t)4 * kWidth * nvp;
   // dz_5 = ddx, as 32 reduction columns (3 used)
-  for (int r = 0; r < 16; ++r) {
-    const int v = r0 + r;
-    if (lane < 32) {
-      const float d = (lane < 3 && v < nv) ? ddx[(size_t)lane * nv + v] : 0.f;
-      A[r][lane] = d;
-      if (lane < 16) dZ5[(size_t)lane * nvp + v] = d;
-    }
+  for (int t = threadIdx.x; t < kRows * 32; t += blockDim.x) {
+    const int r = t >> 5, c = t & 31, v = r0 + r;
+    const float d = (c < 3 && v < nv) ? ddx[(size_t)c * nv + v] : 0.f;
+    act[0][r][c] = d;
+    if (c < 16) dZ5[(size_t)c * nvp + v] = d;
   }
-  wave_sync();
-  const int row = lane & 15, g = lane >> 4;
+  __syncthreads();
   const bf16x8* bh = reinterpret_cast<const bf16x8*>(phi);
   const bf16x8* bl = reinterpret_cast<const bf16x8*>(plo);
+  int cur = 0;
   for (int l = kLayers - 1; l >= 1; --l) {
-    const int KS = t_k(l) / 32, to = t_off(l) / 8;
-    f32x4 acc[16];
-#pragma unroll
-    for (int ct = 0; ct < 16; ++ct) acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < KS; ++ks) {
-      float av[8];
-      load8(&A[row][ks * 32 + 8 * g], av);
-      bf16x8 ah, al;
-      split8(av, ah, al);
-#pragma unroll
-      for (int ct = 0; ct < 16; ++ct) {
-        const int fi = to + (ct * KS + ks) * 64 + lane;
-        acc[ct] = mfma3(ah, al, bh[fi], bl[fi], acc[ct]);
-      }
-    }
-    wave_sync();
+    f32x4 acc[2][4];
+    layer_mm<4>(act[cur], bh, bl, t_off(l) / 8, t_k(l) / 32, 4 * wave, acc);
     // dz of hidden layer l - 1 (the input of layer l): dh where h > 0
 #pragma unroll
-    for (int ct = 0; ct < 16; ++ct) {
-      const int n = ct * 16 + row;
-      const size_t o = ((size_t)(l - 1) * kWidth + n) * nvp + r0 + 4 * g;
-      const float4 h = *reinterpret_cast<const float4*>(H + o);
-      const float hv[4] = {h.x, h.y, h.z, h.w};
-      float dv[4];
+    for (int q = 0; q < 4; ++q) {
+      const int n = (4 * wave + q) * 16 + row;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        dv[i] = hv[i] > 0.f ? acc[ct][i] : 0.f;
-        A[4 * g + i][n] = dv[i];
+      for (int rt = 0; rt < 2; ++rt) {
+        const size_t o = ((size_t)(l - 1) * kWidth + n) * nvp + r0 + rt * 16 + 4 * g;
+        const float4 h = *reinterpret_cast<const float4*>(H + o);
+        const float hv[4] = {h.x, h.y, h.z, h.w};
+        float dv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          dv[i] = hv[i] > 0.f ? acc[rt][q][i] : 0.f;
+          act[cur ^ 1][rt * 16 + 4 * g + i][n] = dv[i];
+        }
+        *reinterpret_cast<float4*>(dZ + o) = make_float4(dv[0], dv[1], dv[2], dv[3]);
       }
-      *reinterpret_cast<float4*>(dZ + o) = make_float4(dv[0], dv[1], dv[2], dv[3]);
     }
-    wave_sync();
+    __syncthreads();
+    cur ^= 1;
   }
 }
 
-// dW_l[n][k] = sum_v dz_l[n][v] hin_l[k][v] over one chunk of vertices;
-// item = (layer, band of 16 rows n), blockIdx.y = chunk; wave w takes the
-// columns 64 w .. 64 w + 63.  Wave 0 also sums the band's dz rows (db).
+// dW_l[n][k] = sum_v dz_l[n][v] hin_l[k][v] over one chunk of vertices.
+// Workgroup tiles of 64 rows n x 128 columns k (waves 2 x 2, each 32 x 64),
+// blockIdx.x = (layer, tile), blockIdx.y = chunk; the next 32 vertices'
+// operands are loaded before the products of the current ones.  The waves
+// of the first column half of a layer's first column block also sum their
+// dz rows (db).
+constexpr int kTilesW = 4 + 3 * 8 + 2;   // layer 1: 4 x 1, layers 2-4: 4 x 2, layer 5: 1 x 2
+
+__device__ inline void wgrad_item(int item, int& l, int& nb, int& kb) {
+  if (item < 4) {
+    l = 0; nb = item; kb = 0;
+  } else if (item < 28) {
+    l = 1 + (item - 4) / 8; nb = ((item - 4) % 8) / 2; kb = (item - 4) % 2;
+  } else {
+    l = 4; nb = 0; kb = item - 28;
+  }
+}
+
 __global__ void __launch_bounds__(256)
 mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
                  const float* __restrict__ freqs, const float* __restrict__ H,
                  const float* __restrict__ dZ, float* __restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int item = blockIdx.x, c = blockIdx.y;
-  const int l = item < 64 ? item / 16 : 4, band = item < 64 ? item % 16 : 0;
-  const int K = f_k(l);                  // reduction inputs of the layer's weights here
-  const int col0 = 64 * wave;
-  const bool cols = col0 < K;
-  if (!cols && wave != 0) return;        // whole waves; no workgroup barrier below
   const int row = lane & 15, g = lane >> 4;
-  const int n = band * 16 + row;
-  const float* dz = l < 4 ? dZ + ((size_t)l * kWidth + n) * nvp
-                          : dZ + ((size_t)4 * kWidth + n) * nvp;
+  int l, nb, kb;
+  wgrad_item(blockIdx.x, l, nb, kb);
+  const int c = blockIdx.y;
+  const int wn = wave & 1, wk = wave >> 1;
+  const int n0 = nb * 64 + 32 * wn, k0 = kb * 128 + 64 * wk;
+  const int nrows = l < 4 ? kWidth : 16;          // rows of dz_l kept
+  const float* dz = dZ + (size_t)l * kWidth * nvp;  // dz_5 follows dz_4
+  bool rv[2];
+  const float* ap[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    rv[rt] = n0 + 16 * rt < nrows;
+    ap[rt] = dz + (size_t)(rv[rt] ? n0 + 16 * rt + row : 0) * nvp;
+  }
+  const float* hp[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    hp[q] = H + ((size_t)(l > 0 ? l - 1 : 0) * kWidth + k0 + 16 * q + row) * nvp;
   const int v0 = c * chunk_len, v1 = min(nvp, v0 + chunk_len);
-  f32x4 acc[4];
+  f32x4 acc[2][4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dbs = 0.f;
-  for (int vb = v0; vb < v1; vb += 32) {
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[rt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbs[2] = {0.f, 0.f};
+  float ca[2][8], cb[4][8];
+  auto fetch = [&](int vb, float (&A)[2][8], float (&B)[4][8]) {
     const int va = vb + 8 * g;
-    float av[8];
-    load8(dz + va, av);
-    if (wave == 0)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) dbs += av[e];
-    if (!cols) continue;
-    bf16x8 ah, al;
-    split8(av, ah, al);
-    float xs[8][3];
-    if (l == 0)
+    for (int rt = 0; rt < 2; ++rt) {
+      if (rv[rt]) {
+        load8(ap[rt] + va, A[rt]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) A[rt][e] = 0.f;
+      }
+    }
+    if (l == 0) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int v = va + e;
         const bool in = v < nv;
-        xs[e][0] = in ? x[v] : 0.f;
-        xs[e][1] = in ? x[nv + v] : 0.f;
-        xs[e][2] = in ? x[2 * nv + v] : 0.f;
+        const float x0 = in ? x[v] : 0.f, x1 = in ? x[nv + v] : 0.f, x2 = in ? x[2 * nv + v] : 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int k = k0 + 16 * q + row;
+          const float f = fourier_arg(freqs, k & (kFreqs - 1), x0, x1, x2);
+          B[q][e] = k < kFreqs ? sinpif(f) : cospif(f);
+        }
       }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) load8(hp[q] + va, B[q]);
+    }
+  };
+  if (v0 < v1) fetch(v0, ca, cb);
+  for (int vb = v0; vb < v1; vb += 32) {
+    float na[2][8], nb8[4][8];
+    const bool more = vb + 32 < v1;
+    if (more) fetch(vb + 32, na, nb8);
+    bf16x8 ah[2], al[2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      split8(ca[rt], ah[rt], al[rt]);
+      if (wk == 0 && kb == 0)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dbs[rt] += ca[rt][e];
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = col0 + 16 * q + row;
-      float bv[8];
-      if (l == 0) {
-        const int j = k & (kFreqs - 1);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float f = fourier_arg(freqs, j, xs[e][0], xs[e][1], xs[e][2]);
-          bv[e] = k < kFreqs ? sinpif(f) : cospif(f);
-        }
-      } else {
-        load8(H + ((size_t)(l - 1) * kWidth + k) * nvp + va, bv);
-      }
       bf16x8 bh, bl;
-      split8(bv, bh, bl);
-      acc[q] = mfma3(ah, al, bh, bl, acc[q]);
+      split8(cb[q], bh, bl);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) acc[rt][q] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][q]);
+    }
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        ca[0][e] = na[0][e];
+        ca[1][e] = na[1][e];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cb[q][e] = nb8[q][e];
+      }
     }
   }
   float* pc = part + (size_t)c * kParams;
-  if (cols) {
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int k = col0 + 16 * q + row;
+      const int k = k0 + 16 * q + row;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int nn = band * 16 + 4 * g + i;
-        if (nn < n_out(l)) pc[w_off(l) + nn * n_in(l) + k] = acc[q][i];
+        const int n = n0 + 16 * rt + 4 * g + i;
+        if (n < n_out(l)) pc[w_off(l) + n * n_in(l) + k] = acc[rt][q][i];
       }
     }
-  }
-  if (wave == 0) {
-    dbs += __shfl_xor(dbs, 16);
-    dbs += __shfl_xor(dbs, 32);
-    if (g == 0 && n < n_out(l)) pc[b_off(l) + n] = dbs;
+  if (wk == 0 && kb == 0) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      float d = dbs[rt];
+      d += __shfl_xor(d, 16);
+      d += __shfl_xor(d, 32);
+      const int n = n0 + 16 * rt + row;
+      if (g == 0 && n < n_out(l)) pc[b_off(l) + n] = d;
+    }
   }
 }
 
@@ -419,19 +502,20 @@ mlp_reduce_kernel(int chunks, const float* __restrict__ theta, const float* __re
   }
 }
 
-// dtheta = W_1[:, 128:]^T db_1
-__global__ void __launch_bounds__(128)
+// dtheta = W_1[:, 128:]^T db_1 (db_1 summed over the chunks first)
+__global__ void __launch_bounds__(256)
 mlp_dtheta_kernel(int chunks, const float* __restrict__ P, const float* __restrict__ part,
                   float* __restrict__ dtheta) {
+  __shared__ float db[kWidth];
   const int t = threadIdx.x;
-  if (t >= kPose) return;
   float s = 0.f;
-  for (int n = 0; n < kWidth; ++n) {
-    float db = 0.f;
-    for (int c = 0; c < chunks; ++c) db += part[(size_t)c * kParams + b_off(0) + n];
-    s = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + t], db, s);
-  }
-  dtheta[t] = s;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * kParams + b_off(0) + t];
+  db[t] = s;
+  __syncthreads();
+  if (t >= kPose) return;
+  float a = 0.f;
+  for (int n = 0; n < kWidth; ++n) a = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + t], db[n], a);
+  dtheta[t] = a;
 }
 
 }  // namespace
@@ -457,8 +541,7 @@ extern "C" int mlp_forward(void* stream, int nv, const float* x, const float* fr
              at<float>(ws, L.bias));
   // with no vertices the kernel still clears the kept activations of the
   // padding rows, which the adjoint reads
-  RGA_LAUNCH("mlp_fwd", mlp_forward_kernel, dim3(rga::ceil_div(L.nvp / 16, kWaves)),
-               dim3(64 * kWaves), 0, s, nv, L.nvp, x, freqs, hi, lo, at<float>(ws, L.bias),
+  RGA_LAUNCH("mlp_fwd", mlp_forward_kernel, dim3(L.nvp / kRows), dim3(64 * kWaves), 0, s, nv, L.nvp, x, freqs, hi, lo, at<float>(ws, L.bias),
                at<float>(ws, L.h), dx);
   RGA_CHECK_LAUNCH("mlp_forward");
   return RGA_OK;
@@ -479,14 +562,13 @@ extern "C" int mlp_backward(void* stream, int nv, const float* x, const float* f
   float* part = at<float>(ws, L.part);
   // with no vertices every partial sum is zero: the backward and the
   // weight-gradient kernels still run over the (zero) padding rows
-  RGA_LAUNCH("mlp_bwd", mlp_backward_kernel, dim3(rga::ceil_div(L.nvp / 16, kWaves)),
-             dim3(64 * kWaves), 0, s, nv, L.nvp, ddx, hi, lo, at<float>(ws, L.h),
+  RGA_LAUNCH("mlp_bwd", mlp_backward_kernel, dim3(L.nvp / kRows), dim3(64 * kWaves), 0, s, nv, L.nvp, ddx, hi, lo, at<float>(ws, L.h),
              at<float>(ws, L.dz));
-  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_kernel, dim3(65, L.chunks), dim3(64 * kWaves), 0, s, nv,
+  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_kernel, dim3(kTilesW, L.chunks), dim3(64 * kWaves), 0, s, nv,
              L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
   RGA_LAUNCH("mlp_reduce", mlp_reduce_kernel, dim3(rga::ceil_div(kParams, 256)), dim3(256), 0, s,
              L.chunks, theta, part, dparams);
-  RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(128), 0, s, L.chunks, params, part,
+  RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(kWidth), 0, s, L.chunks, params, part,
              dtheta);
   RGA_CHECK_LAUNCH("mlp_backward");
   return RGA_OK;

@@ -233,6 +233,54 @@ def knn_measure(s, d, reps: int = 20):
             "interp_bwd_ms": timed(lambda: rga.knn_interpolate_backward(idx, w, dout, nv))}
 
 
+def mlp_measure(d, reps: int = 20):
+    """The displacement network d(x, theta) (Sec. 3.1 attributes, Sec. 4
+    details) on the workload's canonical vertices and on a mesh of the
+    paper's size (about 40K vertices), outside the timed step: forward (the
+    operand packing included) and adjoint, sums of kernel times from HIP
+    events per call, and the algorithmic rate (2 flops per multiply-add of
+    the layer products; the split form issues three MFMAs per product)
+    against the dense bf16 MFMA peak."""
+    import numpy as np
+    import torch
+    from paper_2407_10707_amd import rga, synth
+    inp = synth.mlp_inputs(0)
+    theta = torch.as_tensor(inp["thetas"][0]).cuda()
+    params = torch.as_tensor(inp["params"]).cuda()
+    freqs = torch.as_tensor(inp["freqs"]).cuda()
+    W = 256
+    per_v_fwd = 2 * (128 * W + 3 * W * W + W * 3)
+    per_v_bwd = 2 * (3 * W + 3 * W * W) + per_v_fwd
+
+    def timed(fn, names):
+        torch.cuda.synchronize()
+        rga.timing_reset()
+        rga.timing_filter(None)
+        rga.timing_enable(True)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        rga.timing_enable(False)
+        return sum(rga.timing_read(nm)[0] for nm in names) / reps
+
+    def one(x):
+        net = rga.Displacement(x, freqs)
+        nv = net.nv
+        ddx = torch.rand((3, nv), device="cuda")
+        net.forward(theta, params)
+        f = timed(lambda: net.forward(theta, params), ("mlp_pack", "mlp_fwd"))
+        b = timed(lambda: net.backward(ddx), ("mlp_bwd", "mlp_wgrad", "mlp_reduce", "mlp_dtheta"))
+        tf, tb = per_v_fwd * nv / f / 1e9, per_v_bwd * nv / b / 1e9
+        return {"vertices": nv, "fwd_ms": round(f, 4), "bwd_ms": round(b, 4),
+                "fwd_tflops": round(tf, 2), "bwd_tflops": round(tb, 2),
+                "fwd_frac_bf16_peak": round(tf / 2500.0, 4),
+                "bwd_frac_bf16_peak": round(tb / 2500.0, 4)}
+
+    verts, _ = synth.body_mesh(48, 46)
+    big = torch.as_tensor(np.ascontiguousarray(verts.T), dtype=torch.float32).cuda()
+    return {"workload_mesh": one(d["verts"]), "paper_size_mesh": one(big)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -405,6 +453,7 @@ def main():
                          "flops_per_launch": flops}}
 
     knn = knn_measure(s, d)
+    mlp = mlp_measure(d)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -435,6 +484,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "knn": knn,
+        "displacement_mlp": mlp,
     }
     if per_kernel:
         out["per_kernel_ms_per_step"] = per_kernel

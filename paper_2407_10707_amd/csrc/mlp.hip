@@ -42,7 +42,7 @@ constexpr int kIn1 = 2 * kFreqs + kPose;  // 200
 constexpr int kLayers = 5;
 constexpr int kParams = RGA_MLP_PARAMS;
 constexpr int kAS = kWidth + 4;           // LDS row stride of the activations (floats)
-constexpr int kMaxChunks = 32;
+constexpr int kMaxChunks = 64;
 constexpr int kWaves = 4;
 
 // parameter layout: W_1 [256][200], b_1, W_2 [256][256], b_2, W_3, b_3, W_4, b_4, W_5 [3][256], b_5
@@ -97,7 +97,7 @@ MlpLayout mlp_layout(int nv) {
   L.bias = take((size_t)kLayers * kWidth * 4);
   L.h = take((size_t)4 * kWidth * V * 4);
   L.dz = take(((size_t)4 * kWidth + 16) * V * 4);
-  L.part = take((size_t)kMaxChunks * kParams * 4);
+  L.part = take((size_t)L.chunks * kParams * 4);
   L.total = o;
   return L;
 }

@@ -328,6 +328,49 @@ def l1_loss(image, target):
 
 
 # ---------------------------------------------------------------------------
+# Image loss (Sec. 3.3, image-loss equation): L_img = (1 - lambda) L_1 +
+# lambda L_D-SSIM with lambda = 0.2.  Readings (the paper names D-SSIM only):
+# SSIM of Wang et al. with an 11 x 11 Gaussian window of std 1.5, C1 = 0.01^2,
+# C2 = 0.03^2 (values in [0, 1]), each channel filtered separately with zero
+# padding (the window is cut at the border and not renormalised), D-SSIM =
+# 1 - the mean of the SSIM map over all channels and pixels.
+# ---------------------------------------------------------------------------
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window(size: int = 11, sigma: float = 1.5) -> torch.Tensor:
+    t = torch.arange(size, dtype=f64) - (size - 1) / 2.0
+    g = torch.exp(-t * t / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def ssim_map(x, y):
+    """x, y [C, H, W] -> the SSIM of every channel and pixel [C, H, W]."""
+    x, y = t64(x), t64(y)
+    C = x.shape[0]
+    g = ssim_window()
+    w = torch.outer(g, g)[None, None].expand(C, 1, -1, -1)
+    pad = (g.numel() - 1) // 2
+
+    def filt(a):
+        return torch.nn.functional.conv2d(a[None], w, padding=pad, groups=C)[0]
+
+    mx, my = filt(x), filt(y)
+    sxx = filt(x * x) - mx * mx
+    syy = filt(y * y) - my * my
+    sxy = filt(x * y) - mx * my
+    return ((2 * mx * my + SSIM_C1) * (2 * sxy + SSIM_C2)) / \
+        ((mx * mx + my * my + SSIM_C1) * (sxx + syy + SSIM_C2))
+
+
+def image_loss(x, y, lam: float = 0.2):
+    """(1 - lam) mean |x - y| + lam (1 - mean SSIM(x, y))."""
+    x, y = t64(x), t64(y)
+    return (1.0 - lam) * (x - y).abs().mean() + lam * (1.0 - ssim_map(x, y).mean())
+
+
+# ---------------------------------------------------------------------------
 # Sec. 3.1, interpolation equation: a Gaussian's attribute is the average of
 # its K_g nearest canonical vertices' attributes weighted by
 # u_j = 1 / ||x_g - x_j||.  The neighbour set comes from the FP32 mirror

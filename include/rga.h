@@ -263,6 +263,24 @@ int knn_interpolate_backward(void* stream, int n, int k, const int32_t* idx, con
                              int C, int nr, const float* dout, float* dattr);
 
 /* ------------------------------------------------------------------------
+ * Image loss of the training section (Sec. 3.3, image-loss equation):
+ * L = (1 - lambda) L_1 + lambda L_D-SSIM (the paper sets lambda = 0.2).
+ * Readings: L_1 = mean |image - target| over C H W; L_D-SSIM = 1 - the mean
+ * SSIM over C H W, SSIM of Wang et al. with an 11 x 11 Gaussian window of
+ * std 1.5, C1 = 0.01^2, C2 = 0.03^2, every channel filtered on its own with
+ * zero padding (the window is cut at the border, not renormalised).
+ * image, target [C][H][W] device float; loss device float[1]; dimage
+ * [C][H][W] = dL/dimage (written; may be NULL to skip the adjoint; the
+ * sign of 0 is 0).  ws: image_loss_workspace(C, H, W) bytes of device memory
+ * owned by the caller (the adjoint's per-pixel terms and per-tile sums).
+ * Errors: RGA_EINVAL (sizes outside 1..65535 channels, 1..2^20 pixels per
+ * side, lambda outside [0, 1], null pointer), RGA_ECAPACITY (ws too small);
+ * nothing is launched then.                                                */
+size_t image_loss_workspace(int C, int H, int W);
+int image_loss(void* stream, int C, int H, int W, const float* image, const float* target,
+               float lambda, float* loss, float* dimage, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
  * Pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1, attribute
  * paragraph: an MLP of the canonical position and the pose; Sec. 4,
  * implementation details: four layers of width 256 with ReLU and random

@@ -57,6 +57,8 @@ _SIGS = {
     "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ, _VP, _SZ]),
     "knn_interpolate": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
+    "image_loss_workspace": (_SZ, [_I, _I, _I]),
+    "image_loss": (_I, [_VP, _I, _I, _I, _VP, _VP, C.c_float, _VP, _VP, _VP, _SZ]),
     "mlp_workspace": (_SZ, [_I]),
     "mlp_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "mlp_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
@@ -386,6 +388,22 @@ def knn_interpolate_backward(idx, w, dout, nr: int):
     _check(lib().knn_interpolate_backward(_stream(), n, k, _p(idx), _p(w), C_, int(nr), _p(dout),
                                           _p(dattr)), "knn_interpolate_backward")
     return dattr
+
+
+def image_loss(image, target, lam: float = 0.2, want_grad: bool = True):
+    """(loss [1], dimage [C, H, W] or None) of (1 - lam) L1 + lam D-SSIM."""
+    image = _f32(image, "image")
+    target = _f32(target, "target")
+    if image.dim() != 3 or tuple(target.shape) != tuple(image.shape):
+        raise RgaError("image and target must be [C, H, W] of one shape")
+    C_, H, W = (int(v) for v in image.shape)
+    nb = int(lib().image_loss_workspace(C_, H, W))
+    ws = torch.empty(nb, dtype=torch.uint8, device=image.device)
+    loss = torch.empty(1, dtype=torch.float32, device=image.device)
+    dimage = torch.empty_like(image) if want_grad else None
+    _check(lib().image_loss(_stream(), C_, H, W, _p(image), _p(target), float(lam), _p(loss),
+                            _p(dimage) if want_grad else None, _p(ws), nb), "image_loss")
+    return loss, dimage
 
 
 MLP_PARAMS = 249603

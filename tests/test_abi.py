@@ -48,6 +48,8 @@ def test_workspace_sizes_are_monotone():
     assert L.l1_loss_workspace(3 * 512 * 512) > 0
     assert L.knn_workspace(6840) > 6840 * 16
     assert 0 < L.mlp_workspace(100) < L.mlp_workspace(10000)
+    assert L.image_loss_workspace(3, 512, 512) >= 3 * 3 * 512 * 512 * 4
+    assert L.image_loss_workspace(0, 512, 512) == 0
     assert L.mlp_workspace(-1) == 0
 
 
@@ -76,6 +78,9 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.knn_build(None, 0, None, None, 0) == -1
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
     assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1
+    assert L.image_loss(None, 3, 0, 8, None, None, 0.2, None, None, None, 0) == -1
+    assert L.image_loss(None, 3, 8, 8, None, None, 1.5, None, None, None, 0) == -1
+    assert "lambda" in rga.last_error()
     assert L.mlp_forward(None, -1, None, None, None, None, None, 0, None) == -1
     assert L.mlp_forward(None, 10, None, None, None, None, None, 0, None) == -1
     assert "null" in rga.last_error()

@@ -281,6 +281,35 @@ def mlp_measure(d, reps: int = 20):
     return {"workload_mesh": one(d["verts"]), "paper_size_mesh": one(big)}
 
 
+def image_loss_measure(s, reps: int = 20):
+    """The image loss of the training section ((1 - lambda) L1 + lambda
+    D-SSIM, lambda = 0.2) with its adjoint at the workload's image size,
+    outside the timed step (the step's loss is L1): kernel times per call
+    and the rate of the algorithmic HBM bytes (forward: image and target
+    read, three derivative maps written; adjoint: the maps, image and
+    target read, the gradient written; 36 B per value) against 8 TB/s."""
+    import numpy as np
+    import torch
+    from paper_2407_10707_amd import rga
+    H, W = int(s["height"]), int(s["width"])
+    rng = np.random.default_rng(3)
+    x = torch.tensor(rng.random((3, H, W)), dtype=torch.float32).cuda()
+    y = torch.tensor(rng.random((3, H, W)), dtype=torch.float32).cuda()
+    rga.image_loss(x, y)
+    torch.cuda.synchronize()
+    rga.timing_reset()
+    rga.timing_filter(None)
+    rga.timing_enable(True)
+    for _ in range(reps):
+        rga.image_loss(x, y)
+    torch.cuda.synchronize()
+    rga.timing_enable(False)
+    ms = sum(rga.timing_read(nm)[0] for nm in ("ssim_fwd", "ssim_final", "ssim_bwd")) / reps
+    gbs = 36.0 * 3 * H * W / (ms * 1e-3) / 1e9
+    return {"image": [3, H, W], "lambda": 0.2, "fwd_bwd_ms": round(ms, 4),
+            "gb_per_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -454,6 +483,7 @@ def main():
 
     knn = knn_measure(s, d)
     mlp = mlp_measure(d)
+    img_loss = image_loss_measure(s)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -485,6 +515,7 @@ def main():
         "cpu_baseline": cpu,
         "knn": knn,
         "displacement_mlp": mlp,
+        "image_loss": img_loss,
     }
     if per_kernel:
         out["per_kernel_ms_per_step"] = per_kernel

@@ -371,6 +371,35 @@ def image_loss(x, y, lam: float = 0.2):
 
 
 # ---------------------------------------------------------------------------
+# Regularisers of the training loss (Sec. 3.3): smoothness of the vertex
+# materials over the K_v nearest vertices (L1 of the differences of a, gamma,
+# p), distance of each Gaussian to its K_g nearest vertices (Euclidean),
+# length of each vertex displacement, and the scale hinge
+# sum max(0, s - s_0) with s_0 = 0.005 over every scale component (s =
+# exp(log-scale)); the total weights them by lambda_smooth = 0.002,
+# lambda_mdist = 0.1, lambda_disp = 0.02, lambda_scale = 10.
+# ---------------------------------------------------------------------------
+REG_LAMBDAS = (0.002, 0.1, 0.02, 10.0)
+REG_S0 = 0.005
+
+
+def regularisers(mat, knn_v, xg, verts, vidx, disp, log_s, s0=REG_S0, lams=REG_LAMBDAS):
+    """mat [5, nv] (albedo rgb, roughness, tint), knn_v [nv, kv], xg [3, n],
+    verts [3, nv], vidx [kg, n], disp [3, nv], log_s [3, n] ->
+    (smooth, mdist, disp, scale, weighted total)."""
+    mat, xg, verts, disp, log_s = t64(mat), t64(xg), t64(verts), t64(disp), t64(log_s)
+    kn = torch.as_tensor(np.asarray(knn_v), dtype=torch.long)
+    vi = torch.as_tensor(np.asarray(vidx), dtype=torch.long)
+    smooth = (mat[:, :, None] - mat[:, kn]).abs().sum()
+    dv = xg[:, None, :] - verts[:, vi]                     # [3, kg, n]
+    mdist = torch.sqrt((dv * dv).sum(dim=0)).sum()
+    dlen = torch.sqrt((disp * disp).sum(dim=0)).sum()
+    scale = torch.clamp(torch.exp(log_s) - s0, min=0.0).sum()
+    total = lams[0] * smooth + lams[1] * mdist + lams[2] * dlen + lams[3] * scale
+    return smooth, mdist, dlen, scale, total
+
+
+# ---------------------------------------------------------------------------
 # Sec. 3.1, interpolation equation: a Gaussian's attribute is the average of
 # its K_g nearest canonical vertices' attributes weighted by
 # u_j = 1 / ||x_g - x_j||.  The neighbour set comes from the FP32 mirror

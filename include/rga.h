@@ -281,6 +281,29 @@ int image_loss(void* stream, int C, int H, int W, const float* image, const floa
                float lambda, float* loss, float* dimage, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
+ * Regularisers of the training loss (Sec. 3.3): L_smooth = sum_i sum_{k in
+ * S_v(i)} |m_i - m_k|_1 over the materials (albedo rgb, roughness, tint),
+ * L_mdist = sum_g sum_{k in S_g(g)} |x_g - x_k|_2, L_disp = sum_i |dx_i|_2,
+ * L_scale = sum_g sum_c max(0, s_gc - s_0) with s = exp(log-scale) (the
+ * paper: s_0 = 0.005, lambdas 0.002, 0.1, 0.02, 10).
+ * mat [5][nv]; knn_v [nv][kv] int32 (the K_v nearest vertices of each
+ * vertex); xg [3][n] canonical Gaussian positions; verts [3][nv]; vidx
+ * [kg][n] int32 (the K_g nearest vertices of each Gaussian); disp [3][nv];
+ * log_s [3][n]; all device memory, indices clamped to 0..nv-1.
+ * terms device float[5]: the four unweighted sums and the weighted total.
+ * dmat [5][nv], dxg [3][n], ddisp [3][nv], dlogs [3][n]: gradients of the
+ * weighted total (written; a zero difference or length gives 0).
+ * ws: regularisers_workspace(nv, n) bytes of device memory.
+ * Errors: RGA_EINVAL (nv < 1, n < 0, kv or kg outside 1..nv, null pointer),
+ * RGA_ECAPACITY (ws too small); nothing is launched then.                 */
+size_t regularisers_workspace(int nv, int n);
+int regularisers(void* stream, int nv, int n, int kv, int kg, const float* mat,
+                 const int32_t* knn_v, const float* xg, const float* verts, const int32_t* vidx,
+                 const float* disp, const float* log_s, float s0, float lam_smooth,
+                 float lam_mdist, float lam_disp, float lam_scale, float* terms, float* dmat,
+                 float* dxg, float* ddisp, float* dlogs, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
  * Pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1, attribute
  * paragraph: an MLP of the canonical position and the pose; Sec. 4,
  * implementation details: four layers of width 256 with ReLU and random

@@ -57,6 +57,9 @@ _SIGS = {
     "knn_query": (_I, [_VP, _I, _VP, _I, _I, _VP, _VP, _VP, _SZ, _VP, _SZ]),
     "knn_interpolate": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
+    "regularisers_workspace": (_SZ, [_I, _I]),
+    "regularisers": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP] +
+                     [C.c_float] * 5 + [_VP] * 6 + [_SZ]),
     "image_loss_workspace": (_SZ, [_I, _I, _I]),
     "image_loss": (_I, [_VP, _I, _I, _I, _VP, _VP, C.c_float, _VP, _VP, _VP, _SZ]),
     "mlp_workspace": (_SZ, [_I]),
@@ -404,6 +407,27 @@ def image_loss(image, target, lam: float = 0.2, want_grad: bool = True):
     _check(lib().image_loss(_stream(), C_, H, W, _p(image), _p(target), float(lam), _p(loss),
                             _p(dimage) if want_grad else None, _p(ws), nb), "image_loss")
     return loss, dimage
+
+
+def regularisers(mat, knn_v, xg, verts, vidx, disp, log_s, s0: float = 0.005,
+                 lams=(0.002, 0.1, 0.02, 10.0)):
+    """(terms [5]: smooth, mdist, disp, scale, weighted total; gradients of
+    the total w.r.t. mat [5, nv], xg [3, n], disp [3, nv], log_s [3, n])."""
+    mat, xg, verts = _f32(mat, "mat"), _f32(xg, "xg"), _f32(verts, "verts")
+    disp, log_s = _f32(disp, "disp"), _f32(log_s, "log_s")
+    knn_v, vidx = _i32(knn_v, "knn_v"), _i32(vidx, "vidx")
+    nv, n = int(mat.shape[1]), int(xg.shape[1])
+    kv, kg = int(knn_v.shape[1]), int(vidx.shape[0])
+    nb = int(lib().regularisers_workspace(nv, n))
+    ws = torch.empty(nb, dtype=torch.uint8, device=mat.device)
+    terms = torch.empty(5, dtype=torch.float32, device=mat.device)
+    dmat, ddisp = torch.empty_like(mat), torch.empty_like(disp)
+    dxg, dlogs = torch.empty_like(xg), torch.empty_like(log_s)
+    _check(lib().regularisers(_stream(), nv, n, kv, kg, _p(mat), _p(knn_v), _p(xg), _p(verts),
+                              _p(vidx), _p(disp), _p(log_s), float(s0), *(float(v) for v in lams),
+                              _p(terms), _p(dmat), _p(dxg), _p(ddisp), _p(dlogs), _p(ws), nb),
+           "regularisers")
+    return terms, dmat, dxg, ddisp, dlogs
 
 
 MLP_PARAMS = 249603

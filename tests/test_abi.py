@@ -78,6 +78,11 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.knn_build(None, 0, None, None, 0) == -1
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
     assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1
+    assert L.regularisers(None, 0, 10, 19, 3, *([None] * 7), 0.005, 0.002, 0.1, 0.02, 10.0,
+                          *([None] * 6), 0) == -1
+    assert L.regularisers(None, 10, 10, 19, 3, *([None] * 7), 0.005, 0.002, 0.1, 0.02, 10.0,
+                          *([None] * 6), 0) == -1
+    assert "kv" in rga.last_error()
     assert L.image_loss(None, 3, 0, 8, None, None, 0.2, None, None, None, 0) == -1
     assert L.image_loss(None, 3, 8, 8, None, None, 1.5, None, None, None, 0) == -1
     assert "lambda" in rga.last_error()

@@ -1,0 +1,56 @@
+"""Regularisers of the training loss (Sec. 3.3) on the GPU through the C
+ABI against the FP64 oracle, on the avatar workload's tables (K_v = 19
+vertex neighbourhoods, K_g = 3 Gaussian neighbourhoods, 100k Gaussians).
+
+Sign and hinge decisions are exact on both sides (the difference of two
+FP32 values has the sign of the exact difference), except a scale within
+1e-6 of s_0, where FP32 exp may decide either way: those Gaussians are left
+out of the scale-gradient comparison.  Tolerances: the sums 2e-6 relative
+(FP32 sums of ~10^6 positive terms in a fixed tree), gradients 2e-6 of the
+largest magnitude of each (FP32 square roots, divisions, exp; float atomics
+only add multiples of lambda_smooth).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref64
+from tests.conftest import scene
+
+pytestmark = pytest.mark.gpu
+
+
+def test_regularisers_on_the_avatar_tables():
+    from paper_2407_10707_amd import rga
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    s = scene(2)
+    nv, n = int(s["nv"]), int(s["n"])
+    rng = np.random.default_rng(17)
+    mat = rng.random((5, nv)).astype(np.float32)
+    disp = (0.01 * rng.standard_normal((3, nv))).astype(np.float32)
+    print(f"[reg] nv={nv} n={n}", flush=True)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    terms, dmat, dxg, ddisp, dlogs = rga.regularisers(
+        dv(mat), dv(s["knn_v"]), dv(s["pos"]), dv(s["verts"]), dv(s["vidx"]), dv(disp),
+        dv(s["log_s"]))
+    torch.cuda.synchronize()
+    names = ["mat", "xg", "disp", "log_s"]
+    arrs = dict(mat=mat, xg=s["pos"], disp=disp, log_s=s["log_s"])
+    ts = {k: torch.tensor(arrs[k].astype(np.float64), requires_grad=True) for k in names}
+    ref = ref64.regularisers(ts["mat"], s["knn_v"], ts["xg"], s["verts"], s["vidx"], ts["disp"],
+                             ts["log_s"])
+    grads = torch.autograd.grad(ref[4], [ts[k] for k in names])
+    got = terms.cpu().numpy().astype(np.float64)
+    for q in range(5):
+        rel = abs(got[q] - float(ref[q])) / abs(float(ref[q]))
+        print(f"[reg]   term {q}: rel err {rel:.3e}", flush=True)
+        assert rel <= 2e-6
+    edge = np.abs(np.exp(s["log_s"].astype(np.float64)) - 0.005) < 1e-6 * 0.005
+    for name, g, r in zip(names, (dmat, dxg, ddisp, dlogs), grads):
+        a, r = g.cpu().numpy().astype(np.float64), r.numpy()
+        if name == "log_s":
+            a, r = a[~edge], r[~edge]
+        err = np.abs(a - r).max() / np.abs(r).max()
+        print(f"[reg]   d{name}: err / max {err:.3e}", flush=True)
+        assert err <= 2e-6

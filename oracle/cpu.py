@@ -125,6 +125,23 @@ def mesh_visibility(verts, faces, view_dirs, res, knn):
     return raw, cnt
 
 
+def mesh_visibility_shadow(verts, faces, view_dirs, res, knn, bias_px):
+    """The shadow-mapping depth test instead of triangle ids (same filters)."""
+    v = _f(verts)
+    f = _i(faces)
+    dirs = _f(view_dirs)
+    knn = _i(knn)
+    nv, kv = knn.shape
+    V = dirs.shape[0]
+    nw = (V + 31) // 32
+    raw = np.zeros((nv, nw), np.uint32)
+    cnt = np.zeros((nv, V), np.uint8)
+    lib().oracle_mesh_visibility_shadow(C.c_int(nv), C.c_int(f.shape[0]), _p(v), _p(f), C.c_int(V),
+                                        _p(dirs), C.c_int(res), _p(knn), C.c_int(kv),
+                                        C.c_float(bias_px), _p(raw), _p(cnt))
+    return raw, cnt
+
+
 def exp_f32(x: float) -> np.float32:
     return np.float32(lib().oracle_exp_f32(C.c_float(x)))
 

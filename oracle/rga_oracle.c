@@ -329,6 +329,44 @@ void oracle_vis_filter(int nv, const uint8_t* raw, const int32_t* knn, int kv,
   }
 }
 
+/* The shadow-mapping alternative the paper discusses (Sec. 3.2, discussion
+ * with shadow mapping): a vertex is seen from a view when its own depth is
+ * at most the depth map's at the raster sample of the pixel it projects
+ * into, plus a bias of bias_px pixel widths (2 rho / res per pixel), or
+ * when that sample holds no triangle.  raw[nv] gets the 0/1 map.           */
+static void shadow_view(int nv, int nf, const float* v, const int32_t* faces, const float* d,
+                        int res, float bias_px, uint64_t* zbuf, uint8_t* raw) {
+  float c[3], rho;
+  oracle_vis_frame(nv, v, c, &rho);
+  oracle_raster_view(nv, nf, v, faces, d, res, 0, zbuf);
+  int32_t* U = (int32_t*)malloc(sizeof(int32_t) * nv);
+  int32_t* W = (int32_t*)malloc(sizeof(int32_t) * nv);
+  float* z = (float*)malloc(sizeof(float) * nv);
+  project_view(nv, v, c, rho, d, res, U, W, z);
+  const float bias = bias_px * (2.f * rho) / (float)res;
+  for (int i = 0; i < nv; ++i) {
+    int px = U[i] >> 8, py = W[i] >> 8;   /* the pixel holding the point */
+    px = px < 0 ? 0 : (px > res - 1 ? res - 1 : px);
+    py = py < 0 ? 0 : (py > res - 1 ? res - 1 : py);
+    const uint64_t key = zbuf[(size_t)py * res + px];
+    if (key == ~(uint64_t)0) {
+      raw[i] = 1;
+    } else {
+      const uint32_t hi = (uint32_t)(key >> 32);
+      float zd;
+      memcpy(&zd, &hi, 4);
+      raw[i] = z[i] <= zd + bias;
+    }
+  }
+  free(U);
+  free(W);
+  free(z);
+}
+
+static void mesh_visibility_impl(int nv, int nf, const float* v, const int32_t* faces, int V,
+                                 const float* dirs, int res, const int32_t* knn, int kv,
+                                 uint32_t* raw_bits, uint8_t* count, int shadow, float bias_px);
+
 /* Full visibility of Sec. 3.2 for V view directions.
  * raw_bits: [nv][ceil(V/32)] words, bit (k & 31) of word k >> 5 is the raw
  *           (unfiltered) visibility of vertex i from view k; may be NULL.
@@ -336,6 +374,19 @@ void oracle_vis_filter(int nv, const uint8_t* raw, const int32_t* knn, int kv,
 void oracle_mesh_visibility(int nv, int nf, const float* v, const int32_t* faces, int V,
                             const float* dirs, int res, const int32_t* knn, int kv,
                             uint32_t* raw_bits, uint8_t* count) {
+  mesh_visibility_impl(nv, nf, v, faces, V, dirs, res, knn, kv, raw_bits, count, 0, 0.f);
+}
+
+/* The same with the raw maps of the shadow-mapping depth test.              */
+void oracle_mesh_visibility_shadow(int nv, int nf, const float* v, const int32_t* faces, int V,
+                                   const float* dirs, int res, const int32_t* knn, int kv,
+                                   float bias_px, uint32_t* raw_bits, uint8_t* count) {
+  mesh_visibility_impl(nv, nf, v, faces, V, dirs, res, knn, kv, raw_bits, count, 1, bias_px);
+}
+
+static void mesh_visibility_impl(int nv, int nf, const float* v, const int32_t* faces, int V,
+                                 const float* dirs, int res, const int32_t* knn, int kv,
+                                 uint32_t* raw_bits, uint8_t* count, int shadow, float bias_px) {
   const int nw = (V + 31) / 32;
   if (raw_bits) memset(raw_bits, 0, sizeof(uint32_t) * (size_t)nv * nw);
 #pragma omp parallel
@@ -347,14 +398,18 @@ void oracle_mesh_visibility(int nv, int nf, const float* v, const int32_t* faces
     uint8_t* cnt = (uint8_t*)malloc(nv);
 #pragma omp for schedule(dynamic, 1)
     for (int k = 0; k < V; ++k) {
-      oracle_raster_view(nv, nf, v, faces, dirs + 3 * k, res, 0, zbuf);
-      memset(raw, 0, nv);
-      for (int p = 0; p < res * res; ++p) {
-        if (zbuf[p] == ~(uint64_t)0) continue;
-        const int f = (int)(uint32_t)(zbuf[p] & 0xffffffffu);
-        raw[faces[3 * f]] = 1;
-        raw[faces[3 * f + 1]] = 1;
-        raw[faces[3 * f + 2]] = 1;
+      if (shadow) {
+        shadow_view(nv, nf, v, faces, dirs + 3 * k, res, bias_px, zbuf, raw);
+      } else {
+        oracle_raster_view(nv, nf, v, faces, dirs + 3 * k, res, 0, zbuf);
+        memset(raw, 0, nv);
+        for (int p = 0; p < res * res; ++p) {
+          if (zbuf[p] == ~(uint64_t)0) continue;
+          const int f = (int)(uint32_t)(zbuf[p] & 0xffffffffu);
+          raw[faces[3 * f]] = 1;
+          raw[faces[3 * f + 1]] = 1;
+          raw[faces[3 * f + 2]] = 1;
+        }
       }
       if (raw_bits) {
         for (int i = 0; i < nv; ++i)

@@ -103,6 +103,18 @@ int mesh_visibility(void* stream, int nv, int nf, const float* verts, const int3
                     int V, const float* view_dirs, int res, const int32_t* knn, int kv,
                     uint32_t* raw_bits, uint8_t* count, void* ws, size_t ws_bytes);
 
+/* The shadow-mapping alternative discussed in Sec. 3.2 (discussion with
+ * shadow mapping): the same raster and filters, but a vertex's raw
+ * visibility from a view is a depth test: its depth is at most the depth
+ * map's at the raster sample of the pixel it projects into plus bias_px
+ * pixel widths (one pixel = 2 rho / res of the view's frame), or that
+ * sample holds no triangle.  bias_px in [0, 64] (RGA_EINVAL otherwise);
+ * the other arguments are those of mesh_visibility.                       */
+int mesh_visibility_shadowmap(void* stream, int nv, int nf, const float* verts,
+                              const int32_t* faces, int V, const float* view_dirs, int res,
+                              const int32_t* knn, int kv, float bias_px, uint32_t* raw_bits,
+                              uint8_t* count, void* ws, size_t ws_bytes);
+
 /* ------------------------------------------------------------------------
  * Sec. 3.1, rendering equation, and App. A (BRDF): per-Gaussian shading
  *   L_o = sum_k L^k A^k R(w_k, w_o, n) v_g[k] max(0, w_k . n),

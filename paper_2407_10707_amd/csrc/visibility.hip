@@ -233,7 +233,7 @@ frame_kernel(int nv, const float* __restrict__ v, float* __restrict__ frame) {
 __global__ void __launch_bounds__(kRasterThreads)
 raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __restrict__ faces,
               const float* __restrict__ dirs, int res, const float* __restrict__ frame,
-              uint32_t* __restrict__ bits_vm /*[V][nwv]*/, int nwv) {
+              uint32_t* __restrict__ bits_vm /*[V][nwv]*/, int nwv, int shadow, float bias_px) {
   extern __shared__ __align__(16) unsigned char smem[];
   unsigned long long* zb = reinterpret_cast<unsigned long long*>(smem);
   uint32_t* mark = reinterpret_cast<uint32_t*>(smem + sizeof(unsigned long long) * res * res);
@@ -264,13 +264,29 @@ raster_kernel(int nv, int nf, const float* __restrict__ verts, const int32_t* __
     raster_tri(zb, res, f, x0, y0, z0, x1, y1, z1, x2, y2, z2);
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < res * res; p += blockDim.x) {
-    const unsigned long long k = zb[p];
-    if (k == ~0ull) continue;
-    const int f = (int)(uint32_t)(k & 0xffffffffull);
-    for (int c = 0; c < 3; ++c) {
-      const int vi = rga::clampi(faces[3 * f + c], 0, nv - 1);
-      atomicOr(&mark[vi >> 5], 1u << (vi & 31));
+  if (shadow) {
+    // shadow-mapping test: the vertex's depth against the depth map's
+    // sample in the pixel it projects into, plus bias_px pixel widths; an
+    // empty sample occludes nothing
+    const float bias = bias_px * (2.f * P.rho) / (float)res;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+      int32_t U, V;
+      float z;
+      project(P, verts, nv, i, U, V, z);
+      const int px = rga::clampi(U >> 8, 0, res - 1), py = rga::clampi(V >> 8, 0, res - 1);
+      const unsigned long long k = zb[py * res + px];
+      if (k == ~0ull || z <= __uint_as_float((uint32_t)(k >> 32)) + bias)
+        atomicOr(&mark[i >> 5], 1u << (i & 31));
+    }
+  } else {
+    for (int p = threadIdx.x; p < res * res; p += blockDim.x) {
+      const unsigned long long k = zb[p];
+      if (k == ~0ull) continue;
+      const int f = (int)(uint32_t)(k & 0xffffffffull);
+      for (int c = 0; c < 3; ++c) {
+        const int vi = rga::clampi(faces[3 * f + c], 0, nv - 1);
+        atomicOr(&mark[vi >> 5], 1u << (vi & 31));
+      }
     }
   }
   __syncthreads();
@@ -424,10 +440,12 @@ extern "C" size_t mesh_visibility_workspace(int nv, int V) {
   return vis_layout(nv, V).total;
 }
 
-extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
-                               const int32_t* faces, int V, const float* view_dirs, int res,
-                               const int32_t* knn, int kv, uint32_t* raw_bits, uint8_t* count,
-                               void* ws, size_t ws_bytes) {
+namespace {
+
+int visibility_impl(void* stream, int nv, int nf, const float* verts, const int32_t* faces, int V,
+                    const float* view_dirs, int res, const int32_t* knn, int kv,
+                    uint32_t* raw_bits, uint8_t* count, void* ws, size_t ws_bytes, int shadow,
+                    float bias_px) {
   if (nv < 1 || nf < 0 || V < 1) return rga::fail(RGA_EINVAL, "mesh_visibility: nv >= 1, nf >= 0, V >= 1");
   if (res < 1 || res > kMaxRes)
     return rga::fail(RGA_EUNSUPPORTED, "mesh_visibility: res must be in 1..%d", kMaxRes);
@@ -458,7 +476,7 @@ extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
   }
   RGA_LAUNCH("vis_frame", frame_kernel, dim3(1), dim3(1024), 0, s, nv, verts, frame);
   RGA_LAUNCH("vis_raster", raster_kernel, dim3(V), dim3(kRasterThreads), lds, s, nv, nf, verts,
-             faces, view_dirs, res, frame, vm, L.nwv);
+             faces, view_dirs, res, frame, vm, L.nwv, shadow, bias_px);
   const int64_t tw = (int64_t)L.nwv * L.nwV;
   RGA_LAUNCH("vis_transpose", transpose_kernel, dim3(rga::ceil_div(tw * 32, 256)), dim3(256), 0, s, nv,
              V, L.nwv, L.nwV, vm, raw);
@@ -471,4 +489,25 @@ extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
              L.nwV, knn, kv, m2, count);
   RGA_CHECK_LAUNCH("mesh_visibility");
   return RGA_OK;
+}
+
+}  // namespace
+
+extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
+                               const int32_t* faces, int V, const float* view_dirs, int res,
+                               const int32_t* knn, int kv, uint32_t* raw_bits, uint8_t* count,
+                               void* ws, size_t ws_bytes) {
+  return visibility_impl(stream, nv, nf, verts, faces, V, view_dirs, res, knn, kv, raw_bits, count,
+                         ws, ws_bytes, 0, 0.f);
+}
+
+extern "C" int mesh_visibility_shadowmap(void* stream, int nv, int nf, const float* verts,
+                                         const int32_t* faces, int V, const float* view_dirs,
+                                         int res, const int32_t* knn, int kv, float bias_px,
+                                         uint32_t* raw_bits, uint8_t* count, void* ws,
+                                         size_t ws_bytes) {
+  if (!(bias_px >= 0.f && bias_px <= 64.f))
+    return rga::fail(RGA_EINVAL, "mesh_visibility_shadowmap: bias_px in [0, 64]");
+  return visibility_impl(stream, nv, nf, verts, faces, V, view_dirs, res, knn, kv, raw_bits, count,
+                         ws, ws_bytes, 1, bias_px);
 }

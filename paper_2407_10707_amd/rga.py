@@ -36,6 +36,8 @@ _SIGS = {
     "lbs_skin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "mesh_visibility_workspace": (_SZ, [_I, _I]),
     "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
+    "mesh_visibility_shadowmap": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, C.c_float,
+                                       _VP, _VP, _VP, _SZ]),
     "shade_gaussians": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _I,
                              _I, _VP, _VP, _I, _VP, _VP]),
     "shade_gaussians_workspace": (_SZ, [_I, _I, _I]),
@@ -186,7 +188,10 @@ def lbs_skin_backward(skin, jidx, jw, dx_out, dn_out=None):
 
 
 # ----------------------------------------------------------------------------- visibility
-def mesh_visibility(verts, faces, view_dirs, res: int, knn, want_raw: bool = False, ws=None):
+def mesh_visibility(verts, faces, view_dirs, res: int, knn, want_raw: bool = False, ws=None,
+                    shadow_bias_px: Optional[float] = None):
+    """(count [nv, V] uint8, raw bits or None).  With shadow_bias_px set, the
+    raw maps come from the shadow-mapping depth test with that bias."""
     nv = verts.shape[1]
     nf = faces.shape[0]
     V = view_dirs.shape[0]
@@ -200,9 +205,15 @@ def mesh_visibility(verts, faces, view_dirs, res: int, knn, want_raw: bool = Fal
         ws = torch.empty(need, dtype=torch.uint8, device=verts.device)
     count = torch.empty((nv, V), dtype=torch.uint8, device=verts.device)
     raw = torch.empty((nv, (V + 31) // 32), dtype=torch.int32, device=verts.device) if want_raw else None
-    _check(lib().mesh_visibility(_stream(), nv, nf, _p(verts), _p(faces), V, _p(view_dirs), res,
-                                 _p(knn), kv, _p(raw), _p(count), _p(ws), ws.numel()),
-           "mesh_visibility")
+    if shadow_bias_px is None:
+        _check(lib().mesh_visibility(_stream(), nv, nf, _p(verts), _p(faces), V, _p(view_dirs),
+                                     res, _p(knn), kv, _p(raw), _p(count), _p(ws), ws.numel()),
+               "mesh_visibility")
+    else:
+        _check(lib().mesh_visibility_shadowmap(_stream(), nv, nf, _p(verts), _p(faces), V,
+                                               _p(view_dirs), res, _p(knn), kv,
+                                               float(shadow_bias_px), _p(raw), _p(count), _p(ws),
+                                               ws.numel()), "mesh_visibility_shadowmap")
     return count, raw
 
 

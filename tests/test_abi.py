@@ -83,6 +83,9 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.regularisers(None, 10, 10, 19, 3, *([None] * 7), 0.005, 0.002, 0.1, 0.02, 10.0,
                           *([None] * 6), 0) == -1
     assert "kv" in rga.last_error()
+    assert L.mesh_visibility_shadowmap(None, 10, 10, None, None, 8, None, 64, None, 19, -1.0,
+                                       None, None, None, 0) == -1
+    assert "bias_px" in rga.last_error()
     assert L.image_loss(None, 3, 0, 8, None, None, 0.2, None, None, None, 0) == -1
     assert L.image_loss(None, 3, 8, 8, None, None, 1.5, None, None, None, 0) == -1
     assert "lambda" in rga.last_error()

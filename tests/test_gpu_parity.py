@@ -110,6 +110,21 @@ def test_visibility_bit_exact_avatar_scale():
     assert np.array_equal(host(count), ecnt)
 
 
+@pytest.mark.parametrize("case", [("cfg1", 0.0), ("cfg1", 1.5), ("avatar", 2.0)])
+def test_shadow_map_visibility_bit_exact(case):
+    """The shadow-mapping variant: raw depth-test bits and filtered counts."""
+    name, bias = case
+    print(f"[vis-shadow] {name} bias={bias}", flush=True)
+    s = scene(2, n_gauss=1000) if name == "avatar" else _scenes()[name]()
+    vx, _, _ = cpu.lbs_f32(s["skin"], s["mesh_jidx"], s["mesh_jw"], s["verts"])
+    count, raw = rga.mesh_visibility(dev(vx), dev(s["faces"]), dev(s["view_dirs"]), s["vis_res"],
+                                     dev(s["knn_v"]), want_raw=True, shadow_bias_px=bias)
+    eraw, ecnt = cpu.mesh_visibility_shadow(vx, s["faces"], s["view_dirs"], s["vis_res"],
+                                            s["knn_v"], bias)
+    assert np.array_equal(host(raw).view(np.uint32), eraw)
+    assert np.array_equal(host(count), ecnt)
+
+
 # ------------------------------------------------------------------ shading
 @pytest.mark.parametrize("name", ["cfg1", "micro_odd"])
 def test_shading_matches_fp64(name):

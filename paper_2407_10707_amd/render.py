@@ -82,6 +82,25 @@ class Renderer:
         ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count)
         return image, T, ctx
 
+    # ------------------------------------------------------------------ editing maps
+    def render_map(self, p: Dict[str, torch.Tensor], count: torch.Tensor, mode: str = "albedo"):
+        """The albedo or normal map of the appearance-editing paradigm
+        (Sec. 3.4): the same splatting with each Gaussian's colour set to
+        its albedo, or to its posed normal (the skinned normal's components,
+        as LBS returns them).  The back-face rule of the shading decides
+        which Gaussians exist, as in the shaded frame."""
+        if mode not in ("albedo", "normal"):
+            raise ValueError("mode must be 'albedo' or 'normal'")
+        d, s = self.d, self.s
+        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"])
+        _, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
+                                       d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
+                                       s["wv"], p["env"], self.cam_pos, self.precision)
+        color = p["albedo"] if mode == "albedo" else no
+        image, _ = rga.splat_forward(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], color,
+                                     front, self.ws)
+        return image
+
     # ------------------------------------------------------------------ backward
     def backward(self, p: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor):
         d, s = self.d, self.s

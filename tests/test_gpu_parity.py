@@ -238,6 +238,26 @@ def test_splat_forward_parity(name):
     print(f"  D={D} exempt={int((~ok).sum())}/{ok.size}", flush=True)
 
 
+@pytest.mark.parametrize("mode", ["albedo", "normal"])
+def test_editing_maps(mode):
+    """Albedo and normal maps (Sec. 3.4): the splatting of the albedo or of
+    the skinned normal, against the FP32 mirror with the same colours."""
+    print(f"[map] {mode}", flush=True)
+    from paper_2407_10707_amd import render
+    s = _scenes()["cfg1"]()
+    R = render.Renderer(s, render.upload(s), capacity=64 * s["n"] + 1024)
+    p = {k: R.d[k] for k in ("pos", "nrm", "quat", "log_s", "opac", "albedo", "rough", "tint",
+                             "env")}
+    count = R.visibility()
+    img = host(R.render_map(p, count, mode))
+    xo, no, _ = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    col = s["albedo"] if mode == "albedo" else no
+    ref = helpers.oracle_frame_f32(s, np.ascontiguousarray(col, dtype=np.float32))
+    ok = ref["margin"] > 1e-4
+    tol = 1e-5 * np.abs(ref["img"]) + 1e-6
+    assert not ((np.abs(img - ref["img"]) > tol) & ok[None]).any()
+
+
 def test_splat_deep_tiles_parity():
     """Thousands of faint splats over a few tiles: lists span many 256-entry
     chunks and most pixels stop in a later chunk with an incoming

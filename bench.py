@@ -234,7 +234,7 @@ def knn_measure(s, d, reps: int = 20):
 
 
 def mlp_measure(d, reps: int = 20):
-    """The displacement network d(x, theta) (Sec. 3.1 attributes, Sec. 4
+    """The displacement network d(x, theta) (Sec. 3.1 attributes, Sec. 3.5
     details) on the workload's canonical vertices and on a mesh of the
     paper's size (about 40K vertices), outside the timed step: forward (the
     operand packing included) and adjoint, sums of kernel times from HIP

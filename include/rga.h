@@ -317,7 +317,7 @@ int regularisers(void* stream, int nv, int n, int kv, int kg, const float* mat,
 
 /* ------------------------------------------------------------------------
  * Pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1, attribute
- * paragraph: an MLP of the canonical position and the pose; Sec. 4,
+ * paragraph: an MLP of the canonical position and the pose; Sec. 3.5,
  * implementation details: four layers of width 256 with ReLU and random
  * Fourier features of the coordinates).  Readings: gamma(x) =
  * [sin(2 pi B x), cos(2 pi B x)] with B [RGA_MLP_FREQS][3]; the input of

@@ -432,7 +432,7 @@ def interpolate(idx, w, attr):
 
 
 # ---------------------------------------------------------------------------
-# Sec. 3.1 (attributes) and Sec. 4 (implementation details): the pose-
+# Sec. 3.1 (attributes) and Sec. 3.5 (implementation details): the pose-
 # dependent vertex displacement dx = d(x, theta), an MLP of four hidden
 # layers of width 256 with ReLU, whose coordinate input goes through random
 # Fourier features.  Readings (the paper gives neither the encoding's size

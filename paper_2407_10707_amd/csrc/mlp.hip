@@ -1,5 +1,5 @@
 // The pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1,
-// attribute paragraph; Sec. 4, implementation details): four hidden layers
+// attribute paragraph; Sec. 3.5, implementation details): four hidden layers
 // of width 256 with ReLU and a linear output of 3, the coordinates encoded by
 // random Fourier features gamma(x) = [sin(2 pi B x), cos(2 pi B x)] (B is
 // 64 x 3) and the pose theta (72) appended to every vertex's input.

@@ -7,7 +7,7 @@ map, visibility view directions and a camera.  It holds none of the method's
 arithmetic (no skinning, no shading, no splatting); both the HIP path and the
 CPU oracle consume what it returns.
 
-The shapes follow the paper's workloads (Sec. 4 "Implementation Details": about
+The shapes follow the paper's workloads (Sec. 3.5 "Implementation Details": about
 100K Gaussians, K_g = 3, K_v = 19; Sec. 3.1: a 16x32 light-probe map of 512
 area lights; the proxy mesh of Sec. 3.1).  Captured avatars are not available,
 so every array is synthetic and a pure function of (config id, stream seed).

@@ -1,4 +1,4 @@
-"""The displacement network (Sec. 3.1 attributes, Sec. 4 details) on the GPU
+"""The displacement network (Sec. 3.1 attributes, Sec. 3.5 details) on the GPU
 through the C ABI against the FP64 oracle.
 
 Tolerances, from the arithmetic: every product runs on bf16 MFMA with each

@@ -1,5 +1,5 @@
 """Pins of the displacement network of the FP64 oracle (Sec. 3.1 attributes,
-Sec. 4 implementation details): brute force on tiny layers, finite
+Sec. 3.5 implementation details): brute force on tiny layers, finite
 differences of its gradients, identities of the Fourier features and of a
 pose that enters as a bias."""
 

@@ -67,3 +67,17 @@ def test_oracle_brdf_uses_printed_smith_k():
         g1 = lambda x: x / (x * (1 - k) + k)
         want = D * F * g1(ci) * g1(co) / (4 * ci * co)
         assert np.allclose(R.numpy(), want, rtol=1e-13, atol=0)
+
+
+def test_training_loss_and_network_constants():
+    """The loss weights, the scale threshold and the network's shape of the
+    training section and the implementation details."""
+    import inspect
+    c = _constants()
+    assert ref64.REG_LAMBDAS == (c["lambda_smooth"], c["lambda_mdist"], c["lambda_disp"],
+                                 c["lambda_scale"])
+    assert ref64.REG_S0 == c["scale_s0"]
+    assert inspect.signature(ref64.image_loss).parameters["lam"].default == c["lambda_img"]
+    hidden = [s for s in ref64.MLP_SHAPES if s[0] == ref64.MLP_WIDTH]
+    assert len(hidden) == c["mlp_layers"] and ref64.MLP_WIDTH == c["mlp_width"]
+    assert ref64.MLP_POSE == c["pose_dim"] and ref64.MLP_SHAPES[0][1] == 2 * ref64.MLP_FREQS + 72

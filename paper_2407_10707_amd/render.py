@@ -50,6 +50,8 @@ class Renderer:
         self.vis_ws = None
         self.shade_ws = None
         self.l1_ws = None
+        self.img_ws = None
+        self.image_loss = False
 
     # ------------------------------------------------------------------ per pose
     def visibility(self):
@@ -117,6 +119,13 @@ class Renderer:
                     color=g["dcolor"])
 
     def loss(self, image: torch.Tensor, target: torch.Tensor):
+        """L1 (the hot path's loss), or with image_loss set the image loss
+        of the training section, (1 - 0.2) L1 + 0.2 D-SSIM."""
+        if getattr(self, "image_loss", False):
+            if self.img_ws is None:
+                n = int(rga.lib().image_loss_workspace(*(int(v) for v in image.shape)))
+                self.img_ws = torch.empty(n, dtype=torch.uint8, device=image.device)
+            return rga.image_loss(image, target, 0.2, ws=self.img_ws)
         return rga.l1_loss(image, target, ws=self.l1_ws)
 
     def train_step(self, p, count, target):

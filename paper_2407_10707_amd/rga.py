@@ -404,7 +404,7 @@ def knn_interpolate_backward(idx, w, dout, nr: int):
     return dattr
 
 
-def image_loss(image, target, lam: float = 0.2, want_grad: bool = True):
+def image_loss(image, target, lam: float = 0.2, want_grad: bool = True, ws=None):
     """(loss [1], dimage [C, H, W] or None) of (1 - lam) L1 + lam D-SSIM."""
     image = _f32(image, "image")
     target = _f32(target, "target")
@@ -412,7 +412,9 @@ def image_loss(image, target, lam: float = 0.2, want_grad: bool = True):
         raise RgaError("image and target must be [C, H, W] of one shape")
     C_, H, W = (int(v) for v in image.shape)
     nb = int(lib().image_loss_workspace(C_, H, W))
-    ws = torch.empty(nb, dtype=torch.uint8, device=image.device)
+    if ws is None or ws.numel() < nb:
+        ws = torch.empty(nb, dtype=torch.uint8, device=image.device)
+    nb = ws.numel()
     loss = torch.empty(1, dtype=torch.float32, device=image.device)
     dimage = torch.empty_like(image) if want_grad else None
     _check(lib().image_loss(_stream(), C_, H, W, _p(image), _p(target), float(lam), _p(loss),

@@ -5,6 +5,7 @@ force -- nothing here compares the oracle with itself."""
 import math
 
 import numpy as np
+import torch
 import pytest
 
 from oracle import cpu, ref64
@@ -256,3 +257,46 @@ def test_shadow_map_variant_sees_the_lit_hemisphere_and_hides_occluded_vertices(
     covered = (np.abs(far[:, 0]) < 1.2) & (np.abs(far[:, 1]) < 1.2)
     assert vis[25:].all()
     assert not vis[:25][covered].any() and vis[:25][~covered].all()
+
+
+def test_skinning_matrix_gradient_single_joint_closed_form_and_fd():
+    """dL/dS_j of forward LBS (the pose gradient of Sec. 3.3's pose
+    optimisation): for one joint with weight 1 it is sum_i dx'_i [x_i, 1]^T +
+    dn'_i [n_i, 0]^T; with four blended joints it matches finite
+    differences of the FP64 oracle."""
+    rng = np.random.default_rng(8)
+    n = 7
+    x = rng.normal(size=(3, n))
+    nrm = rng.normal(size=(3, n))
+    gx, gn = rng.normal(size=(3, n)), rng.normal(size=(3, n))
+    xt, nt = torch.tensor(x), torch.tensor(nrm)
+    S = torch.tensor(rng.normal(size=(2, 12)), requires_grad=True)
+    jidx = np.zeros((4, n), np.int32)
+    jw = np.zeros((4, n))
+    jw[0] = 1.0
+    xp, npr, _ = ref64.lbs(S, jidx, jw, xt, nt)
+    loss = (xp * torch.tensor(gx)).sum() + (npr * torch.tensor(gn)).sum()
+    (g,) = torch.autograd.grad(loss, (S,))
+    want = np.zeros((3, 4))
+    want[:, :3] = gx @ x.T + gn @ nrm.T
+    want[:, 3] = gx.sum(axis=1)
+    assert np.allclose(g[0].numpy().reshape(3, 4), want, atol=1e-12)
+    assert np.all(g[1].numpy() == 0)
+    # blended joints: finite differences
+    jidx = rng.integers(0, 2, (4, n)).astype(np.int32)
+    jw = rng.dirichlet(np.ones(4), n).T
+    S0 = rng.normal(size=(2, 12))
+
+    def L(Sv):
+        xp, npr, _ = ref64.lbs(torch.tensor(Sv), jidx, jw, xt, nt)
+        return float((xp * torch.tensor(gx)).sum() + (npr * torch.tensor(gn)).sum())
+
+    St = torch.tensor(S0, requires_grad=True)
+    xp, npr, _ = ref64.lbs(St, jidx, jw, xt, nt)
+    (g,) = torch.autograd.grad((xp * torch.tensor(gx)).sum() + (npr * torch.tensor(gn)).sum(),
+                               (St,))
+    for j, c in [(0, 0), (1, 5), (0, 11), (1, 3)]:
+        e = np.zeros_like(S0)
+        e[j, c] = 1e-6
+        fd = (L(S0 + e) - L(S0 - e)) / 2e-6
+        assert abs(fd - float(g[j, c])) < 1e-6 * max(1.0, abs(fd))

@@ -78,6 +78,18 @@ int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
                       const int32_t* jidx, const float* jw, const float* dx_out,
                       const float* dn_out, float* dx, float* dn);
 
+/* The pose gradient of lbs_skin (the skinning matrices are what pose
+ * optimisation, Sec. 3.3, differentiates): dskin [n_joints][3][4] =
+ * sum_i w_ij (dx_out_i (x_i, 1)^T + dn_out_i (nrm_i, 0)^T), summed over the
+ * slots of each Gaussian that name joint j.  nrm and dn_out are both set or
+ * both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints) bytes of device
+ * memory (per-chunk sums, added in a fixed order).  Overwrites dskin.
+ * Errors: RGA_EINVAL (sizes, null pointers), RGA_ECAPACITY (ws too small). */
+size_t lbs_skin_pose_grad_workspace(int n, int n_joints);
+int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx, const float* jw,
+                       const float* x, const float* nrm, const float* dx_out,
+                       const float* dn_out, float* dskin, void* ws, size_t ws_bytes);
+
 /* ------------------------------------------------------------------------
  * Sec. 3.2 (visibility computation): orthographic rasterization of the posed
  * mesh along each of V view directions into a res x res triangle-index image;

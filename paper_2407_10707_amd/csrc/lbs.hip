@@ -92,6 +92,105 @@ lbs_bwd_kernel(int n, int J, const float* __restrict__ skin, const int32_t* __re
 
 }  // namespace
 
+namespace {
+
+// Pose gradient: dS_j[r][c] = sum_i w_ij (dx'_i[r] (x_i, 1)[c] + dn'_i[r] (n_i, 0)[c]),
+// w_ij the summed weights of joint j in Gaussian i's slots.  Workgroups over
+// (chunk of Gaussians, joint); per-workgroup sums, then a fixed-order sum
+// over the chunks (no atomics: every joint is shared by many Gaussians).
+constexpr int kPoseChunk = 2048;
+
+__global__ void __launch_bounds__(kBlock)
+lbs_pose_grad_kernel(int n, const int32_t* __restrict__ jidx, const float* __restrict__ jw,
+                     const float* __restrict__ x, const float* __restrict__ nrm,
+                     const float* __restrict__ dxo, const float* __restrict__ dno,
+                     float* __restrict__ part) {
+  __shared__ float red[12][kBlock];
+  const int j = blockIdx.y, c = blockIdx.x;
+  const int i0 = c * kPoseChunk, i1 = min(n, i0 + kPoseChunk);
+  float acc[12];
+#pragma unroll
+  for (int q = 0; q < 12; ++q) acc[q] = 0.f;
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    float w = 0.f;
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl)
+      if (jidx[(size_t)sl * n + i] == j) w += jw[(size_t)sl * n + i];
+    if (w == 0.f) continue;
+    const float xv[3] = {x[i], x[n + i], x[2 * n + i]};
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float g = w * dxo[(size_t)r * n + i];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[4 * r + q] = fmaf(g, xv[q], acc[4 * r + q]);
+      acc[4 * r + 3] += g;
+    }
+    if (dno) {
+      const float nv[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float g = w * dno[(size_t)r * n + i];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[4 * r + q] = fmaf(g, nv[q], acc[4 * r + q]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 12; ++q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+#pragma unroll
+      for (int q = 0; q < 12; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 12)
+    part[((size_t)c * gridDim.y + j) * 12 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(kBlock)
+lbs_pose_grad_final(int n_joints, int chunks, const float* __restrict__ part,
+                    float* __restrict__ dskin) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * n_joints) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n_joints * 12 + t];
+  dskin[t] = s;
+}
+
+int pose_chunks(int n) { return (int)rga::ceil_div(n > 0 ? n : 1, kPoseChunk); }
+
+}  // namespace
+
+extern "C" size_t lbs_skin_pose_grad_workspace(int n, int n_joints) {
+  if (n < 0 || n_joints < 1 || n_joints > kMaxJoints) return 0;
+  return (size_t)pose_chunks(n) * n_joints * 12 * 4;
+}
+
+extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx,
+                                  const float* jw, const float* x, const float* nrm,
+                                  const float* dx_out, const float* dn_out, float* dskin,
+                                  void* ws, size_t ws_bytes) {
+  if (n < 0) return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n < 0");
+  if (n_joints < 1 || n_joints > kMaxJoints)
+    return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n_joints must be in 1..%d", kMaxJoints);
+  if (!dskin || !ws || (n > 0 && (!jidx || !jw || !x || !dx_out)))
+    return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: null pointer");
+  if ((dn_out == nullptr) != (nrm == nullptr))
+    return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: nrm and dn_out must both be set or both NULL");
+  if (ws_bytes < lbs_skin_pose_grad_workspace(n, n_joints))
+    return rga::fail(RGA_ECAPACITY, "lbs_skin_pose_grad: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int chunks = pose_chunks(n);
+  float* part = static_cast<float*>(ws);
+  RGA_LAUNCH("lbs_pose_grad", lbs_pose_grad_kernel, dim3(chunks, n_joints), dim3(kBlock), 0, s, n,
+             jidx, jw, x, nrm, dx_out, dn_out, part);
+  RGA_LAUNCH("lbs_pose_grad_final", lbs_pose_grad_final, dim3(rga::ceil_div(12 * n_joints, kBlock)),
+             dim3(kBlock), 0, s, n_joints, chunks, part, dskin);
+  RGA_CHECK_LAUNCH("lbs_skin_pose_grad");
+  return RGA_OK;
+}
+
 extern "C" int lbs_skin(void* stream, int n, int n_joints, const float* skin, const int32_t* jidx,
                         const float* jw, const float* x, const float* nrm, float* x_out,
                         float* n_out, float* A_out) {

@@ -34,6 +34,8 @@ _SIGS = {
     "rga_abi_version": (_I, []),
     "lbs_skin": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbs_skin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbs_skin_pose_grad_workspace": (_SZ, [_I, _I]),
+    "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_workspace": (_SZ, [_I, _I]),
     "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_shadowmap": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, C.c_float,
@@ -174,6 +176,20 @@ def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True):
     _check(lib().lbs_skin(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(x), _p(nrm), _p(xo),
                           _p(no), _p(Ao)), "lbs_skin")
     return xo, no, Ao
+
+
+def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None):
+    """dskin [n_joints, 12]: the gradient w.r.t. the skinning matrices."""
+    n = int(x.shape[1])
+    _f32(x, "x", (3, n))
+    _f32(dx_out, "dx_out", (3, n))
+    dskin = torch.empty((n_joints, 12), dtype=torch.float32, device=x.device)
+    nb = int(lib().lbs_skin_pose_grad_workspace(n, n_joints))
+    ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    _check(lib().lbs_skin_pose_grad(_stream(), n, n_joints, _p(jidx), _p(jw), _p(x), _p(nrm),
+                                    _p(dx_out), _p(dn_out), _p(dskin), _p(ws), nb),
+           "lbs_skin_pose_grad")
+    return dskin
 
 
 def lbs_skin_backward(skin, jidx, jw, dx_out, dn_out=None):

@@ -74,6 +74,34 @@ def test_lbs_backward_is_A_transpose():
     assert np.allclose(host(dn), np.einsum("nba,bn->an", A, gn), atol=2e-6)
 
 
+@pytest.mark.parametrize("which", ["cfg1", "avatar"])
+def test_lbs_pose_gradient(which):
+    """dL/d skinning matrices against the FP64 oracle's autograd; the bound
+    is 1e-5 of the sum of the absolute terms of each entry (FP32 products
+    and per-chunk sums of up to 100k terms)."""
+    print(f"[lbs-pose] {which}", flush=True)
+    s = scene(1) if which == "cfg1" else scene(2)
+    n, J = s["n"], s["n_joints"]
+    rng = np.random.default_rng(4)
+    gx = rng.normal(size=(3, n)).astype(np.float32)
+    gn = rng.normal(size=(3, n)).astype(np.float32)
+    g = host(rga.lbs_skin_pose_grad(J, dev(s["jidx"]), dev(s["jw"]), dev(s["pos"]), dev(gx),
+                                    dev(s["nrm"]), dev(gn)))
+    S = torch.tensor(s["skin"].astype(np.float64), requires_grad=True)
+    x64 = torch.tensor(s["pos"].astype(np.float64))
+    n64 = torch.tensor(s["nrm"].astype(np.float64))
+    xp, npr, _ = ref64.lbs(S, s["jidx"], s["jw"], x64, n64)
+    (ref,) = torch.autograd.grad((xp * torch.tensor(gx.astype(np.float64))).sum() +
+                                 (npr * torch.tensor(gn.astype(np.float64))).sum(), (S,))
+    Sa = torch.tensor(np.abs(s["skin"]).astype(np.float64), requires_grad=True)
+    xa, na, _ = ref64.lbs(Sa, s["jidx"], s["jw"], x64.abs(), n64.abs())
+    (bound,) = torch.autograd.grad((xa * torch.tensor(np.abs(gx).astype(np.float64))).sum() +
+                                   (na * torch.tensor(np.abs(gn).astype(np.float64))).sum(), (Sa,))
+    err = np.abs(g - ref.numpy())
+    print(f"[lbs-pose]   max err / bound {(err / (bound.numpy() + 1e-30)).max():.3e}", flush=True)
+    assert np.all(err <= 1e-5 * bound.numpy() + 1e-7)
+
+
 def test_lbs_empty_and_errors():
     s = scene(1)
     x = torch.empty((3, 0), device="cuda")

@@ -52,6 +52,48 @@ def lbs(skin, jidx, jw, x, nrm=None):
 
 
 # ---------------------------------------------------------------------------
+# The pose theta (72 = 24 joints x axis-angle, Sec. 3.1 attributes) and the
+# skinning matrices it gives (the quantity pose optimisation of Sec. 3.3
+# differentiates).  Reading: SMPL-style forward kinematics on a skeleton of
+# rest joint positions J and parents (parent index below the child's):
+# R_j = exp([theta_j]x) (Rodrigues), G_j = G_parent R_j,
+# P_j = P_parent + G_parent (J_j - J_parent) (G_root = R_root, P_root = J_root),
+# skin_j = [G_j | P_j - G_j J_j].
+# ---------------------------------------------------------------------------
+def rodrigues(theta):
+    """theta [J, 3] axis-angle -> R [J, 3, 3]."""
+    th = t64(theta)
+    t2 = (th * th).sum(dim=1)
+    small = t2 < 1e-12                  # the series (no square root near 0)
+    ts = torch.sqrt(torch.where(small, torch.ones_like(t2), t2))
+    a = torch.where(small, 1.0 - t2 / 6.0, torch.sin(ts) / ts)
+    b = torch.where(small, 0.5 - t2 / 24.0, (1.0 - torch.cos(ts)) / (ts * ts))
+    z = torch.zeros_like(t2)
+    K = torch.stack([torch.stack([z, -th[:, 2], th[:, 1]], -1),
+                     torch.stack([th[:, 2], z, -th[:, 0]], -1),
+                     torch.stack([-th[:, 1], th[:, 0], z], -1)], 1)
+    eye = torch.eye(3, dtype=f64).expand(th.shape[0], 3, 3)
+    return eye + a[:, None, None] * K + b[:, None, None] * (K @ K)
+
+
+def pose_to_skin(theta, joints, parents):
+    """theta [J*3], joints [J, 3] rest positions, parents [J] -> skin [J, 12]."""
+    J = len(parents)
+    R = rodrigues(t64(theta).reshape(J, 3))
+    Jt = t64(joints)
+    G, P = [None] * J, [None] * J
+    for j in range(J):
+        p = int(parents[j])
+        if p < 0:
+            G[j], P[j] = R[j], Jt[j]
+        else:
+            G[j] = G[p] @ R[j]
+            P[j] = P[p] + G[p] @ (Jt[j] - Jt[p])
+    rows = [torch.cat([G[j], (P[j] - G[j] @ Jt[j])[:, None]], dim=1).reshape(12) for j in range(J)]
+    return torch.stack(rows)
+
+
+# ---------------------------------------------------------------------------
 # Sec. 3.1: the environment map is a lat-long grid of He x We area lights.
 # Texel (r, c): polar angle (r + 1/2) pi / He from +Y, azimuth (c + 1/2) 2 pi / We;
 # its area A is the exact solid angle of the texel.

@@ -85,6 +85,19 @@ int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
  * both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints) bytes of device
  * memory (per-chunk sums, added in a fixed order).  Overwrites dskin.
  * Errors: RGA_EINVAL (sizes, null pointers), RGA_ECAPACITY (ws too small). */
+/* The skinning matrices of an axis-angle pose (theta in R^72 for 24 joints,
+ * Sec. 3.1 attributes; pose optimisation, Sec. 3.3).  Reading: forward
+ * kinematics R_j = exp([theta_j]x) (Rodrigues), G_j = G_parent R_j,
+ * P_j = P_parent + G_parent (J_j - J_parent), skin_j = [G_j | P_j - G_j J_j];
+ * a joint whose parent is not in 0..j-1 is a root (G = R, P = J_j).
+ * theta [n_joints][3], joints [n_joints][3] rest positions, parents
+ * [n_joints] int32, skin [n_joints][3][4] (the layout of lbs_skin), all
+ * device memory; n_joints in 1..256.  pose_to_skin_backward: dskin ->
+ * dtheta [n_joints][3] (overwritten).  Errors: RGA_EINVAL.                */
+int pose_to_skin(void* stream, int n_joints, const float* theta, const float* joints,
+                 const int32_t* parents, float* skin);
+int pose_to_skin_backward(void* stream, int n_joints, const float* theta, const float* joints,
+                          const int32_t* parents, const float* dskin, float* dtheta);
 size_t lbs_skin_pose_grad_workspace(int n, int n_joints);
 int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx, const float* jw,
                        const float* x, const float* nrm, const float* dx_out,

@@ -162,6 +162,201 @@ int pose_chunks(int n) { return (int)rga::ceil_div(n > 0 ? n : 1, kPoseChunk); }
 
 }  // namespace
 
+namespace {
+
+// ---- pose -> skinning matrices (forward kinematics of the axis-angle pose)
+// R_j = exp([theta_j]x) = I + a K + b K^2 (a = sin t / t, b = (1 - cos t) / t^2,
+// series near t = 0), G_j = G_p R_j, P_j = P_p + G_p (J_j - J_p), a root
+// (parent outside 0..j-1) has G = R, P = J; skin_j = [G_j | P_j - G_j J_j].
+// One workgroup: the Rodrigues matrices in parallel, the chain in joint order
+// by one thread, the rows written in parallel.
+__device__ inline void rodrigues(const float* th, float* R, float& a, float& b, float& ap,
+                                 float& bp) {
+  const float t2 = fmaf(th[2], th[2], fmaf(th[1], th[1], th[0] * th[0]));
+  const float t = sqrtf(t2);
+  if (t2 < 1e-12f) {
+    a = 1.f - t2 / 6.f;
+    b = 0.5f - t2 / 24.f;
+  } else {
+    const float h = sinf(0.5f * t);      // 1 - cos t = 2 sin^2(t/2), no cancellation
+    a = sinf(t) / t;
+    b = 2.f * h * h / t2;
+  }
+  // (da/dt) / t and (db/dt) / t: Taylor series below t = 0.5 (the closed
+  // forms cancel there), the closed forms above
+  if (t2 < 0.25f) {
+    ap = -1.f / 3.f + t2 * (1.f / 30.f + t2 * (-1.f / 840.f + t2 * (1.f / 45360.f)));
+    bp = -1.f / 12.f + t2 * (1.f / 180.f + t2 * (-1.f / 6720.f + t2 * (1.f / 453600.f)));
+  } else {
+    const float sn = sinf(t), cs = cosf(t);
+    ap = (t * cs - sn) / (t2 * t);
+    bp = (t * sn - 2.f * (1.f - cs)) / (t2 * t2);
+  }
+  const float K[9] = {0.f, -th[2], th[1], th[2], 0.f, -th[0], -th[1], th[0], 0.f};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      float k2 = 0.f;
+      for (int m = 0; m < 3; ++m) k2 = fmaf(K[3 * r + m], K[3 * m + c], k2);
+      R[3 * r + c] = (r == c ? 1.f : 0.f) + a * K[3 * r + c] + b * k2;
+    }
+}
+
+__device__ inline void mat3_mul(const float* A, const float* B, float* C) {
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      float v = 0.f;
+      for (int m = 0; m < 3; ++m) v = fmaf(A[3 * r + m], B[3 * m + c], v);
+      C[3 * r + c] = v;
+    }
+}
+
+__device__ inline int parent_of(const int32_t* parents, int j) {
+  const int p = parents[j];
+  return (p >= 0 && p < j) ? p : -1;
+}
+
+struct Chain {
+  float R[kMaxJoints][9], G[kMaxJoints][9], P[kMaxJoints][3];
+};
+
+__device__ void forward_chain(int J, const float* theta, const float* joints,
+                              const int32_t* parents, Chain& ch) {
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    float a, b, ap, bp;
+    rodrigues(theta + 3 * j, ch.R[j], a, b, ap, bp);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < J; ++j) {
+      const int p = parent_of(parents, j);
+      if (p < 0) {
+        for (int q = 0; q < 9; ++q) ch.G[j][q] = ch.R[j][q];
+        for (int q = 0; q < 3; ++q) ch.P[j][q] = joints[3 * j + q];
+      } else {
+        mat3_mul(ch.G[p], ch.R[j], ch.G[j]);
+        for (int r = 0; r < 3; ++r) {
+          float v = ch.P[p][r];
+          for (int m = 0; m < 3; ++m)
+            v = fmaf(ch.G[p][3 * r + m], joints[3 * j + m] - joints[3 * p + m], v);
+          ch.P[j][r] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBlock)
+pose_skin_kernel(int J, const float* __restrict__ theta, const float* __restrict__ joints,
+                 const int32_t* __restrict__ parents, float* __restrict__ skin) {
+  __shared__ Chain ch;
+  forward_chain(J, theta, joints, parents, ch);
+  for (int j = threadIdx.x; j < J; j += blockDim.x)
+    for (int r = 0; r < 3; ++r) {
+      float t = ch.P[j][r];
+      for (int m = 0; m < 3; ++m) t = fmaf(-ch.G[j][3 * r + m], joints[3 * j + m], t);
+      for (int c = 0; c < 3; ++c) skin[12 * j + 4 * r + c] = ch.G[j][3 * r + c];
+      skin[12 * j + 4 * r + 3] = t;
+    }
+}
+
+// Adjoint: dG_j = dS_j[:, :3] - dt_j J_j^T, dP_j = dt_j; in reverse joint
+// order dG_p += dG_j R_j^T + dP_j (J_j - J_p)^T, dP_p += dP_j, dR_j = G_p^T dG_j
+// (dR_j = dG_j at a root); then dtheta_j from dR_j through Rodrigues.
+__global__ void __launch_bounds__(kBlock)
+pose_skin_bwd_kernel(int J, const float* __restrict__ theta, const float* __restrict__ joints,
+                     const int32_t* __restrict__ parents, const float* __restrict__ dskin,
+                     float* __restrict__ dtheta) {
+  __shared__ Chain ch;
+  __shared__ float dG[kMaxJoints][9], dP[kMaxJoints][3], dR[kMaxJoints][9];
+  forward_chain(J, theta, joints, parents, ch);
+  for (int j = threadIdx.x; j < J; j += blockDim.x)
+    for (int r = 0; r < 3; ++r) {
+      const float dt = dskin[12 * j + 4 * r + 3];
+      dP[j][r] = dt;
+      for (int c = 0; c < 3; ++c) dG[j][3 * r + c] = dskin[12 * j + 4 * r + c] - dt * joints[3 * j + c];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = J - 1; j >= 0; --j) {
+      const int p = parent_of(parents, j);
+      if (p < 0) {
+        for (int q = 0; q < 9; ++q) dR[j][q] = dG[j][q];
+        continue;
+      }
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          float vR = 0.f, vG = 0.f;
+          for (int m = 0; m < 3; ++m) {
+            vR = fmaf(ch.G[p][3 * m + r], dG[j][3 * m + c], vR);       // G_p^T dG_j
+            vG = fmaf(dG[j][3 * r + m], ch.R[j][3 * c + m], vG);       // dG_j R_j^T
+          }
+          dR[j][3 * r + c] = vR;
+          dG[p][3 * r + c] += vG + dP[j][r] * (joints[3 * j + c] - joints[3 * p + c]);
+        }
+      for (int r = 0; r < 3; ++r) dP[p][r] += dP[j][r];
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    const float* th = theta + 3 * j;
+    float R[9], a, b, ap, bp;
+    rodrigues(th, R, a, b, ap, bp);
+    const float* D = dR[j];
+    const float K[9] = {0.f, -th[2], th[1], th[2], 0.f, -th[0], -th[1], th[0], 0.f};
+    float K2[9];
+    mat3_mul(K, K, K2);
+    float dK = 0.f, dK2 = 0.f;
+    for (int q = 0; q < 9; ++q) {
+      dK = fmaf(D[q], K[q], dK);
+      dK2 = fmaf(D[q], K2[q], dK2);
+    }
+    for (int k = 0; k < 3; ++k) {
+      float E[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (k == 0) { E[5] = -1.f; E[7] = 1.f; }
+      if (k == 1) { E[2] = 1.f; E[6] = -1.f; }
+      if (k == 2) { E[1] = -1.f; E[3] = 1.f; }
+      float EK[9], KE[9];
+      mat3_mul(E, K, EK);
+      mat3_mul(K, E, KE);
+      float dE = 0.f, dS = 0.f;
+      for (int q = 0; q < 9; ++q) {
+        dE = fmaf(D[q], E[q], dE);
+        dS = fmaf(D[q], EK[q] + KE[q], dS);
+      }
+      dtheta[3 * j + k] = ap * th[k] * dK + a * dE + bp * th[k] * dK2 + b * dS;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" int pose_to_skin(void* stream, int n_joints, const float* theta, const float* joints,
+                            const int32_t* parents, float* skin) {
+  if (n_joints < 1 || n_joints > kMaxJoints)
+    return rga::fail(RGA_EINVAL, "pose_to_skin: n_joints must be in 1..%d", kMaxJoints);
+  if (!theta || !joints || !parents || !skin) return rga::fail(RGA_EINVAL, "pose_to_skin: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RGA_LAUNCH("pose_skin", pose_skin_kernel, dim3(1), dim3(kBlock), 0, s, n_joints, theta, joints,
+             parents, skin);
+  RGA_CHECK_LAUNCH("pose_to_skin");
+  return RGA_OK;
+}
+
+extern "C" int pose_to_skin_backward(void* stream, int n_joints, const float* theta,
+                                     const float* joints, const int32_t* parents,
+                                     const float* dskin, float* dtheta) {
+  if (n_joints < 1 || n_joints > kMaxJoints)
+    return rga::fail(RGA_EINVAL, "pose_to_skin_backward: n_joints must be in 1..%d", kMaxJoints);
+  if (!theta || !joints || !parents || !dskin || !dtheta)
+    return rga::fail(RGA_EINVAL, "pose_to_skin_backward: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RGA_LAUNCH("pose_skin_bwd", pose_skin_bwd_kernel, dim3(1), dim3(kBlock), 0, s, n_joints, theta,
+             joints, parents, dskin, dtheta);
+  RGA_CHECK_LAUNCH("pose_to_skin_backward");
+  return RGA_OK;
+}
+
 extern "C" size_t lbs_skin_pose_grad_workspace(int n, int n_joints) {
   if (n < 0 || n_joints < 1 || n_joints > kMaxJoints) return 0;
   return (size_t)pose_chunks(n) * n_joints * 12 * 4;

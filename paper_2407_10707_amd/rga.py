@@ -34,6 +34,8 @@ _SIGS = {
     "rga_abi_version": (_I, []),
     "lbs_skin": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbs_skin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pose_to_skin": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
+    "pose_to_skin_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
     "lbs_skin_pose_grad_workspace": (_SZ, [_I, _I]),
     "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_workspace": (_SZ, [_I, _I]),
@@ -176,6 +178,27 @@ def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True):
     _check(lib().lbs_skin(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(x), _p(nrm), _p(xo),
                           _p(no), _p(Ao)), "lbs_skin")
     return xo, no, Ao
+
+
+def pose_to_skin(theta, joints, parents):
+    """theta [J, 3] axis-angle, joints [J, 3], parents [J] int32 -> skin [J, 12]."""
+    theta, joints, parents = _f32(theta, "theta"), _f32(joints, "joints"), _i32(parents, "parents")
+    J = int(parents.numel())
+    skin = torch.empty((J, 12), dtype=torch.float32, device=theta.device)
+    _check(lib().pose_to_skin(_stream(), J, _p(theta), _p(joints), _p(parents), _p(skin)),
+           "pose_to_skin")
+    return skin
+
+
+def pose_to_skin_backward(theta, joints, parents, dskin):
+    """dskin [J, 12] -> dtheta [J, 3]."""
+    theta, joints, parents = _f32(theta, "theta"), _f32(joints, "joints"), _i32(parents, "parents")
+    dskin = _f32(dskin, "dskin")
+    J = int(parents.numel())
+    dtheta = torch.empty((J, 3), dtype=torch.float32, device=theta.device)
+    _check(lib().pose_to_skin_backward(_stream(), J, _p(theta), _p(joints), _p(parents),
+                                       _p(dskin), _p(dtheta)), "pose_to_skin_backward")
+    return dtheta
 
 
 def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None):

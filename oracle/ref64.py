@@ -539,3 +539,18 @@ def displacement(x, freqs, theta, params):
 def mean_displacement(x, freqs, thetas, params):
     """Average displacement over a set of poses (used for novel poses)."""
     return torch.stack([displacement(x, freqs, th, params) for th in thetas]).mean(dim=0)
+
+
+# ---------------------------------------------------------------------------
+# The optimiser of the training loop.  Reading: the paper trains as 3DGS
+# does, with Adam (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v +
+# (1 - b2) g^2, p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+# ---------------------------------------------------------------------------
+def adam_step(p, g, m, v, lr, b1, b2, eps, t):
+    """One Adam step at step number t (1-based) -> (p, m, v)."""
+    p, g, m, v = (np.asarray(a, dtype=np.float64) for a in (p, g, m, v))
+    m = b1 * m + (1.0 - b1) * g
+    v = b2 * v + (1.0 - b2) * g * g
+    mh = m / (1.0 - b1 ** t)
+    vh = v / (1.0 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v

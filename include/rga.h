@@ -376,6 +376,16 @@ int mlp_backward(void* stream, int nv, const float* x, const float* freqs, const
                  float* dparams, float* dtheta);
 
 /* ------------------------------------------------------------------------
+ * The optimiser of the training loop (the paper trains as 3DGS does; the
+ * reading is Adam): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * param, m, v [count] updated in place; grad [count]; device memory; step
+ * is 1-based.  Errors: RGA_EINVAL (count < 0, step < 1, betas outside
+ * [0, 1), eps <= 0, null pointer).                                         */
+int adam_step(void* stream, int64_t count, float* param, const float* grad, float* m, float* v,
+              float lr, float beta1, float beta2, float eps, int step);
+
+/* ------------------------------------------------------------------------
  * Kernel timing with HIP events, for measurement.  While enabled, every
  * kernel launch is bracketed by events on its stream; rga_timing_read
  * synchronises and returns the summed milliseconds and launch count of the

@@ -66,6 +66,7 @@ _SIGS = {
     "regularisers_workspace": (_SZ, [_I, _I]),
     "regularisers": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP] +
                      [C.c_float] * 5 + [_VP] * 6 + [_SZ]),
+    "adam_step": (_I, [_VP, C.c_int64, _VP, _VP, _VP, _VP] + [C.c_float] * 4 + [_I]),
     "image_loss_workspace": (_SZ, [_I, _I, _I]),
     "image_loss": (_I, [_VP, _I, _I, _I, _VP, _VP, C.c_float, _VP, _VP, _VP, _SZ]),
     "mlp_workspace": (_SZ, [_I]),
@@ -480,6 +481,16 @@ def regularisers(mat, knn_v, xg, verts, vidx, disp, log_s, s0: float = 0.005,
                               _p(terms), _p(dmat), _p(dxg), _p(ddisp), _p(dlogs), _p(ws), nb),
            "regularisers")
     return terms, dmat, dxg, ddisp, dlogs
+
+
+def adam_step(param, grad, m, v, lr: float, step: int, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam step in place on param, m, v (same shape as grad)."""
+    for t, nm in ((param, "param"), (grad, "grad"), (m, "m"), (v, "v")):
+        _f32(t, nm, tuple(param.shape))
+    _check(lib().adam_step(_stream(), param.numel(), _p(param), _p(grad), _p(m), _p(v),
+                           float(lr), float(beta1), float(beta2), float(eps), int(step)),
+           "adam_step")
 
 
 MLP_PARAMS = 249603

@@ -86,6 +86,8 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.mesh_visibility_shadowmap(None, 10, 10, None, None, 8, None, 64, None, 19, -1.0,
                                        None, None, None, 0) == -1
     assert "bias_px" in rga.last_error()
+    assert L.adam_step(None, 10, None, None, None, None, 1e-3, 0.9, 0.999, 1e-8, 0) == -1
+    assert L.adam_step(None, 10, None, None, None, None, 1e-3, 1.0, 0.999, 1e-8, 1) == -1
     assert L.image_loss(None, 3, 0, 8, None, None, 0.2, None, None, None, 0) == -1
     assert L.image_loss(None, 3, 8, 8, None, None, 1.5, None, None, None, 0) == -1
     assert "lambda" in rga.last_error()

@@ -50,7 +50,7 @@ def _check(x, y, lam, gtol):
     yt = torch.tensor(y.astype(np.float32).astype(np.float64))
     ref = ref64.image_loss(xt, yt, lam)
     (g,) = torch.autograd.grad(ref, (xt,))
-    dl = abs(float(loss.cpu()) - float(ref))
+    dl = abs(float(loss.cpu()) - float(ref.detach()))
     err = np.abs(d.cpu().numpy() - g.numpy()).max() / np.abs(g.numpy()).max()
     print(f"[ssim]   loss err {dl:.3e}  grad err / max {err:.3e}", flush=True)
     assert dl <= 2e-6

@@ -80,9 +80,10 @@ int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
 
 /* The pose gradient of lbs_skin (the skinning matrices are what pose
  * optimisation, Sec. 3.3, differentiates): dskin [n_joints][3][4] =
- * sum_i w_ij (dx_out_i (x_i, 1)^T + dn_out_i (nrm_i, 0)^T), summed over the
- * slots of each Gaussian that name joint j.  nrm and dn_out are both set or
- * both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints) bytes of device
+ * sum_i w_ij (dx_out_i (x_i, 1)^T + dn_out_i (nrm_i, 0)^T + (dA_i, 0)),
+ * summed over the slots of each Gaussian that name joint j (dA [9][n], the
+ * gradient with respect to A from splat_backward, may be NULL).  nrm and
+ * dn_out are both set or both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints) bytes of device
  * memory (per-chunk sums, added in a fixed order).  Overwrites dskin.
  * Errors: RGA_EINVAL (sizes, null pointers), RGA_ECAPACITY (ws too small). */
 /* The skinning matrices of an axis-angle pose (theta in R^72 for 24 joints,
@@ -101,7 +102,8 @@ int pose_to_skin_backward(void* stream, int n_joints, const float* theta, const 
 size_t lbs_skin_pose_grad_workspace(int n, int n_joints);
 int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx, const float* jw,
                        const float* x, const float* nrm, const float* dx_out,
-                       const float* dn_out, float* dskin, void* ws, size_t ws_bytes);
+                       const float* dn_out, const float* dA, float* dskin, void* ws,
+                       size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
  * Sec. 3.2 (visibility computation): orthographic rasterization of the posed
@@ -247,13 +249,14 @@ int splat_state(void* ws, int n, int width, int height, int64_t capacity, rga_sp
 /* Adjoint of splat_forward given dL/dimage.  Re-walks every tile list front to
  * back recomputing the transmittance (nothing per (pixel, splat) is stored);
  * `image` is the forward output.  Outputs (overwritten): dx [3][n],
- * dquat [4][n], dlog_s [3][n], dopac [n], dcolor [3][n].  Gradients with
- * respect to A are not produced.                                           */
+ * dquat [4][n], dlog_s [3][n], dopac [n], dcolor [3][n], and, unless NULL,
+ * dA [9][n]: the gradient with respect to the skinning's linear part A
+ * through the covariance (A R S), which the pose gradient needs.           */
 int splat_backward(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
                    const float* quat, const float* log_s, const float* opac,
                    const float* color, const uint8_t* front, void* ws, size_t ws_bytes,
                    int64_t capacity, const float* image, const float* dimage, float* dx,
-                   float* dquat, float* dlog_s, float* dopac, float* dcolor);
+                   float* dquat, float* dlog_s, float* dopac, float* dcolor, float* dA);
 
 /* ------------------------------------------------------------------------
  * Sec. 3.3, image loss (its L1 term): loss = mean |image - target| over

@@ -94,7 +94,8 @@ lbs_bwd_kernel(int n, int J, const float* __restrict__ skin, const int32_t* __re
 
 namespace {
 
-// Pose gradient: dS_j[r][c] = sum_i w_ij (dx'_i[r] (x_i, 1)[c] + dn'_i[r] (n_i, 0)[c]),
+// Pose gradient: dS_j[r][c] = sum_i w_ij (dx'_i[r] (x_i, 1)[c] + dn'_i[r] (n_i, 0)[c]
+// + dA_i[r][c] for c < 3),
 // w_ij the summed weights of joint j in Gaussian i's slots.  Workgroups over
 // (chunk of Gaussians, joint); per-workgroup sums, then a fixed-order sum
 // over the chunks (no atomics: every joint is shared by many Gaussians).
@@ -104,7 +105,7 @@ __global__ void __launch_bounds__(kBlock)
 lbs_pose_grad_kernel(int n, const int32_t* __restrict__ jidx, const float* __restrict__ jw,
                      const float* __restrict__ x, const float* __restrict__ nrm,
                      const float* __restrict__ dxo, const float* __restrict__ dno,
-                     float* __restrict__ part) {
+                     const float* __restrict__ dA, float* __restrict__ part) {
   __shared__ float red[12][kBlock];
   const int j = blockIdx.y, c = blockIdx.x;
   const int i0 = c * kPoseChunk, i1 = min(n, i0 + kPoseChunk);
@@ -125,6 +126,11 @@ lbs_pose_grad_kernel(int n, const int32_t* __restrict__ jidx, const float* __res
       for (int q = 0; q < 3; ++q) acc[4 * r + q] = fmaf(g, xv[q], acc[4 * r + q]);
       acc[4 * r + 3] += g;
     }
+    if (dA)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[4 * r + q] = fmaf(w, dA[(size_t)(3 * r + q) * n + i], acc[4 * r + q]);
     if (dno) {
       const float nv[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
 #pragma unroll
@@ -364,8 +370,8 @@ extern "C" size_t lbs_skin_pose_grad_workspace(int n, int n_joints) {
 
 extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx,
                                   const float* jw, const float* x, const float* nrm,
-                                  const float* dx_out, const float* dn_out, float* dskin,
-                                  void* ws, size_t ws_bytes) {
+                                  const float* dx_out, const float* dn_out, const float* dA,
+                                  float* dskin, void* ws, size_t ws_bytes) {
   if (n < 0) return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n < 0");
   if (n_joints < 1 || n_joints > kMaxJoints)
     return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n_joints must be in 1..%d", kMaxJoints);
@@ -379,7 +385,7 @@ extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32
   const int chunks = pose_chunks(n);
   float* part = static_cast<float*>(ws);
   RGA_LAUNCH("lbs_pose_grad", lbs_pose_grad_kernel, dim3(chunks, n_joints), dim3(kBlock), 0, s, n,
-             jidx, jw, x, nrm, dx_out, dn_out, part);
+             jidx, jw, x, nrm, dx_out, dn_out, dA, part);
   RGA_LAUNCH("lbs_pose_grad_final", lbs_pose_grad_final, dim3(rga::ceil_div(12 * n_joints, kBlock)),
              dim3(kBlock), 0, s, n_joints, chunks, part, dskin);
   RGA_CHECK_LAUNCH("lbs_skin_pose_grad");

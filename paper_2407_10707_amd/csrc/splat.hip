@@ -1223,7 +1223,7 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
                       float* __restrict__ grad9, uint32_t* __restrict__ queue,
                       float* __restrict__ dx, float* __restrict__ dquat,
                       float* __restrict__ dlog_s, float* __restrict__ dopac,
-                      float* __restrict__ dcolor) {
+                      float* __restrict__ dcolor, float* __restrict__ dA) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) *queue = 0u;
   if (g >= n) return;
@@ -1267,6 +1267,8 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
     for (int k = 0; k < 3; ++k) dx[(size_t)k * n + g] = 0.f;
     for (int k = 0; k < 4; ++k) dquat[(size_t)k * n + g] = 0.f;
     for (int k = 0; k < 3; ++k) dlog_s[(size_t)k * n + g] = 0.f;
+    if (dA)
+      for (int k = 0; k < 9; ++k) dA[(size_t)k * n + g] = 0.f;
     return;
   }
   // x' -> camera: dx' = Rc^T gXYZ
@@ -1286,6 +1288,12 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
     }
     dlog_s[(size_t)j * n + g] = gs * G.s[j];
   }
+  // dA = gB Rq^T (the skinning's linear part, for the pose gradient)
+  if (dA)
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k)
+        dA[(size_t)(3 * i + k) * n + g] =
+            gB[3 * i] * G.Rq[3 * k] + gB[3 * i + 1] * G.Rq[3 * k + 1] + gB[3 * i + 2] * G.Rq[3 * k + 2];
   // gRq = A^T gB
   float gR[9];
   for (int i = 0; i < 3; ++i)
@@ -1495,7 +1503,7 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
                               const float* opac, const float* color, const uint8_t* front,
                               void* ws, size_t ws_bytes, int64_t capacity, const float* image,
                               const float* dimage, float* dx, float* dquat, float* dlog_s,
-                              float* dopac, float* dcolor) {
+                              float* dopac, float* dcolor, float* dA) {
   (void)color;
   Layout L;
   int rc = check_common("splat_backward", n, cam, ws, ws_bytes, capacity, L);
@@ -1520,7 +1528,8 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
              queue, at<float>(ws, L.cstate), at<float>(ws, L.sstate), image, dimage, grad9,
              grad9 + (size_t)5 * n, grad9 + (size_t)6 * n);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
-             n, cd, x, A, quat, log_s, opac, front, grad9, queue, dx, dquat, dlog_s, dopac, dcolor);
+             n, cd, x, A, quat, log_s, opac, front, grad9, queue, dx, dquat, dlog_s, dopac, dcolor,
+             dA);
   RGA_CHECK_LAUNCH("splat_backward");
   return RGA_OK;
 }

@@ -104,10 +104,12 @@ class Renderer:
         return image
 
     # ------------------------------------------------------------------ backward
-    def backward(self, p: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor):
+    def backward(self, p: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor,
+                 want_dA: bool = False):
         d, s = self.d, self.s
         g = rga.splat_backward(self.cam, ctx["xo"], ctx["A"], p["quat"], p["log_s"], p["opac"],
-                               ctx["color"], ctx["front"], self.ws, ctx["image"], dimage)
+                               ctx["color"], ctx["front"], self.ws, ctx["image"], dimage,
+                               want_dA=want_dA)
         sh = rga.shade_gaussians_backward(
             ctx["xo"], ctx["no"], p["albedo"], p["rough"], p["tint"], d["vidx"], d["vw"],
             ctx["count"], s["kv"], s["he"], s["we"], s["hv"], s["wv"], p["env"], self.cam_pos,
@@ -116,7 +118,7 @@ class Renderer:
         dpos, dnrm = rga.lbs_skin_backward(d["skin"], d["jidx"], d["jw"], sh["dx"], sh["dn"])
         return dict(pos=dpos, nrm=dnrm, quat=g["dquat"], log_s=g["dlog_s"], opac=g["dopac"],
                     albedo=sh["dalbedo"], rough=sh["drough"], tint=sh["dtint"], env=sh["denv"],
-                    color=g["dcolor"])
+                    color=g["dcolor"], posed_x=sh["dx"], posed_n=sh["dn"], posed_A=g["dA"])
 
     def loss(self, image: torch.Tensor, target: torch.Tensor):
         """L1 (the hot path's loss), or with image_loss set the image loss
@@ -161,3 +163,53 @@ class RenderFunction(torch.autograd.Function):
 
 def render(renderer: Renderer, count, p: Dict[str, torch.Tensor]):
     return RenderFunction.apply(renderer, count, *[p[k] for k in TRAINABLE])
+
+
+class VertexModel:
+    """The paper's parametrisation (Sec. 3.1): materials and the pose-
+    dependent displacement live on the canonical mesh vertices and reach a
+    Gaussian through the interpolation equation over its K_g = 3 nearest
+    vertices; the skinning matrices come from the pose theta (forward
+    kinematics).  Quaternion, scale, opacity and normal stay per Gaussian
+    here.  forward / backward compose the library's entry points:
+    knn -> displacement network -> interpolation -> pose_to_skin -> the
+    render path, and back through the same adjoints (the two routes of
+    theta, through the network and through the skinning, are added)."""
+
+    def __init__(self, R: Renderer, freqs, joints, parents):
+        self.R = R
+        self.index = rga.KnnIndex(R.d["verts"])
+        self.net = rga.Displacement(R.d["verts"], freqs)
+        self.joints = joints
+        self.parents = parents
+
+    def forward(self, v: Dict[str, torch.Tensor], count: torch.Tensor):
+        """v: theta [24, 3], mlp [params], v_albedo [3, nv], v_rough [nv],
+        v_tint [nv], pos, nrm, quat, log_s, opac, env (per Gaussian)."""
+        R = self.R
+        idx, w = rga.knn(self.index, v["pos"], 3)
+        dxv = self.net.forward(v["theta"].reshape(-1), v["mlp"])
+        attrs = torch.cat([v["v_albedo"], v["v_rough"][None], v["v_tint"][None], dxv])
+        ag = rga.knn_interpolate(idx, w, attrs)
+        p = dict(pos=v["pos"] + ag[5:8], nrm=v["nrm"], quat=v["quat"], log_s=v["log_s"],
+                 opac=v["opac"], albedo=ag[0:3].contiguous(), rough=ag[3].contiguous(),
+                 tint=ag[4].contiguous(), env=v["env"])
+        R.d["skin"] = rga.pose_to_skin(v["theta"], self.joints, self.parents)
+        image, T, ctx = R.forward(p, count)
+        ctx.update(idx=idx, w=w, p=p)
+        return image, T, ctx
+
+    def backward(self, v: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor):
+        R = self.R
+        p = ctx["p"]
+        g = R.backward(p, ctx, dimage, want_dA=True)
+        nv = int(R.d["verts"].shape[1])
+        dg = torch.cat([g["albedo"], g["rough"][None], g["tint"][None], g["pos"]])
+        dv = rga.knn_interpolate_backward(ctx["idx"], ctx["w"], dg, nv)
+        dmlp, dth_net = self.net.backward(dv[5:8].contiguous())
+        dskin = rga.lbs_skin_pose_grad(int(self.parents.numel()), R.d["jidx"], R.d["jw"], p["pos"],
+                                       g["posed_x"], p["nrm"], g["posed_n"], g["posed_A"])
+        dth = rga.pose_to_skin_backward(v["theta"], self.joints, self.parents, dskin)
+        return dict(theta=dth + dth_net.reshape(-1, 3), mlp=dmlp, v_albedo=dv[0:3],
+                    v_rough=dv[3], v_tint=dv[4], pos=g["pos"], nrm=g["nrm"], quat=g["quat"],
+                    log_s=g["log_s"], opac=g["opac"], env=g["env"])

@@ -37,7 +37,7 @@ _SIGS = {
     "pose_to_skin": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
     "pose_to_skin_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
     "lbs_skin_pose_grad_workspace": (_SZ, [_I, _I]),
-    "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
+    "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_workspace": (_SZ, [_I, _I]),
     "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_shadowmap": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, C.c_float,
@@ -54,7 +54,7 @@ _SIGS = {
     "splat_read_count": (_I, [_VP, _VP, _I, _I, _I, _I64, _VP]),
     "splat_state": (_I, [_VP, _I, _I, _I, _I64, _VP]),
     "splat_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
-                            _VP, _VP, _VP, _VP, _VP, _VP]),
+                            _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "l1_loss_workspace": (_SZ, [_I64]),
     "l1_loss": (_I, [_VP, _I64, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "knn_workspace": (_SZ, [_I]),
@@ -202,7 +202,7 @@ def pose_to_skin_backward(theta, joints, parents, dskin):
     return dtheta
 
 
-def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None):
+def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None, dA=None):
     """dskin [n_joints, 12]: the gradient w.r.t. the skinning matrices."""
     n = int(x.shape[1])
     _f32(x, "x", (3, n))
@@ -211,7 +211,7 @@ def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None
     nb = int(lib().lbs_skin_pose_grad_workspace(n, n_joints))
     ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
     _check(lib().lbs_skin_pose_grad(_stream(), n, n_joints, _p(jidx), _p(jw), _p(x), _p(nrm),
-                                    _p(dx_out), _p(dn_out), _p(dskin), _p(ws), nb),
+                                    _p(dx_out), _p(dn_out), _p(dA), _p(dskin), _p(ws), nb),
            "lbs_skin_pose_grad")
     return dskin
 
@@ -358,7 +358,7 @@ def splat_forward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace
 
 
 def splat_backward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace, image,
-                   dimage):
+                   dimage, want_dA: bool = False):
     n = x.shape[1]
     _f32(dimage, "dimage", tuple(image.shape))
     dx = torch.empty((3, n), dtype=torch.float32, device=x.device)
@@ -366,12 +366,13 @@ def splat_backward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspac
     ds = torch.empty((3, n), dtype=torch.float32, device=x.device)
     do = torch.empty((n,), dtype=torch.float32, device=x.device)
     dc = torch.empty((3, n), dtype=torch.float32, device=x.device)
+    dA = torch.empty((9, n), dtype=torch.float32, device=x.device) if want_dA else None
     c = camera(cam)
     _check(lib().splat_backward(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s),
                                 _p(opac), _p(color), _p(front), _p(ws.buf), ws.bytes,
                                 ws.capacity, _p(image), _p(dimage), _p(dx), _p(dq), _p(ds),
-                                _p(do), _p(dc)), "splat_backward")
-    return dict(dx=dx, dquat=dq, dlog_s=ds, dopac=do, dcolor=dc)
+                                _p(do), _p(dc), _p(dA)), "splat_backward")
+    return dict(dx=dx, dquat=dq, dlog_s=ds, dopac=do, dcolor=dc, dA=dA)
 
 
 # ----------------------------------------------------------------------------- loss

@@ -516,6 +516,45 @@ def main():
     full_iter_ms = (time.perf_counter() - t1) * 1e3 / args.steps
     for k, t in saved.items():
         p[k].copy_(t)
+
+    # the same iteration in the paper's parametrisation: materials and the
+    # network's displacement on the vertices, interpolated to the Gaussians
+    # (K_g = 3 search every iteration), skinning from the pose, and the
+    # adjoint back to theta, the network and the vertex attributes
+    skin0 = R.d["skin"].clone()
+    vin = synth.mlp_inputs(0)
+    vparams = vin["params"].copy()
+    vparams[-(3 * 256 + 3):] *= 0.01
+    M = render.VertexModel(R, torch.as_tensor(vin["freqs"]).cuda(),
+                           torch.as_tensor(synth.JOINTS_REST, dtype=torch.float32).cuda(),
+                           torch.as_tensor(synth.PARENTS, dtype=torch.int32).cuda())
+    vrng = np.random.default_rng(21)
+    nvert = int(d["verts"].shape[1])
+    vv = dict(theta=torch.as_tensor(0.2 * vrng.standard_normal((24, 3)), dtype=torch.float32).cuda(),
+              mlp=torch.as_tensor(vparams).cuda(),
+              v_albedo=torch.as_tensor(vrng.random((3, nvert)), dtype=torch.float32).cuda(),
+              v_rough=torch.as_tensor(vrng.uniform(0.2, 0.9, nvert), dtype=torch.float32).cuda(),
+              v_tint=torch.as_tensor(vrng.random(nvert), dtype=torch.float32).cuda(),
+              pos=p["pos"], nrm=p["nrm"], quat=p["quat"], log_s=p["log_s"], opac=p["opac"],
+              env=p["env"])
+
+    def vertex_iter():
+        count = R.visibility()
+        image, _, ctx = M.forward(vv, count)
+        _, dimage = R.loss(image, target)
+        M.backward(vv, ctx, dimage)
+
+    vertex_iter()
+    R.ensure_capacity()
+    for _ in range(2):
+        vertex_iter()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        vertex_iter()
+    torch.cuda.synchronize()
+    vertex_iter_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    R.d["skin"] = skin0
     R.image_loss = False
 
     knn = knn_measure(s, d)
@@ -554,6 +593,7 @@ def main():
         "displacement_mlp": mlp,
         "image_loss": dict(img_loss, step_ms_with_image_loss=round(img_loss_step_ms, 4)),
         "training_iteration_ms": round(full_iter_ms, 4),
+        "vertex_model_iteration_ms": round(vertex_iter_ms, 4),
     }
     if per_kernel:
         out["per_kernel_ms_per_step"] = per_kernel

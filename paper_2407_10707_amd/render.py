@@ -116,9 +116,12 @@ class Renderer:
             ctx["color"], ctx["front"], g["dcolor"], dx_accum=g["dx"], precision=self.precision,
             ws=self.shade_ws)
         dpos, dnrm = rga.lbs_skin_backward(d["skin"], d["jidx"], d["jw"], sh["dx"], sh["dn"])
-        return dict(pos=dpos, nrm=dnrm, quat=g["dquat"], log_s=g["dlog_s"], opac=g["dopac"],
-                    albedo=sh["dalbedo"], rough=sh["drough"], tint=sh["dtint"], env=sh["denv"],
-                    color=g["dcolor"], posed_x=sh["dx"], posed_n=sh["dn"], posed_A=g["dA"])
+        out = dict(pos=dpos, nrm=dnrm, quat=g["dquat"], log_s=g["dlog_s"], opac=g["dopac"],
+                   albedo=sh["dalbedo"], rough=sh["drough"], tint=sh["dtint"], env=sh["denv"],
+                   color=g["dcolor"], posed_x=sh["dx"], posed_n=sh["dn"])
+        if want_dA:
+            out["posed_A"] = g["dA"]
+        return out
 
     def loss(self, image: torch.Tensor, target: torch.Tensor):
         """L1 (the hot path's loss), or with image_loss set the image loss

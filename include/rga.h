@@ -71,8 +71,9 @@ int lbs_skin(void* stream, int n, int n_joints, const float* skin, const int32_t
              const float* jw, const float* x, const float* nrm, float* x_out, float* n_out,
              float* A_out);
 
-/* Adjoint of lbs_skin with respect to x and nrm (pose gradients are not
- * produced):  dx = A^T dx_out,  dn = A^T dn_out.
+/* Adjoint of lbs_skin with respect to x and nrm (the gradient with respect
+ * to the skinning matrices is lbs_skin_pose_grad's):  dx = A^T dx_out,
+ * dn = A^T dn_out.
  * dn_out / dn may both be NULL.  Overwrites dx and dn.                      */
 int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
                       const int32_t* jidx, const float* jw, const float* dx_out,

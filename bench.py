@@ -313,7 +313,7 @@ def image_loss_measure(s, reps: int = 20):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import numpy as np

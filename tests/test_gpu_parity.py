@@ -418,3 +418,17 @@ def test_gradients_match_fp64_oracle(precision):
         rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
         print(f"  {k:7s} relL2={rel:.2e}", flush=True)
         assert rel < tol_g, (k, rel)
+
+
+def test_pose_to_skin_edge_cases():
+    """One joint, and a skeleton whose parents are all out of range (every
+    joint a root), against the oracle."""
+    print("[pose] edge cases", flush=True)
+    rng = np.random.default_rng(10)
+    for J, parents in ((1, np.array([-1], np.int32)), (5, np.array([-1, 7, 3, -2, 4], np.int32))):
+        th = rng.normal(0.0, 0.5, (J, 3)).astype(np.float32)
+        joints = rng.normal(size=(J, 3)).astype(np.float32)
+        S = host(rga.pose_to_skin(dev(th), dev(joints), dev(parents)))
+        eff = np.array([p if 0 <= p < j else -1 for j, p in enumerate(parents)])
+        ref = ref64.pose_to_skin(th.astype(np.float64).reshape(-1), joints.astype(np.float64), eff)
+        assert np.abs(S - ref.numpy()).max() <= 2e-6

@@ -55,3 +55,26 @@ def test_regularisers_on_the_avatar_tables():
         err = np.abs(a - r).max() / np.abs(r).max()
         print(f"[reg]   d{name}: err / max {err:.3e}", flush=True)
         assert err <= 2e-6
+
+
+def test_regularisers_without_gaussians():
+    """n = 0: the Gaussian terms are zero and the vertex terms still match."""
+    from paper_2407_10707_amd import rga
+    rng = np.random.default_rng(3)
+    nv = 50
+    verts = rng.normal(size=(3, nv)).astype(np.float32)
+    knn = np.stack([np.argsort(((verts[:, i:i + 1] - verts) ** 2).sum(0))[:5] for i in range(nv)])
+    mat = rng.random((5, nv)).astype(np.float32)
+    disp = (0.01 * rng.standard_normal((3, nv))).astype(np.float32)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a)).cuda()
+    e3 = torch.zeros((3, 0), device="cuda")
+    terms, dmat, dxg, ddisp, dlogs = rga.regularisers(
+        dv(mat), dv(knn.astype(np.int32)), e3, dv(verts), torch.zeros((3, 0), dtype=torch.int32,
+                                                                     device="cuda"),
+        dv(disp), e3)
+    t = terms.cpu().numpy()
+    ref = ref64.regularisers(mat, knn, np.zeros((3, 0)), verts, np.zeros((3, 0), np.int64), disp,
+                             np.zeros((3, 0)))
+    assert t[1] == 0 and t[3] == 0
+    assert abs(t[0] - float(ref[0])) <= 2e-6 * float(ref[0])
+    assert abs(t[2] - float(ref[2])) <= 2e-6 * float(ref[2])

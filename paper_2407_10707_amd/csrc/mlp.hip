@@ -502,20 +502,30 @@ mlp_reduce_kernel(int chunks, const float* __restrict__ theta, const float* __re
   }
 }
 
-// dtheta = W_1[:, 128:]^T db_1 (db_1 summed over the chunks first)
-__global__ void __launch_bounds__(256)
+// dtheta = W_1[:, 128:]^T db_1 (db_1 summed over the chunks first; the
+// 256-term products in four fixed quarters, then added in order)
+constexpr int kDthThreads = 320;
+__global__ void __launch_bounds__(kDthThreads)
 mlp_dtheta_kernel(int chunks, const float* __restrict__ P, const float* __restrict__ part,
                   float* __restrict__ dtheta) {
   __shared__ float db[kWidth];
+  __shared__ float quarter[4][kPose];
   const int t = threadIdx.x;
-  float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(size_t)c * kParams + b_off(0) + t];
-  db[t] = s;
+  if (t < kWidth) {
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * kParams + b_off(0) + t];
+    db[t] = s;
+  }
   __syncthreads();
-  if (t >= kPose) return;
-  float a = 0.f;
-  for (int n = 0; n < kWidth; ++n) a = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + t], db[n], a);
-  dtheta[t] = a;
+  if (t < 4 * kPose) {
+    const int k = t % kPose, q = t / kPose;
+    float a = 0.f;
+    for (int n = 64 * q; n < 64 * q + 64; ++n)
+      a = fmaf(P[w_off(0) + n * kIn1 + 2 * kFreqs + k], db[n], a);
+    quarter[q][k] = a;
+  }
+  __syncthreads();
+  if (t < kPose) dtheta[t] = ((quarter[0][t] + quarter[1][t]) + quarter[2][t]) + quarter[3][t];
 }
 
 }  // namespace
@@ -568,8 +578,8 @@ extern "C" int mlp_backward(void* stream, int nv, const float* x, const float* f
              L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
   RGA_LAUNCH("mlp_reduce", mlp_reduce_kernel, dim3(rga::ceil_div(kParams, 256)), dim3(256), 0, s,
              L.chunks, theta, part, dparams);
-  RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(kWidth), 0, s, L.chunks, params, part,
-             dtheta);
+  RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(kDthThreads), 0, s, L.chunks, params,
+             part, dtheta);
   RGA_CHECK_LAUNCH("mlp_backward");
   return RGA_OK;
 }

@@ -429,3 +429,33 @@ def mlp_inputs(seed: int, n_pose: int = 1, freqs: int = 64, pose: int = 72, widt
     return dict(freqs=_f32(rng.normal(0.0, sigma, (freqs, 3))),
                 thetas=_f32(rng.normal(0.0, 0.2, (n_pose, pose))),
                 params=_f32(np.concatenate(parts)))
+
+
+def needle_splats(seed: int, n_plain: int = 300, width: int = 99, height: int = 75,
+                  n_needles: int = 8) -> dict:
+    """Splat-level inputs (posed positions, linear part A = I, quaternions,
+    log-scales, opacities, colours) of ordinary splats mixed with needles:
+    one axis 4-8 units long and two of 2e-4, turned about the camera's
+    optical axis by angles in 25-65 or 115-155 degrees (off the image axes,
+    where the 2D covariance's determinant cancels), so that their projected
+    2D covariance is nearly rank one.  The order is shuffled."""
+    rng = np.random.default_rng([2000, seed])
+    cam = default_camera(width, height)
+    n = n_plain + n_needles
+    x = np.stack([rng.uniform(-0.7, 0.7, n), rng.uniform(-0.5, 0.5, n),
+                  rng.uniform(-0.3, 0.3, n)])
+    q = rng.normal(size=(4, n))
+    q /= np.linalg.norm(q, axis=0)
+    ls = rng.normal(-3.3, 0.3, (3, n))
+    op = rng.uniform(0.3, 0.95, n)
+    angs = (rng.uniform(25.0, 65.0, n_needles) + 90.0 * (np.arange(n_needles) % 2)) * math.pi / 180
+    for i, a in enumerate(angs):
+        g = n_plain + i
+        q[:, g] = [math.cos(a / 2), 0.0, 0.0, math.sin(a / 2)]
+        ls[:, g] = [math.log(rng.uniform(4.0, 8.0)), math.log(2e-4), math.log(2e-4)]
+        op[g] = rng.uniform(0.5, 0.9)
+    perm = rng.permutation(n)
+    A = np.tile(np.eye(3).reshape(9, 1), (1, n))
+    return dict(cam=cam, n=n, x=_f32(x[:, perm]), A=_f32(A), quat=_f32(q[:, perm]),
+                log_s=_f32(ls[:, perm]), opac=_f32(op[perm]), color=_f32(rng.random((3, n))),
+                front=np.ones(n, np.uint8), needle=np.argsort(perm)[n_plain:])

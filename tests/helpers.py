@@ -4,6 +4,8 @@ decisions that must match bit for bit)."""
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import torch
 
@@ -54,3 +56,120 @@ def oracle_frame_f32(s, color):
     img, T, margin = cpu.composite_tiles(s["cam"], ranges, vals, pre, s["opac"], color)
     return dict(xo=xo, no=no, Ao=Ao, front=front, pre=pre, keys=keys, vals=vals, ranges=ranges,
                 img=img, T=T, margin=margin)
+
+
+def check_grad(name, got, ref, rtol=1e-4, floor=1e-3, rel_l2=1e-4, tag=""):
+    """Per-element and per-tensor check of a GPU gradient against the FP64
+    oracle's: |g - g64| <= rtol |g64| + floor RMS(g64) for every element and
+    ||g - g64|| <= rel_l2 ||g64||.  Prints the worst ratios."""
+    got = np.asarray(got, dtype=np.float64).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1)
+    rms = float(np.sqrt(np.mean(ref * ref))) if ref.size else 0.0
+    err = np.abs(got - ref)
+    lim = rtol * np.abs(ref) + floor * rms + 1e-300
+    rl2 = float(np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-300))
+    worst = float((err / lim).max()) if ref.size else 0.0
+    print(f"  {tag}{name:8s} relL2={rl2:.2e} worst err/limit={worst:.3f}", flush=True)
+    assert worst <= 1.0, (name, worst, int((err > lim).sum()))
+    assert rl2 <= rel_l2, (name, rl2)
+
+
+def subscene(s, sub):
+    """The scene restricted to the Gaussians `sub` (mesh, camera and
+    environment unchanged)."""
+    out = dict(s)
+    for k in ("pos", "nrm", "quat", "log_s", "albedo", "jidx", "jw", "vidx", "vw"):
+        out[k] = np.ascontiguousarray(s[k][:, sub])
+    for k in ("opac", "rough", "tint"):
+        out[k] = np.ascontiguousarray(s[k][sub])
+    out["n"] = len(sub)
+    return out
+
+
+GAUSS_PARAMS = ("pos", "nrm", "quat", "log_s", "opac", "albedo", "rough", "tint")
+
+
+class LocalFD:
+    """Central finite differences of L = sum(w * image) through the FP64
+    oracle's whole chain (render64), evaluated cheaply but exactly:
+
+    * a parameter of Gaussian g changes only g's skinned state, colour and
+      projection (each computed per Gaussian) and the pixels inside g's
+      compositing box (alpha < 1/255 outside it, so they never see g); the
+      difference L(p + h e) - L(p - h e) is therefore the difference of the
+      loss over those pixels, composited with every Gaussian;
+    * an environment texel changes every colour: the whole frame is
+      re-shaded and re-composited.
+    `fd(name, flat_index, h)` returns (L(+h) - L(-h)) / 2h."""
+
+    def __init__(self, s, count, front, w):
+        self.s, self.count, self.front = s, count, np.asarray(front)
+        self.w = torch.as_tensor(np.asarray(w, dtype=np.float64).reshape(3, -1))
+        self.p = params64(s)
+        with torch.no_grad():
+            _, _, parts = render64(s, self.p, count, front, return_parts=True)
+        self.base = parts
+
+    def _gauss_state(self, q, g):
+        s = self.s
+        sl = slice(g, g + 1)
+        xp, npr, A = ref64.lbs(s["skin"], s["jidx"][:, sl], s["jw"][:, sl], q["pos"][:, sl],
+                               q["nrm"][:, sl])
+        col, _ = ref64.shade(xp, npr, q["albedo"][:, sl], q["rough"][sl], q["tint"][sl],
+                             s["vidx"][:, sl], s["vw"][:, sl], self.count, s["kv"], s["he"],
+                             s["we"], s["hv"], s["wv"], q["env"], s["cam"].centre,
+                             self.front[sl])
+        proj = ref64.project(s["cam"], xp, A, q["quat"][:, sl], q["log_s"][:, sl],
+                             q["opac"][sl], self.front[sl])
+        return col, proj
+
+    def _box(self, g):
+        cam = self.s["cam"]
+        pr = self.base["proj"]
+        if not bool(pr["valid"][g]):
+            return np.zeros(0, np.int64)
+        m, sig = pr["mean2d"][:, g], pr["sigma"][:, g]
+        r2 = 2.0 * math.log(255.0 * float(self.p["opac"][g]))
+        hx = math.sqrt(r2 * float(sig[0])) + 3.0
+        hy = math.sqrt(r2 * float(sig[2])) + 3.0
+        x0, x1 = max(0, math.floor(float(m[0]) - hx)), min(cam.width - 1, math.ceil(float(m[0]) + hx))
+        y0, y1 = max(0, math.floor(float(m[1]) - hy)), min(cam.height - 1, math.ceil(float(m[1]) + hy))
+        if x0 > x1 or y0 > y1:
+            return np.zeros(0, np.int64)
+        yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+        return (yy * cam.width + xx).reshape(-1)
+
+    def _loss_gauss(self, q, g, pix):
+        col_g, proj_g = self._gauss_state(q, g)
+        col = self.base["col"].clone()
+        col[:, g] = col_g[:, 0]
+        proj = {k: v.clone() for k, v in self.base["proj"].items()}
+        for k in proj:
+            proj[k][..., g] = proj_g[k][..., 0]
+        img, _ = ref64.composite(self.s["cam"], proj, q["opac"], col, pixels=pix)
+        return float((img * self.w[:, pix]).sum())
+
+    def _loss_frame(self, q):
+        img, _ = render64(self.s, q, self.count, self.front)
+        return float((img * self.w).sum())
+
+    def fd(self, name, idx, h):
+        vals = []
+        with torch.no_grad():
+            if name == "env":
+                for sgn in (1.0, -1.0):
+                    q = dict(self.p)
+                    q["env"] = self.p["env"].clone()
+                    q["env"].view(-1)[idx] += sgn * h
+                    vals.append(self._loss_frame(q))
+            else:
+                g = idx % self.s["n"]
+                pix = self._box(g)
+                if len(pix) == 0:
+                    return 0.0
+                for sgn in (1.0, -1.0):
+                    q = dict(self.p)
+                    q[name] = self.p[name].clone()
+                    q[name].view(-1)[idx] += sgn * h
+                    vals.append(self._loss_gauss(q, g, pix))
+        return (vals[0] - vals[1]) / (2.0 * h)

@@ -5,7 +5,8 @@ back-face flags, per-splat tile rectangles and depth keys, D, tile ranges and
 per-tile lists.  Tolerances: shaded colours vs the FP64 oracle
 |d| <= 1e-5 |ref| + 1e-7; pixels vs the FP32 mirror |d| <= 1e-5 |ref| + 1e-6
 (pixels whose compositing decisions sit within 1e-4 of a threshold are
-exempt and counted); gradients vs the FP64 oracle's autograd, per tensor.
+exempt and counted); gradients vs the FP64 oracle's autograd, per element
+(|g - g64| <= rtol |g64| + 1e-3 RMS(g64)) and per tensor (relative L2 <= 1e-4).
 """
 
 import numpy as np
@@ -410,14 +411,13 @@ def test_gradients_match_fp64_oracle(precision):
     image, T, ctx = R.forward(pd, dev(cnt))
     g = R.backward(pd, ctx, dev(w.astype(np.float32)))
     # forward image against the FP64 oracle as a sanity check of the chain
-    tol_img, tol_g = (2e-5, 2e-3) if precision == "fp32" else (2e-4, 1e-2)
+    # per element |g - g64| <= rtol |g64| + 1e-3 RMS(g64), per tensor relL2 <= 1e-4;
+    # the split bf16 product's colours carry up to 1e-4 relative error, so
+    # its per-element rtol is 1e-3
+    tol_img, rtol = (2e-5, 1e-4) if precision == "fp32" else (2e-4, 1e-3)
     assert np.abs(host(image).reshape(3, -1) - img.detach().numpy()).max() < tol_img
     for k in render.TRAINABLE:
-        ref = p[k].grad.numpy()
-        got = host(g[k])
-        rel = np.linalg.norm(got - ref) / (np.linalg.norm(ref) + 1e-30)
-        print(f"  {k:7s} relL2={rel:.2e}", flush=True)
-        assert rel < tol_g, (k, rel)
+        helpers.check_grad(k, host(g[k]), p[k].grad.numpy(), rtol=rtol)
 
 
 def test_pose_to_skin_edge_cases():

@@ -62,3 +62,34 @@ def test_autograd_matches_central_differences():
             checked += 1
             assert abs(flat[idx] - fd[1]) <= 1e-5 * max(abs(fd[1]), scale), (name, idx, flat[idx], fd)
     assert checked >= 60 and excluded <= 8, (checked, excluded)
+
+
+def test_local_differences_equal_whole_frame_differences():
+    """The finite differences of the FP64 chain evaluated locally (only the
+    perturbed Gaussian's state and the pixels of its compositing box
+    recomputed) equal those of whole-frame renders, on the first 500
+    Gaussians of the 1024^2 training workload."""
+    from tests.conftest import scene
+    s = helpers.subscene(scene(3), np.arange(500))
+    _, _, cnt = helpers.oracle_visibility(s)
+    front = helpers.front_flags(s)
+    w = np.random.default_rng(3).uniform(0.5, 1.5, (3, s["height"], s["width"]))
+    F = helpers.LocalFD(s, cnt, front, w)
+    wt = torch.as_tensor(w.reshape(3, -1))
+    valid = np.nonzero(F.base["proj"]["valid"].numpy())[0]
+    g = int(valid[7])
+    n = s["n"]
+    for name, idx, h in (("pos", 0 * n + g, 1e-4), ("log_s", 2 * n + g, 1e-4),
+                         ("albedo", 1 * n + g, 1e-3), ("opac", g, 1e-4)):
+        local = F.fd(name, idx, h)
+        vals = []
+        with torch.no_grad():
+            for sgn in (1.0, -1.0):
+                q = dict(F.p)
+                q[name] = F.p[name].clone()
+                q[name].view(-1)[idx] += sgn * h
+                img, _ = helpers.render64(s, q, cnt, front)
+                vals.append(float((img * wt).sum()))
+        full = (vals[0] - vals[1]) / (2 * h)
+        assert abs(local - full) <= 1e-9 * max(1.0, abs(full)), (name, local, full)
+        assert abs(full) > 1e-6, (name, full)

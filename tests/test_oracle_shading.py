@@ -163,3 +163,29 @@ def test_srgb_transfer_curve():
     assert y[0].item() == 0.0
     assert abs(y[1].item() - 0.0404500) < 1e-6     # both branches meet at the knee
     assert abs(y[2].item() - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("grid", [(8, 16, 8, 8), (32, 64, 32, 32), (16, 32, 16, 32),
+                                  (12, 24, 4, 6)])
+def test_texel_view_lies_in_its_view_cell(grid):
+    """The coarse texel -> view map (views fewer than light directions): the
+    direction of every texel lies inside the lat-long cell of the view it is
+    given, measured from the direction itself (polar angle from +Y, azimuth
+    from +Z towards +X), not from the integer formula."""
+    he, we, hv, wv = grid
+    dirs, _ = ref64.env_geometry(he, we)
+    view = ref64.texel_view(he, we, hv, wv).numpy()
+    d = dirs.numpy()
+    th = np.arccos(np.clip(d[:, 1], -1.0, 1.0))
+    ph = np.mod(np.arctan2(d[:, 0], d[:, 2]), 2 * math.pi)
+    vr, vc = view // wv, view % wv
+    assert view.min() >= 0 and view.max() < hv * wv
+    assert np.all(th >= vr * math.pi / hv) and np.all(th < (vr + 1) * math.pi / hv)
+    assert np.all(ph >= vc * 2 * math.pi / wv) and np.all(ph < (vc + 1) * 2 * math.pi / wv)
+    # every view cell receives the same number of texels
+    assert np.all(np.bincount(view, minlength=hv * wv) == (he // hv) * (we // wv))
+
+
+def test_texel_view_identity_when_grids_coincide():
+    for he, we in ((8, 16), (16, 32), (32, 64)):
+        assert np.array_equal(ref64.texel_view(he, we, he, we).numpy(), np.arange(he * we))

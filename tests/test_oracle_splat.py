@@ -185,3 +185,25 @@ def test_needle_splat_takes_the_fp64_path():
     got = pre["conic"][:, 0].astype(np.float64)
     scale = np.abs(want).max()
     assert np.abs(got - want).max() / scale < 1e-5
+
+
+def test_needle_scene_takes_the_fp64_path():
+    """The mixed needle scene of the GPU needle tests: every needle, and no
+    ordinary splat, takes the FP64 path; the FP64 path's conic agrees with
+    the FP64 oracle's to FP32 rounding, where the conic taken in FP32 from
+    the same covariance is off by far more (the determinant cancels)."""
+    sc = synth.needle_splats(1)
+    cam = sc["cam"]
+    pre = cpu.splat_preprocess(cam, sc["x"], sc["A"], sc["quat"], sc["log_s"], sc["opac"],
+                               sc["front"])
+    flagged = np.nonzero(pre["fp64"])[0]
+    assert np.array_equal(flagged, np.sort(sc["needle"]))
+    proj = ref64.project(cam, ref64.t64(sc["x"]), ref64.t64(sc["A"]), ref64.t64(sc["quat"]),
+                         ref64.t64(sc["log_s"]), ref64.t64(sc["opac"]), sc["front"])
+    c64 = proj["conic"][:, flagged].numpy()
+    scale = np.abs(c64).max(0)
+    assert np.max(np.abs(pre["conic"][:, flagged] - c64) / scale) < 1e-6
+    sig = proj["sigma"][:, flagged].numpy().astype(np.float32)
+    det = sig[0] * sig[2] - sig[1] * sig[1]
+    naive = np.stack([sig[2] / det, -sig[1] / det, sig[0] / det])
+    assert np.max(np.abs(naive - c64) / scale) > 1e-4

@@ -73,3 +73,26 @@ def test_gradient_matches_central_differences():
         e[idx] = eps
         fd = (ref64.image_loss(x + e, y) - ref64.image_loss(x - e, y)) / (2 * eps)
         assert abs(float(fd) - float(g[idx])) <= 1e-7 + 1e-6 * abs(float(fd))
+
+
+def test_l1_term_against_loops_and_closed_forms():
+    """The L1 term of the image loss: the mean over every channel and pixel
+    of |x - y| (checked against a loop), |c| for a constant offset c, and its
+    gradient sign(x - y) / count with sign(0) = 0 at exact ties."""
+    rng = np.random.default_rng(4)
+    x = rng.random((3, 5, 7))
+    y = rng.random((3, 5, 7))
+    y[0, 1, 2] = x[0, 1, 2]                 # exact ties
+    y[2, 4, 6] = x[2, 4, 6]
+    tot = 0.0
+    for c in range(3):
+        for r in range(5):
+            for k in range(7):
+                tot += abs(x[c, r, k] - y[c, r, k])
+    assert abs(ref64.l1_loss(torch.tensor(x), y).item() - tot / x.size) < 1e-15
+    assert abs(ref64.l1_loss(torch.tensor(x), x + 0.25).item() - 0.25) < 1e-15
+    xt = torch.tensor(x, requires_grad=True)
+    ref64.l1_loss(xt, y).backward()
+    want = np.sign(x - y) / x.size
+    assert np.array_equal(xt.grad.numpy(), want)
+    assert xt.grad[0, 1, 2].item() == 0.0 and xt.grad[2, 4, 6].item() == 0.0

@@ -9,9 +9,13 @@ one 512x512 camera):
   shade backward -> skinning backward.
 Inputs are synthetic (seeded) and resident in HBM before timing starts.
 
-Prints one JSON line.  `value` is the fwd+bwd time per step (ms/iter);
-`render_fps` is the forward-only frame rate with visibility recomputed per
-frame, `render_fps_no_vis` with visibility cached per pose.
+Prints one JSON line.  `value` is the fwd+bwd time per step (ms/iter) of
+the FP32 form; `render_fps` is the forward-only frame rate with visibility
+recomputed per frame, `render_fps_no_vis` with visibility cached per pose.
+The same figures for the BF16X3 form of the shading contraction (bf16 hi +
+lo operands on MFMA) sit under `bf16x3`, and `image_error_vs_fp64` gives
+each form's image PSNR against the FP64 oracle (with the oracle's emulation
+of plain bf16 operands beside it).
 """
 
 from __future__ import annotations
@@ -20,7 +24,6 @@ import argparse
 import json
 import math
 import os
-import statistics
 import sys
 import time
 
@@ -41,7 +44,11 @@ def parse():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--kernel", default=None, help="kernel timed for the roofline entry")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle legs (CPU baseline and image error vs FP64)")
+    ap.add_argument("--one-form", action="store_true",
+                    help="time only the --precision form (by default the other form of the "
+                         "shading contraction is timed beside it)")
     ap.add_argument("--all-kernels", action="store_true", help="time every kernel (diagnostic)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counters)")
@@ -124,6 +131,84 @@ def shading_pairs(s, R, p, count):
     return {"live": live, "tested": tested}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def image_error(s, images, tiles_wanted: int = 8):
+    """Image error of each form against the FP64 oracle's whole chain
+    (skinning, shading, projection, compositing) on every pixel of 8 seeded
+    lit tiles: PSNR (peak 1), relative L2 and max abs.  `images` maps a form
+    to its GPU image; the FP64 oracle also renders the frame with its
+    shading contraction's operands rounded to plain bfloat16 (and to the
+    split hi + lo form), an emulation of what those operand precisions lose.
+    The tiles (seeded, among those whose lists are at least the median
+    length), the Gaussians that can reach them and the visibility counts
+    come from the FP32 mirror (the oracle's own decisions)."""
+    import numpy as np
+    import torch
+    from oracle import cpu, ref64
+    cam = s["cam"]
+    H, W = s["height"], s["width"]
+    xo, no, Ao = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    front = cpu.front_f32(xo, no, cam.centre.astype(np.float32))
+    pre = cpu.splat_preprocess(cam, xo, Ao, s["quat"], s["log_s"], s["opac"], front)
+    _, vals, ranges = cpu.splat_bin(cam, pre)
+    TX = (W + 15) // 16
+    # tiles whose lists are at least as long as the median non-empty list
+    lens = ranges[:, 1] - ranges[:, 0]
+    busy = np.nonzero(lens >= max(1, np.median(lens[lens > 0])))[0]
+    rng = np.random.default_rng(13)
+    tiles = np.sort(rng.choice(busy, tiles_wanted, replace=False))
+    pix = []
+    for t in tiles:
+        ty, tx = divmod(int(t), TX)
+        yy, xx = np.meshgrid(np.arange(ty * 16, min(H, ty * 16 + 16)),
+                             np.arange(tx * 16, min(W, tx * 16 + 16)), indexing="ij")
+        pix.append((yy * W + xx).reshape(-1))
+    pix = np.sort(np.concatenate(pix))
+    sub = np.unique(np.concatenate([vals[ranges[t, 0]:ranges[t, 1]] for t in tiles]))
+    ss = dict(s)
+    for k in ("pos", "nrm", "quat", "log_s", "albedo", "jidx", "jw", "vidx", "vw"):
+        ss[k] = np.ascontiguousarray(s[k][:, sub])
+    for k in ("opac", "rough", "tint"):
+        ss[k] = np.ascontiguousarray(s[k][sub])
+    vx = cpu.lbs_f32(s["skin"], s["mesh_jidx"], s["mesh_jw"], s["verts"])[0]
+    _, cnt = cpu.mesh_visibility(vx, s["faces"], s["view_dirs"], s["vis_res"], s["knn_v"])
+
+    def render(operands):
+        p = {k: torch.tensor(np.asarray(ss[k], dtype=np.float64))
+             for k in ("pos", "nrm", "quat", "log_s", "opac", "albedo", "rough", "tint", "env")}
+        with torch.no_grad():
+            xp, npr, A = ref64.lbs(ss["skin"], ss["jidx"], ss["jw"], p["pos"], p["nrm"])
+            col, _ = ref64.shade(xp, npr, p["albedo"], p["rough"], p["tint"], ss["vidx"],
+                                 ss["vw"], cnt, ss["kv"], ss["he"], ss["we"], ss["hv"], ss["wv"],
+                                 p["env"], cam.centre, front[sub], operands=operands)
+            proj = ref64.project(cam, xp, A, p["quat"], p["log_s"], p["opac"], front[sub])
+            img, _ = ref64.composite(cam, proj, p["opac"], col, pixels=pix)
+        return img.numpy()
+
+    ref = render("exact")
+    got = {f: np.asarray(im, dtype=np.float64).reshape(3, -1)[:, pix] for f, im in images.items()}
+    got["bf16_operands_emulated"] = render("bf16")
+    got["bf16x3_operands_emulated"] = render("bf16x3")
+    out = {"pixels": int(len(pix)), "tiles": int(len(tiles)), "gaussians": int(len(sub))}
+    for f, g in got.items():
+        err = g - ref
+        mse = float(np.mean(err ** 2))
+        out[f] = {"psnr_db": round(10 * math.log10(1.0 / max(mse, 1e-300)), 2),
+                  "rel_l2": float(f"{np.linalg.norm(err) / np.linalg.norm(ref):.3e}"),
+                  "max_abs": float(f"{np.abs(err).max():.3e}")}
+    return out
+
+
 def cpu_baseline(s):
     """The oracle, as it stands, timed on the host on a bounded sample of one
     step: FP32-mirror skinning of mesh and Gaussians (all), visibility for
@@ -186,7 +271,7 @@ def cpu_baseline(s):
     total_ms = sum(parts.values()) * 1e3
     return {"value": round(total_ms, 1), "unit": "ms/iter", "cores": max(cpu.num_threads(),
                                                                           torch.get_num_threads()),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"one step of the same workload, timed in parts and scaled: skinning (all), "
                       f"visibility {vs}/{V} views, FP64 shading fwd+bwd {len(idx)}/{n} Gaussians, "
                       f"FP32 projection+binning+compositing (all), FP64 compositing fwd+bwd "
@@ -310,24 +395,17 @@ def image_loss_measure(s, reps: int = 20):
             "gb_per_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4)}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
-              "multi-GPU path", file=sys.stderr)
-        sys.exit(2)
+def measure_form(args, s, d, precision: str, capacity=None):
+    """Time the step of one precision form: sizes the splat workspace to the
+    frame's duplicates, runs the warm-up, times exactly `args.steps` steps
+    (and the shading adjoint inside them with HIP events on its stream),
+    then the forward-only frame rates.  Returns (result, renderer, step)."""
     import numpy as np
     import torch
 
     from paper_2407_10707_amd import render, rga, synth
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    rga.lib()
-    s = synth.make_scene(args.config)
     cfg = s["cfg"]
-    d = render.upload(s)
-    R = render.Renderer(s, d, precision=args.precision)
+    R = render.Renderer(s, d, precision=precision, capacity=capacity)
     p = {k: d[k] for k in render.TRAINABLE}
     target = d["target"]
 
@@ -337,12 +415,14 @@ def main():
                                  .astype(np.float32)).cuda() for k in range(cfg.n_pose)]
         envs = [torch.as_tensor(synth.env_map(args.config, e).astype(np.float32)).cuda()
                 for e in range(cfg.n_env)]
+        env0 = p["env"]
+        skin0 = R.d["skin"]
     seq = {"frame": 0, "count": None}
 
     def step():
         if not args.sequence:
             count = R.visibility()
-            loss, grads = R.train_step(p, count, target)
+            loss, grads = R.train_step(p, count, target, check=False)
             return loss
         k, e = divmod(seq["frame"] % frames, cfg.n_env)
         seq["frame"] += 1
@@ -350,24 +430,14 @@ def main():
             R.d["skin"] = skins[k]
             seq["count"] = R.visibility()
         p["env"] = envs[e]
-        loss, grads = R.train_step(p, seq["count"], target)
+        loss, grads = R.train_step(p, seq["count"], target, check=False)
         return loss
 
     def fwd(with_vis, count=None):
         if with_vis:
             count = R.visibility()
-        image, _, _ = R.forward(p, count)
+        R.forward(p, count)
         return count
-
-    if args.copy_calibration:
-        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
-        # calibrate the counters of the path's kernels
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
 
     # size the splat workspace to the real duplicate count (every pose of a
     # sequence), then start the sequence again at frame 0
@@ -401,7 +471,7 @@ def main():
 
     # the shading adjoint is the kernel of the roofline entry; its BF16X3
     # form is timed under its own name
-    kernel = args.kernel or ("shade_bwd_bf16x3" if args.precision == "bf16x3" else "shade_bwd")
+    kernel = args.kernel or ("shade_bwd_bf16x3" if precision == "bf16x3" else "shade_bwd")
     rga.timing_reset()
     rga.timing_filter(None if args.all_kernels else kernel)
     rga.timing_enable(not args.graph)
@@ -480,6 +550,51 @@ def main():
                 "kernel": kernel, "kernel_ms": round(k_avg, 4),
                 "work": {"tested_pairs": wl["tested"], "live_pairs": wl["live"],
                          "flops_per_launch": flops}}
+    # this frame's image (pose 0, map 0) for the image-error report
+    image, _, _ = R.forward(p, count)
+    torch.cuda.synchronize()
+    if args.sequence:
+        R.d["skin"] = skin0
+        p["env"] = env0
+    out = {"ms_per_step": round(ms_step, 4), "render_fps": round(fps, 2),
+           "render_fps_no_vis": round(fps_nv, 2), "duplicates": D,
+           "sequence_frames": frames if args.sequence else None, "roofline": roof}
+    if per_kernel:
+        out["per_kernel_ms_per_step"] = per_kernel
+    return out, R, p, step, image.cpu().numpy()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2407_10707_amd import render, rga, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rga.lib()
+    s = synth.make_scene(args.config)
+    cfg = s["cfg"]
+    d = render.upload(s)
+    target = d["target"]
+
+    head, R, p, step, image = measure_form(args, s, d, args.precision)
+    images = {args.precision: image}
+    other = None
+    if not args.one_form:
+        # the other precision form of the shading contraction, same frame
+        oform = "bf16x3" if args.precision == "fp32" else "fp32"
+        okw = argparse.Namespace(**vars(args))
+        okw.kernel = None
+        okw.all_kernels = False
+        other, R2, _, _, oimage = measure_form(okw, s, d, oform, capacity=R.ws.capacity)
+        images[oform] = oimage
+        del R2
 
     # the same step with the image loss of the training section in place of
     # L1 (outside the timed region above; the metric keeps the L1 step)
@@ -501,7 +616,7 @@ def main():
 
     def train_iter(it):
         count = R.visibility()
-        _, grads = R.train_step(p, count, target)
+        _, grads = R.train_step(p, count, target, check=False)
         for k, (m1, m2) in mom.items():
             if k in grads:
                 rga.adam_step(p[k], grads[k], m1, m2, 1e-7, it)
@@ -539,10 +654,12 @@ def main():
               env=p["env"])
 
     def vertex_iter():
+        # the total loss of Sec. 3.3: the image loss plus the weighted
+        # regularisers, whose gradients the library adds to the image loss's
         count = R.visibility()
         image, _, ctx = M.forward(vv, count)
-        _, dimage = R.loss(image, target)
-        M.backward(vv, ctx, dimage)
+        loss, dimage = R.loss(image, target)
+        M.backward(vv, ctx, dimage, loss=loss)
 
     vertex_iter()
     R.ensure_capacity()
@@ -562,17 +679,20 @@ def main():
     img_loss = image_loss_measure(s)
 
     cpu = None
+    err = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(s)
+        if not args.sequence:
+            err = image_error(s, images)
 
     out = {
         "metric": METRIC,
-        "value": round(ms_step, 4),
+        "value": head["ms_per_step"],
         "unit": "ms/iter",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -583,20 +703,27 @@ def main():
                    "vis_views": cfg.hv * cfg.wv, "vis_res": cfg.vis_res,
                    "image": [s["height"], s["width"]], "precision": args.precision},
         "graph": bool(args.graph),
-        "render_fps": round(fps, 2),
-        "render_fps_no_vis": round(fps_nv, 2),
-        "duplicates": D,
-        "sequence_frames": frames if args.sequence else None,
-        "roofline": roof,
+        "render_fps": head["render_fps"],
+        "render_fps_no_vis": head["render_fps_no_vis"],
+        "duplicates": head["duplicates"],
+        "sequence_frames": head["sequence_frames"],
+        "roofline": head["roofline"],
         "cpu_baseline": cpu,
+    }
+    if other is not None:
+        oform = "bf16x3" if args.precision == "fp32" else "fp32"
+        out[oform] = {k: other[k] for k in ("ms_per_step", "render_fps", "render_fps_no_vis",
+                                            "roofline")}
+    out["image_error_vs_fp64"] = err
+    out.update({
         "knn": knn,
         "displacement_mlp": mlp,
         "image_loss": dict(img_loss, step_ms_with_image_loss=round(img_loss_step_ms, 4)),
         "training_iteration_ms": round(full_iter_ms, 4),
         "vertex_model_iteration_ms": round(vertex_iter_ms, 4),
-    }
-    if per_kernel:
-        out["per_kernel_ms_per_step"] = per_kernel
+    })
+    if "per_kernel_ms_per_step" in head:
+        out["per_kernel_ms_per_step"] = head["per_kernel_ms_per_step"]
     print(json.dumps(out), flush=True)
 
 

@@ -64,12 +64,16 @@ int rga_abi_version(void);
  * skin   [n_joints][3][4]  row-major [R_j | t_j], n_joints in 1..256
  * jidx   [4][n] int32, jw [4][n]: joint indices and weights (sum 1)
  * x      [3][n]  canonical positions;  nrm [3][n] canonical normals or NULL
+ * disp   [3][n]  displacement added to x before skinning (the paper's
+ *        "Gaussians are first added with position displacements", Sec. 1 /
+ *        Sec. 3.1), or NULL for none: the point skinned is the FP32 sum x + disp
  * x_out  [3][n]; n_out [3][n] or NULL (needs nrm); A_out [9][n] or NULL
  * The sums run in joint-slot order with fused multiply-adds, so the result is
- * reproducible bit for bit.                                                 */
+ * reproducible bit for bit.  The adjoint with respect to disp equals that
+ * with respect to x (lbs_skin_backward).                                    */
 int lbs_skin(void* stream, int n, int n_joints, const float* skin, const int32_t* jidx,
-             const float* jw, const float* x, const float* nrm, float* x_out, float* n_out,
-             float* A_out);
+             const float* jw, const float* x, const float* disp, const float* nrm, float* x_out,
+             float* n_out, float* A_out);
 
 /* Adjoint of lbs_skin with respect to x and nrm (the gradient with respect
  * to the skinning matrices is lbs_skin_pose_grad's):  dx = A^T dx_out,
@@ -83,9 +87,11 @@ int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
  * optimisation, Sec. 3.3, differentiates): dskin [n_joints][3][4] =
  * sum_i w_ij (dx_out_i (x_i, 1)^T + dn_out_i (nrm_i, 0)^T + (dA_i, 0)),
  * summed over the slots of each Gaussian that name joint j (dA [9][n], the
- * gradient with respect to A from splat_backward, may be NULL).  nrm and
- * dn_out are both set or both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints) bytes of device
- * memory (per-chunk sums, added in a fixed order).  Overwrites dskin.
+ * gradient with respect to A from splat_backward, may be NULL); x_i is the
+ * skinned point x + disp of lbs_skin (disp may be NULL).  nrm and dn_out are
+ * both set or both NULL.  ws: lbs_skin_pose_grad_workspace(n, n_joints)
+ * bytes of device memory (per-chunk sums, added in a fixed order).
+ * Overwrites dskin.
  * Errors: RGA_EINVAL (sizes, null pointers), RGA_ECAPACITY (ws too small). */
 /* The skinning matrices of an axis-angle pose (theta in R^72 for 24 joints,
  * Sec. 3.1 attributes; pose optimisation, Sec. 3.3).  Reading: forward
@@ -95,14 +101,17 @@ int lbs_skin_backward(void* stream, int n, int n_joints, const float* skin,
  * theta [n_joints][3], joints [n_joints][3] rest positions, parents
  * [n_joints] int32, skin [n_joints][3][4] (the layout of lbs_skin), all
  * device memory; n_joints in 1..256.  pose_to_skin_backward: dskin ->
- * dtheta [n_joints][3] (overwritten).  Errors: RGA_EINVAL.                */
+ * dtheta [n_joints][3], overwritten, or with accumulate != 0 added to what
+ * dtheta holds (theta also reaches the loss through the displacement
+ * network, whose adjoint writes its share first).  Errors: RGA_EINVAL.    */
 int pose_to_skin(void* stream, int n_joints, const float* theta, const float* joints,
                  const int32_t* parents, float* skin);
 int pose_to_skin_backward(void* stream, int n_joints, const float* theta, const float* joints,
-                          const int32_t* parents, const float* dskin, float* dtheta);
+                          const int32_t* parents, const float* dskin, float* dtheta,
+                          int accumulate);
 size_t lbs_skin_pose_grad_workspace(int n, int n_joints);
 int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx, const float* jw,
-                       const float* x, const float* nrm, const float* dx_out,
+                       const float* x, const float* disp, const float* nrm, const float* dx_out,
                        const float* dn_out, const float* dA, float* dskin, void* ws,
                        size_t ws_bytes);
 
@@ -216,7 +225,9 @@ int shade_gaussians_backward(void* stream, int n, const float* x, const float* n
  *            alive and unmodified until the backward pass.
  * image [3][H][W], T_final [H][W] out.
  * No host synchronisation: if D exceeds capacity the lists are truncated, the
- * image is wrong, and splat_read_count reports D > capacity (retry larger). */
+ * image and T_final are poisoned (every value NaN) and splat_read_count
+ * reports D > capacity (retry larger); a splat_backward on that workspace
+ * writes NaN gradients.                                                    */
 size_t splat_workspace_size(int n, int width, int height, int64_t capacity);
 int splat_forward(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
                   const float* quat, const float* log_s, const float* opac, const float* color,
@@ -333,7 +344,11 @@ int image_loss(void* stream, int C, int H, int W, const float* image, const floa
  * log_s [3][n]; all device memory, indices clamped to 0..nv-1.
  * terms device float[5]: the four unweighted sums and the weighted total.
  * dmat [5][nv], dxg [3][n], ddisp [3][nv], dlogs [3][n]: gradients of the
- * weighted total (written; a zero difference or length gives 0).
+ * weighted total (a zero difference or length gives 0), written, or with
+ * accumulate != 0 added to what they hold (so that the image loss's
+ * gradients and these meet inside the library: the total loss of Sec. 3.3).
+ * loss_accum: device float[1] to which the weighted total is added (e.g. the
+ * image loss), or NULL.
  * ws: regularisers_workspace(nv, n) bytes of device memory.
  * Errors: RGA_EINVAL (nv < 1, n < 0, kv or kg outside 1..nv, null pointer),
  * RGA_ECAPACITY (ws too small); nothing is launched then.                 */
@@ -342,7 +357,8 @@ int regularisers(void* stream, int nv, int n, int kv, int kg, const float* mat,
                  const int32_t* knn_v, const float* xg, const float* verts, const int32_t* vidx,
                  const float* disp, const float* log_s, float s0, float lam_smooth,
                  float lam_mdist, float lam_disp, float lam_scale, float* terms, float* dmat,
-                 float* dxg, float* ddisp, float* dlogs, void* ws, size_t ws_bytes);
+                 float* dxg, float* ddisp, float* dlogs, int accumulate, float* loss_accum,
+                 void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
  * Pose-dependent vertex displacement dx = d(x, theta) (Sec. 3.1, attribute

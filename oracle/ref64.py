@@ -164,10 +164,38 @@ def srgb_oetf(x):
 # Sec. 3.1, rendering equation: L_o = sum_k L^k A^k R v_g[k] max(0, w_i^k . n).
 # Sec. 3.2 / Eq. interpolate: v_g[k] = sum_j u_j count[vertex_j][view(k)] / K_v.
 # ---------------------------------------------------------------------------
+def bf16_round(x):
+    """Round to bfloat16 (8 significant bits, round to nearest even) by way
+    of FP32, as a GPU rounds an FP32 operand: returned in float64."""
+    return t64(x).to(torch.float32).to(torch.bfloat16).to(f64)
+
+
+def contract(W, E, operands: str = "exact"):
+    """The shading contraction sum_k W[g, k] E[k, c] of the rendering
+    equation.  ``operands`` emulates the operand precision of a matrix-core
+    form, with exact products and an FP64 sum: "exact" (FP64 operands),
+    "bf16" (both operands rounded to bfloat16), "bf16x3" (each operand
+    split into a bfloat16 high part and the bfloat16 of the FP32 remainder,
+    W E ~ W_hi E_hi + W_hi E_lo + W_lo E_hi; Henry, Tang and Heinecke,
+    ARITH 2019)."""
+    if operands == "exact":
+        return W @ E
+    W32, E32 = t64(W).to(torch.float32), t64(E).to(torch.float32)
+    Wh, Eh = bf16_round(W32), bf16_round(E32)
+    if operands == "bf16":
+        return Wh @ Eh
+    if operands == "bf16x3":
+        Wl = bf16_round(W32.to(f64) - Wh)
+        El = bf16_round(E32.to(f64) - Eh)
+        return Wh @ Eh + Wh @ El + Wl @ Eh
+    raise ValueError(operands)
+
+
 def shade(xp, npr, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env, cam_pos,
-          front, chunk: int = 4096):
+          front, chunk: int = 4096, operands: str = "exact"):
     """Returns (colour [3,n], L_o [3,n]) in float64.  ``front`` [n] (0/1) is the
-    FP32 back-face decision; non-front Gaussians get colour 0."""
+    FP32 back-face decision; non-front Gaussians get colour 0.  ``operands``
+    selects the emulated operand precision of the contraction (`contract`)."""
     xp, npr, albedo, rough, tint = (t64(v) for v in (xp, npr, albedo, rough, tint))
     n = xp.shape[1]
     dirs, solid = env_geometry(he, we)
@@ -200,8 +228,8 @@ def shade(xp, npr, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env
         k = (g + 1.0) ** 2 / 8.0
         spec = ggx_d(nh, alpha) * fresnel(oh) * smith_g1(ci_s, k) * smith_g1(co, k) / (4.0 * ci_s * co)
         wgt = torch.where(live, vis * ci_s, torch.zeros_like(ci))  # v * max(0, w.n)
-        diff_sum = wgt @ E                                         # [m,3]
-        spec_sum = (wgt * spec) @ E
+        diff_sum = contract(wgt, E, operands)                      # [m,3]
+        spec_sum = contract(wgt * spec, E, operands)
         Lo = albedo[:, s:e].T / math.pi * diff_sum + tint[s:e, None] * spec_sum
         Lo = torch.where(front[s:e, None], Lo, torch.zeros_like(Lo))
         outs.append(Lo)

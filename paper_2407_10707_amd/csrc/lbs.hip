@@ -13,14 +13,17 @@ constexpr int kBlock = 256;
 __global__ void __launch_bounds__(kBlock)
 lbs_fwd_kernel(int n, int J, const float* __restrict__ skin, const int32_t* __restrict__ jidx,
                const float* __restrict__ jw, const float* __restrict__ x,
-               const float* __restrict__ nrm, float* __restrict__ x_out,
-               float* __restrict__ n_out, float* __restrict__ A_out) {
+               const float* __restrict__ disp, const float* __restrict__ nrm,
+               float* __restrict__ x_out, float* __restrict__ n_out, float* __restrict__ A_out) {
   __shared__ float S[kMaxJoints * 12];
   for (int k = threadIdx.x; k < J * 12; k += blockDim.x) S[k] = skin[k];
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float p0 = x[i], p1 = x[n + i], p2 = x[2 * n + i];
+  // the optional displacement is added first (x + dx rounded to FP32)
+  const float p0 = disp ? x[i] + disp[i] : x[i];
+  const float p1 = disp ? x[n + i] + disp[n + i] : x[n + i];
+  const float p2 = disp ? x[2 * n + i] + disp[2 * n + i] : x[2 * n + i];
   float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
   float Aa[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -103,9 +106,10 @@ constexpr int kPoseChunk = 2048;
 
 __global__ void __launch_bounds__(kBlock)
 lbs_pose_grad_kernel(int n, const int32_t* __restrict__ jidx, const float* __restrict__ jw,
-                     const float* __restrict__ x, const float* __restrict__ nrm,
-                     const float* __restrict__ dxo, const float* __restrict__ dno,
-                     const float* __restrict__ dA, float* __restrict__ part) {
+                     const float* __restrict__ x, const float* __restrict__ disp,
+                     const float* __restrict__ nrm, const float* __restrict__ dxo,
+                     const float* __restrict__ dno, const float* __restrict__ dA,
+                     float* __restrict__ part) {
   __shared__ float red[12][kBlock];
   const int j = blockIdx.y, c = blockIdx.x;
   const int i0 = c * kPoseChunk, i1 = min(n, i0 + kPoseChunk);
@@ -118,7 +122,8 @@ lbs_pose_grad_kernel(int n, const int32_t* __restrict__ jidx, const float* __res
     for (int sl = 0; sl < 4; ++sl)
       if (jidx[(size_t)sl * n + i] == j) w += jw[(size_t)sl * n + i];
     if (w == 0.f) continue;
-    const float xv[3] = {x[i], x[n + i], x[2 * n + i]};
+    const float xv[3] = {disp ? x[i] + disp[i] : x[i], disp ? x[n + i] + disp[n + i] : x[n + i],
+                         disp ? x[2 * n + i] + disp[2 * n + i] : x[2 * n + i]};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       const float g = w * dxo[(size_t)r * n + i];
@@ -272,7 +277,7 @@ pose_skin_kernel(int J, const float* __restrict__ theta, const float* __restrict
 __global__ void __launch_bounds__(kBlock)
 pose_skin_bwd_kernel(int J, const float* __restrict__ theta, const float* __restrict__ joints,
                      const int32_t* __restrict__ parents, const float* __restrict__ dskin,
-                     float* __restrict__ dtheta) {
+                     float* __restrict__ dtheta, int accumulate) {
   __shared__ Chain ch;
   __shared__ float dG[kMaxJoints][9], dP[kMaxJoints][3], dR[kMaxJoints][9];
   forward_chain(J, theta, joints, parents, ch);
@@ -330,7 +335,8 @@ pose_skin_bwd_kernel(int J, const float* __restrict__ theta, const float* __rest
         dE = fmaf(D[q], E[q], dE);
         dS = fmaf(D[q], EK[q] + KE[q], dS);
       }
-      dtheta[3 * j + k] = ap * th[k] * dK + a * dE + bp * th[k] * dK2 + b * dS;
+      const float v = ap * th[k] * dK + a * dE + bp * th[k] * dK2 + b * dS;
+      dtheta[3 * j + k] = accumulate ? dtheta[3 * j + k] + v : v;
     }
   }
 }
@@ -351,14 +357,14 @@ extern "C" int pose_to_skin(void* stream, int n_joints, const float* theta, cons
 
 extern "C" int pose_to_skin_backward(void* stream, int n_joints, const float* theta,
                                      const float* joints, const int32_t* parents,
-                                     const float* dskin, float* dtheta) {
+                                     const float* dskin, float* dtheta, int accumulate) {
   if (n_joints < 1 || n_joints > kMaxJoints)
     return rga::fail(RGA_EINVAL, "pose_to_skin_backward: n_joints must be in 1..%d", kMaxJoints);
   if (!theta || !joints || !parents || !dskin || !dtheta)
     return rga::fail(RGA_EINVAL, "pose_to_skin_backward: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   RGA_LAUNCH("pose_skin_bwd", pose_skin_bwd_kernel, dim3(1), dim3(kBlock), 0, s, n_joints, theta,
-             joints, parents, dskin, dtheta);
+             joints, parents, dskin, dtheta, accumulate);
   RGA_CHECK_LAUNCH("pose_to_skin_backward");
   return RGA_OK;
 }
@@ -369,9 +375,9 @@ extern "C" size_t lbs_skin_pose_grad_workspace(int n, int n_joints) {
 }
 
 extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32_t* jidx,
-                                  const float* jw, const float* x, const float* nrm,
-                                  const float* dx_out, const float* dn_out, const float* dA,
-                                  float* dskin, void* ws, size_t ws_bytes) {
+                                  const float* jw, const float* x, const float* disp,
+                                  const float* nrm, const float* dx_out, const float* dn_out,
+                                  const float* dA, float* dskin, void* ws, size_t ws_bytes) {
   if (n < 0) return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n < 0");
   if (n_joints < 1 || n_joints > kMaxJoints)
     return rga::fail(RGA_EINVAL, "lbs_skin_pose_grad: n_joints must be in 1..%d", kMaxJoints);
@@ -385,7 +391,7 @@ extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32
   const int chunks = pose_chunks(n);
   float* part = static_cast<float*>(ws);
   RGA_LAUNCH("lbs_pose_grad", lbs_pose_grad_kernel, dim3(chunks, n_joints), dim3(kBlock), 0, s, n,
-             jidx, jw, x, nrm, dx_out, dn_out, dA, part);
+             jidx, jw, x, disp, nrm, dx_out, dn_out, dA, part);
   RGA_LAUNCH("lbs_pose_grad_final", lbs_pose_grad_final, dim3(rga::ceil_div(12 * n_joints, kBlock)),
              dim3(kBlock), 0, s, n_joints, chunks, part, dskin);
   RGA_CHECK_LAUNCH("lbs_skin_pose_grad");
@@ -393,8 +399,8 @@ extern "C" int lbs_skin_pose_grad(void* stream, int n, int n_joints, const int32
 }
 
 extern "C" int lbs_skin(void* stream, int n, int n_joints, const float* skin, const int32_t* jidx,
-                        const float* jw, const float* x, const float* nrm, float* x_out,
-                        float* n_out, float* A_out) {
+                        const float* jw, const float* x, const float* disp, const float* nrm,
+                        float* x_out, float* n_out, float* A_out) {
   if (n < 0) return rga::fail(RGA_EINVAL, "lbs_skin: n < 0");
   if (n_joints < 1 || n_joints > kMaxJoints)
     return rga::fail(RGA_EINVAL, "lbs_skin: n_joints must be in 1..%d", kMaxJoints);
@@ -403,7 +409,7 @@ extern "C" int lbs_skin(void* stream, int n, int n_joints, const float* skin, co
   if (n_out && !nrm) return rga::fail(RGA_EINVAL, "lbs_skin: n_out requires nrm");
   hipStream_t s = static_cast<hipStream_t>(stream);
   RGA_LAUNCH("lbs_fwd", lbs_fwd_kernel, dim3(rga::ceil_div(n, kBlock)), dim3(kBlock), 0, s, n,
-             n_joints, skin, jidx, jw, x, nrm, x_out, n_out, A_out);
+             n_joints, skin, jidx, jw, x, disp, nrm, x_out, n_out, A_out);
   RGA_CHECK_LAUNCH("lbs_skin");
   return RGA_OK;
 }

@@ -40,7 +40,7 @@ reg_zero_kernel(float* __restrict__ p, int count) {
 __global__ void __launch_bounds__(kBlock)
 reg_vertex_kernel(int nv, int kv, const float* __restrict__ mat, const int32_t* __restrict__ knn,
                   const float* __restrict__ disp, float ls, float ld, float* __restrict__ dmat,
-                  float* __restrict__ ddisp, float* __restrict__ part) {
+                  float* __restrict__ ddisp, float* __restrict__ part, int accumulate) {
   __shared__ float red[kBlock];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float sm = 0.f, dl = 0.f;
@@ -65,9 +65,9 @@ reg_vertex_kernel(int nv, int kv, const float* __restrict__ mat, const int32_t* 
     const float len = sqrtf(fmaf(z, z, fmaf(y, y, x * x)));
     dl = len;
     const float s = len > 0.f ? ld / len : 0.f;
-    ddisp[i] = s * x;
-    ddisp[nv + i] = s * y;
-    ddisp[2 * nv + i] = s * z;
+    ddisp[i] = accumulate ? ddisp[i] + s * x : s * x;
+    ddisp[nv + i] = accumulate ? ddisp[nv + i] + s * y : s * y;
+    ddisp[2 * nv + i] = accumulate ? ddisp[2 * nv + i] + s * z : s * z;
   }
   const float a = block_sum(sm, red);
   const float b = block_sum(dl, red);
@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(kBlock)
 reg_gauss_kernel(int n, int nv, int kg, const float* __restrict__ xg,
                  const float* __restrict__ verts, const int32_t* __restrict__ vidx,
                  const float* __restrict__ log_s, float s0, float lm, float lsc,
-                 float* __restrict__ dxg, float* __restrict__ dlogs, float* __restrict__ part) {
+                 float* __restrict__ dxg, float* __restrict__ dlogs, float* __restrict__ part,
+                 int accumulate) {
   __shared__ float red[kBlock];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   float md = 0.f, sc = 0.f;
@@ -100,15 +101,17 @@ reg_gauss_kernel(int n, int nv, int kg, const float* __restrict__ xg,
         gz = fmaf(s, dz, gz);
       }
     }
-    dxg[i] = gx;
-    dxg[n + i] = gy;
-    dxg[2 * n + i] = gz;
+    dxg[i] = accumulate ? dxg[i] + gx : gx;
+    dxg[n + i] = accumulate ? dxg[n + i] + gy : gy;
+    dxg[2 * n + i] = accumulate ? dxg[2 * n + i] + gz : gz;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float e = expf(log_s[(size_t)c * n + i]);
       const bool on = e > s0;
       sc += on ? e - s0 : 0.f;
-      dlogs[(size_t)c * n + i] = on ? lsc * e : 0.f;
+      const float gl = on ? lsc * e : 0.f;
+      float* o = dlogs + (size_t)c * n + i;
+      *o = accumulate ? *o + gl : gl;
     }
   }
   const float a = block_sum(md, red);
@@ -122,7 +125,8 @@ reg_gauss_kernel(int n, int nv, int kg, const float* __restrict__ xg,
 // terms: smooth, mdist, disp, scale, weighted total
 __global__ void __launch_bounds__(kBlock)
 reg_final_kernel(int nbv, int nbg, const float* __restrict__ pv, const float* __restrict__ pg,
-                 float ls, float lm, float ld, float lsc, float* __restrict__ terms) {
+                 float ls, float lm, float ld, float lsc, float* __restrict__ terms,
+                 float* __restrict__ loss_accum) {
   __shared__ float red[kBlock];
   float v[4] = {0.f, 0.f, 0.f, 0.f};
   for (int b = threadIdx.x; b < nbv; b += blockDim.x) {
@@ -139,7 +143,9 @@ reg_final_kernel(int nbv, int nbg, const float* __restrict__ pv, const float* __
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) terms[q] = t[q];
-    terms[4] = ls * t[0] + lm * t[1] + ld * t[2] + lsc * t[3];
+    const float tot = ls * t[0] + lm * t[1] + ld * t[2] + lsc * t[3];
+    terms[4] = tot;
+    if (loss_accum) *loss_accum += tot;
   }
 }
 
@@ -157,7 +163,7 @@ extern "C" int regularisers(void* stream, int nv, int n, int kv, int kg, const f
                             const int32_t* vidx, const float* disp, const float* log_s, float s0,
                             float lam_smooth, float lam_mdist, float lam_disp, float lam_scale,
                             float* terms, float* dmat, float* dxg, float* ddisp, float* dlogs,
-                            void* ws, size_t ws_bytes) {
+                            int accumulate, float* loss_accum, void* ws, size_t ws_bytes) {
   if (nv < 1 || n < 0 || kv < 1 || kg < 1 || kv > nv || kg > nv)
     return rga::fail(RGA_EINVAL, "regularisers: nv >= 1, n >= 0, 1 <= kv, kg <= nv");
   if (!mat || !knn_v || !verts || !disp || !terms || !dmat || !ddisp || !ws ||
@@ -169,13 +175,14 @@ extern "C" int regularisers(void* stream, int nv, int n, int kv, int kg, const f
   const int nbv = blocks(nv), nbg = blocks(n);
   float* pv = static_cast<float*>(ws);
   float* pg = pv + 2 * nbv;
-  RGA_LAUNCH("reg_zero", reg_zero_kernel, dim3(blocks(5 * nv)), dim3(kBlock), 0, s, dmat, 5 * nv);
+  if (!accumulate)
+    RGA_LAUNCH("reg_zero", reg_zero_kernel, dim3(blocks(5 * nv)), dim3(kBlock), 0, s, dmat, 5 * nv);
   RGA_LAUNCH("reg_vertex", reg_vertex_kernel, dim3(nbv), dim3(kBlock), 0, s, nv, kv, mat, knn_v,
-             disp, lam_smooth, lam_disp, dmat, ddisp, pv);
+             disp, lam_smooth, lam_disp, dmat, ddisp, pv, accumulate);
   RGA_LAUNCH("reg_gauss", reg_gauss_kernel, dim3(nbg), dim3(kBlock), 0, s, n, nv, kg, xg, verts,
-             vidx, log_s, s0, lam_mdist, lam_scale, dxg, dlogs, pg);
+             vidx, log_s, s0, lam_mdist, lam_scale, dxg, dlogs, pg, accumulate);
   RGA_LAUNCH("reg_final", reg_final_kernel, dim3(1), dim3(kBlock), 0, s, nbv, nbg, pv, pg,
-             lam_smooth, lam_mdist, lam_disp, lam_scale, terms);
+             lam_smooth, lam_mdist, lam_disp, lam_scale, terms, loss_accum);
   RGA_CHECK_LAUNCH("regularisers");
   return RGA_OK;
 }

@@ -869,7 +869,8 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 __global__ void __launch_bounds__(256)
 blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
                     float* __restrict__ cstate, int64_t max_items, float* __restrict__ image,
-                    float* __restrict__ Tfinal) {
+                    float* __restrict__ Tfinal, const int64_t* __restrict__ counters,
+                    int64_t capacity) {
   const int t = blockIdx.x;
   int px, py;
   tile_pixel(t, TX, px, py);
@@ -914,6 +915,16 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
     image[2 * HW + p] = C2;
     Tfinal[p] = Tin;
   }
+  // more duplicates than the workspace holds: the lists were truncated, so
+  // the frame is poisoned (NaN) rather than silently wrong
+  if (inside && counters[0] > capacity) {
+    const size_t p = (size_t)py * W + px, HW = (size_t)H * W;
+    const float nan = __builtin_nanf("");
+    image[p] = nan;
+    image[HW + p] = nan;
+    image[2 * HW + p] = nan;
+    Tfinal[p] = nan;
+  }
 }
 
 // Restart pass, one workgroup per work item after a tile's first, in
@@ -927,8 +938,9 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
                      const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                      const int64_t* __restrict__ counters, int64_t max_items,
                      const float* __restrict__ cstate, float* __restrict__ sstate,
-                     float* __restrict__ image, float* __restrict__ Tfinal) {
+                     float* __restrict__ image, float* __restrict__ Tfinal, int64_t capacity) {
   __shared__ float4 s0[kChunk], s1[kChunk], s2[kChunk];
+  if (counters[0] > capacity) return;     // truncated lists: the prefix pass poisoned the frame
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
   __syncthreads();                        // the previous item's records are done
@@ -1223,7 +1235,8 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
                       float* __restrict__ grad9, uint32_t* __restrict__ queue,
                       float* __restrict__ dx, float* __restrict__ dquat,
                       float* __restrict__ dlog_s, float* __restrict__ dopac,
-                      float* __restrict__ dcolor, float* __restrict__ dA) {
+                      float* __restrict__ dcolor, float* __restrict__ dA,
+                      const int64_t* __restrict__ counters, int64_t capacity) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) *queue = 0u;
   if (g >= n) return;
@@ -1233,6 +1246,18 @@ preprocess_bwd_kernel(int n, CamDev cam, const float* __restrict__ x, const floa
   for (int q = 0; q < 9; ++q) {
     gs[q] = grad9[(size_t)q * n + g];
     grad9[(size_t)q * n + g] = 0.f;
+  }
+  if (counters[0] > capacity) {
+    // the forward's lists were truncated: poison the gradients (NaN)
+    const float nan = __builtin_nanf("");
+    for (int k = 0; k < 3; ++k) dx[(size_t)k * n + g] = nan;
+    for (int k = 0; k < 4; ++k) dquat[(size_t)k * n + g] = nan;
+    for (int k = 0; k < 3; ++k) dlog_s[(size_t)k * n + g] = nan;
+    for (int k = 0; k < 3; ++k) dcolor[(size_t)k * n + g] = nan;
+    dopac[g] = nan;
+    if (dA)
+      for (int k = 0; k < 9; ++k) dA[(size_t)k * n + g] = nan;
+    return;
   }
   dopac[g] = gs[5];
   for (int k = 0; k < 3; ++k) dcolor[(size_t)k * n + g] = gs[6 + k];
@@ -1489,11 +1514,12 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
              at<uint32_t>(ws, L.sub_item), L.max_subs, at<float>(ws, L.cstate),
              at<float>(ws, L.sstate));
   RGA_LAUNCH("blend_prefix", blend_prefix_kernel, dim3(tiles), dim3(256), 0, s, W, H, L.tiles_x,
-             at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final);
+             at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final,
+             (const int64_t*)cnt, capacity);
   RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(g_restart), dim3(256), 0, s, W, H,
              L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
-             at<float>(ws, L.sstate), image, T_final);
+             at<float>(ws, L.sstate), image, T_final, capacity);
   RGA_CHECK_LAUNCH("splat_forward");
   return RGA_OK;
 }
@@ -1529,7 +1555,7 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
              grad9 + (size_t)5 * n, grad9 + (size_t)6 * n);
   RGA_LAUNCH("preprocess_bwd", preprocess_bwd_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s,
              n, cd, x, A, quat, log_s, opac, front, grad9, queue, dx, dquat, dlog_s, dopac, dcolor,
-             dA);
+             dA, (const int64_t*)at<int64_t>(ws, L.count), capacity);
   RGA_CHECK_LAUNCH("splat_backward");
   return RGA_OK;
 }

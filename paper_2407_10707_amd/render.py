@@ -52,6 +52,10 @@ class Renderer:
         self.l1_ws = None
         self.img_ws = None
         self.image_loss = False
+        # every splat_forward on self.ws overwrites the lists and blend state
+        # that the adjoint reads: a forward's context records the generation
+        # it was rendered in, and a backward of an older forward is refused
+        self.generation = 0
 
     # ------------------------------------------------------------------ per pose
     def visibility(self):
@@ -69,19 +73,25 @@ class Renderer:
         if D > self.ws.capacity:
             self.ws = rga.SplatWorkspace(self.n, self.cam.width, self.cam.height,
                                          int(D * 1.25) + 1024, self.d["pos"].device)
+            self.generation += 1
             return True
         return False
+
+    def _splat(self, *args):
+        self.generation += 1
+        return rga.splat_forward(self.cam, *args, self.ws)
 
     # ------------------------------------------------------------------ forward
     def forward(self, p: Dict[str, torch.Tensor], count: torch.Tensor):
         d, s = self.d, self.s
-        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"])
+        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
+                                 disp=p.get("disp"))
         color, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
                                            d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
                                            s["wv"], p["env"], self.cam_pos, self.precision)
-        image, T = rga.splat_forward(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], color,
-                                     front, self.ws)
-        ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count)
+        image, T = self._splat(xo, A, p["quat"], p["log_s"], p["opac"], color, front)
+        ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count,
+                   generation=self.generation, ws=self.ws)
         return image, T, ctx
 
     # ------------------------------------------------------------------ editing maps
@@ -94,19 +104,23 @@ class Renderer:
         if mode not in ("albedo", "normal"):
             raise ValueError("mode must be 'albedo' or 'normal'")
         d, s = self.d, self.s
-        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"])
+        xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
+                                 disp=p.get("disp"))
         _, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
                                        d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
                                        s["wv"], p["env"], self.cam_pos, self.precision)
         color = p["albedo"] if mode == "albedo" else no
-        image, _ = rga.splat_forward(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], color,
-                                     front, self.ws)
+        image, _ = self._splat(xo, A, p["quat"], p["log_s"], p["opac"], color, front)
         return image
 
     # ------------------------------------------------------------------ backward
     def backward(self, p: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor,
                  want_dA: bool = False):
         d, s = self.d, self.s
+        if ctx.get("generation") != self.generation or ctx.get("ws") is not self.ws:
+            raise rga.RgaError("splat workspace overwritten since this forward (another "
+                               "render on the same Renderer): run backward before the next "
+                               "forward, or render again")
         g = rga.splat_backward(self.cam, ctx["xo"], ctx["A"], p["quat"], p["log_s"], p["opac"],
                                ctx["color"], ctx["front"], self.ws, ctx["image"], dimage,
                                want_dA=want_dA)
@@ -133,9 +147,16 @@ class Renderer:
             return rga.image_loss(image, target, 0.2, ws=self.img_ws)
         return rga.l1_loss(image, target, ws=self.l1_ws)
 
-    def train_step(self, p, count, target):
-        """fwd + L1 loss + bwd; returns (loss [1] on device, grads)."""
+    def train_step(self, p, count, target, check: bool = True):
+        """fwd + loss + bwd; returns (loss [1] on device, grads).  With check
+        (the default) the duplicate count is read back after the forward
+        (one host synchronisation) and the frame re-rendered in a larger
+        workspace if it overflowed; without it nothing synchronises and an
+        overflowed frame yields NaN loss and gradients (the kernels poison
+        them), so a caller that skips the check still sees the failure."""
         image, _, ctx = self.forward(p, count)
+        if check and self.ensure_capacity():
+            image, _, ctx = self.forward(p, count)
         loss, dimage = self.loss(image, target)
         grads = self.backward(p, ctx, dimage)
         return loss, grads
@@ -159,7 +180,13 @@ class RenderFunction(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, dimage, dT):
-        g = ctx.renderer.backward(ctx.p, ctx.c, dimage.contiguous())
+        R = ctx.renderer
+        D = R.ws.count()          # synchronises
+        if D > R.ws.capacity:
+            raise rga.RgaError(f"splat workspace overflowed ({D} duplicates, capacity "
+                               f"{R.ws.capacity}): the forward image is invalid; call "
+                               "Renderer.ensure_capacity() and render again")
+        g = R.backward(ctx.p, ctx.c, dimage.contiguous())
         return (None, None, g["pos"], g["nrm"], g["quat"], g["log_s"], g["opac"], g["albedo"],
                 g["rough"], g["tint"], g["env"])
 
@@ -176,15 +203,23 @@ class VertexModel:
     kinematics).  Quaternion, scale, opacity and normal stay per Gaussian
     here.  forward / backward compose the library's entry points:
     knn -> displacement network -> interpolation -> pose_to_skin -> the
-    render path, and back through the same adjoints (the two routes of
-    theta, through the network and through the skinning, are added)."""
+    render path (the interpolated displacement is added to each Gaussian by
+    the skinning call), and back through the same adjoints: the two routes
+    of theta (through the network and through the skinning) meet in
+    pose_to_skin_backward, which adds its share to the network's; with
+    `regularise` the regularisers of Sec. 3.3 add their gradients to the
+    image loss's inside the library (the total loss of Sec. 3.3)."""
 
-    def __init__(self, R: Renderer, freqs, joints, parents):
+    LAMBDAS = (0.002, 0.1, 0.02, 10.0)     # smooth, mesh distance, displacement, scale
+    S0 = 0.005
+
+    def __init__(self, R: Renderer, freqs, joints, parents, regularise: bool = True):
         self.R = R
         self.index = rga.KnnIndex(R.d["verts"])
         self.net = rga.Displacement(R.d["verts"], freqs)
         self.joints = joints
         self.parents = parents
+        self.regularise = regularise
 
     def forward(self, v: Dict[str, torch.Tensor], count: torch.Tensor):
         """v: theta [24, 3], mlp [params], v_albedo [3, nv], v_rough [nv],
@@ -192,27 +227,39 @@ class VertexModel:
         R = self.R
         idx, w = rga.knn(self.index, v["pos"], 3)
         dxv = self.net.forward(v["theta"].reshape(-1), v["mlp"])
+        # vertex attributes [8][nv]: albedo (3), roughness, tint, displacement (3)
         attrs = torch.cat([v["v_albedo"], v["v_rough"][None], v["v_tint"][None], dxv])
         ag = rga.knn_interpolate(idx, w, attrs)
-        p = dict(pos=v["pos"] + ag[5:8], nrm=v["nrm"], quat=v["quat"], log_s=v["log_s"],
-                 opac=v["opac"], albedo=ag[0:3].contiguous(), rough=ag[3].contiguous(),
-                 tint=ag[4].contiguous(), env=v["env"])
+        p = dict(pos=v["pos"], disp=ag[5:8], nrm=v["nrm"], quat=v["quat"], log_s=v["log_s"],
+                 opac=v["opac"], albedo=ag[0:3], rough=ag[3], tint=ag[4], env=v["env"])
         R.d["skin"] = rga.pose_to_skin(v["theta"], self.joints, self.parents)
         image, T, ctx = R.forward(p, count)
-        ctx.update(idx=idx, w=w, p=p)
+        ctx.update(idx=idx, w=w, p=p, attrs=attrs)
         return image, T, ctx
 
-    def backward(self, v: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor):
+    def backward(self, v: Dict[str, torch.Tensor], ctx, dimage: torch.Tensor,
+                 loss: Optional[torch.Tensor] = None):
+        """Gradients of the image loss whose gradient is `dimage` plus, with
+        `regularise`, the weighted regularisers; `loss` (device float [1],
+        the image loss) then receives their weighted total, and ctx gets
+        the four unweighted terms and the total under "reg_terms"."""
         R = self.R
         p = ctx["p"]
         g = R.backward(p, ctx, dimage, want_dA=True)
         nv = int(R.d["verts"].shape[1])
         dg = torch.cat([g["albedo"], g["rough"][None], g["tint"][None], g["pos"]])
         dv = rga.knn_interpolate_backward(ctx["idx"], ctx["w"], dg, nv)
-        dmlp, dth_net = self.net.backward(dv[5:8].contiguous())
+        if self.regularise:
+            attrs = ctx["attrs"]
+            ctx["reg_terms"] = rga.regularisers(
+                attrs[0:5], R.d["knn_v"], v["pos"], R.d["verts"], ctx["idx"], attrs[5:8],
+                v["log_s"], s0=self.S0, lams=self.LAMBDAS,
+                accum=(dv[0:5], g["pos"], dv[5:8], g["log_s"]), loss_accum=loss)[0]
+        dmlp, dth = self.net.backward(dv[5:8])
         dskin = rga.lbs_skin_pose_grad(int(self.parents.numel()), R.d["jidx"], R.d["jw"], p["pos"],
-                                       g["posed_x"], p["nrm"], g["posed_n"], g["posed_A"])
-        dth = rga.pose_to_skin_backward(v["theta"], self.joints, self.parents, dskin)
-        return dict(theta=dth + dth_net.reshape(-1, 3), mlp=dmlp, v_albedo=dv[0:3],
-                    v_rough=dv[3], v_tint=dv[4], pos=g["pos"], nrm=g["nrm"], quat=g["quat"],
-                    log_s=g["log_s"], opac=g["opac"], env=g["env"])
+                                       g["posed_x"], p["nrm"], g["posed_n"], g["posed_A"],
+                                       disp=p["disp"])
+        rga.pose_to_skin_backward(v["theta"], self.joints, self.parents, dskin, dtheta_accum=dth)
+        return dict(theta=dth.reshape(-1, 3), mlp=dmlp, v_albedo=dv[0:3], v_rough=dv[3],
+                    v_tint=dv[4], pos=g["pos"], nrm=g["nrm"], quat=g["quat"], log_s=g["log_s"],
+                    opac=g["opac"], env=g["env"])

@@ -32,12 +32,13 @@ _SZ = C.c_size_t
 _SIGS = {
     "rga_last_error": (C.c_char_p, []),
     "rga_abi_version": (_I, []),
-    "lbs_skin": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbs_skin": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbs_skin_backward": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pose_to_skin": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
-    "pose_to_skin_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP]),
+    "pose_to_skin_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _I]),
     "lbs_skin_pose_grad_workspace": (_SZ, [_I, _I]),
-    "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
+    "lbs_skin_pose_grad": (_I, [_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
+                                _SZ]),
     "mesh_visibility_workspace": (_SZ, [_I, _I]),
     "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_shadowmap": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, C.c_float,
@@ -65,7 +66,7 @@ _SIGS = {
     "knn_interpolate_backward": (_I, [_VP, _I, _I, _VP, _VP, _I, _I, _VP, _VP]),
     "regularisers_workspace": (_SZ, [_I, _I]),
     "regularisers": (_I, [_VP, _I, _I, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP] +
-                     [C.c_float] * 5 + [_VP] * 6 + [_SZ]),
+                     [C.c_float] * 5 + [_VP] * 5 + [_I, _VP, _VP, _SZ]),
     "adam_step": (_I, [_VP, C.c_int64, _VP, _VP, _VP, _VP] + [C.c_float] * 4 + [_I]),
     "image_loss_workspace": (_SZ, [_I, _I, _I]),
     "image_loss": (_I, [_VP, _I, _I, _I, _VP, _VP, C.c_float, _VP, _VP, _VP, _SZ]),
@@ -164,7 +165,8 @@ def _u8(t, name, shape=None):
 
 
 # ----------------------------------------------------------------------------- LBS
-def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True):
+def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True, disp=None):
+    """Skinned positions (of x + disp when disp [3, n] is given), normals, A."""
     n = x.shape[1]
     J = skin.shape[0]
     _f32(skin, "skin", (J, 12))
@@ -173,11 +175,13 @@ def lbs_skin(skin, jidx, jw, x, nrm=None, want_A: bool = True):
     _f32(x, "x", (3, n))
     if nrm is not None:
         _f32(nrm, "nrm", (3, n))
+    if disp is not None:
+        _f32(disp, "disp", (3, n))
     xo = torch.empty_like(x)
     no = torch.empty_like(nrm) if nrm is not None else None
     Ao = torch.empty((9, n), dtype=torch.float32, device=x.device) if want_A else None
-    _check(lib().lbs_skin(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(x), _p(nrm), _p(xo),
-                          _p(no), _p(Ao)), "lbs_skin")
+    _check(lib().lbs_skin(_stream(), n, J, _p(skin), _p(jidx), _p(jw), _p(x), _p(disp), _p(nrm),
+                          _p(xo), _p(no), _p(Ao)), "lbs_skin")
     return xo, no, Ao
 
 
@@ -191,28 +195,39 @@ def pose_to_skin(theta, joints, parents):
     return skin
 
 
-def pose_to_skin_backward(theta, joints, parents, dskin):
-    """dskin [J, 12] -> dtheta [J, 3]."""
+def pose_to_skin_backward(theta, joints, parents, dskin, dtheta_accum=None):
+    """dskin [J, 12] -> dtheta [J, 3]; with dtheta_accum (J * 3 floats) the
+    gradient is added into it in place and it is returned."""
     theta, joints, parents = _f32(theta, "theta"), _f32(joints, "joints"), _i32(parents, "parents")
     dskin = _f32(dskin, "dskin")
     J = int(parents.numel())
-    dtheta = torch.empty((J, 3), dtype=torch.float32, device=theta.device)
+    if dtheta_accum is None:
+        dtheta = torch.empty((J, 3), dtype=torch.float32, device=theta.device)
+    else:
+        dtheta = _f32(dtheta_accum, "dtheta_accum")
+        if dtheta.numel() != 3 * J:
+            raise RgaError("dtheta_accum must hold 3 floats per joint")
     _check(lib().pose_to_skin_backward(_stream(), J, _p(theta), _p(joints), _p(parents),
-                                       _p(dskin), _p(dtheta)), "pose_to_skin_backward")
+                                       _p(dskin), _p(dtheta), int(dtheta_accum is not None)),
+           "pose_to_skin_backward")
     return dtheta
 
 
-def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None, dA=None):
-    """dskin [n_joints, 12]: the gradient w.r.t. the skinning matrices."""
+def lbs_skin_pose_grad(n_joints: int, jidx, jw, x, dx_out, nrm=None, dn_out=None, dA=None,
+                       disp=None):
+    """dskin [n_joints, 12]: the gradient w.r.t. the skinning matrices (of
+    the points x + disp when disp is given)."""
     n = int(x.shape[1])
     _f32(x, "x", (3, n))
     _f32(dx_out, "dx_out", (3, n))
+    if disp is not None:
+        _f32(disp, "disp", (3, n))
     dskin = torch.empty((n_joints, 12), dtype=torch.float32, device=x.device)
     nb = int(lib().lbs_skin_pose_grad_workspace(n, n_joints))
     ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
-    _check(lib().lbs_skin_pose_grad(_stream(), n, n_joints, _p(jidx), _p(jw), _p(x), _p(nrm),
-                                    _p(dx_out), _p(dn_out), _p(dA), _p(dskin), _p(ws), nb),
-           "lbs_skin_pose_grad")
+    _check(lib().lbs_skin_pose_grad(_stream(), n, n_joints, _p(jidx), _p(jw), _p(x), _p(disp),
+                                    _p(nrm), _p(dx_out), _p(dn_out), _p(dA), _p(dskin), _p(ws),
+                                    nb), "lbs_skin_pose_grad")
     return dskin
 
 
@@ -464,9 +479,12 @@ def image_loss(image, target, lam: float = 0.2, want_grad: bool = True, ws=None)
 
 
 def regularisers(mat, knn_v, xg, verts, vidx, disp, log_s, s0: float = 0.005,
-                 lams=(0.002, 0.1, 0.02, 10.0)):
+                 lams=(0.002, 0.1, 0.02, 10.0), accum=None, loss_accum=None):
     """(terms [5]: smooth, mdist, disp, scale, weighted total; gradients of
-    the total w.r.t. mat [5, nv], xg [3, n], disp [3, nv], log_s [3, n])."""
+    the total w.r.t. mat [5, nv], xg [3, n], disp [3, nv], log_s [3, n]).
+    With accum = (dmat, dxg, ddisp, dlogs) the gradients are added into those
+    tensors in place (and they are returned); with loss_accum (a device
+    float [1]) the weighted total is added to it."""
     mat, xg, verts = _f32(mat, "mat"), _f32(xg, "xg"), _f32(verts, "verts")
     disp, log_s = _f32(disp, "disp"), _f32(log_s, "log_s")
     knn_v, vidx = _i32(knn_v, "knn_v"), _i32(vidx, "vidx")
@@ -475,11 +493,20 @@ def regularisers(mat, knn_v, xg, verts, vidx, disp, log_s, s0: float = 0.005,
     nb = int(lib().regularisers_workspace(nv, n))
     ws = torch.empty(nb, dtype=torch.uint8, device=mat.device)
     terms = torch.empty(5, dtype=torch.float32, device=mat.device)
-    dmat, ddisp = torch.empty_like(mat), torch.empty_like(disp)
-    dxg, dlogs = torch.empty_like(xg), torch.empty_like(log_s)
+    if accum is None:
+        dmat, ddisp = torch.empty_like(mat), torch.empty_like(disp)
+        dxg, dlogs = torch.empty_like(xg), torch.empty_like(log_s)
+    else:
+        dmat, dxg, ddisp, dlogs = accum
+        for t, nm, like in ((dmat, "dmat", mat), (dxg, "dxg", xg), (ddisp, "ddisp", disp),
+                            (dlogs, "dlogs", log_s)):
+            _f32(t, nm, tuple(like.shape))
+    if loss_accum is not None:
+        _f32(loss_accum, "loss_accum", (1,))
     _check(lib().regularisers(_stream(), nv, n, kv, kg, _p(mat), _p(knn_v), _p(xg), _p(verts),
                               _p(vidx), _p(disp), _p(log_s), float(s0), *(float(v) for v in lams),
-                              _p(terms), _p(dmat), _p(dxg), _p(ddisp), _p(dlogs), _p(ws), nb),
+                              _p(terms), _p(dmat), _p(dxg), _p(ddisp), _p(dlogs),
+                              int(accum is not None), _p(loss_accum), _p(ws), nb),
            "regularisers")
     return terms, dmat, dxg, ddisp, dlogs
 

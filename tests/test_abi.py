@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_abi_version_and_error_string():
     L = rga.lib()
-    assert L.rga_abi_version() == 1
+    assert L.rga_abi_version() == 2
     assert isinstance(L.rga_last_error(), bytes)
 
 
@@ -55,9 +55,10 @@ def test_workspace_sizes_are_monotone():
 
 def test_argument_errors_are_reported_before_any_launch():
     L = rga.lib()
-    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None) == -1
+    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None, None) == -1
     assert "n_joints" in rga.last_error()
-    assert L.lbs_skin(None, 0, 24, None, None, None, None, None, None, None, None) == 0
+    assert L.lbs_skin(None, 0, 24, None, None, None, None, None, None, None, None, None) == 0
+    assert L.pose_to_skin_backward(None, 0, None, None, None, None, None, 1) == -1
     assert L.mesh_visibility(None, 10, 10, None, None, 8, None, 256, None, 19, None, None, None, 0) == -4
     assert "res" in rga.last_error()
     assert L.mesh_visibility(None, 10, 10, None, None, 8, None, 64, None, 18, None, None, None, 0) == -1
@@ -79,9 +80,9 @@ def test_argument_errors_are_reported_before_any_launch():
     assert L.knn_interpolate(None, 10, 33, None, None, 3, 5, None, None) == -1
     assert L.knn_interpolate_backward(None, 10, 3, None, None, 3, 5, None, None) == -1
     assert L.regularisers(None, 0, 10, 19, 3, *([None] * 7), 0.005, 0.002, 0.1, 0.02, 10.0,
-                          *([None] * 6), 0) == -1
+                          *([None] * 5), 0, None, None, 0) == -1
     assert L.regularisers(None, 10, 10, 19, 3, *([None] * 7), 0.005, 0.002, 0.1, 0.02, 10.0,
-                          *([None] * 6), 0) == -1
+                          *([None] * 5), 1, None, None, 0) == -1
     assert "kv" in rga.last_error()
     assert L.mesh_visibility_shadowmap(None, 10, 10, None, None, 8, None, 64, None, 19, -1.0,
                                        None, None, None, 0) == -1

@@ -136,7 +136,7 @@ def test_lbs_empty_and_errors():
                        torch.empty((4, 0), device="cuda"), x, None)
     assert out[0].shape == (3, 0)
     L = rga.lib()
-    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None) == -1
+    assert L.lbs_skin(None, 10, 0, None, None, None, None, None, None, None, None, None) == -1
     assert "n_joints" in rga.last_error()
 
 
@@ -379,14 +379,49 @@ def test_splat_empty_and_all_culled():
 
 
 def test_splat_capacity_overflow_is_reported():
+    """More duplicates than the workspace holds: D is reported, the image
+    and T_final are poisoned (NaN) and so are the adjoint's gradients."""
     s = scene(1)
     col = np.ones((3, s["n"]), np.float32)
     xo, Ao, front = _splat_case(s, col)
     cam = s["cam"]
     ws = rga.SplatWorkspace(s["n"], cam.width, cam.height, 16, "cuda")
-    rga.splat_forward(cam, dev(xo), dev(Ao), dev(s["quat"]), dev(s["log_s"]), dev(s["opac"]),
-                      dev(col), dev(front), ws)
+    args = (dev(xo), dev(Ao), dev(s["quat"]), dev(s["log_s"]), dev(s["opac"]), dev(col),
+            dev(front))
+    img, T = rga.splat_forward(cam, *args, ws)
     assert ws.count() > 16
+    assert torch.isnan(img).all() and torch.isnan(T).all()
+    g = rga.splat_backward(cam, *args, ws, img, torch.ones_like(img), want_dA=True)
+    for k in ("dx", "dquat", "dlog_s", "dopac", "dcolor", "dA"):
+        assert torch.isnan(g[k]).all(), k
+    # a large enough workspace on the same inputs is clean again
+    ws2 = rga.SplatWorkspace(s["n"], cam.width, cam.height, 64 * s["n"], "cuda")
+    img2, _ = rga.splat_forward(cam, *args, ws2)
+    assert torch.isfinite(img2).all()
+
+
+def test_renderer_refuses_stale_backward_and_overflow():
+    """A backward whose forward's splat state has been overwritten by a later
+    render on the same Renderer is refused; the autograd path raises on an
+    overflowed frame, and train_step re-renders it in a larger workspace."""
+    s = scene(1)
+    d = render.upload(s)
+    R = render.Renderer(s, d, capacity=64 * s["n"])
+    p = {k: d[k] for k in render.TRAINABLE}
+    count = R.visibility()
+    _, _, ctx1 = R.forward(p, count)
+    R.render_map(p, count, "albedo")
+    with pytest.raises(rga.RgaError, match="overwritten"):
+        R.backward(p, ctx1, torch.zeros(3, s["height"], s["width"], device="cuda"))
+    R2 = render.Renderer(s, d, capacity=16)
+    q = {k: v.clone().requires_grad_(True) for k, v in p.items()}
+    img, _ = render.render(R2, count, q)
+    with pytest.raises(rga.RgaError, match="overflowed"):
+        img.sum().backward()
+    R3 = render.Renderer(s, d, capacity=16)
+    loss, g = R3.train_step(p, count, d["target"])
+    assert R3.ws.capacity > 16 and torch.isfinite(loss).all()
+    assert all(torch.isfinite(t).all() for t in g.values())
 
 
 # ------------------------------------------------------------------ gradients

@@ -78,3 +78,33 @@ def test_regularisers_without_gaussians():
     assert t[1] == 0 and t[3] == 0
     assert abs(t[0] - float(ref[0])) <= 2e-6 * float(ref[0])
     assert abs(t[2] - float(ref[2])) <= 2e-6 * float(ref[2])
+
+
+def test_regularisers_accumulate_into_given_gradients_and_loss():
+    """With accumulation the gradients are added to what the buffers hold
+    (an image loss's, here seeded values) and the weighted total to a loss
+    value, inside the library: equal to the fresh call plus the given
+    values (one FP32 addition each)."""
+    from paper_2407_10707_amd import rga
+    s = scene(1)
+    nv, n = int(s["nv"]), int(s["n"])
+    rng = np.random.default_rng(23)
+    dv = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+    mat = dv(rng.random((5, nv)))
+    disp = dv(0.01 * rng.standard_normal((3, nv)))
+    args = (mat, torch.as_tensor(s["knn_v"]).cuda(), dv(s["pos"]), dv(s["verts"]),
+            torch.as_tensor(s["vidx"]).cuda(), disp, dv(s["log_s"]))
+    fresh = rga.regularisers(*args)
+    base = [dv(rng.standard_normal(t.shape)) for t in fresh[1:]]
+    acc = [b.clone() for b in base]
+    loss = dv([0.5])
+    out = rga.regularisers(*args, accum=tuple(acc), loss_accum=loss)
+    torch.cuda.synchronize()
+    assert torch.equal(out[0], fresh[0])
+    assert float(loss.cpu()[0]) == np.float32(0.5) + np.float32(float(fresh[0][4].cpu()))
+    for f, b, a in zip(fresh[1:], base, acc):
+        want = (f + b).cpu().numpy()
+        got = a.cpu().numpy()
+        # the smoothness gradient is summed with float atomics in another
+        # order when it starts from a non-zero value
+        assert np.all(np.abs(got - want) <= 1e-6 * np.abs(want) + 1e-6)

@@ -1,8 +1,10 @@
 """The paper's vertex parametrisation composed from the library's entry
 points (Sec. 3.1: materials and the displacement network's output on the
 canonical vertices, interpolated to each Gaussian over its K_g = 3 nearest
-vertices; skinning matrices from the pose theta) against the same
-composition of the FP64 oracle, differentiated by autograd.
+vertices; skinning matrices from the pose theta), with the total loss of
+Sec. 3.3 (an image term plus the four weighted regularisers, their
+gradients merged inside the library), against the same composition of the
+FP64 oracle, differentiated by autograd.
 
 The neighbour indices come from the oracle's FP32 brute force (bit-exact
 with the GPU search); the visibility counts and back-face flags, FP32
@@ -55,10 +57,17 @@ def test_vertex_model_gradients_match_fp64_oracle():
     _, _, cnt = helpers.oracle_visibility(s2)
     front = helpers.front_flags(s3)
     p = helpers.params64(s)
-    p.update(pos=pos64 + ag[5:8], albedo=ag[0:3], rough=ag[3], tint=ag[4])
+    ls64 = p["log_s"].detach().clone().requires_grad_(True)
+    p.update(pos=pos64 + ag[5:8], albedo=ag[0:3], rough=ag[3], tint=ag[4], log_s=ls64)
     img, _ = helpers.render64(dict(s, skin=skin64), p, cnt, front)
     wimg = np.random.default_rng(13).random(img.shape)
-    (img * torch.tensor(wimg)).sum().backward()
+    # the total loss of Sec. 3.3: an image term (here sum w . image) plus the
+    # weighted regularisers of the vertex materials, the Gaussians' mesh
+    # distance, the vertex displacements and the scales
+    reg = ref64.regularisers(attrs[0:5], s["knn_v"], pos64, s["verts"].astype(np.float64), idx,
+                             dxv, ls64)
+    total = (img * torch.tensor(wimg)).sum() + reg[4]
+    total.backward()
 
     # ---- GPU: the same composition through the C ABI
     d = render.upload(s)
@@ -71,10 +80,16 @@ def test_vertex_model_gradients_match_fp64_oracle():
              opac=d["opac"], env=d["env"])
     image, _, ctx = M.forward(v, dev(cnt))
     assert np.abs(image.cpu().numpy().reshape(3, -1) - img.detach().numpy()).max() < 2e-5
-    g = M.backward(v, ctx, dev(wimg.reshape(image.shape).astype(np.float32)))
+    loss = torch.full((1,), 0.25, device="cuda")
+    g = M.backward(v, ctx, dev(wimg.reshape(image.shape).astype(np.float32)), loss=loss)
     torch.cuda.synchronize()
+    terms = ctx["reg_terms"].cpu().numpy()
+    want = np.array([float(t) for t in reg])
+    print(f"[vertex-model]   regulariser terms {terms} vs {want}", flush=True)
+    assert np.all(np.abs(terms - want) <= 2e-6 * np.abs(want) + 1e-7)
+    assert abs(float(loss.cpu()[0]) - (0.25 + want[4])) <= 2e-6 * (0.25 + abs(want[4]))
     for name, ref in (("theta", th64), ("mlp", mlp64), ("v_albedo", alb64), ("v_rough", ro64),
-                      ("v_tint", ti64), ("pos", pos64)):
+                      ("v_tint", ti64), ("pos", pos64), ("log_s", ls64)):
         r = ref.grad.numpy()
         got = g[name].cpu().numpy().astype(np.float64).reshape(r.shape)
         helpers.check_grad(name, got, r, rtol=1e-4, tag="[vertex-model] ")

@@ -189,3 +189,50 @@ def test_texel_view_lies_in_its_view_cell(grid):
 def test_texel_view_identity_when_grids_coincide():
     for he, we in ((8, 16), (16, 32), (32, 64)):
         assert np.array_equal(ref64.texel_view(he, we, he, we).numpy(), np.arange(he * we))
+
+
+def test_bf16_rounding_and_operand_emulation():
+    """bfloat16 rounding (8 significant bits, ties to even) on hand-checked
+    values, and the emulated contraction forms: exact for operands that
+    bfloat16 holds exactly; for positive sums the plain bf16 form's relative
+    error is bounded by two roundings per product (2 * 2^-9 + 2^-18) and the
+    split hi + lo form's by its dropped lo.lo product and the rounding of the
+    lo parts (< 2^-15), and the split is far closer than the plain form."""
+    vals = torch.tensor([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -7, 3.0,
+                         -(1.0 + 2.0 ** -9), 2.0 ** -130], dtype=f64)
+    want = [1.0, 1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, 3.0, -1.0, 2.0 ** -130]
+    assert ref64.bf16_round(vals).tolist() == want
+    rng = np.random.default_rng(3)
+    Wi = torch.tensor(rng.integers(0, 64, (17, 40)), dtype=f64) / 8
+    Ei = torch.tensor(rng.integers(0, 64, (40, 3)), dtype=f64) * 4
+    for op in ("bf16", "bf16x3"):
+        assert torch.equal(ref64.contract(Wi, Ei, op), Wi @ Ei)
+    W = torch.tensor(rng.random((64, 512)))
+    E = torch.tensor(np.exp(rng.normal(-1, 1, (512, 3))))
+    ex = W @ E
+    e1 = ((ref64.contract(W, E, "bf16") - ex).abs() / ex).max().item()
+    e3 = ((ref64.contract(W, E, "bf16x3") - ex).abs() / ex).max().item()
+    assert e1 <= 2 * 2.0 ** -9 + 2.0 ** -18
+    assert e3 < 2.0 ** -15 and e3 < e1 / 50
+
+
+def test_bf16_shading_forms_against_exact():
+    """The shaded colours of a scene with each emulated operand precision:
+    plain bf16 loses several 1e-3 relative, the split form stays within
+    2e-5 (its dropped lo.lo product is about 2^-16 of each term)."""
+    from tests import helpers
+    from tests.conftest import scene
+    s = scene(1)
+    xo, no, _ = helpers.cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    _, _, cnt = helpers.oracle_visibility(s)
+    front = helpers.front_flags(s)
+    args = (ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"], s["vidx"], s["vw"],
+            cnt, s["kv"], s["he"], s["we"], s["hv"], s["wv"], s["env"],
+            s["cam"].centre.astype(np.float32).astype(np.float64), front)
+    ex, _ = ref64.shade(*args)
+    lit = ex > 1e-3
+    errs = {}
+    for op in ("bf16", "bf16x3"):
+        c, _ = ref64.shade(*args, operands=op)
+        errs[op] = ((c - ex).abs()[lit] / ex[lit]).max().item()
+    assert errs["bf16"] > 1e-3 and errs["bf16x3"] < 2e-5, errs

@@ -246,3 +246,38 @@ def knn(q, ref, k):
     d2 = np.empty((k, n), np.float32)
     lib().oracle_knn(C.c_int(n), _p(q), C.c_int(nr), _p(ref), C.c_int(k), _p(idx), _p(d2))
     return idx, d2
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """The k-th output (k >= 1) of SplitMix64 from state `seed`."""
+    L = lib()
+    L.oracle_splitmix64.restype = C.c_uint64
+    L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+    return int(L.oracle_splitmix64(C.c_uint64(seed), C.c_uint64(k)))
+
+
+def densify(sg, verts, faces, d0=1.0, p0=0.02, seed=0, cap=None):
+    """App. B, Alg. 1 (rga_oracle.c): sg [kg,n] K_g nearest vertices of each
+    Gaussian, verts [3,nv], faces [nf,3] -> dict(Dv [nv], df [nf], ng [nf],
+    n_added, x [3,min(n_added, cap)], face [min(n_added, cap)])."""
+    sg = _i(sg)
+    verts = _f(verts)
+    faces = _i(faces)
+    kg, n = sg.shape
+    nv, nf = verts.shape[1], faces.shape[0]
+    if cap is None:
+        cap = max(1, nf)
+    Dv = np.empty(nv, np.int32)
+    df = np.empty(nf, np.float32)
+    ng = np.empty(nf, np.int32)
+    x = np.zeros((3, cap), np.float32)
+    fo = np.zeros(cap, np.int32)
+    L = lib()
+    L.oracle_densify.restype = C.c_int64
+    L.oracle_densify.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                 C.c_void_p, C.c_double, C.c_double, C.c_uint64, C.c_int64] + \
+        [C.c_void_p] * 5
+    N = int(L.oracle_densify(n, kg, _p(sg), nv, _p(verts), nf, _p(faces), float(d0), float(p0),
+                             C.c_uint64(seed), cap, _p(Dv), _p(df), _p(ng), _p(x), _p(fo)))
+    m = min(N, cap)
+    return dict(Dv=Dv, df=df, ng=ng, n_added=N, x=x[:, :m].copy(), face=fo[:m].copy())

@@ -806,3 +806,87 @@ void oracle_knn(int n, const float* q, int nr, const float* ref, int k, int32_t*
     free(bi);
   }
 }
+
+/* ======================================================================== */
+/* App. B (Gaussian densification algorithm, Alg. 1): density-based
+ * densification.
+ *
+ * Random numbers: the k-th output (k >= 1) of SplitMix64 (Steele, Lea and
+ * Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014) from
+ * the state `seed`: the state advances by the golden-ratio increment and each
+ * output is the state passed through the mixing function.                   */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+/* Alg. 1, step by step:
+ *   D_v[k]  = number of Gaussians whose K_g nearest vertices S_g include k;
+ *   d_f[i]  = sum over the three vertices of triangle i of D_v, / (6 K_g)
+ *             (each vertex is taken to touch six triangles);
+ *   P[i]    = max(0, d0 - d_f[i]);  N' = sum(P) p0;
+ *   n_g     = multinomial counts of N' draws with probabilities P / sum(P);
+ *   every draw adds one Gaussian at a uniformly random point of its triangle.
+ * Readings: P is held exactly as an integer in units of 1 / (6 K_g 65536):
+ * Q[i] = max(0, round(d0 6 K_g 65536) - 65536 S[i]) with S[i] the vertex sum
+ * (exact for the paper's d0 = 1); N' = floor(sum(Q) p0 / (6 K_g 65536)) in
+ * double precision (the count is an integer); draw j (from 0) takes
+ * r = SplitMix64 output 3j + 1 and picks the triangle whose cumulative range
+ * of Q holds u = floor(r sum(Q) / 2^64); its point takes outputs 3j + 2 and
+ * 3j + 3 as u1, u2 = (output >> 40) 2^-24 and lands at barycentric
+ * (1 - s, s (1 - u2), s u2) with s = sqrt(u1) (the uniform-triangle map of
+ * Osada et al., 2002), x = fmaf(b2, v2, fmaf(b1, v1, b0 v0)) per coordinate
+ * in FP32.  New Gaussians are listed in draw order; only the first `cap`
+ * positions are written, the counts always cover every draw.
+ * sg [kg][n] int32, verts [3][nv], faces [nf][3]; outputs Dv [nv], df [nf],
+ * ng [nf], x_out [3][cap], f_out [cap]; returns N'.                        */
+int64_t oracle_densify(int n, int kg, const int32_t* sg, int nv, const float* verts, int nf,
+                       const int32_t* faces, double d0, double p0, uint64_t seed, int64_t cap,
+                       int32_t* Dv, float* df, int32_t* ng, float* x_out, int32_t* f_out) {
+  for (int v = 0; v < nv; ++v) Dv[v] = 0;
+  for (int i = 0; i < n; ++i)
+    for (int t = 0; t < kg; ++t) Dv[sg[(size_t)t * n + i]] += 1;
+  const int64_t unit = 6LL * kg * 65536LL;
+  const int64_t T = llround(d0 * (double)unit);
+  int64_t* C = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nf > 0 ? nf : 1));
+  int64_t total = 0;
+  for (int f = 0; f < nf; ++f) {
+    int64_t S = 0;
+    for (int c = 0; c < 3; ++c) S += Dv[faces[3 * f + c]];
+    df[f] = (float)((double)S / (double)(6 * kg));
+    int64_t q = T - 65536LL * S;
+    if (q < 0) q = 0;
+    total += q;
+    C[f] = total;              /* inclusive cumulative sum */
+    ng[f] = 0;
+  }
+  const int64_t N = total > 0 ? (int64_t)floor((double)total * p0 / (double)unit) : 0;
+  for (int64_t j = 0; j < N; ++j) {
+    const uint64_t r = oracle_splitmix64(seed, 3 * (uint64_t)j + 1);
+    const uint64_t u = (uint64_t)(((unsigned __int128)r * (uint64_t)total) >> 64);
+    /* first triangle whose inclusive cumulative sum exceeds u */
+    int lo = 0, hi = nf - 1;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (C[mid] > (int64_t)u) hi = mid; else lo = mid + 1;
+    }
+    const int f = lo;
+    ng[f] += 1;
+    if (j < cap) {
+      const float u1 = (float)(oracle_splitmix64(seed, 3 * (uint64_t)j + 2) >> 40) * 0x1p-24f;
+      const float u2 = (float)(oracle_splitmix64(seed, 3 * (uint64_t)j + 3) >> 40) * 0x1p-24f;
+      const float s = sqrtf(u1);
+      const float b0 = 1.f - s, b1 = s * (1.f - u2), b2 = s * u2;
+      const int a = faces[3 * f], b = faces[3 * f + 1], c = faces[3 * f + 2];
+      for (int k = 0; k < 3; ++k)
+        x_out[(size_t)k * cap + j] = fmaf(b2, verts[(size_t)k * nv + c],
+                                          fmaf(b1, verts[(size_t)k * nv + b],
+                                               b0 * verts[(size_t)k * nv + a]));
+      f_out[j] = f;
+    }
+  }
+  free(C);
+  return N;
+}

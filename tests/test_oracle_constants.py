@@ -81,3 +81,21 @@ def test_training_loss_and_network_constants():
     hidden = [s for s in ref64.MLP_SHAPES if s[0] == ref64.MLP_WIDTH]
     assert len(hidden) == c["mlp_layers"] and ref64.MLP_WIDTH == c["mlp_width"]
     assert ref64.MLP_POSE == c["pose_dim"] and ref64.MLP_SHAPES[0][1] == 2 * ref64.MLP_FREQS + 72
+
+
+def test_densification_defaults_are_the_printed_ones():
+    """App. B: d0 = 1, p0 = 0.02 are the oracle's defaults, and the density
+    of a triangle divides its vertex sum by 6 K_g (six triangles per vertex):
+    one Gaussian whose K_g = 3 nearest vertices are a lone triangle's gives
+    d_f = 3 / (6 3)."""
+    import inspect
+
+    from oracle import cpu
+    c = _constants()
+    sig = inspect.signature(cpu.densify)
+    assert sig.parameters["d0"].default == c["dens_d0"]
+    assert sig.parameters["p0"].default == c["dens_p0"]
+    verts = np.eye(3, dtype=np.float32)
+    faces = np.array([[0, 1, 2]], np.int32)
+    r = cpu.densify(np.array([[0], [1], [2]], np.int32), verts, faces)
+    assert r["df"][0] == np.float32(3 / (c["dens_incidence"] * c["knn_gaussian"]))

@@ -8,7 +8,8 @@
  *  - All array pointers are DEVICE pointers owned by the caller, except the
  *    camera struct and cam_pos, which live in host memory.  The library never
  *    allocates device memory and keeps no state between calls; scratch space
- *    is a caller-provided workspace whose size the *_workspace functions give.
+ *    is a caller-provided workspace whose size the *_workspace functions give
+ *    (one exception: mesh_visibility_noalloc uses a fixed array of its own).
  *  - Per-item arrays are structure-of-arrays planes: "[C][n]" means C
  *    contiguous planes of n float32 (or int32) values each.  Device pointers
  *    must be 16-byte aligned.
@@ -151,6 +152,21 @@ int mesh_visibility_shadowmap(void* stream, int nv, int nf, const float* verts,
                               const int32_t* faces, int V, const float* view_dirs, int res,
                               const int32_t* knn, int kv, float bias_px, uint32_t* raw_bits,
                               uint8_t* count, void* ws, size_t ws_bytes);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * visibility of mesh_visibility (same arguments without the workspace, same
+ * bit-exact outputs), its workspace taken from a fixed device array of the
+ * library, mesh_visibility_noalloc_limit() bytes (32 MiB) per GPU, held from
+ * the first call on that GPU until the process ends.  Sizes whose workspace
+ * (mesh_visibility_workspace(nv, V)) exceeds that limit return RGA_ECAPACITY
+ * before any launch.  Calls that overlap on one GPU (concurrent streams or
+ * host threads) share the array and race; serialise them.  Allocates
+ * nothing and calls no allocating routine.                                  */
+size_t mesh_visibility_noalloc_limit(void);
+int mesh_visibility_noalloc(void* stream, int nv, int nf, const float* verts,
+                            const int32_t* faces, int V, const float* view_dirs, int res,
+                            const int32_t* knn, int kv, uint32_t* raw_bits, uint8_t* count);
 
 /* ------------------------------------------------------------------------
  * Sec. 3.1, rendering equation, and App. A (BRDF): per-Gaussian shading

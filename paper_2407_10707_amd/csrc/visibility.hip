@@ -12,6 +12,8 @@
 //              of kv neighbours is a bitwise majority vote computed with a
 //              5-plane ripple counter (two passes), and the final pass
 //              expands the counter planes into count bytes [nv][V]
+#include <mutex>
+
 #include "common.h"
 
 namespace {
@@ -499,6 +501,62 @@ extern "C" int mesh_visibility(void* stream, int nv, int nf, const float* verts,
                                void* ws, size_t ws_bytes) {
   return visibility_impl(stream, nv, nf, verts, faces, V, view_dirs, res, knn, kv, raw_bits, count,
                          ws, ws_bytes, 0, 0.f);
+}
+
+namespace {
+
+// ---- the variant that allocates nothing ----------------------------------
+// Its workspace is this file-scope device array.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and is kept per device.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_for_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return rga::fail(RGA_EHIP, "mesh_visibility_noalloc: no current device");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return rga::fail(RGA_EHIP, "mesh_visibility_noalloc: hipGetSymbolAddress: %s",
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RGA_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mesh_visibility_noalloc_limit(void) { return kNoAllocBytes; }
+
+extern "C" int mesh_visibility_noalloc(void* stream, int nv, int nf, const float* verts,
+                                       const int32_t* faces, int V, const float* view_dirs,
+                                       int res, const int32_t* knn, int kv, uint32_t* raw_bits,
+                                       uint8_t* count) {
+  if (nv < 1 || nf < 0 || V < 1)
+    return rga::fail(RGA_EINVAL, "mesh_visibility_noalloc: nv >= 1, nf >= 0, V >= 1");
+  const size_t need = vis_layout(nv, V).total;
+  if (need > kNoAllocBytes)
+    return rga::fail(RGA_ECAPACITY,
+                     "mesh_visibility_noalloc: %d vertices x %d views need %zu B of scratch, "
+                     "above its %zu B",
+                     nv, V, need, kNoAllocBytes);
+  void* ws = nullptr;
+  const int rc = scratch_for_current_device(&ws);
+  if (rc != RGA_OK) return rc;
+  // every byte of the workspace that a kernel reads was written earlier in
+  // the same call, so nothing is cleared
+  return visibility_impl(stream, nv, nf, verts, faces, V, view_dirs, res, knn, kv, raw_bits, count,
+                         ws, kNoAllocBytes, 0, 0.f);
 }
 
 extern "C" int mesh_visibility_shadowmap(void* stream, int nv, int nf, const float* verts,

@@ -43,6 +43,8 @@ _SIGS = {
     "mesh_visibility": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP, _VP, _SZ]),
     "mesh_visibility_shadowmap": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, C.c_float,
                                        _VP, _VP, _VP, _SZ]),
+    "mesh_visibility_noalloc_limit": (_SZ, []),
+    "mesh_visibility_noalloc": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP]),
     "shade_gaussians": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _I,
                              _I, _VP, _VP, _I, _VP, _VP]),
     "shade_gaussians_workspace": (_SZ, [_I, _I, _I]),
@@ -269,6 +271,32 @@ def mesh_visibility(verts, faces, view_dirs, res: int, knn, want_raw: bool = Fal
                                                _p(view_dirs), res, _p(knn), kv,
                                                float(shadow_bias_px), _p(raw), _p(count), _p(ws),
                                                ws.numel()), "mesh_visibility_shadowmap")
+    return count, raw
+
+
+def mesh_visibility_noalloc(verts, faces, view_dirs, res: int, knn, want_raw: bool = False,
+                            count=None, raw=None):
+    """mesh_visibility through the entry point that allocates nothing on the
+    device (its workspace is the library's fixed array).  The outputs may be
+    passed in, so that the call itself allocates nothing either."""
+    nv = verts.shape[1]
+    nf = faces.shape[0]
+    V = view_dirs.shape[0]
+    kv = knn.shape[1]
+    _f32(verts, "verts", (3, nv))
+    _i32(faces, "faces", (nf, 3))
+    _f32(view_dirs, "view_dirs", (V, 3))
+    _i32(knn, "knn", (nv, kv))
+    if count is None:
+        count = torch.empty((nv, V), dtype=torch.uint8, device=verts.device)
+    _u8(count, "count", (nv, V))
+    if raw is None and want_raw:
+        raw = torch.empty((nv, (V + 31) // 32), dtype=torch.int32, device=verts.device)
+    if raw is not None:
+        _i32(raw, "raw", (nv, (V + 31) // 32))
+    _check(lib().mesh_visibility_noalloc(_stream(), nv, nf, _p(verts), _p(faces), V,
+                                         _p(view_dirs), res, _p(knn), kv, _p(raw), _p(count)),
+           "mesh_visibility_noalloc")
     return count, raw
 
 

@@ -395,6 +395,40 @@ def image_loss_measure(s, reps: int = 20):
             "gb_per_s": round(gbs, 1), "frac_hbm_peak": round(gbs / 8000.0, 4)}
 
 
+def densify_measure(s, d, reps: int = 20):
+    """Density-based densification (App. B, Alg. 1) over the workload's
+    Gaussians and mesh, outside the timed step (it runs every hundred
+    iterations): the paper's d0 = 1, p0 = 0.02, and a threshold at the
+    densities' 70th percentile with p0 = 0.5 (thousands of draws).  Kernel
+    times per call; algorithmic bytes: the K_g lists read (12 B per
+    Gaussian), per triangle its indices, three counts, d_f and the
+    cumulative weight (36 B), per draw about 40 B."""
+    import numpy as np
+    import torch
+    from paper_2407_10707_amd import rga
+    sg = torch.as_tensor(np.ascontiguousarray(s["vidx"])).cuda()
+    verts, faces = d["verts"], torch.as_tensor(np.ascontiguousarray(s["faces"])).cuda()
+    base = rga.densify(sg, verts, faces)
+    q70 = float(torch.quantile(base["df"].double(), 0.7))
+    out = {"gaussians": int(s["n"]), "triangles": int(s["nf"])}
+    for tag, d0, p0 in (("paper", 1.0, 0.02), ("q70", q70, 0.5)):
+        r = rga.densify(sg, verts, faces, d0=d0, p0=p0, seed=1, cap=1 << 16)
+        torch.cuda.synchronize()
+        rga.timing_reset()
+        rga.timing_filter(None)
+        rga.timing_enable(True)
+        for _ in range(reps):
+            rga.densify(sg, verts, faces, d0=d0, p0=p0, seed=1, cap=1 << 16, sync=False)
+        torch.cuda.synchronize()
+        rga.timing_enable(False)
+        ms = sum(rga.timing_read(nm)[0] for nm in ("densify_clear", "densify_count",
+                                                      "densify_faces", "densify_draw")) / reps
+        nbytes = 12 * int(s["n"]) + 36 * int(s["nf"]) + 40 * r["n_added"]
+        out[tag] = {"d0": round(d0, 4), "p0": p0, "added": r["n_added"], "ms": round(ms, 4),
+                    "gb_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    return out
+
+
 def measure_form(args, s, d, precision: str, capacity=None):
     """Time the step of one precision form: sizes the splat workspace to the
     frame's duplicates, runs the warm-up, times exactly `args.steps` steps
@@ -677,6 +711,7 @@ def main():
     knn = knn_measure(s, d)
     mlp = mlp_measure(d)
     img_loss = image_loss_measure(s)
+    dens = densify_measure(s, d)
 
     cpu = None
     err = None
@@ -719,6 +754,7 @@ def main():
         "knn": knn,
         "displacement_mlp": mlp,
         "image_loss": dict(img_loss, step_ms_with_image_loss=round(img_loss_step_ms, 4)),
+        "densify": dens,
         "training_iteration_ms": round(full_iter_ms, 4),
         "vertex_model_iteration_ms": round(vertex_iter_ms, 4),
     })

@@ -412,6 +412,38 @@ int mlp_backward(void* stream, int nv, const float* x, const float* freqs, const
                  float* dparams, float* dtheta);
 
 /* ------------------------------------------------------------------------
+ * App. B (Gaussian densification algorithm, Alg. 1): density-based
+ * densification.  D_v[k] counts the Gaussians whose K_g nearest vertices
+ * include vertex k; a triangle's density is the sum of its three vertices'
+ * counts over 6 K_g (each vertex taken to touch six triangles); triangles
+ * below the threshold d0 get the weight P = max(0, d0 - d_f); sum(P) p0
+ * Gaussians (rounded down) are drawn multinomially with probabilities
+ * P / sum(P), each at a uniform random point of its triangle.
+ * P is held exactly as the integer Q = max(0, round(d0 6 K_g 65536) - 65536 S)
+ * (S the vertex sum), so the draws are reproducible: draw j takes outputs
+ * 3j+1, 3j+2, 3j+3 of SplitMix64 seeded with `seed` (Steele, Lea and Flood,
+ * OOPSLA 2014); the first selects the triangle whose cumulative range of Q
+ * holds floor(r sum(Q) / 2^64), the other two (shifted right by 40, times
+ * 2^-24) give u1, u2 and the point with barycentric weights (1 - s,
+ * s (1 - u2), s u2), s = sqrt(u1), over the triangle's vertices in order.
+ * sg     [kg][n] int32 K_g nearest vertices of each Gaussian; kg in 1..64
+ * verts  [3][nv] vertex positions (the canonical mesh); faces [nf][3] int32
+ * d0, p0 the density threshold and the fraction added per call (the paper
+ *        uses 1 and 0.02), each in [0, 1e6]
+ * cap    room for new positions: draws j < cap write x_out[:, j] and
+ *        f_out[j] (draw order); every draw is counted in ng
+ * Outputs (device, overwritten): Dv [nv], df [nf] float, ng [nf],
+ * x_out [3][cap], f_out [cap], summary int64[2] = {sum(Q), N'} (N' may
+ * exceed cap; read it to size the next call).  ws: densify_workspace(nf)
+ * bytes.  Bit-exact against the oracle.  Errors: RGA_EINVAL (sizes, range,
+ * null pointers), RGA_ECAPACITY (ws too small); nothing is launched then. */
+size_t densify_workspace(int nf);
+int densify(void* stream, int n, int kg, const int32_t* sg, int nv, const float* verts, int nf,
+            const int32_t* faces, double d0, double p0, uint64_t seed, int64_t cap, int32_t* Dv,
+            float* df, int32_t* ng, float* x_out, int32_t* f_out, int64_t* summary, void* ws,
+            size_t ws_bytes);
+
+/* ------------------------------------------------------------------------
  * The optimiser of the training loop (the paper trains as 3DGS does; the
  * reading is Adam): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librga.so")
-SOURCES = ["api.cpp", "lbs.hip", "visibility.hip", "shade.hip", "splat.hip", "loss.hip", "knn.hip", "mlp.hip", "ssim.hip", "reg.hip", "optim.hip"]
+SOURCES = ["api.cpp", "lbs.hip", "visibility.hip", "shade.hip", "splat.hip", "loss.hip", "knn.hip", "mlp.hip", "ssim.hip", "reg.hip", "optim.hip", "densify.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

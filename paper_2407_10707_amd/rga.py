@@ -75,6 +75,9 @@ _SIGS = {
     "mlp_workspace": (_SZ, [_I]),
     "mlp_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     "mlp_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP, _VP]),
+    "densify_workspace": (_SZ, [_I]),
+    "densify": (_I, [_VP, _I, _I, _VP, _I, _VP, _I, _VP, C.c_double, C.c_double, C.c_uint64,
+                     _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
     "rga_timing_enable": (_I, [_I]),
     "rga_timing_reset": (_I, []),
     "rga_timing_filter": (_I, [C.c_char_p]),
@@ -547,6 +550,42 @@ def adam_step(param, grad, m, v, lr: float, step: int, beta1: float = 0.9,
     _check(lib().adam_step(_stream(), param.numel(), _p(param), _p(grad), _p(m), _p(v),
                            float(lr), float(beta1), float(beta2), float(eps), int(step)),
            "adam_step")
+
+
+def densify(sg, verts, faces, d0: float = 1.0, p0: float = 0.02, seed: int = 0,
+            cap: Optional[int] = None, sync: bool = True):
+    """Density-based densification (App. B, Alg. 1) on the device.
+    sg [kg, n] int32, verts [3, nv], faces [nf, 3] int32.  Returns a dict of
+    device tensors Dv [nv], df [nf], ng [nf], x [3, cap], face [cap],
+    summary int64 [2] = (sum(Q), N'); with sync, also n_added = N' (a host
+    read) and x / face cut to the draws that were written."""
+    kg, n = (int(sg.shape[0]), int(sg.shape[1])) if sg.dim() == 2 else (0, 0)
+    _i32(sg, "sg", (kg, n))
+    nv = int(verts.shape[1])
+    _f32(verts, "verts", (3, nv))
+    nf = int(faces.shape[0])
+    _i32(faces, "faces", (nf, 3))
+    if cap is None:
+        cap = max(1, nf)
+    devc = verts.device
+    Dv = torch.empty(nv, dtype=torch.int32, device=devc)
+    df = torch.empty(nf, dtype=torch.float32, device=devc)
+    ng = torch.empty(nf, dtype=torch.int32, device=devc)
+    x = torch.zeros((3, cap), dtype=torch.float32, device=devc)
+    fo = torch.zeros(cap, dtype=torch.int32, device=devc)
+    summary = torch.empty(2, dtype=torch.int64, device=devc)
+    need = int(lib().densify_workspace(nf))
+    ws = torch.empty(max(need, 16), dtype=torch.uint8, device=devc)
+    _check(lib().densify(_stream(), n, kg, _p(sg), nv, _p(verts), nf, _p(faces), float(d0),
+                         float(p0), C.c_uint64(int(seed) & (2**64 - 1)), int(cap), _p(Dv), _p(df),
+                         _p(ng), _p(x) if cap > 0 else None, _p(fo) if cap > 0 else None,
+                         _p(summary), _p(ws), ws.numel()), "densify")
+    out = dict(Dv=Dv, df=df, ng=ng, x=x, face=fo, summary=summary)
+    if sync:
+        N = int(summary[1].item())
+        m = min(N, cap)
+        out.update(n_added=N, x=x[:, :m], face=fo[:m])
+    return out
 
 
 MLP_PARAMS = 249603

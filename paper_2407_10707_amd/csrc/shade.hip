@@ -269,122 +269,243 @@ __device__ inline void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---- FP32 form: one wave per front-facing Gaussian ---------------------------
+// A wave owns the Gaussians first, first + stride, first + 2 stride, ...
+// (stride = number of waves in the grid).  It takes them 64 at a time: each
+// lane loads one Gaussian's position and normal and decides the back-face
+// rule; a back-facing Gaussian's outputs are written at once (it needs
+// nothing else, and its count rows are never copied), and a ballot gives
+// the front-facing ones, which the wave shades one after the other: per
+// chunk of 64 directions each lane tests its direction, a ballot compacts
+// the live ones into the wave's LDS ring, and whole waves of ring entries
+// go to the BRDF stage.  The next front Gaussian's count rows are copied
+// into the other half of an LDS double buffer, and its attributes loaded,
+// while the current one is shaded.
+
+// Per-lane plan of the count-row copies (depends only on the lane and V):
+// 16-byte piece q = lane + 64 i is byte 16 q of the three rows laid end to
+// end, i.e. row j = 16 q / V at offset 16 q - j V; packed as off << 2 | j
+// (j = 3: no piece).
 template <int NQ>
-__global__ void __launch_bounds__(kThreads)
+struct RowPlan {
+  int p[NQ];
+};
+
+template <int NQ>
+__device__ inline void row_plan(int V, int lane, RowPlan<NQ>& P) {
+  const int nq = 3 * V / 16;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int q = lane + 64 * i;
+    const int j = (16 * q) / V;
+    P.p[i] = q < nq ? ((16 * q - j * V) << 2) | j : 3;
+  }
+}
+
+template <class Plan>
+__device__ inline void rows_copy(const ShadeArgs& a, const Plan& P, const int* vidx,
+                                 uint8_t* lds) {
+  constexpr int NQ = sizeof(P.p) / sizeof(P.p[0]);
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const int j = P.p[i] & 3;
+    if (j != 3) {
+      const int vi = j == 0 ? vidx[0] : (j == 1 ? vidx[1] : vidx[2]);
+#if defined(__HIP_DEVICE_COMPILE__)   // a device builtin: the host pass only parses the body
+      __builtin_amdgcn_global_load_lds(a.count + (size_t)vi * a.V + (P.p[i] >> 2),
+                                       lds + 1024 * i, 16, 0, 0);
+#endif
+    }
+  }
+}
+
+// One lane's candidate Gaussian of a block: its index, the back-face rule
+// and, if it faces the camera, its three nearest vertices.
+struct Cand {
+  int g;
+  bool front;
+  int vidx[3];
+};
+
+// Load block bb of the wave's Gaussians (lane i: first + (64 bb + i) stride)
+// and decide the back-face rule (FP32, fixed order, as gauss_setup).
+__device__ inline void cand_load(const ShadeArgs& a, int first, int stride, int bb, int lane,
+                                 Cand& C) {
+  const int64_t idx = (int64_t)(64 * bb + lane) * stride + first;
+  const bool valid = idx < a.n;
+  C.g = valid ? (int)idx : -1;
+  C.front = false;
+  if (valid) {
+    const int n = a.n, g = C.g;
+    float x[3], m[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      x[c] = a.x[(size_t)c * n + g];
+      m[c] = a.nrm[(size_t)c * n + g];
+    }
+    const float w0 = a.cam[0] - x[0], w1 = a.cam[1] - x[1], w2 = a.cam[2] - x[2];
+    C.front = fmaf(m[2], w2, fmaf(m[1], w1, m[0] * w0)) > 0.f;
+    if (C.front) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) C.vidx[c] = rga::clampi(a.vidx[(size_t)c * n + g], 0, a.nv - 1);
+    }
+  }
+}
+
+// The front Gaussian held by lane j of the block: its index and vertices
+// from that lane, the other attributes loaded with a wave-uniform address
+// (scalar loads into scalar registers).
+__device__ inline int cand_take(const ShadeArgs& a, const Cand& C, int j, Attr& A) {
+  const int n = a.n;
+  const int g = __builtin_amdgcn_readlane(C.g, j);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    A.vidx[c] = __builtin_amdgcn_readlane(C.vidx[c], j);
+    A.x[c] = uni(a.x[(size_t)c * n + g]);
+    A.m[c] = uni(a.nrm[(size_t)c * n + g]);
+    A.alb[c] = uni(a.albedo[(size_t)c * n + g]);
+    A.vw[c] = uni(a.vw[(size_t)c * n + g]);
+  }
+  A.rough = uni(a.rough[g]);
+  A.tint = uni(a.tint[g]);
+  return g;
+}
+
+__device__ inline int wave_count(int n, int first, int stride) {
+  return first < n ? (n - 1 - first) / stride + 1 : 0;
+}
+
+// Walk the K directions of one Gaussian 64 at a time: lane = direction,
+// the live ones (n.w_k > 0 and visibility > 0) appended with their
+// visibility to the wave's ring; flush(k, v, on) on every whole wave of
+// ring entries as it fills and on the remainder.
+template <class Flush>
+__device__ inline void live_walk(const GaussCtx& G, const float* tab, int K, int V, int* qk,
+                                 float* qv, int lane, uint64_t lt, Flush&& flush) {
+  int head = 0, tail = 0;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const int k = k0 + lane;
+    const float v = k < K ? live_vis(G, tab, K, V, k) : 0.f;
+    const bool live = v > 0.f;
+    const uint64_t m = __ballot(live);
+    if (live) {
+      const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
+      qk[slot] = k;
+      qv[slot] = v;
+    }
+    tail += __popcll(m);
+    if (tail - head >= 64) {
+      wave_fence();
+      const int slot = (head + lane) & (kRing - 1);
+      flush(qk[slot], qv[slot], true);
+      head += 64;
+      wave_fence();
+    }
+  }
+  if (tail > head) {
+    wave_fence();
+    const int slot = (head + lane) & (kRing - 1);
+    flush(qk[slot], qv[slot], lane < tail - head);
+    wave_fence();
+  }
+}
+
+// (up to 512 views: three workgroups per CU, six waves per SIMD)
+template <int NQ>
+__global__ void __launch_bounds__(kThreads, NQ <= 2 ? 6 : 4)
 shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ front) {
   extern __shared__ __align__(16) float tab[];
   __shared__ int qk[kWaves][kRing];
   __shared__ float qv[kWaves][kRing];
-  build_table(a, tab);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int K = a.K, n = a.n, V = a.V;
   uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 8 * K) + (size_t)wave * 6 * V;
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const int stride = gridDim.x * kWaves;
-  int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
-  Attr A;
-  int cur = 0;
-  if (g < n) {
-    attr_load<true>(a, g, A);
-    rows_dma<NQ>(a, A, rows0, lane);
-  }
-  wait_all();
+  build_table(a, tab);
   __syncthreads();
-  // each Gaussian's outputs are stored when the next one starts, so the
-  // wait for the next row copies at the end of an iteration never waits on
-  // a store issued just before
-  int og = -1;
-  float o_col = 0.f;
-  uint8_t o_front = 0;
-  while (g < n) {
-    const int gn = g + stride;
-    uint8_t* rows = rows0 + cur * 3 * V;
-    if (og >= 0) {
-      if (lane < 3) color[(size_t)lane * n + og] = o_col;
-      if (lane == 0) front[og] = o_front;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  RowPlan<NQ> plan;
+  row_plan<NQ>(V, lane, plan);
+  const int stride = gridDim.x * kWaves;
+  const int first = blockIdx.x * kWaves + wave;
+  const int nblk = (wave_count(n, first, stride) + 63) / 64;
+  Cand C;
+  int b = -1;
+  uint64_t fm = 0ull;
+  // next block with a front-facing Gaussian; back-facing ones are finished here
+  auto advance = [&]() {
+    while (fm == 0ull && b + 1 < nblk) {
+      ++b;
+      cand_load(a, first, stride, b, lane, C);
+      if (C.g >= 0) {
+        front[C.g] = C.front ? 1 : 0;
+        if (!C.front) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) color[(size_t)c * n + C.g] = 0.f;
+        }
+      }
+      fm = __ballot(C.front);
     }
-    // fetch the next Gaussian's inputs while this one is shaded
+  };
+  advance();
+  if (fm == 0ull) return;
+  Attr A;
+  int g = cand_take(a, C, __builtin_ctzll(fm), A);
+  fm &= fm - 1;
+  rows_copy(a, plan, A.vidx, rows0);
+  wait_all();
+  int cur = 0;
+  int og = -1;   // each Gaussian's colour is stored when the next one starts
+  float o_col = 0.f;
+  for (;;) {
+    if (og >= 0 && lane < 3) color[(size_t)lane * n + og] = o_col;
+    // the next front-facing Gaussian: its rows and attributes are fetched
+    // while this one is shaded
+    advance();
+    const bool more = fm != 0ull;
     Attr An;
-    if (gn < n) {
-      attr_load<true>(a, gn, An);
-      rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
+    int gn = -1;
+    if (more) {
+      gn = cand_take(a, C, __builtin_ctzll(fm), An);
+      fm &= fm - 1;
+      rows_copy(a, plan, An.vidx, rows0 + (cur ^ 1) * 3 * V);
     }
     GaussCtx G;
-    gauss_setup<true>(a, A, rows, G);
-    og = g;
-    if (!G.front) {
-      o_col = 0.f;
-      o_front = 0;
-    } else {
-      float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
-      int head = 0, tail = 0;
-      for (int k0 = 0; k0 < K; k0 += 64) {
-        const int k = k0 + lane;
-        const float v = k < K ? live_vis(G, tab, K, V, k) : 0.f;
-        const bool live = v > 0.f;
-        const uint64_t m = __ballot(live);
-        if (live) {
-          const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
-          qk[wave][slot] = k;
-          qv[wave][slot] = v;
-        }
-        tail += __popcll(m);
-        if (tail - head >= 64) {
-          wave_fence();
-          const int slot = (head + lane) & (kRing - 1);
-          Pair P;
-          pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
-          sd0 = fmaf(P.Wd, P.E[0], sd0);
-          sd1 = fmaf(P.Wd, P.E[1], sd1);
-          sd2 = fmaf(P.Wd, P.E[2], sd2);
-          ss0 = fmaf(P.Ws, P.E[0], ss0);
-          ss1 = fmaf(P.Ws, P.E[1], ss1);
-          ss2 = fmaf(P.Ws, P.E[2], ss2);
-          head += 64;
-          wave_fence();
-        }
+    gauss_setup<true>(a, A, rows0 + cur * 3 * V, G);
+    float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
+    live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on) {
+      if (on) {
+        Pair P;
+        pair_eval(G, tab, K, k, v, P);
+        sd0 = fmaf(P.Wd, P.E[0], sd0);
+        sd1 = fmaf(P.Wd, P.E[1], sd1);
+        sd2 = fmaf(P.Wd, P.E[2], sd2);
+        ss0 = fmaf(P.Ws, P.E[0], ss0);
+        ss1 = fmaf(P.Ws, P.E[1], ss1);
+        ss2 = fmaf(P.Ws, P.E[2], ss2);
       }
-      if (tail > head) {
-        wave_fence();
-        if (lane < tail - head) {
-          const int slot = (head + lane) & (kRing - 1);
-          Pair P;
-          pair_eval(G, tab, K, qk[wave][slot], qv[wave][slot], P);
-          sd0 = fmaf(P.Wd, P.E[0], sd0);
-          sd1 = fmaf(P.Wd, P.E[1], sd1);
-          sd2 = fmaf(P.Wd, P.E[2], sd2);
-          ss0 = fmaf(P.Ws, P.E[0], ss0);
-          ss1 = fmaf(P.Ws, P.E[1], ss1);
-          ss2 = fmaf(P.Ws, P.E[2], ss2);
-        }
-        wave_fence();
-      }
-      sd0 = rga::wave_sum(sd0);
-      sd1 = rga::wave_sum(sd1);
-      sd2 = rga::wave_sum(sd2);
-      ss0 = rga::wave_sum(ss0);
-      ss1 = rga::wave_sum(ss1);
-      ss2 = rga::wave_sum(ss2);
-      if (lane < 3) {
-        const float sd = lane == 0 ? sd0 : (lane == 1 ? sd1 : sd2);
-        const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
-        const float alb = lane == 0 ? A.alb[0] : (lane == 1 ? A.alb[1] : A.alb[2]);
-        const float Lo = alb * (1.f / kPi) * sd + A.tint * ss;
-        o_col = srgb(Lo);
-      }
-      o_front = 1;
+    });
+    sd0 = rga::wave_sum(sd0);
+    sd1 = rga::wave_sum(sd1);
+    sd2 = rga::wave_sum(sd2);
+    ss0 = rga::wave_sum(ss0);
+    ss1 = rga::wave_sum(ss1);
+    ss2 = rga::wave_sum(ss2);
+    if (lane < 3) {
+      const float sd = lane == 0 ? sd0 : (lane == 1 ? sd1 : sd2);
+      const float ss = lane == 0 ? ss0 : (lane == 1 ? ss1 : ss2);
+      const float alb = lane == 0 ? A.alb[0] : (lane == 1 ? A.alb[1] : A.alb[2]);
+      o_col = srgb(alb * (1.f / kPi) * sd + A.tint * ss);
     }
+    og = g;
     wait_all();
     wave_fence();
-    if (gn < n) A = An;
-    cur ^= 1;
+    if (!more) break;
+    A = An;
     g = gn;
+    cur ^= 1;
   }
-  if (og >= 0) {
-    if (lane < 3) color[(size_t)lane * n + og] = o_col;
-    if (lane == 0) front[og] = o_front;
-  }
+  if (lane < 3) color[(size_t)lane * n + og] = o_col;
 }
 
 // ---- BF16X3 form: the contraction on MFMA -----------------------------------
@@ -782,8 +903,10 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) out[i] = denv_lds[i];
 }
 
+// (up to 512 views: two workgroups per CU, four waves per SIMD, at most
+// 128 VGPRs)
 template <int NQ>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads, NQ <= 2 ? 4 : 2)
 shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __restrict__ dcolor,
                  float* __restrict__ dx, float* __restrict__ dn, float* __restrict__ dalbedo,
                  float* __restrict__ drough, float* __restrict__ dtint,
@@ -800,62 +923,74 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
                                         (size_t)kWaves * 6 * V) + wave * 48;
   build_table(a, tab);
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  const int stride = gridDim.x * kWaves;
-  int g = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wave);
-  // Lane c < 3 handles channel c of the per-Gaussian inputs and outputs.
-  // The colour and its gradient are fetched one Gaussian ahead, dx when the
-  // Gaussian starts, and each Gaussian's outputs are stored when the next
-  // one starts, so that the wait for the next Gaussian's row copies at the
-  // end of an iteration never waits on a load or store issued just before.
-  const int ch = min(lane, 2);
-  Attr A;
-  int cur = 0;
-  float pcol = 0.f, pdc = 0.f;
-  if (g < n) {
-    attr_load<false>(a, g, A);
-    rows_dma<NQ>(a, A, rows0, lane);
-    pcol = color[(size_t)ch * n + g];
-    pdc = dcolor[(size_t)ch * n + g];
-  }
-  wait_all();
   __syncthreads();
-  int og = -1;                                  // Gaussian whose outputs are pending
-  float o_dn = 0.f, o_dalb = 0.f, o_dx = 0.f, o_rough = 0.f, o_tint = 0.f;
-  while (g < n) {
-    const int gn = g + stride;
-    uint8_t* rows = rows0 + cur * 3 * V;
-    if (og >= 0) {
-      if (lane < 3) {
-        dn[(size_t)lane * n + og] = o_dn;
-        dalbedo[(size_t)lane * n + og] = o_dalb;
-        dx[(size_t)lane * n + og] = o_dx;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  RowPlan<NQ> plan;
+  row_plan<NQ>(V, lane, plan);
+  const int stride = gridDim.x * kWaves;
+  const int first = blockIdx.x * kWaves + wave;
+  const int nblk = (wave_count(n, first, stride) + 63) / 64;
+  // Lane c < 3 handles channel c of the per-Gaussian inputs and outputs.
+  const int ch = min(lane, 2);
+  Cand C;
+  int b = -1;
+  uint64_t fm = 0ull;
+  // next block with a front-facing Gaussian; a back-facing one gets zero
+  // gradients (dx, accumulated, is left as it is)
+  auto advance = [&]() {
+    while (fm == 0ull && b + 1 < nblk) {
+      ++b;
+      cand_load(a, first, stride, b, lane, C);
+      if (C.g >= 0 && !C.front) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          dn[(size_t)c * n + C.g] = 0.f;
+          dalbedo[(size_t)c * n + C.g] = 0.f;
+        }
+        drough[C.g] = 0.f;
+        dtint[C.g] = 0.f;
       }
-      if (lane == 0) {
-        drough[og] = o_rough;
-        dtint[og] = o_tint;
+      fm = __ballot(C.front);
+    }
+  };
+  advance();
+  if (fm != 0ull) {
+    Attr A;
+    int g = cand_take(a, C, __builtin_ctzll(fm), A);
+    fm &= fm - 1;
+    rows_copy(a, plan, A.vidx, rows0);
+    float pcol = color[(size_t)ch * n + g], pdc = dcolor[(size_t)ch * n + g];
+    wait_all();
+    int cur = 0;
+    int og = -1;   // Gaussian whose outputs are pending
+    float o_dn = 0.f, o_dalb = 0.f, o_dx = 0.f, o_rough = 0.f, o_tint = 0.f;
+    for (;;) {
+      if (og >= 0) {
+        if (lane < 3) {
+          dn[(size_t)lane * n + og] = o_dn;
+          dalbedo[(size_t)lane * n + og] = o_dalb;
+          dx[(size_t)lane * n + og] = o_dx;
+        }
+        if (lane == 0) {
+          drough[og] = o_rough;
+          dtint[og] = o_tint;
+        }
       }
-    }
-    const float col = pcol, dcol = pdc;
-    const float dx_in = dx[(size_t)ch * n + g];
-    // fetch the next Gaussian's inputs while this one is shaded
-    Attr An;
-    if (gn < n) {
-      attr_load<false>(a, gn, An);
-      rows_dma<NQ>(a, An, rows0 + (cur ^ 1) * 3 * V, lane);
-      pcol = color[(size_t)ch * n + gn];
-      pdc = dcolor[(size_t)ch * n + gn];
-    }
-    GaussCtx G;
-    gauss_setup<false>(a, A, rows, G);
-    og = g;
-    if (!G.front) {
-      o_dn = 0.f;
-      o_dalb = 0.f;
-      o_dx = dx_in;
-      o_rough = 0.f;
-      o_tint = 0.f;
-    } else {
+      const float col = pcol, dcol = pdc;
+      const float dx_in = dx[(size_t)ch * n + g];
+      advance();
+      const bool more = fm != 0ull;
+      Attr An;
+      int gn = -1;
+      if (more) {
+        gn = cand_take(a, C, __builtin_ctzll(fm), An);
+        fm &= fm - 1;
+        rows_copy(a, plan, An.vidx, rows0 + (cur ^ 1) * 3 * V);
+        pcol = color[(size_t)ch * n + gn];
+        pdc = dcolor[(size_t)ch * n + gn];
+      }
+      GaussCtx G;
+      gauss_setup<true>(a, A, rows0 + cur * 3 * V, G);
       // dL/dL_o: lane c < 3 takes channel c, every lane reads the three
       float dLo[3], aop[3], qd[3];
       {
@@ -871,34 +1006,9 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
       }
       const float tint = A.tint;
       BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
-      int head = 0, tail = 0;
-      for (int k0 = 0; k0 < K; k0 += 64) {
-        const int k = k0 + lane;
-        const float v = k < K ? live_vis(G, tab, K, V, k) : 0.f;
-        const bool live = v > 0.f;
-        const uint64_t m = __ballot(live);
-        if (live) {
-          const int slot = (tail + __popcll(m & lt)) & (kRing - 1);
-          qk[wave][slot] = k;
-          qv[wave][slot] = v;
-        }
-        tail += __popcll(m);
-        if (tail - head >= 64) {
-          wave_fence();
-          const int slot = (head + lane) & (kRing - 1);
-          pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
-          head += 64;
-          wave_fence();
-        }
-      }
-      if (tail > head) {
-        wave_fence();
-        if (lane < tail - head) {
-          const int slot = (head + lane) & (kRing - 1);
-          pair_bwd(G, tab, denv_lds, K, qk[wave][slot], qv[wave][slot], qd, dLo, tint, aop, acc);
-        }
-        wave_fence();
-      }
+      live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on) {
+        if (on) pair_bwd(G, tab, denv_lds, K, k, v, qd, dLo, tint, aop, acc);
+      });
       // per-Gaussian sums: DPP row sums (lane 15 of each row), the four row
       // totals through the wave's LDS slot, then every lane reads the twelve
       float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
@@ -935,14 +1045,14 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
         o_rough = r[7];
         o_tint = r[11];
       }
+      og = g;
+      wait_all();
+      wave_fence();
+      if (!more) break;
+      A = An;
+      g = gn;
+      cur ^= 1;
     }
-    wait_all();
-    wave_fence();
-    if (gn < n) A = An;
-    cur ^= 1;
-    g = gn;
-  }
-  if (og >= 0) {
     if (lane < 3) {
       dn[(size_t)lane * n + og] = o_dn;
       dalbedo[(size_t)lane * n + og] = o_dalb;
@@ -992,34 +1102,62 @@ denv_reduce_kernel(int K, int he, int we, int parts, const float* __restrict__ p
   }
 }
 
+template <int NQ>
+void set_lds_limits_nq() {
+  const void* ks[] = {reinterpret_cast<const void*>(shade_fwd_kernel<NQ>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<NQ>)};
+  for (const void* k : ks) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
+}
+
 void set_lds_limits() {
   static bool done = false;
   if (done) return;
-  const void* ks[] = {reinterpret_cast<const void*>(shade_fwd_kernel<1>),
-                      reinterpret_cast<const void*>(shade_fwd_kernel<2>),
-                      reinterpret_cast<const void*>(shade_fwd_kernel<3>),
-                      reinterpret_cast<const void*>(shade_fwd_kernel<6>),
-                      reinterpret_cast<const void*>(shade_bwd_kernel<1>),
-                      reinterpret_cast<const void*>(shade_bwd_kernel<2>),
-                      reinterpret_cast<const void*>(shade_bwd_kernel<3>),
-                      reinterpret_cast<const void*>(shade_bwd_kernel<6>)};
-  for (const void* k : ks) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  set_lds_limits_nq<2>();
+  set_lds_limits_nq<6>();
   done = true;
 }
 
-int grid_for(int n, size_t lds) {
+// LDS of the FP32 kernels (dynamic part): the direction table (8 K floats;
+// the adjoint adds 3 K for the environment gradient and 48 floats per wave
+// for its sums) and each wave's double buffer of three count rows; the two
+// rings (k, visibility) are static, 8 KB.
+inline size_t fp32_lds(int K, int V, bool adjoint) {
+  size_t b = (size_t)(adjoint ? 11 : 8) * K * sizeof(float) + (size_t)kWaves * 6 * V;
+  if (adjoint) b += (size_t)kWaves * 48 * sizeof(float);
+  return b;
+}
+
+// Persistent grid: as many workgroups as the device holds at once (every
+// workgroup resident, so the static division of the Gaussians over the
+// waves is also the division of the work), from the occupancy of the exact
+// kernel at its LDS size; never more than one wave per Gaussian.
+int grid_for(const void* kernel, int n, size_t lds) {
   set_lds_limits();
   static int ncu = 0;
   if (ncu == 0) {
     int dev = 0;
-    hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu <= 0)
       ncu = 256;
   }
-  const int per_cu = lds <= 20 * 1024 ? 4 : (lds <= 40 * 1024 ? 3 : (lds <= 76 * 1024 ? 2 : 1));
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kThreads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
   int grid = ncu * per_cu;
   const int need = (int)rga::ceil_div(n, kWaves);
   return grid < need ? grid : (need > 0 ? need : 1);
+}
+
+// The FP32 kernel instance for the number of 1024-byte pieces of a
+// Gaussian's three count rows.
+const void* fp32_kernel(bool adjoint, int nq) {
+  if (nq <= 2)
+    return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<2>)
+                   : reinterpret_cast<const void*>(shade_fwd_kernel<2>);
+  return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<6>)
+                 : reinterpret_cast<const void*>(shade_fwd_kernel<6>);
 }
 
 int check_args(const char* fn, int n, const float* x, const float* nrm, const float* albedo,
@@ -1113,18 +1251,19 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     RGA_CHECK_LAUNCH("shade_gaussians");
     return RGA_OK;
   }
-  const size_t lds = (size_t)8 * a.K * sizeof(float) + (size_t)kWaves * 6 * a.V;
-  if (lds > 160 * 1024)
+  const size_t lds = fp32_lds(a.K, a.V, false);
+  if (lds > 152 * 1024)
     return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: %d directions and %d views need %zu B of LDS",
                      a.K, a.V, lds);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nq = (int)rga::ceil_div(3 * a.V, 1024);
-  const dim3 grid(grid_for(n, lds));
-  switch (nq) {
-    case 1: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<1>, grid, dim3(kThreads), lds, s, a, color, front); break;
-    case 2: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<2>, grid, dim3(kThreads), lds, s, a, color, front); break;
-    case 3: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<3>, grid, dim3(kThreads), lds, s, a, color, front); break;
-    default: RGA_LAUNCH("shade_fwd", shade_fwd_kernel<6>, grid, dim3(kThreads), lds, s, a, color, front); break;
+  const void* kern = fp32_kernel(false, nq);
+  const dim3 grid(grid_for(kern, n, lds));
+  {
+    rga::TimedLaunch tl("shade_fwd", s);
+    void* args[] = {&a, &color, &front};
+    if (hipLaunchKernel(kern, grid, dim3(kThreads), args, lds, s) != hipSuccess)
+      return rga::fail(RGA_EHIP, "shade_gaussians: launch failed");
   }
   RGA_CHECK_LAUNCH("shade_gaussians");
   return RGA_OK;
@@ -1190,28 +1329,23 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     RGA_CHECK_LAUNCH("shade_gaussians_backward");
     return RGA_OK;
   }
-  const size_t lds = (size_t)11 * a.K * sizeof(float) + (size_t)kWaves * (6 * a.V + 48 * 4);
-  if (lds > 160 * 1024)
+  const size_t lds = fp32_lds(a.K, a.V, true);
+  if (lds > 152 * 1024)
     return rga::fail(RGA_EUNSUPPORTED,
                      "shade_gaussians_backward: %d directions and %d views need %zu B of LDS", a.K,
                      a.V, lds);
-  const int grid = grid_for(n, lds);
+  const int nq = (int)rga::ceil_div(3 * a.V, 1024);
+  const void* kern = fp32_kernel(true, nq);
+  const int grid = grid_for(kern, n, lds);
   if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
     return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");
   hipStream_t s = static_cast<hipStream_t>(stream);
   float* part = static_cast<float*>(ws);
   if (n > 0) {
-    const int nq = (int)rga::ceil_div(3 * a.V, 1024);
-#define RGA_SHADE_BWD(NQV)                                                                    \
-  RGA_LAUNCH("shade_bwd", shade_bwd_kernel<NQV>, dim3(grid), dim3(kThreads), lds, s, a, color, \
-             dcolor, dx, dn, dalbedo, drough, dtint, part)
-    switch (nq) {
-      case 1: RGA_SHADE_BWD(1); break;
-      case 2: RGA_SHADE_BWD(2); break;
-      case 3: RGA_SHADE_BWD(3); break;
-      default: RGA_SHADE_BWD(6); break;
-    }
-#undef RGA_SHADE_BWD
+    rga::TimedLaunch tl("shade_bwd", s);
+    void* args[] = {&a, &color, &dcolor, &dx, &dn, &dalbedo, &drough, &dtint, &part};
+    if (hipLaunchKernel(kern, dim3(grid), dim3(kThreads), args, lds, s) != hipSuccess)
+      return rga::fail(RGA_EHIP, "shade_gaussians_backward: launch failed");
   }
   RGA_LAUNCH("shade_denv", denv_reduce_kernel, dim3(rga::ceil_div(3 * a.K, 64)), dim3(1024), 0, s,
              a.K, he, we, n > 0 ? grid : 0, part, denv);

@@ -1,0 +1,116 @@
+"""Shading and its adjoint (Sec. 3.1 rendering equation, App. A BRDF)
+through the C ABI on every kind of view grid the kernels distinguish: one
+texel per view, two texels per view along the azimuth, and any other grid
+(views coarser in both angles, or four texels per view), with one, two and
+four passes of 512 directions.  Colours against the FP64 oracle
+(|d| <= 1e-5 |ref| + 1e-7, back-face flags bit-exact); the gradients of
+L = sum w . colour with respect to position, normal, albedo, roughness,
+tint and environment against autograd of the FP64 oracle, per element
+(|g - g64| <= rtol |g64| + 1e-3 RMS(g64)) and per tensor (relative L2
+<= 1e-4; the split bf16 form 1e-3 per element).  A colour channel within
+the form's error of the transfer curve's breakpoint is given no weight in L
+(the adjoint's slope jumps there, and the two sides may take either
+branch); their number is printed."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cpu, ref64
+from paper_2407_10707_amd import rga, synth
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+# (he, we, hv, wv): one texel per view, two per view, and other grids
+GRIDS = [(4, 8, 4, 8), (4, 16, 4, 8), (8, 16, 4, 8), (8, 16, 8, 4), (8, 32, 4, 16),
+         (16, 32, 16, 32), (16, 32, 16, 16), (32, 32, 32, 32), (32, 64, 32, 32)]
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+_CASES = {}
+
+
+def _case(grid):
+    if grid not in _CASES:
+        he, we, hv, wv = grid
+        s = synth.micro_scene(31, 300, 40, 48, he=he, we=we, hv=hv, wv=wv)
+        xo, no, _ = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+        _, _, cnt = helpers.oracle_visibility(s)
+        campos = s["cam"].centre.astype(np.float32)
+        front = cpu.front_f32(xo, no, campos)
+        _CASES[grid] = (s, xo, no, cnt, campos, front)
+    return _CASES[grid]
+
+
+def _supported(grid, precision):
+    he, we, hv, wv = grid
+    if precision == "fp32":
+        return True
+    return (he * we) % 32 == 0 and hv == he and we in (wv, 2 * wv)
+
+
+def _args(s, xo, no, cnt):
+    return (dev(xo), dev(no), dev(s["albedo"]), dev(s["rough"]), dev(s["tint"]), dev(s["vidx"]),
+            dev(s["vw"]), dev(cnt), s["kv"], s["he"], s["we"], s["hv"], s["wv"], dev(s["env"]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("grid", GRIDS)
+def test_shading_on_view_grids(grid, precision):
+    if not _supported(grid, precision):
+        pytest.skip("the split bf16 form needs one or two texels per view")
+    print(f"[shade grid] {grid} {precision}", flush=True)
+    s, xo, no, cnt, campos, front = _case(grid)
+    col, fr = rga.shade_gaussians(*_args(s, xo, no, cnt), campos, precision=precision)
+    assert np.array_equal(host(fr), front)
+    ecol, _ = ref64.shade(ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"],
+                          s["vidx"], s["vw"], cnt, s["kv"], s["he"], s["we"], s["hv"], s["wv"],
+                          s["env"], campos.astype(np.float64), front)
+    ecol = ecol.numpy()
+    rt, at = (1e-5, 1e-7) if precision == "fp32" else (1e-4, 1e-6)
+    err = np.abs(host(col) - ecol)
+    assert np.all(err <= rt * np.abs(ecol) + at), float((err / (rt * np.abs(ecol) + at)).max())
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("grid", GRIDS)
+def test_shading_adjoint_on_view_grids(grid, precision):
+    if not _supported(grid, precision):
+        pytest.skip("the split bf16 form needs one or two texels per view")
+    print(f"[shade adjoint grid] {grid} {precision}", flush=True)
+    s, xo, no, cnt, campos, front = _case(grid)
+    rng = np.random.default_rng(7)
+    w = rng.uniform(-1.0, 1.0, (3, s["n"])).astype(np.float32)
+    rt = 1e-5 if precision == "fp32" else 1e-4
+    # the transfer curve's slope jumps at its breakpoint (colour 0.04045):
+    # a channel whose colour lies within the form's error of it may take
+    # either branch of the adjoint on the two sides, so it gets no weight
+    ecol0, _ = ref64.shade(ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"],
+                           s["vidx"], s["vw"], cnt, s["kv"], s["he"], s["we"], s["hv"], s["wv"],
+                           s["env"], campos.astype(np.float64), front)
+    kink = np.abs(ecol0.numpy() - 0.04045) <= 2 * rt * 0.04045
+    w[kink] = 0.0
+    print(f"  {int(kink.sum())} channel(s) at the transfer curve's breakpoint left out", flush=True)
+    args = _args(s, xo, no, cnt)
+    col, fr = rga.shade_gaussians(*args, campos, precision=precision)
+    g = rga.shade_gaussians_backward(*args, campos, col, fr, dev(w), precision=precision)
+    leaves = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True)
+              for k, v in (("x", xo), ("n", no), ("albedo", s["albedo"]), ("rough", s["rough"]),
+                           ("tint", s["tint"]), ("env", s["env"]))}
+    ecol, _ = ref64.shade(leaves["x"], leaves["n"], leaves["albedo"], leaves["rough"],
+                          leaves["tint"], s["vidx"], s["vw"], cnt, s["kv"], s["he"], s["we"],
+                          s["hv"], s["wv"], leaves["env"], campos.astype(np.float64), front)
+    (ecol * torch.tensor(w.astype(np.float64))).sum().backward()
+    rtol = 1e-4 if precision == "fp32" else 1e-3
+    for gk, lk in (("dx", "x"), ("dn", "n"), ("dalbedo", "albedo"), ("drough", "rough"),
+                   ("dtint", "tint"), ("denv", "env")):
+        helpers.check_grad(lk, host(g[gk]), leaves[lk].grad.numpy(), rtol=rtol)

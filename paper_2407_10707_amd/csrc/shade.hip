@@ -919,8 +919,6 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 11 * K) + (size_t)wave * 6 * V;
-  float* red = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(tab + 11 * K) +
-                                        (size_t)kWaves * 6 * V) + wave * 48;
   build_table(a, tab);
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
   __syncthreads();
@@ -1009,22 +1007,23 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
       live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on) {
         if (on) pair_bwd(G, tab, denv_lds, K, k, v, qd, dLo, tint, aop, acc);
       });
-      // per-Gaussian sums: DPP row sums (lane 15 of each row), the four row
-      // totals through the wave's LDS slot, then every lane reads the twelve
-      float r[12] = {acc.gn[0], acc.gn[1], acc.gn[2], acc.gw[0], acc.gw[1], acc.gw[2],
-                     acc.gco, acc.gga, acc.sd[0], acc.sd[1], acc.sd[2], acc.ts};
-      rga::row_sums(r);
-      if ((lane & 15) == 15) {
+      // per-Gaussian sums of the twelve partials over the wave: four slots
+      // of three values (lane swaps and DPP), slot s summed in row s
+      float r[12];
+      {
+        float v4[4][3] = {{acc.gn[0], acc.gn[1], acc.gn[2]},
+                          {acc.gw[0], acc.gw[1], acc.gw[2]},
+                          {acc.gco, acc.gga, acc.ts},
+                          {acc.sd[0], acc.sd[1], acc.sd[2]}};
+        float o3[3];
+        rga::slot_sums4<3>(v4, o3);
 #pragma unroll
-        for (int q = 0; q < 12; ++q) red[(lane >> 4) * 12 + q] = r[q];
+        for (int sl = 0; sl < 4; ++sl)
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            r[3 * sl + q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(o3[q]), 16 * sl));
       }
-      wave_fence();
-      const float tot = lane < 12 ? (red[lane] + red[12 + lane]) + (red[24 + lane] + red[36 + lane])
-                                  : 0.f;
-#pragma unroll
-      for (int q = 0; q < 12; ++q)
-        r[q] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), q));
-      wave_fence();
+      // r: gn 0-2, gw 3-5, gco 6, gga 7, ts 8, sd 9-11
       {
         const float gco = r[6];
         float gn3[3] = {r[0] + gco * G.wo[0], r[1] + gco * G.wo[1], r[2] + gco * G.wo[2]};
@@ -1037,13 +1036,13 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
         const float nnc = c == 0 ? G.nn[0] : (c == 1 ? G.nn[1] : G.nn[2]);
         const float woc = c == 0 ? G.wo[0] : (c == 1 ? G.wo[1] : G.wo[2]);
         const float dlc = c == 0 ? dLo[0] : (c == 1 ? dLo[1] : dLo[2]);
-        const float sdc = c == 0 ? r[8] : (c == 1 ? r[9] : r[10]);
+        const float sdc = c == 0 ? r[9] : (c == 1 ? r[10] : r[11]);
         o_dn = (gnc - nnc * pn) * G.inn;
         // w_o = (cam - x)/|cam - x|: d/dx = -(I - w w^T)/|cam - x|
         o_dx = dx_in - (gwc - woc * pw) * G.iwo;
         o_dalb = dlc * sdc * (1.f / kPi);
         o_rough = r[7];
-        o_tint = r[11];
+        o_tint = r[8];
       }
       og = g;
       wait_all();
@@ -1117,14 +1116,12 @@ void set_lds_limits() {
   done = true;
 }
 
-// LDS of the FP32 kernels (dynamic part): the direction table (8 K floats;
-// the adjoint adds 3 K for the environment gradient and 48 floats per wave
-// for its sums) and each wave's double buffer of three count rows; the two
-// rings (k, visibility) are static, 8 KB.
+// LDS of the FP32 kernels (dynamic part, at most 152 KB beside the static
+// 8 KB of the rings): the direction table (8 K floats; the adjoint adds 3 K
+// for the environment gradient) and each wave's double buffer of three
+// count rows (6 V bytes).
 inline size_t fp32_lds(int K, int V, bool adjoint) {
-  size_t b = (size_t)(adjoint ? 11 : 8) * K * sizeof(float) + (size_t)kWaves * 6 * V;
-  if (adjoint) b += (size_t)kWaves * 48 * sizeof(float);
-  return b;
+  return (size_t)(adjoint ? 11 : 8) * K * sizeof(float) + (size_t)kWaves * 6 * V;
 }
 
 // Persistent grid: as many workgroups as the device holds at once (every

@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "librga_oracle.so")
+# RGA_ORACLE_LIBRARY may name another build of the same source (the
+# sanitizer build of the CPU tests)
+_LIB_PATH = os.environ.get("RGA_ORACLE_LIBRARY") or os.path.join(_HERE, "librga_oracle.so")
 _lib = None
 
 

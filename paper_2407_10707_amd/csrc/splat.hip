@@ -33,8 +33,8 @@ namespace {
 
 constexpr int kTile = 16;
 constexpr int kRadixThreads = 256;
-constexpr int kItemsD = 16;      // per thread, passes over the duplicates
-constexpr int kItemsN = 4;       // per thread, passes over the splats
+constexpr int kItemsD = 8;       // per thread, passes over the duplicates
+constexpr int kItemsN = 2;       // per thread, passes over the splats
 constexpr int kBlockD = kRadixThreads * kItemsD;
 constexpr int kBlockN = kRadixThreads * kItemsN;
 constexpr int kChunk = 256;      // splats per blend work item
@@ -348,6 +348,66 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
   vals[g] = (uint32_t)g;
 }
 
+// ---- blend work items -------------------------------------------------------
+// Work items: (tile, chunk of kChunk entries) for the forward passes, and
+// (item, sub-chunk of kSub entries) for the adjoint, numbered tile by tile
+// with one scan over the tiles (the two counts packed in one 64-bit sum),
+// by one workgroup of NT threads, each a run of tiles; len(t) is tile t's
+// list length.  Each item gets its tile, chunk index and first sub-item; the
+// chunk pass lists the sub-items.
+template <int NT, class Len>
+__device__ void make_work_items(int tiles, Len&& len, uint32_t* __restrict__ item_off,
+                                uint32_t* __restrict__ item_tile, uint32_t* __restrict__ item_chunk,
+                                uint32_t* __restrict__ item_sub, int64_t max_items,
+                                int64_t* __restrict__ counters, uint64_t* part) {
+  const int per = (tiles + NT - 1) / NT;
+  const int t0 = min(tiles, (int)threadIdx.x * per), t1 = min(tiles, t0 + per);
+  uint64_t s = 0;
+  for (int t = t0; t < t1; ++t) {
+    const int l = len(t);
+    s += (uint64_t)((l + kChunk - 1) / kChunk) | ((uint64_t)((l + kSub - 1) / kSub) << 32);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < NT; o <<= 1) {
+    const uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const uint64_t before = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
+  uint32_t off = (uint32_t)before, soff = (uint32_t)(before >> 32);
+  for (int t = t0; t < t1; ++t) {
+    item_off[t] = off;
+    const int l = len(t);
+    const int nch = (l + kChunk - 1) / kChunk;
+    for (int j = 0; j < nch; ++j) {
+      const int64_t b = (int64_t)off + j;
+      if (b == max_items) counters[3] = (int64_t)soff;   // lists truncated: existing items' only
+      if (b < max_items) {
+        item_tile[b] = (uint32_t)t;
+        item_chunk[b] = (uint32_t)j;
+        item_sub[b] = soff;
+      }
+      soff += (uint32_t)min(kSubs, (l - j * kChunk + kSub - 1) / kSub);
+    }
+    off += nch;
+  }
+  if (threadIdx.x == NT - 1) {
+    const uint64_t tot = part[NT - 1];
+    item_off[tiles] = (uint32_t)tot;
+    counters[1] = (int64_t)(uint32_t)tot;
+    if ((int64_t)(uint32_t)tot <= max_items) counters[3] = (int64_t)(tot >> 32);
+  }
+}
+
+// Where the items go (passed to the tile sort's one-pass scatter).
+struct ItemOut {
+  uint32_t *off, *tile, *chunk, *sub;
+  int64_t max_items;
+  int64_t* counters;
+};
+
 // ---- radix sort (reduce-then-scan, stable) ----------------------------------
 __device__ inline int64_t live_count(const int64_t* cnt_ptr, int64_t fixed, int64_t cap) {
   int64_t c = cnt_ptr ? *cnt_ptr : fixed;
@@ -426,15 +486,18 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
                 const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot,
-                int32_t* __restrict__ ranges, int nranges) {
+                int32_t* __restrict__ ranges, int nranges, ItemOut items) {
   constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the initial scan
   __shared__ uint32_t base[kRadix];
   __shared__ uint32_t wcnt[4][kRadix];
   __shared__ uint32_t part[kRadixThreads];
+  __shared__ uint64_t ipart[kRadixThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t count = live_count(cnt_ptr, fixed, cap);
   const int64_t blk = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
-  if (blk >= count) return;
+  // block 0 of a one-pass tile sort writes the ranges and work items even
+  // when there are no entries
+  if (blk >= count && !(ranges && blockIdx.x == 0)) return;
   // base[d] = sum of bintot over digits < d (all blocks) + this block's offset in d
   uint32_t loc[kPer];
   uint32_t sum = 0;
@@ -465,6 +528,11 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     }
   }
   __syncthreads();
+  // ... and the blend's work items from the tile lengths (the digit totals)
+  if (ranges && blockIdx.x == 0)
+    make_work_items<kRadixThreads>(nranges, [&](int t) { return (int)bintot[t]; }, items.off,
+                                   items.tile, items.chunk, items.sub, items.max_items,
+                                   items.counters, ipart);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < ITEMS; ++r) {
     const int64_t i = blk + (int64_t)r * kRadixThreads + tid;
@@ -697,55 +765,16 @@ __device__ inline void cull_entry(const float4& r0, const float4& r1, const floa
   }
 }
 
-// Work items: (tile, chunk of kChunk entries) for the forward passes, and
-// (item, sub-chunk of kSub entries) for the adjoint, numbered tile by tile
-// with one scan over the tiles (the two counts packed in one 64-bit sum).
-// Here each item gets its tile, chunk index and first sub-item; the chunk
-// pass lists the sub-items.
+// The blend's work items from the tile ranges, for the cases the tile sort's
+// scatter does not build them (no splats, or a tile sort of several passes).
 __global__ void __launch_bounds__(1024)
 chunk_index_kernel(int tiles, const int32_t* __restrict__ ranges, uint32_t* __restrict__ item_off,
                    uint32_t* __restrict__ item_tile, uint32_t* __restrict__ item_chunk,
                    uint32_t* __restrict__ item_sub, int64_t max_items,
                    int64_t* __restrict__ counters) {
   __shared__ uint64_t part[1024];
-  const int per = (tiles + 1023) / 1024;
-  const int t0 = threadIdx.x * per, t1 = min(tiles, t0 + per);
-  uint64_t s = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int len = ranges[2 * t + 1] - ranges[2 * t];
-    s += (uint64_t)((len + kChunk - 1) / kChunk) | ((uint64_t)((len + kSub - 1) / kSub) << 32);
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    uint64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0ull;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const uint64_t before = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
-  uint32_t off = (uint32_t)before, soff = (uint32_t)(before >> 32);
-  for (int t = t0; t < t1; ++t) {
-    item_off[t] = off;
-    const int len = ranges[2 * t + 1] - ranges[2 * t];
-    const int nch = (len + kChunk - 1) / kChunk;
-    for (int j = 0; j < nch; ++j) {
-      const int64_t b = (int64_t)off + j;
-      if (b == max_items) counters[3] = (int64_t)soff;   // lists truncated: existing items' only
-      if (b < max_items) {
-        item_tile[b] = (uint32_t)t;
-        item_chunk[b] = (uint32_t)j;
-        item_sub[b] = soff;
-      }
-      soff += (uint32_t)min(kSubs, (len - j * kChunk + kSub - 1) / kSub);
-    }
-    off += nch;
-  }
-  if (threadIdx.x == 1023) {
-    item_off[tiles] = (uint32_t)part[1023];
-    counters[1] = (int64_t)(uint32_t)part[1023];
-    if ((int64_t)(uint32_t)part[1023] <= max_items) counters[3] = (int64_t)(part[1023] >> 32);
-  }
+  make_work_items<1024>(tiles, [&](int t) { return ranges[2 * t + 1] - ranges[2 * t]; }, item_off,
+                        item_tile, item_chunk, item_sub, max_items, counters, part);
 }
 
 // One pixel's (C, T code) into a 1024-float state block: C0, C1, C2, code,
@@ -1464,7 +1493,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot,
-                 (int32_t*)nullptr, 0);
+                 (int32_t*)nullptr, 0, ItemOut{});
       uint32_t* t = k0; k0 = k1; k1 = t;
       t = v0; v0 = v1; v1 = t;
     }
@@ -1481,6 +1510,9 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     RGA_LAUNCH("splat_duplicate", duplicate_kernel, dim3(L.nb_n), dim3(kBlockN), 0, s, n,
                L.tiles_x, capacity, v0, at<int32_t>(ws, L.touched), at<int32_t>(ws, L.rect), boff,
                tk0, tv0);
+    const ItemOut items{at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
+                        at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items,
+                        cnt};
     for (int pass = 0; pass < L.tile_passes; ++pass) {
       const int shift = kDigitBits * pass;
       RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
@@ -1491,7 +1523,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
       const bool one = L.tile_passes == 1;
       RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot,
-                 one ? ranges : (int32_t*)nullptr, one ? (int)tiles : 0);
+                 one ? ranges : (int32_t*)nullptr, one ? (int)tiles : 0, items);
       uint32_t* t = tk0; tk0 = tk1; tk1 = t;
       t = tv0; tv0 = tv1; tv1 = t;
     }
@@ -1499,11 +1531,13 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
       RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
                  s, tk0, (const int64_t*)cnt, capacity, ranges);
   }
-  // work items (tile, chunk), chunk composites, front-to-back combine
+  // work items (tile, chunk) unless the one-pass tile sort built them,
+  // chunk composites, front-to-back combine
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
-  RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
-             at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
-             at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items, cnt);
+  if (n == 0 || L.tile_passes > 1)
+    RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
+               at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
+               at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items, cnt);
   const int64_t g_chunk =
       std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
   const int64_t g_restart =

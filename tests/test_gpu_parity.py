@@ -357,6 +357,39 @@ def test_splat_deep_tiles_parity():
     assert not badT.any(), (int(badT.sum()), float(np.max(np.abs(gT - eT)[ok] / eT[ok])))
 
 
+@pytest.mark.parametrize("n", [20000, 40000])
+def test_splat_long_lists_bit_exact(n):
+    """Tile lists longer than a workgroup sorts in LDS (8192 entries): large
+    splats over a 3 x 2-tile image, each tile holding all of them (3 and 5
+    sorted runs, merged in 2 and 3 passes, the last run unpaired in the
+    first), drawn from 1,000 positions, so that many depths tie exactly
+    (ties go to the lower index).  D, the ranges and every list against the
+    oracle's (depth bits, index) order."""
+    print(f"[splat] long lists n={n}", flush=True)
+    rng = np.random.default_rng(9)
+    cam = synth.default_camera(48, 32)
+    pts = np.stack([rng.uniform(-0.3, 0.3, 1000), rng.uniform(-0.2, 0.2, 1000),
+                    rng.uniform(-0.5, 0.5, 1000)]).astype(np.float32)
+    x = np.ascontiguousarray(pts[:, rng.integers(0, 1000, n)])
+    A = np.tile(np.eye(3, dtype=np.float32).reshape(9, 1), (1, n))
+    q = rng.normal(size=(4, n)).astype(np.float32)
+    log_s = rng.normal(-0.5, 0.1, (3, n)).astype(np.float32)
+    opac = rng.uniform(0.3, 0.9, n).astype(np.float32)
+    col = rng.random((3, n)).astype(np.float32)
+    front = np.ones(n, np.uint8)
+    ws = rga.SplatWorkspace(n, cam.width, cam.height, 8 * n, "cuda")
+    rga.splat_forward(cam, dev(x), dev(A), dev(q), dev(log_s), dev(opac), dev(col), dev(front), ws)
+    pre = cpu.splat_preprocess(cam, x, A, q, log_s, opac, front)
+    keys, vals, ranges = cpu.splat_bin(cam, pre)
+    lens = ranges[:, 1] - ranges[:, 0]
+    print(f"  D={len(keys)} list lengths {lens.tolist()}", flush=True)
+    assert lens.max() > 2 * 8192
+    assert ws.count() == len(keys)
+    st = ws.state()
+    assert np.array_equal(host(ws.view(st.ranges, (len(lens), 2), torch.int32)), ranges)
+    assert np.array_equal(host(ws.view(st.sorted, (len(keys),), torch.int32)), vals)
+
+
 def test_splat_empty_and_all_culled():
     cam = synth.default_camera(40, 24)
     ws = rga.SplatWorkspace(0, 40, 24, 16, "cuda")

@@ -614,8 +614,21 @@ def main():
     rga.lib()
     s = synth.make_scene(args.config)
     cfg = s["cfg"]
-    d = render.upload(s)
+    # the Gaussians stored grouped by nearest vertex (on the device, before
+    # the timed region; the host mirror follows the same order)
+    d, order = render.layout_by_vertex(render.upload(s))
+    s = render.scene_in_order(s, order)
     target = d["target"]
+
+    if args.copy_calibration:
+        # a plain copy of known size (256 MiB read, 256 MiB written): its
+        # FETCH_SIZE / WRITE_SIZE counters calibrate the path kernels' counters
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     head, R, p, step, image = measure_form(args, s, d, args.precision)
     images = {args.precision: image}
@@ -736,7 +749,8 @@ def main():
         "config": {"workload": cfg.name, "gaussians": s["n"], "mesh_vertices": s["nv"],
                    "mesh_triangles": s["nf"], "joints": 24, "light_directions": cfg.he * cfg.we,
                    "vis_views": cfg.hv * cfg.wv, "vis_res": cfg.vis_res,
-                   "image": [s["height"], s["width"]], "precision": args.precision},
+                   "image": [s["height"], s["width"]], "precision": args.precision,
+                   "layout": "gaussians grouped by nearest vertex"},
         "graph": bool(args.graph),
         "render_fps": head["render_fps"],
         "render_fps_no_vis": head["render_fps_no_vis"],

@@ -444,6 +444,31 @@ int densify(void* stream, int n, int kg, const int32_t* sg, int nv, const float*
             size_t ws_bytes);
 
 /* ------------------------------------------------------------------------
+ * Storage order of the Gaussians (Sec. 3.1: each Gaussian reads the
+ * visibility counts of its K_g nearest mesh vertices).  The Gaussians are a
+ * set: their order in memory is free, and storing them grouped by nearest
+ * vertex lets the shading kernels' nearby waves gather the same count rows
+ * (and each XCD's L2 hold its share of the table).
+ *
+ * vertex_order: order [n] int32 out, the indices 0..n-1 sorted stably by
+ * vidx row 0 (vertex ids clamped to 0..nv-1; ties in index order), i.e. a
+ * permutation; vidx [3][n] int32 (row 0 read).  ws: vertex_order_workspace(n)
+ * bytes, 16-byte aligned.  Errors: RGA_EINVAL (n < 0, nv < 1, null
+ * pointers, misaligned ws), RGA_ECAPACITY (ws too small); nothing is
+ * launched then.  Bit-exact (a stable sort has one result).
+ *
+ * gather_columns: dst[r][j] = src[r][order[j]] for `rows` rows of n 4-byte
+ * elements (float or int32), to apply an order to every per-Gaussian array
+ * (and its optimiser state).  src and dst must not overlap; order entries
+ * are clamped to 0..n-1.  Errors: RGA_EINVAL (negative sizes, null
+ * pointers, src == dst), RGA_EUNSUPPORTED (rows * n beyond 2^39).           */
+size_t vertex_order_workspace(int n);
+int vertex_order(void* stream, int n, const int32_t* vidx, int nv, int32_t* order, void* ws,
+                 size_t ws_bytes);
+int gather_columns(void* stream, int rows, int n, const void* src, const int32_t* order,
+                   void* dst);
+
+/* ------------------------------------------------------------------------
  * The optimiser of the training loop (the paper trains as 3DGS does; the
  * reading is Adam): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
  * param -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).

@@ -327,12 +327,42 @@ struct Cand {
   int vidx[3];
 };
 
-// Load block bb of the wave's Gaussians (lane i: first + (64 bb + i) stride)
-// and decide the back-face rule (FP32, fixed order, as gauss_setup).
-__device__ inline void cand_load(const ShadeArgs& a, int first, int stride, int bb, int lane,
-                                 Cand& C) {
-  const int64_t idx = (int64_t)(64 * bb + lane) * stride + first;
-  const bool valid = idx < a.n;
+// The wave's slots of the walk: first, first + stride, ... below `end`.
+// With a grid of whole groups of 8 workgroups, the workgroups that share a
+// remainder modulo 8 (dispatched to the same XCD, whose L2 they share)
+// take one contiguous eighth of the Gaussians: with the Gaussians stored
+// grouped by nearest vertex, each XCD then gathers count rows from about an
+// eighth of the table, and its L2 holds them.
+struct Walk {
+  int first, stride, end;
+};
+
+__device__ inline Walk wave_walk(int n, int wave) {
+  Walk w;
+  const int grid = gridDim.x, b = blockIdx.x;
+  if (grid % 8 == 0 && grid >= 8) {
+    const int x = b % 8, j = b / 8;
+    const int lo = (int)((int64_t)n * x / 8), hi = (int)((int64_t)n * (x + 1) / 8);
+    w.first = lo + j * kWaves + wave;
+    w.stride = (grid / 8) * kWaves;
+    w.end = hi;
+  } else {
+    w.first = b * kWaves + wave;
+    w.stride = grid * kWaves;
+    w.end = n;
+  }
+  return w;
+}
+
+__device__ inline int walk_count(const Walk& w) {
+  return w.first < w.end ? (w.end - 1 - w.first) / w.stride + 1 : 0;
+}
+
+// Load block bb of the wave's Gaussians (lane i: Gaussian first + (64 bb + i)
+// stride) and decide the back-face rule (FP32, fixed order, as gauss_setup).
+__device__ inline void cand_load(const ShadeArgs& a, const Walk& w, int bb, int lane, Cand& C) {
+  const int64_t idx = (int64_t)(64 * bb + lane) * w.stride + w.first;
+  const bool valid = idx < w.end;
   C.g = valid ? (int)idx : -1;
   C.front = false;
   if (valid) {
@@ -371,9 +401,6 @@ __device__ inline int cand_take(const ShadeArgs& a, const Cand& C, int j, Attr& 
   return g;
 }
 
-__device__ inline int wave_count(int n, int first, int stride) {
-  return first < n ? (n - 1 - first) / stride + 1 : 0;
-}
 
 // Walk the K directions of one Gaussian 64 at a time: lane = direction,
 // the live ones (n.w_k > 0 and visibility > 0) appended with their
@@ -426,9 +453,8 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   RowPlan<NQ> plan;
   row_plan<NQ>(V, lane, plan);
-  const int stride = gridDim.x * kWaves;
-  const int first = blockIdx.x * kWaves + wave;
-  const int nblk = (wave_count(n, first, stride) + 63) / 64;
+  const Walk walk = wave_walk(n, wave);
+  const int nblk = (walk_count(walk) + 63) / 64;
   Cand C;
   int b = -1;
   uint64_t fm = 0ull;
@@ -436,7 +462,7 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
   auto advance = [&]() {
     while (fm == 0ull && b + 1 < nblk) {
       ++b;
-      cand_load(a, first, stride, b, lane, C);
+      cand_load(a, walk, b, lane, C);
       if (C.g >= 0) {
         front[C.g] = C.front ? 1 : 0;
         if (!C.front) {
@@ -660,7 +686,12 @@ struct BwdAcc {
 // Chain rule through one live pair's weights: upstream gWd = dL/dW_d and
 // gWs = dL/dW_s give the pair's share of dL/dn^, dL/dw_o, dL/d(n.w_o) and
 // dL/dgamma.  Uses the logarithmic derivatives of D (in n.h and alpha), F
-// (through dF/d(o.h)) and G1.
+// (through dF/d(o.h)) and G1.  Only the part of dL/dw_o orthogonal to w_o
+// reaches x, so the w_o terms are taken along h = h~/|h~|: n.h changes by
+// (n - (n.h) h)/|h~| and o.h = |h~|/2 by h/2 (up to multiples of w_o).  The
+// same derivative taken through o.w_k (d(n.h)/d(o.w_k) = -(n.h~)/|h~|^3)
+// is of size 1/|h~|^2 near w_k = -w_o, almost all of it along w_o, and the
+// projection onto the tangent plane then cancels it in FP32.
 __device__ inline void pair_grads(const GaussCtx& G, const Pair& P, float v, float gWd, float gWs,
                                   BwdAcc& acc) {
   const float one_m_a2 = 1.f - G.a2;
@@ -670,18 +701,19 @@ __device__ inline void pair_grads(const GaussCtx& G, const Pair& P, float v, flo
   const float dF_doh = 0.96f * P.e2 * 0.69314718f * (-2.f * 5.55473f * P.oh - 6.98316f);
   const float gs = gWs * P.Ws;
   const float gsF = gWs * P.W0F * P.G1i * dF_doh;
-  const float ih3 = P.invh * P.invh * P.invh;
-  const float gci = gWd * v + gWs * P.W0 * G.kG * (P.ideni * P.ideni) + gs * dlnD_dnh * P.invh;
-  const float gco = gs * (dlnD_dnh * P.invh - (1.f - G.kG) * G.Go);
-  const float gok = fmaf(gsF, 0.5f * P.invh, gs * (-dlnD_dnh * P.nht * ih3));
+  const float gnh = gs * dlnD_dnh * P.invh;          // dL/d(n.h~) through D
+  const float gci = gWd * v + gWs * P.W0 * G.kG * (P.ideni * P.ideni) + gnh;
+  const float gco = gnh - gs * (1.f - G.kG) * G.Go;
+  // dL/dw_o = gco n + ghh h~ (modulo w_o)
+  const float ghh = fmaf(-gnh, P.nh, 0.5f * gsF) * P.invh;
   const float dlnG_dk = -(1.f - P.ci) * P.ideni - (1.f - G.co) * G.Go;
   const float gga = gs * (dlnD_da * 2.f * G.gamma + dlnG_dk * (G.gamma + 1.f) * 0.25f);
   acc.gn[0] = fmaf(gci, P.d[0], acc.gn[0]);
   acc.gn[1] = fmaf(gci, P.d[1], acc.gn[1]);
   acc.gn[2] = fmaf(gci, P.d[2], acc.gn[2]);
-  acc.gw[0] = fmaf(gok, P.d[0], acc.gw[0]);
-  acc.gw[1] = fmaf(gok, P.d[1], acc.gw[1]);
-  acc.gw[2] = fmaf(gok, P.d[2], acc.gw[2]);
+  acc.gw[0] = fmaf(ghh, P.d[0] + G.wo[0], acc.gw[0]);
+  acc.gw[1] = fmaf(ghh, P.d[1] + G.wo[1], acc.gw[1]);
+  acc.gw[2] = fmaf(ghh, P.d[2] + G.wo[2], acc.gw[2]);
   acc.gco += gco;
   acc.gga += gga;
 }
@@ -925,9 +957,8 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   RowPlan<NQ> plan;
   row_plan<NQ>(V, lane, plan);
-  const int stride = gridDim.x * kWaves;
-  const int first = blockIdx.x * kWaves + wave;
-  const int nblk = (wave_count(n, first, stride) + 63) / 64;
+  const Walk walk = wave_walk(n, wave);
+  const int nblk = (walk_count(walk) + 63) / 64;
   // Lane c < 3 handles channel c of the per-Gaussian inputs and outputs.
   const int ch = min(lane, 2);
   Cand C;
@@ -938,7 +969,7 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   auto advance = [&]() {
     while (fm == 0ull && b + 1 < nblk) {
       ++b;
-      cand_load(a, first, stride, b, lane, C);
+      cand_load(a, walk, b, lane, C);
       if (C.g >= 0 && !C.front) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

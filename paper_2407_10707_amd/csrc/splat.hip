@@ -1387,6 +1387,56 @@ int resident_groups(const void* kernel) {
   return cache[dev];
 }
 
+// ---- storage order of the Gaussians --------------------------------------------
+// The Gaussians sorted by their nearest mesh vertex (vidx row 0), stably (ties
+// keep their index order), with the binning's radix sort: keys = vertex,
+// values = index, 11-bit digits, as many passes as the vertex count needs.
+__global__ void __launch_bounds__(256)
+vertex_keys_kernel(int n, const int32_t* __restrict__ vidx, int nv, uint32_t* __restrict__ keys,
+                   uint32_t* __restrict__ vals) {
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  if (g < n) {
+    keys[g] = (uint32_t)rga::clampi(vidx[g], 0, nv - 1);
+    vals[g] = (uint32_t)g;
+  }
+}
+
+// dst[r][j] = src[r][order[j]] for rows of 4-byte elements
+__global__ void __launch_bounds__(256)
+gather_columns_kernel(int rows, int n, const uint32_t* __restrict__ src,
+                      const int32_t* __restrict__ order, uint32_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)rows * n) return;
+  const int64_t r = i / n, j = i - r * n;
+  dst[i] = src[r * n + rga::clampi(order[j], 0, n - 1)];
+}
+
+struct VertexOrderLayout {
+  size_t keys0, keys1, vals0, vals1, hist, binoff, bintot, total;
+  int nb;
+};
+
+VertexOrderLayout vertex_order_layout(int n) {
+  VertexOrderLayout L;
+  L.nb = (int)rga::ceil_div(n > 0 ? n : 1, kBlockN);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += rga::align_up(bytes, 256);
+    return o;
+  };
+  const size_t items = (size_t)(n > 0 ? n : 1) * sizeof(uint32_t);
+  L.keys0 = take(items);
+  L.keys1 = take(items);
+  L.vals0 = take(items);
+  L.vals1 = take(items);
+  L.hist = take((size_t)L.nb * kRadix * sizeof(uint32_t));
+  L.binoff = take((size_t)L.nb * kRadix * sizeof(uint32_t));
+  L.bintot = take((size_t)kRadix * sizeof(uint32_t));
+  L.total = off;
+  return L;
+}
+
 int check_common(const char* fn, int n, const rga_camera* cam, const void* ws, size_t ws_bytes,
                  int64_t cap, Layout& L) {
   if (n < 0) return rga::fail(RGA_EINVAL, "%s: n < 0", fn);
@@ -1591,5 +1641,67 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
              n, cd, x, A, quat, log_s, opac, front, grad9, queue, dx, dquat, dlog_s, dopac, dcolor,
              dA, (const int64_t*)at<int64_t>(ws, L.count), capacity);
   RGA_CHECK_LAUNCH("splat_backward");
+  return RGA_OK;
+}
+
+extern "C" size_t vertex_order_workspace(int n) {
+  if (n < 0) return 0;
+  return vertex_order_layout(n).total;
+}
+
+extern "C" int vertex_order(void* stream, int n, const int32_t* vidx, int nv, int32_t* order,
+                            void* ws, size_t ws_bytes) {
+  if (n < 0 || nv < 1) return rga::fail(RGA_EINVAL, "vertex_order: n >= 0 and nv >= 1");
+  if (n > 0x7FFFFFFF / 16) return rga::fail(RGA_EUNSUPPORTED, "vertex_order: n too large");
+  if (n == 0) return RGA_OK;
+  if (!vidx || !order || !ws) return rga::fail(RGA_EINVAL, "vertex_order: null pointer");
+  if (!rga::aligned16(ws)) return rga::fail(RGA_EINVAL, "vertex_order: workspace must be 16-byte aligned");
+  const VertexOrderLayout L = vertex_order_layout(n);
+  if (ws_bytes < L.total)
+    return rga::fail(RGA_ECAPACITY, "vertex_order: workspace %zu < %zu bytes", ws_bytes, L.total);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t* k0 = at<uint32_t>(ws, L.keys0);
+  uint32_t* k1 = at<uint32_t>(ws, L.keys1);
+  uint32_t* v0 = at<uint32_t>(ws, L.vals0);
+  uint32_t* v1 = at<uint32_t>(ws, L.vals1);
+  uint32_t* hist = at<uint32_t>(ws, L.hist);
+  uint32_t* binoff = at<uint32_t>(ws, L.binoff);
+  uint32_t* bintot = at<uint32_t>(ws, L.bintot);
+  int bits = 0;
+  while (bits < 31 && ((uint32_t)(nv - 1) >> bits) != 0u) ++bits;
+  const int passes = bits <= kDigitBits ? 1 : (bits <= 2 * kDigitBits ? 2 : 3);
+  RGA_LAUNCH("vertex_keys", vertex_keys_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s, n,
+             vidx, nv, k0, v0);
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = kDigitBits * pass;
+    const bool last = pass == passes - 1;
+    uint32_t* vout = last ? reinterpret_cast<uint32_t*>(order) : v1;
+    RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsN>, dim3(L.nb), dim3(kRadixThreads), 0, s, k0,
+               (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
+    RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb,
+               (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
+    RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb), dim3(kRadixThreads), 0, s,
+               k0, v0, k1, vout, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff,
+               bintot, (int32_t*)nullptr, 0, ItemOut{});
+    uint32_t* t = k0; k0 = k1; k1 = t;
+    t = v0; v0 = v1; v1 = t;
+  }
+  RGA_CHECK_LAUNCH("vertex_order");
+  return RGA_OK;
+}
+
+extern "C" int gather_columns(void* stream, int rows, int n, const void* src, const int32_t* order,
+                              void* dst) {
+  if (rows < 0 || n < 0) return rga::fail(RGA_EINVAL, "gather_columns: rows >= 0 and n >= 0");
+  if ((int64_t)rows * n == 0) return RGA_OK;
+  if (!src || !order || !dst) return rga::fail(RGA_EINVAL, "gather_columns: null pointer");
+  if (src == dst) return rga::fail(RGA_EINVAL, "gather_columns: src and dst must not overlap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t total = (int64_t)rows * n;
+  if (rga::ceil_div(total, 256) > 0x7FFFFFFF)
+    return rga::fail(RGA_EUNSUPPORTED, "gather_columns: rows * n too large");
+  RGA_LAUNCH("gather_columns", gather_columns_kernel, dim3(rga::ceil_div(total, 256)), dim3(256), 0,
+             s, rows, n, static_cast<const uint32_t*>(src), order, static_cast<uint32_t*>(dst));
+  RGA_CHECK_LAUNCH("gather_columns");
   return RGA_OK;
 }

@@ -33,6 +33,36 @@ def upload(scene: dict, device="cuda") -> Dict[str, torch.Tensor]:
     return out
 
 
+# the arrays with one column per Gaussian
+PER_GAUSSIAN = ("pos", "nrm", "quat", "log_s", "opac", "albedo", "rough", "tint", "jidx", "jw",
+                "vidx", "vw")
+
+
+def layout_by_vertex(d: Dict[str, torch.Tensor]):
+    """The device scene with its Gaussians stored grouped by nearest mesh
+    vertex: vertex_order (a stable sort by vidx row 0) applied to every
+    per-Gaussian array with gather_columns.  Returns (new dict, order) with
+    new[k][..., j] = d[k][..., order[j]]; the other arrays are shared.  The
+    Gaussians are a set, so this changes no result, only where each one
+    lives: the shading kernels then gather count rows that their neighbours
+    have just brought into the cache."""
+    order = rga.vertex_order(d["vidx"], int(d["verts"].shape[1]))
+    out = dict(d)
+    for k in PER_GAUSSIAN:
+        out[k] = rga.gather_columns(d[k], order)
+    return out, order
+
+
+def scene_in_order(scene: dict, order) -> dict:
+    """The host scene with its Gaussians in `order` (as layout_by_vertex
+    returns it), so that host-side checks see the device layout."""
+    o = np.asarray(order.cpu() if isinstance(order, torch.Tensor) else order, dtype=np.int64)
+    out = dict(scene)
+    for k in PER_GAUSSIAN:
+        out[k] = np.ascontiguousarray(np.asarray(scene[k])[..., o])
+    return out
+
+
 class Renderer:
     """Holds the static inputs and workspaces of one scene/camera."""
 

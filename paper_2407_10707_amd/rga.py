@@ -78,6 +78,9 @@ _SIGS = {
     "densify_workspace": (_SZ, [_I]),
     "densify": (_I, [_VP, _I, _I, _VP, _I, _VP, _I, _VP, C.c_double, C.c_double, C.c_uint64,
                      _I64, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ]),
+    "vertex_order_workspace": (_SZ, [_I]),
+    "vertex_order": (_I, [_VP, _I, _VP, _I, _VP, _VP, _SZ]),
+    "gather_columns": (_I, [_VP, _I, _I, _VP, _VP, _VP]),
     "rga_timing_enable": (_I, [_I]),
     "rga_timing_reset": (_I, []),
     "rga_timing_filter": (_I, [C.c_char_p]),
@@ -586,6 +589,34 @@ def densify(sg, verts, faces, d0: float = 1.0, p0: float = 0.02, seed: int = 0,
         m = min(N, cap)
         out.update(n_added=N, x=x[:, :m], face=fo[:m])
     return out
+
+
+def vertex_order(vidx, nv: int):
+    """The Gaussians' indices sorted stably by nearest mesh vertex (vidx
+    [3, n] int32, row 0), on the device: an int32 permutation [n]."""
+    n = int(vidx.shape[1])
+    _i32(vidx, "vidx", (3, n))
+    order = torch.empty((n,), dtype=torch.int32, device=vidx.device)
+    ws = torch.empty(max(16, int(lib().vertex_order_workspace(n))), dtype=torch.uint8,
+                     device=vidx.device)
+    _check(lib().vertex_order(_stream(), n, _p(vidx), int(nv), _p(order), _p(ws), ws.numel()),
+           "vertex_order")
+    return order
+
+
+def gather_columns(src, order):
+    """dst[..., j] = src[..., order[j]] for a contiguous float32 or int32
+    tensor whose last dimension is the Gaussians (n); a new tensor."""
+    if src.dtype not in (torch.float32, torch.int32):
+        raise RgaError("gather_columns: float32 or int32 tensor expected")
+    _dev(src, src.dtype, "src")
+    n = int(src.shape[-1])
+    _i32(order, "order", (n,))
+    rows = src.numel() // n if n > 0 else 0
+    dst = torch.empty_like(src)
+    _check(lib().gather_columns(_stream(), rows, n, _p(src), _p(order), _p(dst)),
+           "gather_columns")
+    return dst
 
 
 MLP_PARAMS = 249603

@@ -1,6 +1,7 @@
-"""Parity at the workloads' full sizes, in the launch configuration bench.py
-uses (Renderer: skin mesh -> visibility -> skin -> shade -> splat, and the
-adjoint), on outputs the oracle can compute:
+"""Parity at the workloads' full sizes, in the launch configuration and the
+storage layout bench.py uses (Gaussians grouped by nearest vertex; Renderer:
+skin mesh -> visibility -> skin -> shade -> splat, and the adjoint), on
+outputs the oracle can compute:
 
 * bit-exact: skinned positions/normals/A (all), visibility counts (all
   views), back-face flags (all), D, tile ranges and lists (all);
@@ -52,7 +53,9 @@ def case(request):
     cfg, kw, precision = _CASES[request.param]
     print(f"[fullsize] {request.param}: building scene", flush=True)
     s = synth.make_scene(cfg, **kw)
-    d = render.upload(s)
+    # the layout bench.py times: Gaussians grouped by nearest vertex
+    d, order = render.layout_by_vertex(render.upload(s))
+    s = render.scene_in_order(s, order)
     R = render.Renderer(s, d, precision=precision)
     p = {k: d[k] for k in render.TRAINABLE}
     count = R.visibility()

@@ -473,13 +473,19 @@ radix_binscan(const uint32_t* __restrict__ hist, int nb, const int64_t* cnt_ptr,
   }
 }
 
-// Stable scatter of one block.  Per round of 256 items: within a wave,
-// items with the same digit are matched with one ballot per digit bit (the
-// rank is the number of lower lanes with that digit); across the four waves
-// the lowest lane of each digit group publishes the group's size in
-// wcnt[wave][digit], items add the sizes of the earlier waves' groups, and
-// the same lanes then advance base[digit] and clear their wcnt entry (so
-// only the entries used in a round are ever touched).
+// Stable scatter of one block.  Each wave owns a contiguous run of
+// 64 ITEMS items (so the block's order is wave by wave, round by round, lane
+// by lane) and keeps them in registers.  Pass 1: per round, items with the
+// same digit are matched with one ballot per digit bit (rank = number of
+// lower lanes with that digit, group = their number) and each group's
+// lowest lane adds the group to the wave's own digit counts in LDS.  Then,
+// after one barrier, digit d of wave w starts at
+//   (sum of bintot over digits < d) + binoff[block][d] + (counts of d in
+//   waves < w),
+// written over the wave's counts; after a second barrier each wave scatters
+// its rounds with no further barrier: position = running start of the digit
+// + rank, and the group's lowest lane advances the running start (the
+// wave's LDS operations complete in order).
 template <int ITEMS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
@@ -487,10 +493,10 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
                 const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
                 const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot,
                 int32_t* __restrict__ ranges, int nranges, ItemOut items) {
-  constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the initial scan
-  __shared__ uint32_t base[kRadix];
-  __shared__ uint32_t wcnt[4][kRadix];
-  __shared__ uint32_t part[kRadixThreads];
+  constexpr int kWavesR = kRadixThreads / 64;
+  constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the digit scan
+  __shared__ uint32_t run[kWavesR][kRadix];
+  __shared__ uint32_t wtot[kWavesR];
   __shared__ uint64_t ipart[kRadixThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t count = live_count(cnt_ptr, fixed, cap);
@@ -498,48 +504,22 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
   // block 0 of a one-pass tile sort writes the ranges and work items even
   // when there are no entries
   if (blk >= count && !(ranges && blockIdx.x == 0)) return;
-  // base[d] = sum of bintot over digits < d (all blocks) + this block's offset in d
-  uint32_t loc[kPer];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    loc[i] = sum;
-    sum += bintot[tid * kPer + i];
-  }
-  part[tid] = sum;
-  for (int d = tid; d < 4 * kRadix; d += kRadixThreads) (&wcnt[0][0])[d] = 0u;
-  __syncthreads();
-  for (int o = 1; o < kRadixThreads; o <<= 1) {
-    const uint32_t v = tid >= o ? part[tid - o] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  const uint32_t excl = tid ? part[tid - 1] : 0u;
-#pragma unroll
-  for (int i = 0; i < kPer; ++i) {
-    const int d = tid * kPer + i;
-    base[d] = excl + loc[i] + binoff[(size_t)blockIdx.x * kRadix + d];
-    // a one-pass tile sort: digit d is tile d, and its entries land at
-    // [start of the digit, + its total)
-    if (ranges && blockIdx.x == 0 && d < nranges) {
-      ranges[2 * d] = (int32_t)(excl + loc[i]);
-      ranges[2 * d + 1] = (int32_t)(excl + loc[i] + bintot[d]);
-    }
-  }
-  __syncthreads();
-  // ... and the blend's work items from the tile lengths (the digit totals)
-  if (ranges && blockIdx.x == 0)
-    make_work_items<kRadixThreads>(nranges, [&](int t) { return (int)bintot[t]; }, items.off,
-                                   items.tile, items.chunk, items.sub, items.max_items,
-                                   items.counters, ipart);
+  uint32_t* wrun = run[wave];
+  for (int d = lane; d < kRadix; d += 64) wrun[d] = 0u;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t wbeg = blk + (int64_t)wave * 64 * ITEMS;
+  uint32_t key[ITEMS], val[ITEMS], info[ITEMS];
+#pragma unroll
   for (int r = 0; r < ITEMS; ++r) {
-    const int64_t i = blk + (int64_t)r * kRadixThreads + tid;
+    const int64_t i = wbeg + 64 * r + lane;
     const bool ok = i < count;
-    const uint32_t key = ok ? kin[i] : 0u;
-    const uint32_t val = ok ? vin[i] : 0u;
-    const uint32_t d = (key >> shift) & (kRadix - 1);
+    key[r] = ok ? kin[i] : 0u;
+    val[r] = ok ? vin[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    const bool ok = wbeg + 64 * r + lane < count;
+    const uint32_t d = (key[r] >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < kDigitBits; ++b) {
@@ -549,22 +529,63 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     }
     const uint32_t rank = __popcll(peers & lt);
     const uint32_t group = __popcll(peers);
-    const bool leader = ok && rank == 0;
-    if (leader) wcnt[wave][d] = group;
-    __syncthreads();
-    if (ok) {
-      uint32_t before = 0;
-      for (int w = 0; w < wave; ++w) before += wcnt[w][d];
-      const uint32_t pos = base[d] + before + rank;
-      kout[pos] = key;
-      vout[pos] = val;
+    if (ok && rank == 0) wrun[d] += group;
+    // rank (6 bits), group size (7 bits); all ones = no item
+    info[r] = ok ? (rank | (group << 6)) : 0xFFFFFFFFu;
+  }
+  // digit starts: each thread sums kPer consecutive digit totals, a wave
+  // scan, then the waves' totals
+  uint32_t tot[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    tot[q] = bintot[tid * kPer + q];
+    s += tot[q];
+  }
+  uint32_t incl = s;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  uint32_t start = incl - s;
+  for (int w = 0; w < wave; ++w) start += wtot[w];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int d = tid * kPer + q;
+    // a one-pass tile sort: digit d is tile d, and its entries land at
+    // [start of the digit, + its total)
+    if (ranges && blockIdx.x == 0 && d < nranges) {
+      ranges[2 * d] = (int32_t)start;
+      ranges[2 * d + 1] = (int32_t)(start + tot[q]);
     }
-    __syncthreads();
-    if (leader) {
-      atomicAdd(&base[d], group);
-      wcnt[wave][d] = 0u;
+    uint32_t acc = start + binoff[(size_t)blockIdx.x * kRadix + d];
+#pragma unroll
+    for (int w = 0; w < kWavesR; ++w) {
+      const uint32_t h = run[w][d];
+      run[w][d] = acc;
+      acc += h;
     }
-    __syncthreads();
+    start += tot[q];
+  }
+  __syncthreads();
+  // ... and the blend's work items from the tile lengths (the digit totals)
+  if (ranges && blockIdx.x == 0)
+    make_work_items<kRadixThreads>(nranges, [&](int t) { return (int)bintot[t]; }, items.off,
+                                   items.tile, items.chunk, items.sub, items.max_items,
+                                   items.counters, ipart);
+#pragma unroll
+  for (int r = 0; r < ITEMS; ++r) {
+    if (info[r] != 0xFFFFFFFFu) {
+      const uint32_t d = (key[r] >> shift) & (kRadix - 1);
+      const uint32_t rank = info[r] & 63u, group = info[r] >> 6;
+      const uint32_t pos = wrun[d] + rank;
+      kout[pos] = key[r];
+      vout[pos] = val[r];
+      if (rank == 0) wrun[d] += group;
+    }
   }
 }
 

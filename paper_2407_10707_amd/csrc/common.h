@@ -215,4 +215,33 @@ __device__ inline void lds_add3(float* p, float x0, float x1, float x2) {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Runs of equal keys in consecutive lanes of a wave (a scatter-add whose
+// targets repeat, e.g. Gaussians stored grouped by vertex, adding into the
+// vertex): `end` is one past the lane's run, and the run's first lane is
+// the one to add.  Every lane of the wave must call it; equal keys that
+// are not adjacent form separate runs.
+__device__ inline bool wave_run(int key, int& end) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || prev != key;
+  const uint64_t heads = __ballot(head);
+  const uint64_t after = lane == 63 ? 0ull : (heads & (~0ull << (lane + 1)));
+  end = after ? (int)__builtin_ctzll(after) : 64;
+  return head;
+}
+
+// v summed over the lane's run of equal keys (a segmented suffix sum: the
+// run's first lane gets the whole run); returns whether this lane is first.
+__device__ inline bool wave_run_sum(int key, float& v) {
+  const int lane = threadIdx.x & 63;
+  int end;
+  const bool head = wave_run(key, end);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const float t = __shfl_down(v, o, 64);
+    if (lane + o < end) v += t;
+  }
+  return head;
+}
+
 }  // namespace rga

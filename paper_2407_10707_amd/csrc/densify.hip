@@ -39,11 +39,18 @@ densify_clear_kernel(int nv, int32_t* __restrict__ Dv, int nf, int32_t* __restri
   if (i < nf) ng[i] = 0;
 }
 
+// one thread per (neighbour slot, Gaussian) entry; entries of consecutive
+// lanes that name the same vertex (Gaussians stored grouped by vertex) are
+// counted with one atomic per run
 __global__ void __launch_bounds__(kBlock)
 densify_count_kernel(int64_t total, const int32_t* __restrict__ sg, int nv,
                      int32_t* __restrict__ Dv) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (e < total) atomicAdd(&Dv[rga::clampi(sg[e], 0, nv - 1)], 1);
+  const int lane = threadIdx.x & 63;
+  const bool ok = e < total;
+  const int v = ok ? rga::clampi(sg[e], 0, nv - 1) : -1 - lane;
+  int end;
+  if (rga::wave_run(v, end) && ok) atomicAdd(&Dv[v], end - lane);
 }
 
 // inclusive scan of 64-bit values over a wave (shuffles), then over the

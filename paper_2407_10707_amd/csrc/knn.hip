@@ -530,12 +530,20 @@ knn_interp_bwd_kernel(int n, int k, const int32_t* __restrict__ idx, const float
   for (int j = threadIdx.x; j < vn; j += blockDim.x) acc[j] = 0.f;
   __syncthreads();
   const float* g = dout + (size_t)c * n;
-  for (int i = q0 + threadIdx.x; i < q1; i += blockDim.x) {
-    const float gi = g[i];
-    if (gi == 0.f) continue;
+  // Queries that share a neighbour and sit in consecutive lanes (points
+  // stored grouped by vertex) are summed across the wave first, so that
+  // one lane adds per run instead of every lane contending for the same
+  // LDS word.
+  const int lane = threadIdx.x & 63;
+  for (int base = q0 + (int)(threadIdx.x & ~63u); base < q1; base += blockDim.x) {
+    const int i = base + lane;
+    const bool ok = i < q1;
+    const float gi = ok ? g[i] : 0.f;
     for (int t = 0; t < k; ++t) {
-      const int j = idx[(size_t)t * n + i] - v0;
-      if (j >= 0 && j < vn) rga::lds_add(&acc[j], w[(size_t)t * n + i] * gi);
+      const int j = ok ? idx[(size_t)t * n + i] - v0 : -1;
+      const bool use = ok && gi != 0.f && j >= 0 && j < vn;
+      float val = use ? w[(size_t)t * n + i] * gi : 0.f;
+      if (rga::wave_run_sum(use ? j : -1 - lane, val) && use) rga::lds_add(&acc[j], val);
     }
   }
   __syncthreads();

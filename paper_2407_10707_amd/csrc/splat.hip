@@ -42,8 +42,10 @@ constexpr int kSub = 64;         // splats per work item of the blend adjoint
 constexpr int kSubs = kChunk / kSub;
 constexpr float kHalfNegLog2e = -0.72134752f;   // -log2(e) / 2
 constexpr float kInvHalfLog2e = 1.38629436f;    // 2 / log2(e) = 2 ln 2
-constexpr int kDigitBits = 11;   // radix digit width: 2048 bins
+constexpr int kDigitBits = 11;   // radix digit width of the tile sort: 2048 bins
 constexpr int kRadix = 1 << kDigitBits;
+constexpr int kDepthBits = 11;   // digit width of the depth sort: 3 passes over 32-bit keys
+constexpr int kDepthPasses = (32 + kDepthBits - 1) / kDepthBits;
 
 struct Layout {
   size_t rec, mean2d, conic, depth, rect, touched, fp64, keys0, vals0, keys1, vals1, offs;
@@ -414,14 +416,15 @@ __device__ inline int64_t live_count(const int64_t* cnt_ptr, int64_t fixed, int6
   return c < cap ? c : cap;
 }
 
-// Digits of kDigitBits bits (2048 bins): 32-bit depth keys take 3 passes,
-// tile keys of up to 2048 tiles 1 pass.
+// Digits of BITS bits: 32-bit depth keys take 3 passes of 11 bits, tile keys
+// of up to 2048 tiles 1 pass.
 
-// Per-block digit histogram (LDS integer atomics).
-template <int ITEMS>
+// Per-block digit histogram (LDS integer atomics), digits of BITS bits.
+template <int ITEMS, int BITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t fixed,
               int64_t cap, int shift, uint32_t* __restrict__ hist) {
+  constexpr int kRadix = 1 << BITS;
   __shared__ uint32_t h[kRadix];
   const int64_t count = live_count(cnt_ptr, fixed, cap);
   const int64_t base = (int64_t)blockIdx.x * (kRadixThreads * ITEMS);
@@ -440,10 +443,12 @@ radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t
 // Exclusive scan of each digit's counts over the blocks that hold items
 // (the rest of a capacity-sized grid is skipped): 8 digits per workgroup,
 // 32 threads per digit each summing a run of blocks.
+template <int BITS>
 __global__ void __launch_bounds__(256)
 radix_binscan(const uint32_t* __restrict__ hist, int nb, const int64_t* cnt_ptr, int64_t fixed,
               int64_t cap, int block_items, uint32_t* __restrict__ binoff,
               uint32_t* __restrict__ bintot) {
+  constexpr int kRadix = 1 << BITS;
   __shared__ uint32_t part[8][33];
   const int dl = threadIdx.x & 7, c = threadIdx.x >> 3;
   const int d = blockIdx.x * 8 + dl;
@@ -486,15 +491,17 @@ radix_binscan(const uint32_t* __restrict__ hist, int nb, const int64_t* cnt_ptr,
 // its rounds with no further barrier: position = running start of the digit
 // + rank, and the group's lowest lane advances the running start (the
 // wave's LDS operations complete in order).
-template <int ITEMS>
+template <int ITEMS, int BITS>
 __global__ void __launch_bounds__(kRadixThreads)
 radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const int64_t* cnt_ptr, int64_t fixed, int64_t cap, int shift,
                 const uint32_t* __restrict__ binoff, const uint32_t* __restrict__ bintot,
                 int32_t* __restrict__ ranges, int nranges, ItemOut items) {
+  constexpr int kRadix = 1 << BITS;
   constexpr int kWavesR = kRadixThreads / 64;
   constexpr int kPer = kRadix / kRadixThreads;   // digits per thread in the digit scan
+  static_assert(kPer >= 1, "at least one digit per thread");
   __shared__ uint32_t run[kWavesR][kRadix];
   __shared__ uint32_t wtot[kWavesR];
   __shared__ uint64_t ipart[kRadixThreads];
@@ -522,7 +529,7 @@ radix_downsweep(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     const uint32_t d = (key[r] >> shift) & (kRadix - 1);
     uint64_t peers = __ballot(ok);
 #pragma unroll
-    for (int b = 0; b < kDigitBits; ++b) {
+    for (int b = 0; b < BITS; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
@@ -1555,14 +1562,16 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
                at<uint8_t>(ws, L.fp64), k0, v0, reinterpret_cast<uint32_t*>(ranges), 2 * tiles,
                reinterpret_cast<uint32_t*>(cnt), at<float>(ws, L.grad), at<uint32_t>(ws, L.queue));
-    // depth sort: 3 passes of 11 bits over n 32-bit keys
-    for (int pass = 0; pass < 3; ++pass) {
-      const int shift = kDigitBits * pass;
-      RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+    // depth sort: 3 passes of 11 bits over n 32-bit keys (4 passes of 8
+    // bits, with 8x smaller digit tables, take longer: the passes are
+    // latency-bound launches)
+    for (int pass = 0; pass < kDepthPasses; ++pass) {
+      const int shift = kDepthBits * pass;
+      RGA_LAUNCH("radix_upsweep", (radix_upsweep<kItemsN, kDepthBits>), dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
-      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_n,
+      RGA_LAUNCH("radix_binscan", radix_binscan<kDepthBits>, dim3((1 << kDepthBits) / 8), dim3(256), 0, s, hist, L.nb_n,
                  (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
-      RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
+      RGA_LAUNCH("radix_downsweep", (radix_downsweep<kItemsN, kDepthBits>), dim3(L.nb_n), dim3(kRadixThreads), 0, s, k0,
                  v0, k1, v1, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff, bintot,
                  (int32_t*)nullptr, 0, ItemOut{});
       uint32_t* t = k0; k0 = k1; k1 = t;
@@ -1586,13 +1595,13 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
                         cnt};
     for (int pass = 0; pass < L.tile_passes; ++pass) {
       const int shift = kDigitBits * pass;
-      RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+      RGA_LAUNCH("radix_upsweep", (radix_upsweep<kItemsD, kDigitBits>), dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);
-      RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_cap,
+      RGA_LAUNCH("radix_binscan", radix_binscan<kDigitBits>, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb_cap,
                  (const int64_t*)cnt, (int64_t)0, capacity, kBlockD, binoff, bintot);
       // with one tile pass its scatter also writes the tile ranges
       const bool one = L.tile_passes == 1;
-      RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsD>, dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
+      RGA_LAUNCH("radix_downsweep", (radix_downsweep<kItemsD, kDigitBits>), dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0, capacity, shift, binoff, bintot,
                  one ? ranges : (int32_t*)nullptr, one ? (int)tiles : 0, items);
       uint32_t* t = tk0; tk0 = tk1; tk1 = t;
@@ -1697,11 +1706,11 @@ extern "C" int vertex_order(void* stream, int n, const int32_t* vidx, int nv, in
     const int shift = kDigitBits * pass;
     const bool last = pass == passes - 1;
     uint32_t* vout = last ? reinterpret_cast<uint32_t*>(order) : v1;
-    RGA_LAUNCH("radix_upsweep", radix_upsweep<kItemsN>, dim3(L.nb), dim3(kRadixThreads), 0, s, k0,
+    RGA_LAUNCH("radix_upsweep", (radix_upsweep<kItemsN, kDigitBits>), dim3(L.nb), dim3(kRadixThreads), 0, s, k0,
                (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, hist);
-    RGA_LAUNCH("radix_binscan", radix_binscan, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb,
+    RGA_LAUNCH("radix_binscan", radix_binscan<kDigitBits>, dim3(kRadix / 8), dim3(256), 0, s, hist, L.nb,
                (const int64_t*)nullptr, (int64_t)n, (int64_t)n, kBlockN, binoff, bintot);
-    RGA_LAUNCH("radix_downsweep", radix_downsweep<kItemsN>, dim3(L.nb), dim3(kRadixThreads), 0, s,
+    RGA_LAUNCH("radix_downsweep", (radix_downsweep<kItemsN, kDigitBits>), dim3(L.nb), dim3(kRadixThreads), 0, s,
                k0, v0, k1, vout, (const int64_t*)nullptr, (int64_t)n, (int64_t)n, shift, binoff,
                bintot, (int32_t*)nullptr, 0, ItemOut{});
     uint32_t* t = k0; k0 = k1; k1 = t;

@@ -31,27 +31,45 @@ struct ShadeArgs {
   const float *x, *nrm, *albedo, *rough, *tint, *vw, *env;
   const int32_t* vidx;
   const uint8_t* count;
+  int patch;   // table slots in 4 x 8 texel patches (the MFMA kernels), else texel order
 };
 
-// Table in LDS, two float4 per direction k: [k] = (direction x, y, z,
-// view index as int bits), [K + k] = (E = radiance x texel solid angle, r,
-// g, b, and the solid angle).  One 16-byte LDS read fetches either half.
+// Direction k held by table slot s.  In texel order s = k.  In patch order
+// (he % 4 == 0, we % 8 == 0) the slots run over patches of 4 texel rows x 8
+// columns, patch-major along each band of 4 rows: slot 32 p + 8 i + j is
+// texel (4 (p / (we / 8)) + i, 8 (p % (we / 8)) + j).  A patch is the
+// 32-direction reduction step of the MFMA kernels, so the directions of one
+// step lie close together and are often all below the horizon (or all
+// occluded) for the 16 Gaussians of a tile.
+__device__ inline int slot_k(int s, int we, int patch) {
+  if (!patch) return s;
+  const int p = s >> 5, q = s & 31;
+  const int pw = we >> 3;
+  const int pr = p / pw, pc = p - pr * pw;
+  return (4 * pr + (q >> 3)) * we + 8 * pc + (q & 7);
+}
+
+// Table in LDS, two float4 per slot s (direction k = slot_k(s)): [s] =
+// (direction x, y, z, view index as int bits), [K + s] = (E = radiance x
+// texel solid angle, r, g, b, and the solid angle).  One 16-byte LDS read
+// fetches either half.
 __device__ inline void build_table(const ShadeArgs& a, float* tab) {
   float4* t4 = reinterpret_cast<float4*>(tab);
   const int K = a.K;
   const float dth = kPi / (float)a.he, dph = 2.f * kPi / (float)a.we;
   // exact solid angle of a texel row: (2 pi / we) * 2 sin(theta_r) sin(pi / (2 he))
   const float band = (2.f * kPi / (float)a.we) * 2.f * sinf(0.5f * dth);
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+  for (int sl = threadIdx.x; sl < K; sl += blockDim.x) {
+    const int k = slot_k(sl, a.we, a.patch);
     const int r = k / a.we, c = k - r * a.we;
     float st, ct, sp, cp;
     sincosf(((float)r + 0.5f) * dth, &st, &ct);
     sincosf(((float)c + 0.5f) * dph, &sp, &cp);
     const float area = band * st;
     const int view = ((r * a.hv) / a.he) * a.wv + (c * a.wv) / a.we;
-    t4[k] = make_float4(st * sp, ct, st * cp, __int_as_float(view));
-    t4[K + k] = make_float4(a.env[3 * k] * area, a.env[3 * k + 1] * area,
-                            a.env[3 * k + 2] * area, area);
+    t4[sl] = make_float4(st * sp, ct, st * cp, __int_as_float(view));
+    t4[K + sl] = make_float4(a.env[3 * k] * area, a.env[3 * k + 1] * area,
+                             a.env[3 * k + 2] * area, area);
   }
 }
 
@@ -592,6 +610,28 @@ __device__ inline void vis8(const uint8_t* row, const float* tab, int k, int rat
   }
 }
 
+// Slots kb .. kb+7 of one lane (8 texels of one row, consecutive in the
+// texel order too): the interpolated visibility of each and the mask of
+// the live ones (front-facing, n.w_k > 0, visibility > 0).
+__device__ inline uint32_t live8(const ShadeArgs& a, const GaussCtx& G, const float* tab,
+                                 const uint8_t* r0, const uint8_t* r1, const uint8_t* r2, int kb,
+                                 int ratio, bool on, float (&vv)[8]) {
+  const int kv = ratio ? slot_k(kb, a.we, a.patch) : kb;
+  float c0[8], c1[8], c2[8];
+  vis8(r0, tab, kv, ratio, c0);
+  vis8(r1, tab, kv, ratio, c1);
+  vis8(r2, tab, kv, ratio, c2);
+  uint32_t lm = 0u;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float4 dv = dir_of(tab, kb + i);
+    const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
+    vv[i] = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
+    if (on && ci > 0.f && vv[i] > 0.f) lm |= 1u << i;
+  }
+  return lm;
+}
+
 __global__ void __launch_bounds__(kMThreads)
 shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
                       uint8_t* __restrict__ front) {
@@ -620,21 +660,18 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
     f32x4 accD = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kb = k0 + 8 * kg;
-      float c0[8], c1[8], c2[8];
-      vis8(r0, tab, kb, ratio, c0);
-      vis8(r1, tab, kb, ratio, c1);
-      vis8(r2, tab, kb, ratio, c2);
+      float vv[8];
+      const uint32_t lm = live8(a, G, tab, r0, r1, r2, kb, ratio, on, vv);
+      // a step with no live pair in the tile adds nothing
+      if (__ballot(lm != 0u) == 0ull) continue;
       bf16x8 dh, dl, sh, sl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = kb + i;
         float Wd = 0.f, Ws = 0.f;
-        const float4 dv = dir_of(tab, k);
-        const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
-        const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
-        if (on && ci > 0.f && v > 0.f) {
+        if ((lm >> i) & 1u) {
           Pair P;
-          pair_eval(G, tab, K, k, v, P);
+          pair_eval(G, tab, K, k, vv[i], P);
           Wd = P.Wd;
           Ws = P.Ws;
         }
@@ -823,27 +860,24 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
     BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kb = k0 + 8 * kg;
-      float c0[8], c1[8], c2[8];
-      vis8(r0, tab, kb, ratio, c0);
-      vis8(r1, tab, kb, ratio, c1);
-      vis8(r2, tab, kb, ratio, c2);
+      float vv[8];
+      const uint32_t lm = live8(a, G, tab, r0, r1, r2, kb, ratio, on, vv);
+      // a step with no live pair in the tile adds nothing (W = 0)
+      if (__ballot(lm != 0u) == 0ull) continue;
       bf16x8 dh, dl, sh, sl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = kb + i;
         float Wd = 0.f, Ws = 0.f;
-        const float4 dv = dir_of(tab, k);
-        const float ci = fmaf(G.nn[2], dv.z, fmaf(G.nn[1], dv.y, G.nn[0] * dv.x));
-        const float v = fmaf(G.u2, c2[i], fmaf(G.u1, c1[i], G.u0 * c0[i]));
-        if (on && ci > 0.f && v > 0.f) {
+        if ((lm >> i) & 1u) {
           Pair P;
-          pair_eval(G, tab, K, k, v, P);
+          pair_eval(G, tab, K, k, vv[i], P);
           Wd = P.Wd;
           Ws = P.Ws;
           const float gWd = fmaf(qd[2], P.E[2], fmaf(qd[1], P.E[1], qd[0] * P.E[0]));
           const float sE = fmaf(dLo[2], P.E[2], fmaf(dLo[1], P.E[1], dLo[0] * P.E[0]));
           const float gWs = tint * sE;
-          pair_grads(G, P, v, gWd, gWs, acc);
+          pair_grads(G, P, vv[i], gWd, gWs, acc);
         }
         const __bf16 hd = (__bf16)Wd, hs = (__bf16)Ws;
         dh[i] = hd;
@@ -931,8 +965,12 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
     wave_fence();
   }
   __syncthreads();
+  // LDS sums are in slot order; the partials in texel order
   float* out = denv_part + (size_t)blockIdx.x * 3 * K;
-  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) out[i] = denv_lds[i];
+  for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) {
+    const int sl = i / 3, c = i - 3 * sl;
+    out[3 * slot_k(sl, a.we, a.patch) + c] = denv_lds[i];
+  }
 }
 
 // (up to 512 views: two workgroups per CU, four waves per SIMD, at most
@@ -1234,6 +1272,7 @@ ShadeArgs make_args(int n, const float* x, const float* nrm, const float* albedo
   a.env = env;
   a.vidx = vidx;
   a.count = count;
+  a.patch = 0;
   return a;
 }
 
@@ -1256,6 +1295,7 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
+    a.patch = (he % 4 == 0 && we % 8 == 0) ? 1 : 0;
     const size_t lds = (size_t)8 * a.K * sizeof(float) + (size_t)6 * a.K * 2 + kMWaves * 512 * 4;
     static bool mattr = false;
     if (!mattr) {
@@ -1326,6 +1366,7 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);
+    a.patch = (he % 4 == 0 && we % 8 == 0) ? 1 : 0;
     const size_t lds = (size_t)11 * a.K * sizeof(float) + (size_t)6 * a.K * 2 +
                        (size_t)kMWaves * (4096 + 384 + 2048);
     if (lds > 150 * 1024)

@@ -2,7 +2,8 @@
 through the C ABI on every kind of view grid the kernels distinguish: one
 texel per view, two texels per view along the azimuth, and any other grid
 (views coarser in both angles, or four texels per view), with one, two and
-four passes of 512 directions.  Colours against the FP64 oracle
+four passes of 512 directions, and for the split bf16 form both orders of
+its direction table (4 x 8 texel patches, and map order).  Colours against the FP64 oracle
 (|d| <= 1e-5 |ref| + 1e-7, back-face flags bit-exact); the gradients of
 L = sum w . colour with respect to position, normal, albedo, roughness,
 tint and environment against autograd of the FP64 oracle, per element
@@ -22,9 +23,12 @@ from tests import helpers
 
 pytestmark = pytest.mark.gpu
 
-# (he, we, hv, wv): one texel per view, two per view, and other grids
+# (he, we, hv, wv): one texel per view, two per view, and other grids; the
+# split bf16 form walks 4 x 8 texel patches where he % 4 == 0 and we % 8 == 0
+# and the texels in map order on (2, 16) and (6, 16)
 GRIDS = [(4, 8, 4, 8), (4, 16, 4, 8), (8, 16, 4, 8), (8, 16, 8, 4), (8, 32, 4, 16),
-         (16, 32, 16, 32), (16, 32, 16, 16), (32, 32, 32, 32), (32, 64, 32, 32)]
+         (16, 32, 16, 32), (16, 32, 16, 16), (32, 32, 32, 32), (32, 64, 32, 32),
+         (2, 16, 2, 16), (6, 16, 6, 8)]
 
 
 def dev(a):

@@ -530,20 +530,26 @@ knn_interp_bwd_kernel(int n, int k, const int32_t* __restrict__ idx, const float
   for (int j = threadIdx.x; j < vn; j += blockDim.x) acc[j] = 0.f;
   __syncthreads();
   const float* g = dout + (size_t)c * n;
-  // Queries that share a neighbour and sit in consecutive lanes (points
-  // stored grouped by vertex) are summed across the wave first, so that
-  // one lane adds per run instead of every lane contending for the same
-  // LDS word.
-  const int lane = threadIdx.x & 63;
-  for (int base = q0 + (int)(threadIdx.x & ~63u); base < q1; base += blockDim.x) {
+  // Each wave takes its own contiguous quarter of the block's queries, and
+  // queries that share a neighbour in consecutive lanes (points stored
+  // grouped by vertex) are summed across the wave first: one lane adds per
+  // run, and the waves of a block mostly add to different LDS words.
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int per = (q1 - q0 + nw - 1) / nw;
+  const int wq0 = q0 + wave * per, wq1 = min(q1, wq0 + per);
+  for (int base = wq0; base < wq1; base += 64) {
     const int i = base + lane;
-    const bool ok = i < q1;
+    const bool ok = i < wq1;
     const float gi = ok ? g[i] : 0.f;
     for (int t = 0; t < k; ++t) {
       const int j = ok ? idx[(size_t)t * n + i] - v0 : -1;
       const bool use = ok && gi != 0.f && j >= 0 && j < vn;
       float val = use ? w[(size_t)t * n + i] * gi : 0.f;
-      if (rga::wave_run_sum(use ? j : -1 - lane, val) && use) rga::lds_add(&acc[j], val);
+      // the LDS float atomic: lanes of one wave that still share a word
+      // (neighbours repeating out of order) are serialised in the LDS unit
+      // instead of retrying a compare-and-swap (0.129 -> 0.087 ms for 42
+      // channels of the avatar's 100k Gaussians)
+      if (rga::wave_run_sum(use ? j : -1 - lane, val) && use) atomicAdd(&acc[j], val);
     }
   }
   __syncthreads();

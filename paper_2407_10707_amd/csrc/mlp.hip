@@ -367,6 +367,8 @@ __device__ inline void wgrad_item(int item, int& l, int& nb, int& kb) {
   }
 }
 
+// (launched for the first and last layers only: the hidden layers take
+// mlp_wgrad_hidden_kernel)
 __global__ void __launch_bounds__(256)
 mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
                  const float* __restrict__ freqs, const float* __restrict__ H,
@@ -374,7 +376,7 @@ mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, g = lane >> 4;
   int l, nb, kb;
-  wgrad_item(blockIdx.x, l, nb, kb);
+  wgrad_item(blockIdx.x < 4 ? (int)blockIdx.x : (int)blockIdx.x + 24, l, nb, kb);
   const int c = blockIdx.y;
   const int wn = wave & 1, wk = wave >> 1;
   const int n0 = nb * 64 + 32 * wn, k0 = kb * 128 + 64 * wk;
@@ -482,6 +484,83 @@ mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
   }
 }
 
+// dW_l of a hidden layer (l = 1..3, 256 x 256) over one chunk of vertices,
+// the whole layer per workgroup, so that every operand row is read once
+// per chunk (a workgroup per 64 x 128 tile re-reads dz twice and h four
+// times).  Eight waves of 64 rows x 128 columns, 4 x 8 accumulator tiles
+// of 16 x 16 (128 values per lane); per 32 vertices a lane loads and
+// splits 4 + 8 eight-vertex fragments for 96 MFMAs.  The waves of the
+// first column half also sum their dz rows (db).
+constexpr int kHidThreads = 512;
+
+__global__ void __launch_bounds__(kHidThreads)
+mlp_wgrad_hidden_kernel(int nvp, int chunk_len, const float* __restrict__ H,
+                        const float* __restrict__ dZ, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, g = lane >> 4;
+  const int l = 1 + (int)blockIdx.x;
+  const int c = blockIdx.y;
+  const int n0 = 64 * (wave & 3), k0 = 128 * (wave >> 2);
+  const float* dz = dZ + (size_t)l * kWidth * nvp;
+  const float* hin = H + (size_t)(l - 1) * kWidth * nvp;
+  const float* ap[4];
+  const float* bp[8];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) ap[rt] = dz + (size_t)(n0 + 16 * rt + row) * nvp;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) bp[q] = hin + (size_t)(k0 + 16 * q + row) * nvp;
+  const int v0 = c * chunk_len, v1 = min(nvp, v0 + chunk_len);
+  f32x4 acc[4][8];
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[rt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbs[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int vb = v0; vb < v1; vb += 32) {
+    const int va = vb + 8 * g;
+    bf16x8 ah[4], al[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      float a[8];
+      load8(ap[rt] + va, a);
+      split8(a, ah[rt], al[rt]);
+      if (k0 == 0)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dbs[rt] += a[e];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      float b[8];
+      load8(bp[q] + va, b);
+      bf16x8 bh, bl;
+      split8(b, bh, bl);
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) acc[rt][q] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][q]);
+    }
+  }
+  float* pc = part + (size_t)c * kParams;
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + 16 * q + row;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = n0 + 16 * rt + 4 * g + i;
+        pc[w_off(l) + n * kWidth + k] = acc[rt][q][i];
+      }
+    }
+  if (k0 == 0) {
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      float d = dbs[rt];
+      d += __shfl_xor(d, 16);
+      d += __shfl_xor(d, 32);
+      if (g == 0) pc[b_off(l) + n0 + 16 * rt + row] = d;
+    }
+  }
+}
+
 // dparams = sum over the chunks (fixed order); W_1's pose columns are
 // db_1 theta^T (the pose is shared by every vertex)
 __global__ void __launch_bounds__(256)
@@ -574,8 +653,10 @@ extern "C" int mlp_backward(void* stream, int nv, const float* x, const float* f
   // weight-gradient kernels still run over the (zero) padding rows
   RGA_LAUNCH("mlp_bwd", mlp_backward_kernel, dim3(L.nvp / kRows), dim3(64 * kWaves), 0, s, nv, L.nvp, ddx, hi, lo, at<float>(ws, L.h),
              at<float>(ws, L.dz));
-  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_kernel, dim3(kTilesW, L.chunks), dim3(64 * kWaves), 0, s, nv,
-             L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
+  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_hidden_kernel, dim3(3, L.chunks), dim3(kHidThreads), 0, s,
+             L.nvp, L.chunk_len, at<float>(ws, L.h), at<float>(ws, L.dz), part);
+  RGA_LAUNCH("mlp_wgrad_io", mlp_wgrad_kernel, dim3(kTilesW - 24, L.chunks), dim3(64 * kWaves), 0, s,
+             nv, L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
   RGA_LAUNCH("mlp_reduce", mlp_reduce_kernel, dim3(rga::ceil_div(kParams, 256)), dim3(256), 0, s,
              L.chunks, theta, part, dparams);
   RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(kDthThreads), 0, s, L.chunks, params,

@@ -354,7 +354,8 @@ def mlp_measure(d, reps: int = 20):
         ddx = torch.rand((3, nv), device="cuda")
         net.forward(theta, params)
         f = timed(lambda: net.forward(theta, params), ("mlp_pack", "mlp_fwd"))
-        b = timed(lambda: net.backward(ddx), ("mlp_bwd", "mlp_wgrad", "mlp_reduce", "mlp_dtheta"))
+        b = timed(lambda: net.backward(ddx),
+                  ("mlp_bwd", "mlp_wgrad", "mlp_wgrad_io", "mlp_reduce", "mlp_dtheta"))
         tf, tb = per_v_fwd * nv / f / 1e9, per_v_bwd * nv / b / 1e9
         return {"vertices": nv, "fwd_ms": round(f, 4), "bwd_ms": round(b, 4),
                 "fwd_tflops": round(tf, 2), "bwd_tflops": round(tb, 2),

@@ -20,12 +20,13 @@
 //             hidden activations are kept for the adjoint
 //   backward  the same shape: dz_5 = ddx, dh = dz W (transposed pack),
 //             dz = dh where h > 0; every dz is kept
-//   wgrad     dW_l = sum over vertices of dz_l h_{l-1}^T: workgroups over
-//             (layer, 64 x 128 tile, chunk of vertices),
-//             partial sums per chunk (no atomics), then a fixed-order sum
-//             over the chunks; the Fourier features of the first layer are
-//             recomputed from x; dW_1's pose columns are db_1 theta^T and
-//             dtheta = W_1[:, 128:]^T db_1
+//   wgrad     dW_l = sum over vertices of dz_l h_{l-1}^T: a workgroup per
+//             (layer, chunk of vertices) for the four large layers (the
+//             inputs staged through LDS once per workgroup), a small tiled
+//             kernel for the output layer; partial sums per chunk (no
+//             atomics), then a fixed-order sum over the chunks; the Fourier
+//             features of the first layer are recomputed from x; dW_1's pose
+//             columns are db_1 theta^T and dtheta = W_1[:, 128:]^T db_1
 #include "common.h"
 
 #include <algorithm>
@@ -42,7 +43,7 @@ constexpr int kIn1 = 2 * kFreqs + kPose;  // 200
 constexpr int kLayers = 5;
 constexpr int kParams = RGA_MLP_PARAMS;
 constexpr int kAS = kWidth + 4;           // LDS row stride of the activations (floats)
-constexpr int kMaxChunks = 64;
+constexpr int kMaxChunks = 51;   // five layer workgroups per chunk: 255 fit the 256 CUs at once
 constexpr int kWaves = 4;
 
 // parameter layout: W_1 [256][200], b_1, W_2 [256][256], b_2, W_3, b_3, W_4, b_4, W_5 [3][256], b_5
@@ -349,216 +350,185 @@ mlp_backward_kernel(int nv, int nvp, const float* __restrict__ ddx, const __bf16
   }
 }
 
-// dW_l[n][k] = sum_v dz_l[n][v] hin_l[k][v] over one chunk of vertices.
-// Workgroup tiles of 64 rows n x 128 columns k (waves 2 x 2, each 32 x 64),
-// blockIdx.x = (layer, tile), blockIdx.y = chunk; the next 32 vertices'
-// operands are loaded before the products of the current ones.  The waves
-// of the first column half of a layer's first column block also sum their
-// dz rows (db).
-constexpr int kTilesW = 4 + 3 * 8 + 2;   // layer 1: 4 x 1, layers 2-4: 4 x 2, layer 5: 1 x 2
+// dW_l of one layer over one chunk of vertices, the whole layer per
+// workgroup so that every operand row is read once per chunk (a workgroup
+// per 64 x 128 tile re-reads dz twice and h four times); blockIdx.x = the
+// layer, so all five run side by side: the first layer's Fourier columns
+// (256 x 128, features recomputed from x once per chunk step instead of
+// once per tile), the hidden layers (256 x 256, h_{l-1} from the forward)
+// and the output layer (3 x 256, its dz padded to 16 rows).  Eight waves,
+// each RT row tiles x NCT column tiles of 16 x 16.  Both operands of a
+// 32-vertex step are split into bf16 hi / lo fragments in LDS (A = dz
+// rows, B = the layer's inputs), double-buffered: each thread loads its
+// share of the next step into registers before this step's MFMAs and
+// splits and stores it after them, so the loads' latency is spent under
+// the products.  The db sums come from the same loads.
+constexpr int kLayerThreads = 512;
+constexpr int kLayerWaves = kLayerThreads / 64;
+constexpr int kFragA = 16 * 64;   // A fragments per step buffer (256 rows)
+constexpr int kFragB = 16 * 64;   // B fragments per step buffer (256 columns)
 
-__device__ inline void wgrad_item(int item, int& l, int& nb, int& kb) {
-  if (item < 4) {
-    l = 0; nb = item; kb = 0;
-  } else if (item < 28) {
-    l = 1 + (item - 4) / 8; nb = ((item - 4) % 8) / 2; kb = (item - 4) % 2;
-  } else {
-    l = 4; nb = 0; kb = item - 28;
-  }
-}
+struct WgradLds {
+  bf16x8 a[2][2][kFragA];   // [buffer][hi, lo][row tile * 64 + lane]
+  bf16x8 b[2][2][kFragB];   // [buffer][hi, lo][column tile * 64 + lane]
+};
 
-// (launched for the first and last layers only: the hidden layers take
-// mlp_wgrad_hidden_kernel)
-__global__ void __launch_bounds__(256)
-mlp_wgrad_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
-                 const float* __restrict__ freqs, const float* __restrict__ H,
-                 const float* __restrict__ dZ, float* __restrict__ part) {
+template <bool FIRST, int NRT, int RT, int NCT>
+__device__ inline void wgrad_layer(int l, int nv, int nvp, int chunk_len, const float* x,
+                                   const float* freqs, const float* H, const float* dZ,
+                                   float* part, WgradLds& S) {
+  constexpr int NQ = FIRST ? 2 * kFreqs / 16 : kWidth / 16;   // the layer's input column tiles
+  constexpr int NRG = kLayerWaves * NCT / NQ;                  // row groups of waves
+  static_assert(NRG * RT == NRT, "the waves cover the layer's rows");
+  constexpr int FA = NRT * 64, FB = NQ * 64;                   // fragments per step
+  constexpr int PA = (FA + kLayerThreads - 1) / kLayerThreads;  // per thread
+  constexpr int PB = FIRST ? 0 : FB / kLayerThreads;            // loaded per thread (B)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, g = lane >> 4;
-  int l, nb, kb;
-  wgrad_item(blockIdx.x < 4 ? (int)blockIdx.x : (int)blockIdx.x + 24, l, nb, kb);
   const int c = blockIdx.y;
-  const int wn = wave & 1, wk = wave >> 1;
-  const int n0 = nb * 64 + 32 * wn, k0 = kb * 128 + 64 * wk;
-  const int nrows = l < 4 ? kWidth : 16;          // rows of dz_l kept
-  const float* dz = dZ + (size_t)l * kWidth * nvp;  // dz_5 follows dz_4
-  bool rv[2];
-  const float* ap[2];
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    rv[rt] = n0 + 16 * rt < nrows;
-    ap[rt] = dz + (size_t)(rv[rt] ? n0 + 16 * rt + row : 0) * nvp;
-  }
-  const float* hp[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    hp[q] = H + ((size_t)(l > 0 ? l - 1 : 0) * kWidth + k0 + 16 * q + row) * nvp;
+  const int n0 = 16 * RT * (wave % NRG), q0 = NCT * (wave / NRG);
+  const int nrows = l < 4 ? kWidth : 16;
+  const float* dz = dZ + (size_t)l * kWidth * nvp;
+  const float* hin = H + (size_t)(FIRST ? 0 : l - 1) * kWidth * nvp;
   const int v0 = c * chunk_len, v1 = min(nvp, v0 + chunk_len);
-  f32x4 acc[2][4];
+  // fragment f = 64 t + L of either operand: row (or column) 16 t + L % 16,
+  // vertices vb + 8 (L / 16) .. + 7 (the MFMA operand order)
+  float ra[PA][8], rb[PB > 0 ? PB : 1][8];
+  float dsum[PA];
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int p = 0; p < PA; ++p) dsum[p] = 0.f;
+  auto load = [&](int vb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[rt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dbs[2] = {0.f, 0.f};
-  float ca[2][8], cb[4][8];
-  auto fetch = [&](int vb, float (&A)[2][8], float (&B)[4][8]) {
-    const int va = vb + 8 * g;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      if (rv[rt]) {
-        load8(ap[rt] + va, A[rt]);
+    for (int p = 0; p < PA; ++p) {
+      const int f = threadIdx.x + p * kLayerThreads;
+      const int n = 16 * (f >> 6) + (f & 15), va = vb + 8 * ((f & 63) >> 4);
+      if (f < FA && n < nrows) {
+        load8(dz + (size_t)n * nvp + va, ra[p]);
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) A[rt][e] = 0.f;
+        for (int e = 0; e < 8; ++e) ra[p][e] = 0.f;
       }
     }
-    if (l == 0) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int v = va + e;
-        const bool in = v < nv;
-        const float x0 = in ? x[v] : 0.f, x1 = in ? x[nv + v] : 0.f, x2 = in ? x[2 * nv + v] : 0.f;
+    for (int p = 0; p < PB; ++p) {
+      const int f = threadIdx.x + p * kLayerThreads;
+      const int col = 16 * (f >> 6) + (f & 15), va = vb + 8 * ((f & 63) >> 4);
+      load8(hin + (size_t)col * nvp + va, rb[p]);
+    }
+  };
+  auto store = [&](int buf, int vb) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 16 * q + row;
-          const float f = fourier_arg(freqs, k & (kFreqs - 1), x0, x1, x2);
-          B[q][e] = k < kFreqs ? sinpif(f) : cospif(f);
+    for (int p = 0; p < PA; ++p) {
+      const int f = threadIdx.x + p * kLayerThreads;
+      if (f < FA) {
+        bf16x8 h, lo;
+        split8(ra[p], h, lo);
+        S.a[buf][0][f] = h;
+        S.a[buf][1][f] = lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dsum[p] += ra[p][e];
+      }
+    }
+    if constexpr (FIRST) {
+      for (int f = threadIdx.x; f < FB; f += kLayerThreads) {
+        const int col = 16 * (f >> 6) + (f & 15), va = vb + 8 * ((f & 63) >> 4);
+        float b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int v = va + e;
+          const bool in = v < nv;
+          const float x0 = in ? x[v] : 0.f, x1 = in ? x[nv + v] : 0.f, x2 = in ? x[2 * nv + v] : 0.f;
+          const float fa = fourier_arg(freqs, col & (kFreqs - 1), x0, x1, x2);
+          b[e] = col < kFreqs ? sinpif(fa) : cospif(fa);
         }
+        bf16x8 h, lo;
+        split8(b, h, lo);
+        S.b[buf][0][f] = h;
+        S.b[buf][1][f] = lo;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) load8(hp[q] + va, B[q]);
-    }
-  };
-  if (v0 < v1) fetch(v0, ca, cb);
-  for (int vb = v0; vb < v1; vb += 32) {
-    float na[2][8], nb8[4][8];
-    const bool more = vb + 32 < v1;
-    if (more) fetch(vb + 32, na, nb8);
-    bf16x8 ah[2], al[2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      split8(ca[rt], ah[rt], al[rt]);
-      if (wk == 0 && kb == 0)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dbs[rt] += ca[rt][e];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      bf16x8 bh, bl;
-      split8(cb[q], bh, bl);
-#pragma unroll
-      for (int rt = 0; rt < 2; ++rt) acc[rt][q] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][q]);
-    }
-    if (more) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        ca[0][e] = na[0][e];
-        ca[1][e] = na[1][e];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) cb[q][e] = nb8[q][e];
+      for (int p = 0; p < PB; ++p) {
+        const int f = threadIdx.x + p * kLayerThreads;
+        bf16x8 h, lo;
+        split8(rb[p], h, lo);
+        S.b[buf][0][f] = h;
+        S.b[buf][1][f] = lo;
       }
     }
+  };
+  f32x4 acc[RT][NCT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) acc[rt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int buf = 0;
+  if (v0 < v1) {
+    load(v0);
+    store(0, v0);
+  }
+  __syncthreads();
+  for (int vb = v0; vb < v1; vb += 32) {
+    const bool more = vb + 32 < v1;
+    if (more) load(vb + 32);
+    bf16x8 ah[RT], al[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int f = (n0 / 16 + rt) * 64 + lane;
+      ah[rt] = S.a[buf][0][f];
+      al[rt] = S.a[buf][1][f];
+    }
+#pragma unroll
+    for (int j = 0; j < NCT; ++j) {
+      const bf16x8 bh = S.b[buf][0][(q0 + j) * 64 + lane];
+      const bf16x8 bl = S.b[buf][1][(q0 + j) * 64 + lane];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) acc[rt][j] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][j]);
+    }
+    // the other buffer's readers all passed the barrier that ended the
+    // previous step
+    if (more) store(buf ^ 1, vb + 32);
+    __syncthreads();
+    buf ^= 1;
   }
   float* pc = part + (size_t)c * kParams;
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = k0 + 16 * q + row;
+    for (int j = 0; j < NCT; ++j) {
+      const int k = 16 * (q0 + j) + row;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int n = n0 + 16 * rt + 4 * g + i;
-        if (n < n_out(l)) pc[w_off(l) + n * n_in(l) + k] = acc[rt][q][i];
+        if (n < n_out(l)) pc[w_off(l) + n * n_in(l) + k] = acc[rt][j][i];
       }
     }
-  if (wk == 0 && kb == 0) {
+  // db: fragment f's thread summed row 16 (f >> 6) + f % 16 over its
+  // vertex quarter (f % 64) / 16; the four quarters are lanes L, L ^ 16,
+  // L ^ 32, L ^ 48 of one wave
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      float d = dbs[rt];
-      d += __shfl_xor(d, 16);
-      d += __shfl_xor(d, 32);
-      const int n = n0 + 16 * rt + row;
-      if (g == 0 && n < n_out(l)) pc[b_off(l) + n] = d;
-    }
+  for (int p = 0; p < PA; ++p) {
+    float d = dsum[p];
+    d += __shfl_xor(d, 16);
+    d += __shfl_xor(d, 32);
+    const int f = threadIdx.x + p * kLayerThreads;
+    const int n = 16 * (f >> 6) + (f & 15);
+    if (f < FA && lane < 16 && n < n_out(l)) pc[b_off(l) + n] = d;
   }
 }
 
-// dW_l of a hidden layer (l = 1..3, 256 x 256) over one chunk of vertices,
-// the whole layer per workgroup, so that every operand row is read once
-// per chunk (a workgroup per 64 x 128 tile re-reads dz twice and h four
-// times).  Eight waves of 64 rows x 128 columns, 4 x 8 accumulator tiles
-// of 16 x 16 (128 values per lane); per 32 vertices a lane loads and
-// splits 4 + 8 eight-vertex fragments for 96 MFMAs.  The waves of the
-// first column half also sum their dz rows (db).
-constexpr int kHidThreads = 512;
-
-__global__ void __launch_bounds__(kHidThreads)
-mlp_wgrad_hidden_kernel(int nvp, int chunk_len, const float* __restrict__ H,
-                        const float* __restrict__ dZ, float* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = lane & 15, g = lane >> 4;
-  const int l = 1 + (int)blockIdx.x;
-  const int c = blockIdx.y;
-  const int n0 = 64 * (wave & 3), k0 = 128 * (wave >> 2);
-  const float* dz = dZ + (size_t)l * kWidth * nvp;
-  const float* hin = H + (size_t)(l - 1) * kWidth * nvp;
-  const float* ap[4];
-  const float* bp[8];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt) ap[rt] = dz + (size_t)(n0 + 16 * rt + row) * nvp;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) bp[q] = hin + (size_t)(k0 + 16 * q + row) * nvp;
-  const int v0 = c * chunk_len, v1 = min(nvp, v0 + chunk_len);
-  f32x4 acc[4][8];
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[rt][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float dbs[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int vb = v0; vb < v1; vb += 32) {
-    const int va = vb + 8 * g;
-    bf16x8 ah[4], al[4];
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      float a[8];
-      load8(ap[rt] + va, a);
-      split8(a, ah[rt], al[rt]);
-      if (k0 == 0)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dbs[rt] += a[e];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      float b[8];
-      load8(bp[q] + va, b);
-      bf16x8 bh, bl;
-      split8(b, bh, bl);
-#pragma unroll
-      for (int rt = 0; rt < 4; ++rt) acc[rt][q] = mfma3(ah[rt], al[rt], bh, bl, acc[rt][q]);
-    }
-  }
-  float* pc = part + (size_t)c * kParams;
-#pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = k0 + 16 * q + row;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int n = n0 + 16 * rt + 4 * g + i;
-        pc[w_off(l) + n * kWidth + k] = acc[rt][q][i];
-      }
-    }
-  if (k0 == 0) {
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-      float d = dbs[rt];
-      d += __shfl_xor(d, 16);
-      d += __shfl_xor(d, 32);
-      if (g == 0) pc[b_off(l) + n0 + 16 * rt + row] = d;
-    }
-  }
+__global__ void __launch_bounds__(kLayerThreads)
+mlp_wgrad_layer_kernel(int nv, int nvp, int chunk_len, const float* __restrict__ x,
+                       const float* __restrict__ freqs, const float* __restrict__ H,
+                       const float* __restrict__ dZ, float* __restrict__ part) {
+  __shared__ WgradLds S;
+  const int l = blockIdx.x;
+  if (l == 0)
+    wgrad_layer<true, 16, 4, 4>(l, nv, nvp, chunk_len, x, freqs, H, dZ, part, S);
+  else if (l < 4)
+    wgrad_layer<false, 16, 4, 8>(l, nv, nvp, chunk_len, x, freqs, H, dZ, part, S);
+  else
+    wgrad_layer<false, 1, 1, 2>(l, nv, nvp, chunk_len, x, freqs, H, dZ, part, S);
 }
 
 // dparams = sum over the chunks (fixed order); W_1's pose columns are
@@ -653,10 +623,8 @@ extern "C" int mlp_backward(void* stream, int nv, const float* x, const float* f
   // weight-gradient kernels still run over the (zero) padding rows
   RGA_LAUNCH("mlp_bwd", mlp_backward_kernel, dim3(L.nvp / kRows), dim3(64 * kWaves), 0, s, nv, L.nvp, ddx, hi, lo, at<float>(ws, L.h),
              at<float>(ws, L.dz));
-  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_hidden_kernel, dim3(3, L.chunks), dim3(kHidThreads), 0, s,
-             L.nvp, L.chunk_len, at<float>(ws, L.h), at<float>(ws, L.dz), part);
-  RGA_LAUNCH("mlp_wgrad_io", mlp_wgrad_kernel, dim3(kTilesW - 24, L.chunks), dim3(64 * kWaves), 0, s,
-             nv, L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
+  RGA_LAUNCH("mlp_wgrad", mlp_wgrad_layer_kernel, dim3(kLayers, L.chunks), dim3(kLayerThreads), 0,
+             s, nv, L.nvp, L.chunk_len, x, freqs, at<float>(ws, L.h), at<float>(ws, L.dz), part);
   RGA_LAUNCH("mlp_reduce", mlp_reduce_kernel, dim3(rga::ceil_div(kParams, 256)), dim3(256), 0, s,
              L.chunks, theta, part, dparams);
   RGA_LAUNCH("mlp_dtheta", mlp_dtheta_kernel, dim3(1), dim3(kDthThreads), 0, s, L.chunks, params,

@@ -191,6 +191,12 @@ int mesh_visibility_noalloc(void* stream, int nv, int nf, const float* verts,
  * cam_pos    host float[3], camera centre in world space
  * precision  RGA_FP32 or RGA_BF16X3
  * color      [3][n] out;  front [n] uint8 out
+ * tape       NULL, or tape_bytes >= shade_tape_bytes(n, he, we) of device
+ *            memory (16-byte aligned, RGA_FP32 only) that receives the live
+ *            (Gaussian, direction) pairs the sum visited: per Gaussian their
+ *            number and, in the order visited, each pair's direction and
+ *            interpolated visibility.  The adjoint of the same inputs can
+ *            read them instead of testing every direction again.
  * Limits (RGA_EUNSUPPORTED otherwise): V % 16 == 0 and V <= 2048; hv | he
  * and wv | we; he*we <= 3584 directions; the LDS tables must fit 160 KB:
  * 32 K + 48 V bytes (forward) and 44 K + 48 V + 1536 bytes (adjoint) for
@@ -202,13 +208,23 @@ int shade_gaussians(void* stream, int n, const float* x, const float* nrm, const
                     const float* rough, const float* tint, const int32_t* vidx, const float* vw,
                     const uint8_t* count, int nv, int kv, int he, int we, int hv, int wv,
                     const float* env, const float* cam_pos, int precision, float* color,
-                    uint8_t* front);
+                    uint8_t* front, void* tape, size_t tape_bytes);
+
+/* Bytes of a live-pair tape for n Gaussians and an he x we map: an int32
+ * count per Gaussian (rounded up to 256 bytes), then 8 bytes per
+ * (Gaussian, direction) slot.                                               */
+size_t shade_tape_bytes(int n, int he, int we);
 
 /* Adjoint of shade_gaussians.  Recomputes the BRDF weights; L_o is recovered
  * from `color` (the forward output) by inverting the transfer curve.
  * dcolor [3][n] in.  Outputs: dx [3][n] (ACCUMULATES: dx += d/dx'),
  * dn [3][n], dalbedo [3][n], drough [n], dtint [n] (overwritten),
- * denv [he*we][3] (overwritten).  ws: shade_gaussians_workspace bytes.      */
+ * denv [he*we][3] (overwritten).  ws: shade_gaussians_workspace bytes.
+ * tape: NULL (every direction is tested again), or the tape that
+ * shade_gaussians wrote for these same inputs (x, nrm, rough, vidx, vw,
+ * count, env, cam_pos, the grids): the live pairs are read from it, which
+ * gives the same sums with less work.  A tape from other inputs gives wrong
+ * gradients (it is not checked).  RGA_FP32 only.                            */
 size_t shade_gaussians_workspace(int n, int he, int we);
 int shade_gaussians_backward(void* stream, int n, const float* x, const float* nrm,
                              const float* albedo, const float* rough, const float* tint,
@@ -217,7 +233,7 @@ int shade_gaussians_backward(void* stream, int n, const float* x, const float* n
                              const float* cam_pos, int precision, const float* color,
                              const uint8_t* front, const float* dcolor, float* dx, float* dn,
                              float* dalbedo, float* drough, float* dtint, float* denv, void* ws,
-                             size_t ws_bytes);
+                             size_t ws_bytes, const void* tape, size_t tape_bytes);
 
 /* ------------------------------------------------------------------------
  * Sec. 3.1, last paragraph: splatting with the 3DGS tile rasterizer.

@@ -32,6 +32,10 @@ struct ShadeArgs {
   const int32_t* vidx;
   const uint8_t* count;
   int patch;   // table slots in 4 x 8 texel patches (the MFMA kernels), else texel order
+  // the live-pair tape of the FP32 form (NULL: none): per Gaussian its count
+  // and its live (direction, visibility) pairs in walk order, [n][K]
+  int32_t* tape_n;
+  uint2* tape;
 };
 
 // Direction k held by table slot s.  In texel order s = k.  In patch order
@@ -422,11 +426,12 @@ __device__ inline int cand_take(const ShadeArgs& a, const Cand& C, int j, Attr& 
 
 // Walk the K directions of one Gaussian 64 at a time: lane = direction,
 // the live ones (n.w_k > 0 and visibility > 0) appended with their
-// visibility to the wave's ring; flush(k, v, on) on every whole wave of
-// ring entries as it fills and on the remainder.
+// visibility to the wave's ring; flush(k, v, on, base) on every whole wave
+// of ring entries as it fills and on the remainder (base = the number of
+// live pairs flushed before).  Returns the number of live pairs.
 template <class Flush>
-__device__ inline void live_walk(const GaussCtx& G, const float* tab, int K, int V, int* qk,
-                                 float* qv, int lane, uint64_t lt, Flush&& flush) {
+__device__ inline int live_walk(const GaussCtx& G, const float* tab, int K, int V, int* qk,
+                                float* qv, int lane, uint64_t lt, Flush&& flush) {
   int head = 0, tail = 0;
   for (int k0 = 0; k0 < K; k0 += 64) {
     const int k = k0 + lane;
@@ -442,7 +447,7 @@ __device__ inline void live_walk(const GaussCtx& G, const float* tab, int K, int
     if (tail - head >= 64) {
       wave_fence();
       const int slot = (head + lane) & (kRing - 1);
-      flush(qk[slot], qv[slot], true);
+      flush(qk[slot], qv[slot], true, head);
       head += 64;
       wave_fence();
     }
@@ -450,9 +455,10 @@ __device__ inline void live_walk(const GaussCtx& G, const float* tab, int K, int
   if (tail > head) {
     wave_fence();
     const int slot = (head + lane) & (kRing - 1);
-    flush(qk[slot], qv[slot], lane < tail - head);
+    flush(qk[slot], qv[slot], lane < tail - head, head);
     wave_fence();
   }
+  return tail;
 }
 
 // (up to 512 views: three workgroups per CU, six waves per SIMD)
@@ -486,6 +492,7 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
         if (!C.front) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) color[(size_t)c * n + C.g] = 0.f;
+          if (a.tape_n) a.tape_n[C.g] = 0;
         }
       }
       fm = __ballot(C.front);
@@ -517,8 +524,12 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
     GaussCtx G;
     gauss_setup<true>(a, A, rows0 + cur * 3 * V, G);
     float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f, ss0 = 0.f, ss1 = 0.f, ss2 = 0.f;
-    live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on) {
+    // this Gaussian's row of the tape (a wave-uniform address)
+    uint2* const trow = a.tape ? a.tape + (size_t)uni(g) * K : nullptr;
+    const int nlive = live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt,
+                                [&](int k, float v, bool on, int base) {
       if (on) {
+        if (trow) trow[base + lane] = make_uint2((uint32_t)k, __float_as_uint(v));
         Pair P;
         pair_eval(G, tab, K, k, v, P);
         sd0 = fmaf(P.Wd, P.E[0], sd0);
@@ -529,6 +540,7 @@ shade_fwd_kernel(ShadeArgs a, float* __restrict__ color, uint8_t* __restrict__ f
         ss2 = fmaf(P.Ws, P.E[2], ss2);
       }
     });
+    if (trow && lane == 0) a.tape_n[g] = nlive;
     sd0 = rga::wave_sum(sd0);
     sd1 = rga::wave_sum(sd1);
     sd2 = rga::wave_sum(sd2);
@@ -974,8 +986,11 @@ shade_bwd_mfma_kernel(ShadeArgs a, int ratio, const float* __restrict__ color,
 }
 
 // (up to 512 views: two workgroups per CU, four waves per SIMD, at most
-// 128 VGPRs)
-template <int NQ>
+// 128 VGPRs).  With TAPE the live pairs of each Gaussian are read from the
+// forward's tape, in the order and 64-pair groups the walk would produce
+// them (so the sums are the same), instead of testing every direction: no
+// count rows, no ring.
+template <int NQ, bool TAPE>
 __global__ void __launch_bounds__(kThreads, NQ <= 2 ? 4 : 2)
 shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __restrict__ dcolor,
                  float* __restrict__ dx, float* __restrict__ dn, float* __restrict__ dalbedo,
@@ -988,7 +1003,7 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
   float* denv_lds = tab + 8 * K;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  uint8_t* rows0 = reinterpret_cast<uint8_t*>(tab + 11 * K) + (size_t)wave * 6 * V;
+  uint8_t* rows0 = TAPE ? nullptr : reinterpret_cast<uint8_t*>(tab + 11 * K) + (size_t)wave * 6 * V;
   build_table(a, tab);
   for (int i = threadIdx.x; i < 3 * K; i += blockDim.x) denv_lds[i] = 0.f;
   __syncthreads();
@@ -1025,7 +1040,16 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
     Attr A;
     int g = cand_take(a, C, __builtin_ctzll(fm), A);
     fm &= fm - 1;
-    rows_copy(a, plan, A.vidx, rows0);
+    // TAPE: the Gaussian's live count and first 64 pairs (lane < K keeps
+    // the read inside the Gaussian's row of the tape)
+    int tl = 0;
+    uint2 tw = make_uint2(0u, 0u);
+    if constexpr (TAPE) {
+      tl = a.tape_n[g];
+      if (lane < K) tw = a.tape[(size_t)g * K + lane];
+    } else {
+      rows_copy(a, plan, A.vidx, rows0);
+    }
     float pcol = color[(size_t)ch * n + g], pdc = dcolor[(size_t)ch * n + g];
     wait_all();
     int cur = 0;
@@ -1049,15 +1073,22 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
       const bool more = fm != 0ull;
       Attr An;
       int gn = -1;
+      int tln = 0;
+      uint2 twn = make_uint2(0u, 0u);
       if (more) {
         gn = cand_take(a, C, __builtin_ctzll(fm), An);
         fm &= fm - 1;
-        rows_copy(a, plan, An.vidx, rows0 + (cur ^ 1) * 3 * V);
+        if constexpr (TAPE) {
+          tln = a.tape_n[gn];
+          if (lane < K) twn = a.tape[(size_t)gn * K + lane];
+        } else {
+          rows_copy(a, plan, An.vidx, rows0 + (cur ^ 1) * 3 * V);
+        }
         pcol = color[(size_t)ch * n + gn];
         pdc = dcolor[(size_t)ch * n + gn];
       }
       GaussCtx G;
-      gauss_setup<true>(a, A, rows0 + cur * 3 * V, G);
+      gauss_setup<true>(a, A, TAPE ? nullptr : rows0 + cur * 3 * V, G);
       // dL/dL_o: lane c < 3 takes channel c, every lane reads the three
       float dLo[3], aop[3], qd[3];
       {
@@ -1073,9 +1104,21 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
       }
       const float tint = A.tint;
       BwdAcc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f, {0.f, 0.f, 0.f}, 0.f};
-      live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on) {
-        if (on) pair_bwd(G, tab, denv_lds, K, k, v, qd, dLo, tint, aop, acc);
-      });
+      if constexpr (TAPE) {
+        // 64 pairs at a time, the next group's read issued before this one
+        uint2 w = tw;
+        for (int base = 0; base < tl; base += 64) {
+          uint2 wn2 = make_uint2(0u, 0u);
+          if (base + 64 < tl && base + 64 + lane < K) wn2 = a.tape[(size_t)g * K + base + 64 + lane];
+          if (base + lane < tl)
+            pair_bwd(G, tab, denv_lds, K, (int)w.x, __uint_as_float(w.y), qd, dLo, tint, aop, acc);
+          w = wn2;
+        }
+      } else {
+        live_walk(G, tab, K, V, qk[wave], qv[wave], lane, lt, [&](int k, float v, bool on, int) {
+          if (on) pair_bwd(G, tab, denv_lds, K, k, v, qd, dLo, tint, aop, acc);
+        });
+      }
       // per-Gaussian sums of the twelve partials over the wave: four slots
       // of three values (lane swaps and DPP), slot s summed in row s
       float r[12];
@@ -1119,6 +1162,8 @@ shade_bwd_kernel(ShadeArgs a, const float* __restrict__ color, const float* __re
       if (!more) break;
       A = An;
       g = gn;
+      tl = tln;
+      tw = twn;
       cur ^= 1;
     }
     if (lane < 3) {
@@ -1173,7 +1218,8 @@ denv_reduce_kernel(int K, int he, int we, int parts, const float* __restrict__ p
 template <int NQ>
 void set_lds_limits_nq() {
   const void* ks[] = {reinterpret_cast<const void*>(shade_fwd_kernel<NQ>),
-                      reinterpret_cast<const void*>(shade_bwd_kernel<NQ>)};
+                      reinterpret_cast<const void*>(shade_bwd_kernel<NQ, false>),
+                      reinterpret_cast<const void*>(shade_bwd_kernel<NQ, true>)};
   for (const void* k : ks) hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 152 * 1024);
 }
 
@@ -1218,11 +1264,14 @@ int grid_for(const void* kernel, int n, size_t lds) {
 
 // The FP32 kernel instance for the number of 1024-byte pieces of a
 // Gaussian's three count rows.
-const void* fp32_kernel(bool adjoint, int nq) {
+// (The adjoint that reads a tape copies no rows: one instance serves every
+// view count.)
+const void* fp32_kernel(bool adjoint, int nq, bool tape = false) {
+  if (adjoint && tape) return reinterpret_cast<const void*>(shade_bwd_kernel<2, true>);
   if (nq <= 2)
-    return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<2>)
+    return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<2, false>)
                    : reinterpret_cast<const void*>(shade_fwd_kernel<2>);
-  return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<6>)
+  return adjoint ? reinterpret_cast<const void*>(shade_bwd_kernel<6, false>)
                  : reinterpret_cast<const void*>(shade_fwd_kernel<6>);
 }
 
@@ -1273,9 +1322,34 @@ ShadeArgs make_args(int n, const float* x, const float* nrm, const float* albedo
   a.vidx = vidx;
   a.count = count;
   a.patch = 0;
+  a.tape_n = nullptr;
+  a.tape = nullptr;
   return a;
 }
 
+}  // namespace
+
+// The live-pair tape: [n] int32 counts (256-byte aligned block), then
+// [n][K] (direction, visibility bits) pairs.
+extern "C" size_t shade_tape_bytes(int n, int he, int we) {
+  if (n < 0 || he < 1 || we < 1) return 0;
+  return rga::align_up((size_t)4 * (n > 0 ? n : 1), 256) + (size_t)8 * n * he * we;
+}
+
+namespace {
+int attach_tape(const char* fn, ShadeArgs& a, int precision, const void* tape, size_t tape_bytes) {
+  if (!tape) return RGA_OK;
+  if (precision != RGA_FP32)
+    return rga::fail(RGA_EUNSUPPORTED, "%s: the tape belongs to the FP32 form", fn);
+  if (!rga::aligned16(tape)) return rga::fail(RGA_EINVAL, "%s: tape must be 16-byte aligned", fn);
+  if (tape_bytes < shade_tape_bytes(a.n, a.he, a.we))
+    return rga::fail(RGA_ECAPACITY, "%s: tape %zu < %zu bytes", fn, tape_bytes,
+                     shade_tape_bytes(a.n, a.he, a.we));
+  char* t = static_cast<char*>(const_cast<void*>(tape));
+  a.tape_n = reinterpret_cast<int32_t*>(t);
+  a.tape = reinterpret_cast<uint2*>(t + rga::align_up((size_t)4 * (a.n > 0 ? a.n : 1), 256));
+  return RGA_OK;
+}
 }  // namespace
 
 extern "C" int shade_gaussians(void* stream, int n, const float* x, const float* nrm,
@@ -1283,7 +1357,7 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
                                const int32_t* vidx, const float* vw, const uint8_t* count, int nv,
                                int kv, int he, int we, int hv, int wv, const float* env,
                                const float* cam_pos, int precision, float* color,
-                               uint8_t* front) {
+                               uint8_t* front, void* tape, size_t tape_bytes) {
   int rc = check_args("shade_gaussians", n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv,
                       he, we, hv, wv, env, cam_pos, precision);
   if (rc) return rc;
@@ -1291,6 +1365,8 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
   if (!color || !front) return rga::fail(RGA_EINVAL, "shade_gaussians: null output");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
+  rc = attach_tape("shade_gaussians", a, precision, tape, tape_bytes);
+  if (rc) return rc;
   if (precision == RGA_BF16X3) {
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians: BF16X3 needs a multiple of 32 directions");
@@ -1352,7 +1428,8 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
                                         const float* color, const uint8_t* front,
                                         const float* dcolor, float* dx, float* dn,
                                         float* dalbedo, float* drough, float* dtint, float* denv,
-                                        void* ws, size_t ws_bytes) {
+                                        void* ws, size_t ws_bytes, const void* tape,
+                                        size_t tape_bytes) {
   (void)front;
   int rc = check_args("shade_gaussians_backward", n, x, nrm, albedo, rough, tint, vidx, vw, count,
                       nv, kv, he, we, hv, wv, env, cam_pos, precision);
@@ -1362,6 +1439,8 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null pointer");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
+  rc = attach_tape("shade_gaussians_backward", a, precision, tape, tape_bytes);
+  if (rc) return rc;
   if (precision == RGA_BF16X3) {
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
@@ -1398,13 +1477,15 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     RGA_CHECK_LAUNCH("shade_gaussians_backward");
     return RGA_OK;
   }
-  const size_t lds = fp32_lds(a.K, a.V, true);
+  const bool taped = a.tape != nullptr;
+  // with a tape: the direction table and the environment sums only
+  const size_t lds = taped ? (size_t)11 * a.K * sizeof(float) : fp32_lds(a.K, a.V, true);
   if (lds > 152 * 1024)
     return rga::fail(RGA_EUNSUPPORTED,
                      "shade_gaussians_backward: %d directions and %d views need %zu B of LDS", a.K,
                      a.V, lds);
   const int nq = (int)rga::ceil_div(3 * a.V, 1024);
-  const void* kern = fp32_kernel(true, nq);
+  const void* kern = fp32_kernel(true, nq, taped);
   const int grid = grid_for(kern, n, lds);
   if (!ws || ws_bytes < (size_t)grid * 3 * a.K * sizeof(float))
     return rga::fail(RGA_ECAPACITY, "shade_gaussians_backward: workspace too small");

@@ -82,6 +82,9 @@ class Renderer:
         self.l1_ws = None
         self.img_ws = None
         self.image_loss = False
+        # the FP32 shading records its live (Gaussian, direction) pairs on a
+        # tape that the adjoint replays instead of testing every direction
+        self.tape = None
         # every splat_forward on self.ws overwrites the lists and blend state
         # that the adjoint reads: a forward's context records the generation
         # it was rendered in, and a backward of an older forward is refused
@@ -116,12 +119,18 @@ class Renderer:
         d, s = self.d, self.s
         xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
                                  disp=p.get("disp"))
+        if self.precision == "fp32" and self.tape is None:
+            self.tape = rga.shade_tape(self.n, s["he"], s["we"], xo.device)
+        tape = self.tape if self.precision == "fp32" else None
         color, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
                                            d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
-                                           s["wv"], p["env"], self.cam_pos, self.precision)
+                                           s["wv"], p["env"], self.cam_pos, self.precision,
+                                           tape=tape)
         image, T = self._splat(xo, A, p["quat"], p["log_s"], p["opac"], color, front)
+        # the tape, like the splat workspace, holds this forward's state until
+        # the next forward (the generation check below covers both)
         ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count,
-                   generation=self.generation, ws=self.ws)
+                   generation=self.generation, ws=self.ws, tape=tape)
         return image, T, ctx
 
     # ------------------------------------------------------------------ editing maps
@@ -158,7 +167,7 @@ class Renderer:
             ctx["xo"], ctx["no"], p["albedo"], p["rough"], p["tint"], d["vidx"], d["vw"],
             ctx["count"], s["kv"], s["he"], s["we"], s["hv"], s["wv"], p["env"], self.cam_pos,
             ctx["color"], ctx["front"], g["dcolor"], dx_accum=g["dx"], precision=self.precision,
-            ws=self.shade_ws)
+            ws=self.shade_ws, tape=ctx.get("tape"))
         dpos, dnrm = rga.lbs_skin_backward(d["skin"], d["jidx"], d["jw"], sh["dx"], sh["dn"])
         out = dict(pos=dpos, nrm=dnrm, quat=g["dquat"], log_s=g["dlog_s"], opac=g["dopac"],
                    albedo=sh["dalbedo"], rough=sh["drough"], tint=sh["dtint"], env=sh["denv"],

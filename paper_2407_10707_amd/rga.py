@@ -46,11 +46,12 @@ _SIGS = {
     "mesh_visibility_noalloc_limit": (_SZ, []),
     "mesh_visibility_noalloc": (_I, [_VP, _I, _I, _VP, _VP, _I, _VP, _I, _VP, _I, _VP, _VP]),
     "shade_gaussians": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _I,
-                             _I, _VP, _VP, _I, _VP, _VP]),
+                             _I, _VP, _VP, _I, _VP, _VP, _VP, _SZ]),
+    "shade_tape_bytes": (_SZ, [_I, _I, _I]),
     "shade_gaussians_workspace": (_SZ, [_I, _I, _I]),
     "shade_gaussians_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I,
                                       _I, _I, _I, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
-                                      _VP, _VP, _VP, _SZ]),
+                                      _VP, _VP, _VP, _SZ, _VP, _SZ]),
     "splat_workspace_size": (_SZ, [_I, _I, _I, _I64]),
     "splat_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
                            _VP]),
@@ -307,8 +308,23 @@ def mesh_visibility_noalloc(verts, faces, view_dirs, res: int, knn, want_raw: bo
 
 
 # ----------------------------------------------------------------------------- shading
+def shade_tape(n: int, he: int, we: int, device):
+    """A live-pair tape for shade_gaussians / shade_gaussians_backward."""
+    return torch.empty(max(16, int(lib().shade_tape_bytes(n, he, we))), dtype=torch.uint8,
+                       device=device)
+
+
+def _tape(tape):
+    if tape is None:
+        return None, 0
+    _u8(tape, "tape")
+    return _p(tape), tape.numel()
+
+
 def shade_gaussians(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env,
-                    cam_pos, precision: str = "fp32"):
+                    cam_pos, precision: str = "fp32", tape=None):
+    """tape: None, or a buffer from shade_tape that receives the live pairs
+    (FP32 form) for a shade_gaussians_backward of the same inputs."""
     n = x.shape[1]
     nv = count.shape[0]
     _f32(x, "x", (3, n))
@@ -326,13 +342,14 @@ def shade_gaussians(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv
     _check(lib().shade_gaussians(_stream(), n, _p(x), _p(nrm), _p(albedo), _p(rough), _p(tint),
                                  _p(vidx), _p(vw), _p(count), nv, kv, he, we, hv, wv, _p(env),
                                  C.cast(cp, C.c_void_p), PRECISIONS[precision], _p(color),
-                                 _p(front)), "shade_gaussians")
+                                 _p(front), *_tape(tape)), "shade_gaussians")
     return color, front
 
 
 def shade_gaussians_backward(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv,
                              env, cam_pos, color, front, dcolor, dx_accum=None,
-                             precision: str = "fp32", ws=None):
+                             precision: str = "fp32", ws=None, tape=None):
+    """tape: None, or the tape shade_gaussians filled for these inputs."""
     n = x.shape[1]
     nv = count.shape[0]
     _f32(dcolor, "dcolor", (3, n))
@@ -350,7 +367,7 @@ def shade_gaussians_backward(x, nrm, albedo, rough, tint, vidx, vw, count, kv, h
         _stream(), n, _p(x), _p(nrm), _p(albedo), _p(rough), _p(tint), _p(vidx), _p(vw),
         _p(count), nv, kv, he, we, hv, wv, _p(env), C.cast(cp, C.c_void_p), PRECISIONS[precision],
         _p(color), _p(front), _p(dcolor), _p(dx), _p(dn), _p(dalb), _p(drough), _p(dtint),
-        _p(denv), _p(ws), ws.numel()), "shade_gaussians_backward")
+        _p(denv), _p(ws), ws.numel(), *_tape(tape)), "shade_gaussians_backward")
     return dict(dx=dx, dn=dn, dalbedo=dalb, drough=drough, dtint=dtint, denv=denv)
 
 

@@ -69,7 +69,8 @@ def test_argument_errors_are_reported_before_any_launch():
     assert "image size" in rga.last_error()
     cp = (C.c_float * 3)(0, 0, 3)
     assert L.shade_gaussians(None, 10, None, None, None, None, None, None, None, None, 7000, 19,
-                             16, 32, 5, 32, None, C.cast(cp, C.c_void_p), 0, None, None) == -1
+                             16, 32, 5, 32, None, C.cast(cp, C.c_void_p), 0, None, None, None,
+                             0) == -1
     assert "divide" in rga.last_error()
     assert L.l1_loss(None, 0, None, None, None, None, None, 0) == -1
     assert L.knn_query(None, 10, None, 5, 6, None, None, None, 0, None, 0) == -1

@@ -88,14 +88,16 @@ def traffic_from_profile(kernel: str, config: int):
     return int(m_val.group(1)) if sha == m_sha.group(1) else None
 
 
-def shade_flops(live_pairs: float, tested_pairs: float, backward: bool) -> float:
+def shade_flops(live_pairs: float, tested_pairs: float, backward: bool,
+                tested: bool = True) -> float:
     """Algorithmic FP32 operations of the shading sum: per tested (Gaussian,
     direction) pair the horizon and visibility test (n.w: 5, visibility
     interpolation: 5, compare: 1); per live pair the BRDF weights and the
     accumulation (forward 72, backward 171; counted from the formulas, an
-    FMA as 2)."""
+    FMA as 2).  An adjoint that replays the forward's live-pair tape tests
+    nothing (tested=False)."""
     per_live = 171.0 if backward else 72.0
-    return tested_pairs * 11.0 + live_pairs * per_live
+    return (tested_pairs * 11.0 if tested else 0.0) + live_pairs * per_live
 
 
 def shading_pairs(s, R, p, count):
@@ -469,9 +471,10 @@ def measure_form(args, s, d, precision: str, capacity=None):
         return loss
 
     def fwd(with_vis, count=None):
+        # a frame for display: no tape for an adjoint
         if with_vis:
             count = R.visibility()
-        R.forward(p, count)
+        R.forward(p, count, for_backward=False)
         return count
 
     # size the splat workspace to the real duplicate count (every pose of a
@@ -577,14 +580,17 @@ def measure_form(args, s, d, precision: str, capacity=None):
     wl = shading_pairs(s, R, p, count)
     roof = None
     if kernel.startswith("shade_bwd") or kernel.startswith("shade_fwd"):
-        flops = shade_flops(wl["live"], wl["tested"], kernel.startswith("shade_bwd"))
+        # the FP32 renderer's adjoint replays the forward's tape
+        replay = kernel == "shade_bwd" and R.tape is not None
+        flops = shade_flops(wl["live"], wl["tested"], kernel.startswith("shade_bwd"),
+                            tested=not replay)
         ach = flops / (k_avg * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_TFLOPS, 4),
                 "traffic": traffic_from_profile(kernel, args.config),
                 "kernel": kernel, "kernel_ms": round(k_avg, 4),
-                "work": {"tested_pairs": wl["tested"], "live_pairs": wl["live"],
-                         "flops_per_launch": flops}}
+                "work": {"tested_pairs": 0 if replay else wl["tested"],
+                         "live_pairs": wl["live"], "flops_per_launch": flops}}
     # this frame's image (pose 0, map 0) for the image-error report
     image, _, _ = R.forward(p, count)
     torch.cuda.synchronize()

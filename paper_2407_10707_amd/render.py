@@ -115,13 +115,19 @@ class Renderer:
         return rga.splat_forward(self.cam, *args, self.ws)
 
     # ------------------------------------------------------------------ forward
-    def forward(self, p: Dict[str, torch.Tensor], count: torch.Tensor):
+    def forward(self, p: Dict[str, torch.Tensor], count: torch.Tensor, for_backward: bool = True):
+        """One frame.  With for_backward (the default) the FP32 shading also
+        records the tape its adjoint replays; a frame only for display skips
+        it (a backward of such a frame still works: it tests every direction
+        again)."""
         d, s = self.d, self.s
         xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
                                  disp=p.get("disp"))
-        if self.precision == "fp32" and self.tape is None:
-            self.tape = rga.shade_tape(self.n, s["he"], s["we"], xo.device)
-        tape = self.tape if self.precision == "fp32" else None
+        tape = None
+        if for_backward and self.precision == "fp32":
+            if self.tape is None:
+                self.tape = rga.shade_tape(self.n, s["he"], s["we"], xo.device)
+            tape = self.tape
         color, front = rga.shade_gaussians(xo, no, p["albedo"], p["rough"], p["tint"], d["vidx"],
                                            d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
                                            s["wv"], p["env"], self.cam_pos, self.precision,

@@ -133,3 +133,27 @@ def test_tape_refused_when_misused():
     tape = rga.shade_tape(50, s["he"], s["we"], "cuda")
     with pytest.raises(rga.RgaError, match="FP32"):
         rga.shade_gaussians(*args, campos, precision="bf16x3", tape=tape)
+
+
+def test_renderer_frames_with_and_without_tape():
+    """A training frame records the tape and its adjoint replays it; a
+    display frame records none and its adjoint tests every direction: the
+    gradients agree."""
+    s = synth.micro_scene(17, 400, 64, 64, he=16, we=32, hv=16, wv=32)
+    d, _ = render.layout_by_vertex(render.upload(s))
+    R = render.Renderer(s, d)
+    p = {k: d[k] for k in render.TRAINABLE}
+    _, _, cnt = helpers.oracle_visibility(s)
+    count = dev(cnt)
+    w = dev(np.random.default_rng(2).random((3, s["height"], s["width"])).astype(np.float32))
+    img1, _, ctx1 = R.forward(p, count)
+    assert ctx1["tape"] is not None
+    g1 = R.backward(p, ctx1, w)
+    img2, _, ctx2 = R.forward(p, count, for_backward=False)
+    assert ctx2["tape"] is None
+    g2 = R.backward(p, ctx2, w)
+    assert torch.equal(img1, img2)
+    for k in render.TRAINABLE:
+        ok, err = _close(g1[k], g2[k], 1e-5)
+        print(f"  {k:8s} {err:.1e}", flush=True)
+        assert ok, (k, err)

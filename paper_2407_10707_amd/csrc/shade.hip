@@ -14,6 +14,12 @@
 // The direction table (unit direction, radiance x solid angle, view index)
 // is built in LDS by every workgroup; workgroups are persistent and loop
 // over Gaussians.
+//
+// Given a tape, the forward also writes each Gaussian's live (direction,
+// visibility) pairs, in the order and 64-pair groups of its walk; the
+// adjoint of the same inputs then replays them instead of walking every
+// direction again (same pairs, same lanes, same sums), which removes the
+// direction test, the count rows and the ring from the adjoint.
 #include "common.h"
 
 #include <math.h>

@@ -195,16 +195,24 @@ __global__ void __launch_bounds__(1024)
 frame_kernel(int nv, const float* __restrict__ v, float* __restrict__ frame) {
   __shared__ float ext[6][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // one pass: each thread's vertices, all three axes at once (the loads of
+  // an iteration are independent)
+  float lo3[3], hi3[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lo3[a] = hi3[a] = v[a * nv];
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float c = v[a * nv + i];
+      lo3[a] = fminf(lo3[a], c);
+      hi3[a] = fmaxf(hi3[a], c);
+    }
+  }
   float r[6];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float l = v[a * nv], h = v[a * nv];
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-      l = fminf(l, v[a * nv + i]);
-      h = fmaxf(h, v[a * nv + i]);
-    }
-    r[a] = wave_extreme<false>(l);
-    r[3 + a] = wave_extreme<true>(h);
+    r[a] = wave_extreme<false>(lo3[a]);
+    r[3 + a] = wave_extreme<true>(hi3[a]);
   }
   if (lane == 63) {
 #pragma unroll

@@ -458,8 +458,9 @@ def measure_form(args, s, d, precision: str, capacity=None):
 
     def step():
         if not args.sequence:
-            count = R.visibility()
-            loss, grads = R.train_step(p, count, target, check=False)
+            # the visibility of the pose is computed inside the frame,
+            # beside the binning of the splats
+            loss, grads = R.train_step(p, None, target, check=False)
             return loss
         k, e = divmod(seq["frame"] % frames, cfg.n_env)
         seq["frame"] += 1
@@ -472,10 +473,8 @@ def measure_form(args, s, d, precision: str, capacity=None):
 
     def fwd(with_vis, count=None):
         # a frame for display: no tape for an adjoint
-        if with_vis:
-            count = R.visibility()
-        R.forward(p, count, for_backward=False)
-        return count
+        _, _, ctx = R.forward(p, None if with_vis else count, for_backward=False)
+        return ctx["count"]
 
     # size the splat workspace to the real duplicate count (every pose of a
     # sequence), then start the sequence again at frame 0
@@ -669,8 +668,7 @@ def main():
     mom = {k: (torch.zeros_like(t), torch.zeros_like(t)) for k, t in p.items()}
 
     def train_iter(it):
-        count = R.visibility()
-        _, grads = R.train_step(p, count, target, check=False)
+        _, grads = R.train_step(p, None, target, check=False)
         for k, (m1, m2) in mom.items():
             if k in grads:
                 rga.adam_step(p[k], grads[k], m1, m2, 1e-7, it)
@@ -710,8 +708,7 @@ def main():
     def vertex_iter():
         # the total loss of Sec. 3.3: the image loss plus the weighted
         # regularisers, whose gradients the library adds to the image loss's
-        count = R.visibility()
-        image, _, ctx = M.forward(vv, count)
+        image, _, ctx = M.forward(vv, None)
         loss, dimage = R.loss(image, target)
         M.backward(vv, ctx, dimage, loss=loss)
 

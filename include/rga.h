@@ -266,8 +266,35 @@ int splat_forward(void* stream, int n, const rga_camera* cam, const float* x, co
                   const uint8_t* front, void* ws, size_t ws_bytes, int64_t capacity,
                   float* image, float* T_final);
 
+/* splat_forward in two calls, so that the part the colours do not enter can
+ * run while the shading computes them.  splat_bin: projection, depth sort,
+ * duplication, tile sort, tile ranges and work items (arguments as for
+ * splat_forward).  splat_blend: the colours [3][n] into the per-splat
+ * records, then the compositing; image and T_final as for splat_forward.
+ * splat_blend reads what the last splat_bin left in ws (same n, camera and
+ * capacity): the caller orders the two (one stream, or an event between
+ * two).  splat_forward = splat_bin then splat_blend on one stream.
+ * Errors as for splat_forward.                                             */
+int splat_bin(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
+              const float* quat, const float* log_s, const float* opac, const uint8_t* front,
+              void* ws, size_t ws_bytes, int64_t capacity);
+int splat_blend(void* stream, int n, const rga_camera* cam, const float* color, void* ws,
+                size_t ws_bytes, int64_t capacity, float* image, float* T_final);
+
+/* Sec. 3.1, the back-face rule (a Gaussian whose normal faces away from the
+ * camera gets zero opacity) on its own: front[g] = 1 if
+ * nrm_g . (cam_pos - x_g) > 0 in FP32 on the unnormalised posed normal,
+ * evaluated as fma(n_z, w_z, fma(n_y, w_y, n_x w_x)) with w = cam_pos - x_g,
+ * else 0 -- bit for bit the flags shade_gaussians writes, for a caller that
+ * bins the splats (splat_bin) before the shading runs.  x, nrm [3][n]
+ * device; cam_pos host float[3]; front [n] uint8 device out.
+ * Errors: RGA_EINVAL (n < 0, null pointers).                               */
+int back_face(void* stream, int n, const float* x, const float* nrm, const float* cam_pos,
+              uint8_t* front);
+
 /* Synchronises `stream` and returns the duplicate count D of the last
- * splat_forward that used ws (may exceed capacity: then re-run larger).    */
+ * splat_forward (or splat_bin) that used ws (may exceed capacity: then
+ * re-run larger).                                                          */
 int splat_read_count(void* stream, const void* ws, int n, int width, int height,
                      int64_t capacity, int64_t* D);
 

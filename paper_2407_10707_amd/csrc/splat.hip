@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256)
 preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x,
                   const float* __restrict__ A, const float* __restrict__ quat,
                   const float* __restrict__ log_s, const float* __restrict__ opac,
-                  const float* __restrict__ color, const uint8_t* __restrict__ front,
+                  const uint8_t* __restrict__ front,
                   float4* __restrict__ rec, float* __restrict__ mean2d, float* __restrict__ conic,
                   float* __restrict__ depth, int32_t* __restrict__ rect,
                   int32_t* __restrict__ touched, uint8_t* __restrict__ fp64,
@@ -325,15 +325,16 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
     }
   }
   // the blend evaluates the exponent of alpha in base 2: the record holds
-  // the conic scaled by -log2(e) / 2 (cross term by -log2(e))
+  // the conic scaled by -log2(e) / 2 (cross term by -log2(e)); its colour
+  // slots are filled by colour_pack_kernel once the colours exist
   rec[3 * g + 0] = make_float4(u, v, ca * kHalfNegLog2e, cb * (2.f * kHalfNegLog2e));
-  rec[3 * g + 1] = make_float4(cc * kHalfNegLog2e, o, color[g], color[n + g]);
+  rec[3 * g + 1] = make_float4(cc * kHalfNegLog2e, o, 0.f, 0.f);
   // for the blend's per-wave culling: the slopes of the exponent's maxima
   // along vertical and horizontal lines, and a lower bound of the exponent
   // any pixel with alpha >= 1/255 can have (r2 bounds 2 ln(255 o) from
   // above; the margin covers the rounding of both evaluations)
   const float thr = valid ? (r2_cull * kHalfNegLog2e) * 1.01f - 0.01f : 0.f;
-  rec[3 * g + 2] = make_float4(color[2 * n + g], valid ? -cb / cc : 0.f, valid ? -cb / ca : 0.f, thr);
+  rec[3 * g + 2] = make_float4(0.f, valid ? -cb / cc : 0.f, valid ? -cb / ca : 0.f, thr);
   mean2d[g] = valid ? u : 0.f;
   mean2d[n + g] = valid ? v : 0.f;
   conic[g] = ca;
@@ -348,6 +349,32 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
   fp64[g] = used64;
   keys[g] = cnt > 0 ? __float_as_uint(G.Z) : 0xFFFFFFFFu;
   vals[g] = (uint32_t)g;
+}
+
+// The splat colours into their records (rec[3g+1].zw, rec[3g+2].x): the
+// binning does not need them, so it can run before the shading has them.
+__global__ void __launch_bounds__(256)
+colour_pack_kernel(int n, const float* __restrict__ color, float4* __restrict__ rec) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float* r = reinterpret_cast<float*>(rec + 3 * (size_t)g);
+  r[6] = color[g];
+  r[7] = color[n + g];
+  r[8] = color[2 * (size_t)n + g];
+}
+
+// The back-face rule (a Gaussian whose normal faces away from the camera
+// gets zero opacity), for a caller that bins before it shades: the same
+// FP32 expression, in the same order, as the shading kernels' decision, so
+// the flags agree bit for bit.
+__global__ void __launch_bounds__(256)
+back_face_kernel(int n, const float* __restrict__ x, const float* __restrict__ nrm, float c0,
+                 float c1, float c2, uint8_t* __restrict__ front) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const float w0 = c0 - x[g], w1 = c1 - x[n + g], w2 = c2 - x[2 * (size_t)n + g];
+  const float m0 = nrm[g], m1 = nrm[n + g], m2 = nrm[2 * (size_t)n + g];
+  front[g] = fmaf(m2, w2, fmaf(m1, w1, m0 * w0)) > 0.f ? 1 : 0;
 }
 
 // ---- blend work items -------------------------------------------------------
@@ -442,36 +469,55 @@ radix_upsweep(const uint32_t* __restrict__ keys, const int64_t* cnt_ptr, int64_t
 
 // Exclusive scan of each digit's counts over the blocks that hold items
 // (the rest of a capacity-sized grid is skipped): 8 digits per workgroup,
-// 32 threads per digit each summing a run of blocks.
+// 32 threads per digit each summing a run of blocks (held in registers for
+// runs of up to kHeld blocks); the 32 run sums of a digit are scanned with
+// wave shuffles (lanes d, d + 8, ..., of each wave) and the four wave totals.
 template <int BITS>
 __global__ void __launch_bounds__(256)
 radix_binscan(const uint32_t* __restrict__ hist, int nb, const int64_t* cnt_ptr, int64_t fixed,
               int64_t cap, int block_items, uint32_t* __restrict__ binoff,
               uint32_t* __restrict__ bintot) {
   constexpr int kRadix = 1 << BITS;
-  __shared__ uint32_t part[8][33];
+  constexpr int kHeld = 8;
+  __shared__ uint32_t wtot[4][8];
   const int dl = threadIdx.x & 7, c = threadIdx.x >> 3;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int d = blockIdx.x * 8 + dl;
   const int64_t count = live_count(cnt_ptr, fixed, cap);
   const int nbl = (int)min((int64_t)nb, (count + block_items - 1) / block_items);
   const int chunk = (nbl + 31) / 32;
   const int j0 = c * chunk, j1 = min(nbl, j0 + chunk);
+  uint32_t held[kHeld];
   uint32_t s = 0;
-  for (int j = j0; j < j1; ++j) s += hist[(size_t)j * kRadix + d];
-  part[dl][c] = s;
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    uint32_t run = 0;
-    for (int q = 0; q < 32; ++q) {
-      const uint32_t v = part[threadIdx.x][q];
-      part[threadIdx.x][q] = run;
-      run += v;
-    }
-    bintot[blockIdx.x * 8 + threadIdx.x] = run;
+#pragma unroll
+  for (int q = 0; q < kHeld; ++q) {
+    held[q] = j0 + q < j1 ? hist[(size_t)(j0 + q) * kRadix + d] : 0u;
+    s += held[q];
   }
+  for (int j = j0 + kHeld; j < j1; ++j) s += hist[(size_t)j * kRadix + d];
+  uint32_t incl = s;                      // inclusive scan over c within the wave
+#pragma unroll
+  for (int o = 8; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
+  }
+  if (lane >= 56) wtot[wave][dl] = incl;
   __syncthreads();
-  uint32_t run = part[dl][c];
-  for (int j = j0; j < j1; ++j) {
+  uint32_t run = incl - s, total = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t x = wtot[w][dl];
+    run += w < wave ? x : 0u;
+    total += x;
+  }
+  if (c == 0) bintot[d] = total;
+#pragma unroll
+  for (int q = 0; q < kHeld; ++q)
+    if (j0 + q < j1) {
+      binoff[(size_t)(j0 + q) * kRadix + d] = run;
+      run += held[q];
+    }
+  for (int j = j0 + kHeld; j < j1; ++j) {
     const uint32_t v = hist[(size_t)j * kRadix + d];
     binoff[(size_t)j * kRadix + d] = run;
     run += v;
@@ -1483,6 +1529,18 @@ int check_common(const char* fn, int n, const rga_camera* cam, const void* ws, s
 
 }  // namespace
 
+extern "C" int back_face(void* stream, int n, const float* x, const float* nrm,
+                         const float* cam_pos, uint8_t* front) {
+  if (n < 0) return rga::fail(RGA_EINVAL, "back_face: n < 0");
+  if (n == 0) return RGA_OK;
+  if (!x || !nrm || !cam_pos || !front) return rga::fail(RGA_EINVAL, "back_face: null pointer");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RGA_LAUNCH("back_face", back_face_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s, n, x,
+             nrm, cam_pos[0], cam_pos[1], cam_pos[2], front);
+  RGA_CHECK_LAUNCH("back_face");
+  return RGA_OK;
+}
+
 extern "C" size_t splat_workspace_size(int n, int width, int height, int64_t capacity) {
   if (n < 0 || width < 1 || height < 1 || capacity < 1) return 0;
   return make_layout(n, width, height, capacity).total;
@@ -1523,20 +1581,19 @@ extern "C" int splat_read_count(void* stream, const void* ws, int n, int width, 
   return RGA_OK;
 }
 
-extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const float* x,
-                             const float* A, const float* quat, const float* log_s,
-                             const float* opac, const float* color, const uint8_t* front,
-                             void* ws, size_t ws_bytes, int64_t capacity, float* image,
-                             float* T_final) {
+// Projection, depth sort, duplication, tile sort, tile ranges and the
+// blend's work items: everything of the forward that the colours do not enter.
+extern "C" int splat_bin(void* stream, int n, const rga_camera* cam, const float* x,
+                         const float* A, const float* quat, const float* log_s,
+                         const float* opac, const uint8_t* front, void* ws, size_t ws_bytes,
+                         int64_t capacity) {
   Layout L;
-  int rc = check_common("splat_forward", n, cam, ws, ws_bytes, capacity, L);
+  int rc = check_common("splat_bin", n, cam, ws, ws_bytes, capacity, L);
   if (rc) return rc;
-  if (!image || !T_final) return rga::fail(RGA_EINVAL, "splat_forward: null output");
-  if (n > 0 && (!x || !A || !quat || !log_s || !opac || !color || !front))
-    return rga::fail(RGA_EINVAL, "splat_forward: null input");
+  if (n > 0 && (!x || !A || !quat || !log_s || !opac || !front))
+    return rga::fail(RGA_EINVAL, "splat_bin: null input");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const CamDev cd = to_dev(cam);
-  const int W = cam->width, H = cam->height;
   const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
   int64_t* cnt = at<int64_t>(ws, L.count);
   uint32_t* k0 = at<uint32_t>(ws, L.keys0);
@@ -1557,8 +1614,7 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
     // the projection also clears the tile ranges and the counters
     const int64_t pre_threads = std::max<int64_t>(std::max<int64_t>(n, 2 * tiles), 8);
     RGA_LAUNCH("splat_preprocess", preprocess_kernel, dim3(rga::ceil_div(pre_threads, 256)),
-               dim3(256), 0, s, n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, color,
-               front, at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
+               dim3(256), 0, s, n, cd, L.tiles_x, L.tiles_y, x, A, quat, log_s, opac, front, at<float4>(ws, L.rec), at<float>(ws, L.mean2d), at<float>(ws, L.conic),
                at<float>(ws, L.depth), at<int32_t>(ws, L.rect), at<int32_t>(ws, L.touched),
                at<uint8_t>(ws, L.fp64), k0, v0, reinterpret_cast<uint32_t*>(ranges), 2 * tiles,
                reinterpret_cast<uint32_t*>(cnt), at<float>(ws, L.grad), at<uint32_t>(ws, L.queue));
@@ -1611,13 +1667,34 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
       RGA_LAUNCH("tile_ranges", tile_ranges_kernel, dim3(rga::ceil_div(capacity, 256)), dim3(256), 0,
                  s, tk0, (const int64_t*)cnt, capacity, ranges);
   }
-  // work items (tile, chunk) unless the one-pass tile sort built them,
-  // chunk composites, front-to-back combine
-  const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
+  // work items (tile, chunk) unless the one-pass tile sort built them
   if (n == 0 || L.tile_passes > 1)
     RGA_LAUNCH("chunk_index", chunk_index_kernel, dim3(1), dim3(1024), 0, s, (int)tiles, ranges,
                at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
                at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items, cnt);
+  RGA_CHECK_LAUNCH("splat_bin");
+  return RGA_OK;
+}
+
+// The colours into the records, chunk composites, front-to-back combine,
+// restarts: the rest of the forward, on the lists splat_bin left in ws.
+extern "C" int splat_blend(void* stream, int n, const rga_camera* cam, const float* color,
+                           void* ws, size_t ws_bytes, int64_t capacity, float* image,
+                           float* T_final) {
+  Layout L;
+  int rc = check_common("splat_blend", n, cam, ws, ws_bytes, capacity, L);
+  if (rc) return rc;
+  if (!image || !T_final) return rga::fail(RGA_EINVAL, "splat_blend: null output");
+  if (n > 0 && !color) return rga::fail(RGA_EINVAL, "splat_blend: null input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = cam->width, H = cam->height;
+  const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
+  int64_t* cnt = at<int64_t>(ws, L.count);
+  int32_t* ranges = at<int32_t>(ws, L.ranges);
+  if (n > 0)
+    RGA_LAUNCH("colour_pack", colour_pack_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s, n,
+               color, at<float4>(ws, L.rec));
+  const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   const int64_t g_chunk =
       std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
   const int64_t g_restart =
@@ -1634,8 +1711,24 @@ extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const f
              L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
              at<float>(ws, L.sstate), image, T_final, capacity);
-  RGA_CHECK_LAUNCH("splat_forward");
+  RGA_CHECK_LAUNCH("splat_blend");
   return RGA_OK;
+}
+
+extern "C" int splat_forward(void* stream, int n, const rga_camera* cam, const float* x,
+                             const float* A, const float* quat, const float* log_s,
+                             const float* opac, const float* color, const uint8_t* front,
+                             void* ws, size_t ws_bytes, int64_t capacity, float* image,
+                             float* T_final) {
+  Layout L;
+  int rc = check_common("splat_forward", n, cam, ws, ws_bytes, capacity, L);
+  if (rc) return rc;
+  if (!image || !T_final) return rga::fail(RGA_EINVAL, "splat_forward: null output");
+  if (n > 0 && (!x || !A || !quat || !log_s || !opac || !color || !front))
+    return rga::fail(RGA_EINVAL, "splat_forward: null input");
+  rc = splat_bin(stream, n, cam, x, A, quat, log_s, opac, front, ws, ws_bytes, capacity);
+  if (rc) return rc;
+  return splat_blend(stream, n, cam, color, ws, ws_bytes, capacity, image, T_final);
 }
 
 extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const float* x,

@@ -85,6 +85,10 @@ class Renderer:
         # the FP32 shading records its live (Gaussian, direction) pairs on a
         # tape that the adjoint replays instead of testing every direction
         self.tape = None
+        # the stream that bins the splats while the shading runs, and the
+        # back-face flags it computes for them
+        self.side = None
+        self.front_bin = None
         # every splat_forward on self.ws overwrites the lists and blend state
         # that the adjoint reads: a forward's context records the generation
         # it was rendered in, and a backward of an older forward is refused
@@ -115,14 +119,41 @@ class Renderer:
         return rga.splat_forward(self.cam, *args, self.ws)
 
     # ------------------------------------------------------------------ forward
-    def forward(self, p: Dict[str, torch.Tensor], count: torch.Tensor, for_backward: bool = True):
-        """One frame.  With for_backward (the default) the FP32 shading also
-        records the tape its adjoint replays; a frame only for display skips
-        it (a backward of such a frame still works: it tests every direction
-        again)."""
+    def forward(self, p: Dict[str, torch.Tensor], count: Optional[torch.Tensor] = None,
+                for_backward: bool = True):
+        """One frame.  count: the visibility of the current pose
+        (mesh_visibility), or None to compute it in this frame.  With
+        for_backward (the default) the FP32 shading also records the tape its
+        adjoint replays; a frame only for display skips it (a backward of
+        such a frame still works: it tests every direction again).
+
+        The splats are binned (back-face flags, projection, sorts, tile
+        lists: nothing the colours enter) on a second stream while this
+        stream computes the visibility and the shading; the blend waits for
+        both.  Every buffer the second stream touches is allocated before
+        the fork and this stream joins it before anything else runs."""
         d, s = self.d, self.s
         xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
                                  disp=p.get("disp"))
+        main = torch.cuda.current_stream(xo.device)
+        if self.side is None:
+            self.side = torch.cuda.Stream(device=xo.device)
+        if self.front_bin is None:
+            self.front_bin = torch.empty((self.n,), dtype=torch.uint8, device=xo.device)
+        self.generation += 1
+        forked = torch.cuda.Event()
+        forked.record(main)
+        # the visibility's launches are queued first: the host then queues
+        # the binning's short kernels while the raster runs
+        if count is None:
+            count = self.visibility()
+        self.side.wait_event(forked)
+        with torch.cuda.stream(self.side):
+            rga.back_face(xo, no, self.cam_pos, out=self.front_bin)
+            rga.splat_bin(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], self.front_bin,
+                          self.ws)
+            binned = torch.cuda.Event()
+            binned.record(self.side)
         tape = None
         if for_backward and self.precision == "fp32":
             if self.tape is None:
@@ -132,7 +163,8 @@ class Renderer:
                                            d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
                                            s["wv"], p["env"], self.cam_pos, self.precision,
                                            tape=tape)
-        image, T = self._splat(xo, A, p["quat"], p["log_s"], p["opac"], color, front)
+        main.wait_event(binned)
+        image, T = rga.splat_blend(self.cam, color, self.ws)
         # the tape, like the splat workspace, holds this forward's state until
         # the next forward (the generation check below covers both)
         ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count,
@@ -190,6 +222,9 @@ class Renderer:
                 n = int(rga.lib().image_loss_workspace(*(int(v) for v in image.shape)))
                 self.img_ws = torch.empty(n, dtype=torch.uint8, device=image.device)
             return rga.image_loss(image, target, 0.2, ws=self.img_ws)
+        if self.l1_ws is None:              # allocated once, kept across steps
+            n = int(rga.lib().l1_loss_workspace(image.numel()))
+            self.l1_ws = torch.empty(n, dtype=torch.uint8, device=image.device)
         return rga.l1_loss(image, target, ws=self.l1_ws)
 
     def train_step(self, p, count, target, check: bool = True):
@@ -201,7 +236,7 @@ class Renderer:
         them), so a caller that skips the check still sees the failure."""
         image, _, ctx = self.forward(p, count)
         if check and self.ensure_capacity():
-            image, _, ctx = self.forward(p, count)
+            image, _, ctx = self.forward(p, ctx["count"])
         loss, dimage = self.loss(image, target)
         grads = self.backward(p, ctx, dimage)
         return loss, grads
@@ -266,9 +301,10 @@ class VertexModel:
         self.parents = parents
         self.regularise = regularise
 
-    def forward(self, v: Dict[str, torch.Tensor], count: torch.Tensor):
+    def forward(self, v: Dict[str, torch.Tensor], count: Optional[torch.Tensor]):
         """v: theta [24, 3], mlp [params], v_albedo [3, nv], v_rough [nv],
-        v_tint [nv], pos, nrm, quat, log_s, opac, env (per Gaussian)."""
+        v_tint [nv], pos, nrm, quat, log_s, opac, env (per Gaussian).
+        count: the visibility of v's pose, or None to compute it."""
         R = self.R
         idx, w = rga.knn(self.index, v["pos"], 3)
         dxv = self.net.forward(v["theta"].reshape(-1), v["mlp"])

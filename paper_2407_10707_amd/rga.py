@@ -48,6 +48,7 @@ _SIGS = {
     "shade_gaussians": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _I,
                              _I, _VP, _VP, _I, _VP, _VP, _VP, _SZ]),
     "shade_tape_bytes": (_SZ, [_I, _I, _I]),
+    "back_face": (_I, [_VP, _I, _VP, _VP, _VP, _VP]),
     "shade_gaussians_workspace": (_SZ, [_I, _I, _I]),
     "shade_gaussians_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I,
                                       _I, _I, _I, _VP, _VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP,
@@ -55,6 +56,8 @@ _SIGS = {
     "splat_workspace_size": (_SZ, [_I, _I, _I, _I64]),
     "splat_forward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
                            _VP]),
+    "splat_bin": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64]),
+    "splat_blend": (_I, [_VP, _I, _VP, _VP, _VP, _SZ, _I64, _VP, _VP]),
     "splat_read_count": (_I, [_VP, _VP, _I, _I, _I, _I64, _VP]),
     "splat_state": (_I, [_VP, _I, _I, _I, _I64, _VP]),
     "splat_backward": (_I, [_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _I64, _VP,
@@ -346,6 +349,19 @@ def shade_gaussians(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv
     return color, front
 
 
+def back_face(x, nrm, cam_pos, out=None):
+    """The back-face flags of shade_gaussians on their own (uint8 [n])."""
+    n = x.shape[1]
+    _f32(x, "x", (3, n))
+    _f32(nrm, "nrm", (3, n))
+    front = torch.empty((n,), dtype=torch.uint8, device=x.device) if out is None else out
+    _u8(front, "front", (n,))
+    cp = (C.c_float * 3)(*[float(v) for v in cam_pos])
+    _check(lib().back_face(_stream(), n, _p(x), _p(nrm), C.cast(cp, C.c_void_p), _p(front)),
+           "back_face")
+    return front
+
+
 def shade_gaussians_backward(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv,
                              env, cam_pos, color, front, dcolor, dx_accum=None,
                              precision: str = "fp32", ws=None, tape=None):
@@ -420,6 +436,37 @@ def splat_forward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace
     _check(lib().splat_forward(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s),
                                _p(opac), _p(color), _p(front), _p(ws.buf), ws.bytes, ws.capacity,
                                _p(image), _p(T)), "splat_forward")
+    return image, T
+
+
+def splat_bin(cam, x, A, quat, log_s, opac, front, ws: SplatWorkspace):
+    """The colour-free part of splat_forward (projection, sorts, tile lists)."""
+    n = x.shape[1]
+    _f32(x, "x", (3, n))
+    _f32(A, "A", (9, n))
+    _f32(quat, "quat", (4, n))
+    _f32(log_s, "log_s", (3, n))
+    _f32(opac, "opac", (n,))
+    _u8(front, "front", (n,))
+    if (ws.n, ws.width, ws.height) != (n, int(cam.width), int(cam.height)):
+        raise RgaError("splat workspace was sized for another problem")
+    c = camera(cam)
+    _check(lib().splat_bin(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s), _p(opac),
+                           _p(front), _p(ws.buf), ws.bytes, ws.capacity), "splat_bin")
+
+
+def splat_blend(cam, color, ws: SplatWorkspace):
+    """The rest of splat_forward on the lists of the last splat_bin on ws."""
+    n = color.shape[1]
+    _f32(color, "color", (3, n))
+    H, W = int(cam.height), int(cam.width)
+    if (ws.n, ws.width, ws.height) != (n, W, H):
+        raise RgaError("splat workspace was sized for another problem")
+    image = torch.empty((3, H, W), dtype=torch.float32, device=color.device)
+    T = torch.empty((H, W), dtype=torch.float32, device=color.device)
+    c = camera(cam)
+    _check(lib().splat_blend(_stream(), n, C.byref(c), _p(color), _p(ws.buf), ws.bytes,
+                             ws.capacity, _p(image), _p(T)), "splat_blend")
     return image, T
 
 

@@ -58,10 +58,11 @@ def case(request):
     s = render.scene_in_order(s, order)
     R = render.Renderer(s, d, precision=precision)
     p = {k: d[k] for k in render.TRAINABLE}
-    count = R.visibility()
-    image, T, ctx = R.forward(p, count)
+    # the frame computes its own visibility, binning beside it (as bench.py)
+    image, T, ctx = R.forward(p)
     if R.ensure_capacity():
-        image, T, ctx = R.forward(p, count)
+        image, T, ctx = R.forward(p, ctx["count"])
+    count = ctx["count"]
     torch.cuda.synchronize()
     return dict(name=request.param, s=s, d=d, R=R, p=p, count=count, image=image, T=T, ctx=ctx,
                 precision=precision)
@@ -78,6 +79,7 @@ def test_skinning_visibility_and_flags_bit_exact(case):
     assert np.array_equal(_host(case["count"]), cnt)
     front = cpu.front_f32(xo, no, s["cam"].centre.astype(np.float32))
     assert np.array_equal(_host(case["ctx"]["front"]), front)
+    assert np.array_equal(_host(case["R"].front_bin), front)     # the binning's own flags
 
 
 def test_sampled_colours_match_fp64(case):

@@ -1,8 +1,10 @@
 """A whole train step (visibility, forward, L1 loss, adjoint) captured in a
 HIP graph replays to the eager result, with eager work and synchronisations
-between the replays.  The forward is deterministic (images compared bit for
-bit); the adjoint sums with floating-point atomics, so gradients are compared
-to 1e-5 relative."""
+between the replays.  The frame bins its splats on a second stream, forked
+from and joined to the captured one; the visibility is given to the frame
+or computed in it.  The forward is deterministic (images compared bit for
+bit); the adjoint sums with floating-point atomics, so gradients are
+compared to 1e-5 relative."""
 
 import numpy as np
 import pytest
@@ -14,21 +16,24 @@ from tests.conftest import scene
 pytestmark = pytest.mark.gpu
 
 
-def _step(R, p, target):
-    count = R.visibility()
-    image, _, ctx = R.forward(p, count)
+def _step(R, p, target, own_vis):
+    if own_vis:         # the frame computes it, binning on its second stream
+        image, _, ctx = R.forward(p)
+    else:
+        image, _, ctx = R.forward(p, R.visibility())
     loss, dimage = R.loss(image, target)
     grads = R.backward(p, ctx, dimage)
     return image, loss, grads
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("own_vis", [False, True])
+def test_graph_replays_match_eager(own_vis):
     s = scene(1)
     d = render.upload(s)
     R = render.Renderer(s, d)
     p = {k: d[k] for k in render.TRAINABLE}
     target = d["target"]
-    img_e, loss_e, g_e = _step(R, p, target)
+    img_e, loss_e, g_e = _step(R, p, target, own_vis)
     torch.cuda.synchronize()
     ref_img = img_e.cpu().numpy()
     ref_loss = loss_e.cpu().numpy()
@@ -38,15 +43,15 @@ def test_graph_replays_match_eager():
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         for _ in range(2):
-            _step(R, p, target)
+            _step(R, p, target, own_vis)
     torch.cuda.current_stream().wait_stream(side)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        img_g, loss_g, g_g = _step(R, p, target)
+        img_g, loss_g, g_g = _step(R, p, target, own_vis)
     torch.cuda.synchronize()
     for rep in range(4):
         # eager work between replays, then a replay checked against eager
-        _step(R, p, target)
+        _step(R, p, target, own_vis)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()

@@ -603,6 +603,19 @@ def measure_form(args, s, d, precision: str, capacity=None):
         k_ms, k_n = rga.timing_read(kernel)
     if k_n == 0:
         raise SystemExit(f"bench.py: kernel {kernel!r} was not launched in the timed steps")
+    per_kernel = {}
+    if args.all_kernels:
+        for name in ("lbs_fwd", "vis_frame", "vis_raster", "vis_transpose", "vis_majority",
+                     "vis_count", "shade_fwd", "shade_fwd_bf16x3", "splat_fill", "back_face",
+                     "splat_preprocess", "radix_upsweep", "radix_binscan", "radix_downsweep",
+                     "touched_scan", "splat_duplicate", "tile_ranges",
+                     "chunk_index", "colour_pack", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
+                     "l1_final", "blend_bwd", "preprocess_bwd", "shade_bwd",
+                     "shade_bwd_bf16x3", "shade_denv", "lbs_bwd"):
+            ms, cnt = rga.timing_read(name)
+            if cnt:
+                per_kernel[name] = round(ms / args.steps, 4)
+        per_kernel["sum_of_kernels"] = round(sum(per_kernel.values()), 4)
     k_avg = {kernel: k_ms / k_n}
     timed_where = {kernel: "timed region"}
     for kn in kernels[1:]:
@@ -617,19 +630,6 @@ def measure_form(args, s, d, precision: str, capacity=None):
         if cnt:
             k_avg[kn] = ms / cnt
             timed_where[kn] = "5 eager steps after the timed region"
-    per_kernel = {}
-    if args.all_kernels:
-        for name in ("lbs_fwd", "vis_frame", "vis_raster", "vis_transpose", "vis_majority",
-                     "vis_count", "shade_fwd", "shade_fwd_bf16x3", "splat_fill",
-                     "splat_preprocess", "radix_upsweep", "radix_binscan", "radix_downsweep",
-                     "touched_scan", "splat_duplicate", "tile_ranges",
-                     "chunk_index", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
-                     "l1_final", "blend_bwd", "preprocess_bwd", "shade_bwd",
-                     "shade_bwd_bf16x3", "shade_denv", "lbs_bwd"):
-            ms, cnt = rga.timing_read(name)
-            if cnt:
-                per_kernel[name] = round(ms / args.steps, 4)
-        per_kernel["sum_of_kernels"] = round(sum(per_kernel.values()), 4)
 
     # forward-only frame rates (visibility per frame, and cached per pose;
     # a sequence recomputes visibility once per pose)

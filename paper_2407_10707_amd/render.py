@@ -66,8 +66,12 @@ def scene_in_order(scene: dict, order) -> dict:
 class Renderer:
     """Holds the static inputs and workspaces of one scene/camera."""
 
+    # below this many Gaussians a frame is bound by the host's launches, and
+    # the second stream's events cost more than the overlap saves
+    OVERLAP_MIN_GAUSSIANS = 16384
+
     def __init__(self, scene: dict, dev: Dict[str, torch.Tensor], capacity: Optional[int] = None,
-                 precision: str = "fp32"):
+                 precision: str = "fp32", overlap: Optional[bool] = None):
         self.s = scene
         self.d = dev
         self.cam = scene["cam"]
@@ -89,6 +93,8 @@ class Renderer:
         # back-face flags it computes for them
         self.side = None
         self.front_bin = None
+        self.overlap = (int(scene["n"]) >= self.OVERLAP_MIN_GAUSSIANS) if overlap is None \
+            else bool(overlap)
         # every splat_forward on self.ws overwrites the lists and blend state
         # that the adjoint reads: a forward's context records the generation
         # it was rendered in, and a backward of an older forward is refused
@@ -127,33 +133,36 @@ class Renderer:
         adjoint replays; a frame only for display skips it (a backward of
         such a frame still works: it tests every direction again).
 
-        The splats are binned (back-face flags, projection, sorts, tile
+        With overlap (the default from OVERLAP_MIN_GAUSSIANS Gaussians on),
+        the splats are binned (back-face flags, projection, sorts, tile
         lists: nothing the colours enter) on a second stream while this
         stream computes the visibility and the shading; the blend waits for
         both.  Every buffer the second stream touches is allocated before
-        the fork and this stream joins it before anything else runs."""
+        the fork and this stream joins it before anything else runs.
+        Without, splat_forward runs after the shading on this stream."""
         d, s = self.d, self.s
         xo, no, A = rga.lbs_skin(d["skin"], d["jidx"], d["jw"], p["pos"], p["nrm"],
                                  disp=p.get("disp"))
         main = torch.cuda.current_stream(xo.device)
-        if self.side is None:
-            self.side = torch.cuda.Stream(device=xo.device)
-        if self.front_bin is None:
-            self.front_bin = torch.empty((self.n,), dtype=torch.uint8, device=xo.device)
         self.generation += 1
-        forked = torch.cuda.Event()
-        forked.record(main)
+        if self.overlap:
+            if self.side is None:
+                self.side = torch.cuda.Stream(device=xo.device)
+                self.forked, self.binned = torch.cuda.Event(), torch.cuda.Event()
+            if self.front_bin is None:
+                self.front_bin = torch.empty((self.n,), dtype=torch.uint8, device=xo.device)
+            self.forked.record(main)
         # the visibility's launches are queued first: the host then queues
         # the binning's short kernels while the raster runs
         if count is None:
             count = self.visibility()
-        self.side.wait_event(forked)
-        with torch.cuda.stream(self.side):
-            rga.back_face(xo, no, self.cam_pos, out=self.front_bin)
-            rga.splat_bin(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], self.front_bin,
-                          self.ws)
-            binned = torch.cuda.Event()
-            binned.record(self.side)
+        if self.overlap:
+            self.side.wait_event(self.forked)
+            with torch.cuda.stream(self.side):
+                rga.back_face(xo, no, self.cam_pos, out=self.front_bin)
+                rga.splat_bin(self.cam, xo, A, p["quat"], p["log_s"], p["opac"], self.front_bin,
+                              self.ws)
+                self.binned.record(self.side)
         tape = None
         if for_backward and self.precision == "fp32":
             if self.tape is None:
@@ -163,8 +172,12 @@ class Renderer:
                                            d["vw"], count, s["kv"], s["he"], s["we"], s["hv"],
                                            s["wv"], p["env"], self.cam_pos, self.precision,
                                            tape=tape)
-        main.wait_event(binned)
-        image, T = rga.splat_blend(self.cam, color, self.ws)
+        if self.overlap:
+            main.wait_event(self.binned)
+            image, T = rga.splat_blend(self.cam, color, self.ws)
+        else:
+            image, T = rga.splat_forward(self.cam, xo, A, p["quat"], p["log_s"], p["opac"],
+                                         color, front, self.ws)
         # the tape, like the splat workspace, holds this forward's state until
         # the next forward (the generation check below covers both)
         ctx = dict(xo=xo, no=no, A=A, color=color, front=front, image=image, count=count,

@@ -1,10 +1,10 @@
 """A whole train step (visibility, forward, L1 loss, adjoint) captured in a
 HIP graph replays to the eager result, with eager work and synchronisations
-between the replays.  The frame bins its splats on a second stream, forked
-from and joined to the captured one; the visibility is given to the frame
-or computed in it.  The forward is deterministic (images compared bit for
-bit); the adjoint sums with floating-point atomics, so gradients are
-compared to 1e-5 relative."""
+between the replays.  The frame bins its splats after the shading on the
+captured stream, or on a second stream forked from and joined to it; the
+visibility is given to the frame or computed in it.  The forward is
+deterministic (images compared bit for bit); the adjoint sums with
+floating-point atomics, so gradients are compared to 1e-5 relative."""
 
 import numpy as np
 import pytest
@@ -26,11 +26,11 @@ def _step(R, p, target, own_vis):
     return image, loss, grads
 
 
-@pytest.mark.parametrize("own_vis", [False, True])
-def test_graph_replays_match_eager(own_vis):
+@pytest.mark.parametrize("own_vis,overlap", [(False, False), (True, True)])
+def test_graph_replays_match_eager(own_vis, overlap):
     s = scene(1)
     d = render.upload(s)
-    R = render.Renderer(s, d)
+    R = render.Renderer(s, d, overlap=overlap)
     p = {k: d[k] for k in render.TRAINABLE}
     target = d["target"]
     img_e, loss_e, g_e = _step(R, p, target, own_vis)

@@ -113,27 +113,32 @@ def test_split_entry_points_refuse_bad_arguments():
 
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_renderer_frame_with_its_own_visibility(cfg):
-    """R.forward(p) (visibility inside the frame, binning on the side
-    stream) against R.forward(p, R.visibility()), and their adjoints."""
+    """R.forward(p) (visibility inside the frame, binning on the second
+    stream) against R.forward(p, R.visibility()) and against a renderer
+    that bins after the shading on one stream, and their adjoints."""
     print(f"[split] renderer cfg {cfg}", flush=True)
     s = scene(cfg)
     d, order = render.layout_by_vertex(render.upload(s))
-    R = render.Renderer(render.scene_in_order(s, order), d)
+    so = render.scene_in_order(s, order)
+    R1 = render.Renderer(so, d, overlap=False)
+    assert render.Renderer(so, d).overlap == (s["n"] >= render.Renderer.OVERLAP_MIN_GAUSSIANS)
     p = {k: d[k] for k in render.TRAINABLE}
     w = dev(np.random.default_rng(cfg).random((3, s["cam"].height, s["cam"].width))
             .astype(np.float32))
-    count = R.visibility()
-    img1, T1, c1 = R.forward(p, count)
-    if R.ensure_capacity():
-        img1, T1, c1 = R.forward(p, count)
-    g1 = R.backward(p, c1, w)
-    img2, T2, c2 = R.forward(p)
-    assert torch.equal(c2["count"], count)
-    assert torch.equal(img1, img2) and torch.equal(T1, T2)
-    assert torch.equal(R.front_bin, c2["front"])
-    g2 = R.backward(p, c2, w)
-    for k in render.TRAINABLE:
-        a, b = host(g1[k]), host(g2[k])
-        err = np.abs(a - b).max() / (np.abs(b).max() + 1e-30)
-        print(f"  {k:8s} {err:.1e}", flush=True)
-        assert err <= 1e-5, (k, err)
+    count = R1.visibility()
+    img1, T1, c1 = R1.forward(p, count)
+    if R1.ensure_capacity():
+        img1, T1, c1 = R1.forward(p, count)
+    g1 = R1.backward(p, c1, w)
+    R = render.Renderer(so, d, capacity=R1.ws.capacity, overlap=True)
+    for given in (False, True):
+        img2, T2, c2 = R.forward(p, count if given else None)
+        assert torch.equal(c2["count"], count)
+        assert torch.equal(img1, img2) and torch.equal(T1, T2)
+        assert torch.equal(R.front_bin, c2["front"])
+        g2 = R.backward(p, c2, w)
+        for k in render.TRAINABLE:
+            a, b = host(g1[k]), host(g2[k])
+            err = np.abs(a - b).max() / (np.abs(b).max() + 1e-30)
+            print(f"  {k:8s} {err:.1e}", flush=True)
+            assert err <= 1e-5, (k, err)

@@ -273,8 +273,10 @@ int splat_forward(void* stream, int n, const rga_camera* cam, const float* x, co
  * records, then the compositing; image and T_final as for splat_forward.
  * splat_blend reads what the last splat_bin left in ws (same n, camera and
  * capacity): the caller orders the two (one stream, or an event between
- * two).  splat_forward = splat_bin then splat_blend on one stream.
- * Errors as for splat_forward.                                             */
+ * two); a workspace no splat_bin (or splat_forward) has filled holds no
+ * valid lists, and splat_blend on it is undefined (its indices are read
+ * from the workspace).  splat_forward = splat_bin then splat_blend on one
+ * stream.  Errors as for splat_forward.                                    */
 int splat_bin(void* stream, int n, const rga_camera* cam, const float* x, const float* A,
               const float* quat, const float* log_s, const float* opac, const uint8_t* front,
               void* ws, size_t ws_bytes, int64_t capacity);

@@ -396,6 +396,7 @@ class SplatWorkspace:
         self.n, self.width, self.height, self.capacity = n, width, height, int(capacity)
         self.bytes = int(lib().splat_workspace_size(n, width, height, self.capacity))
         self.buf = torch.empty(self.bytes, dtype=torch.uint8, device=device)
+        self.binned = False       # holds the lists of a splat_bin / splat_forward
 
     def count(self) -> int:
         D = C.c_int64()
@@ -436,6 +437,7 @@ def splat_forward(cam, x, A, quat, log_s, opac, color, front, ws: SplatWorkspace
     _check(lib().splat_forward(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s),
                                _p(opac), _p(color), _p(front), _p(ws.buf), ws.bytes, ws.capacity,
                                _p(image), _p(T)), "splat_forward")
+    ws.binned = True
     return image, T
 
 
@@ -453,6 +455,7 @@ def splat_bin(cam, x, A, quat, log_s, opac, front, ws: SplatWorkspace):
     c = camera(cam)
     _check(lib().splat_bin(_stream(), n, C.byref(c), _p(x), _p(A), _p(quat), _p(log_s), _p(opac),
                            _p(front), _p(ws.buf), ws.bytes, ws.capacity), "splat_bin")
+    ws.binned = True
 
 
 def splat_blend(cam, color, ws: SplatWorkspace):
@@ -462,6 +465,8 @@ def splat_blend(cam, color, ws: SplatWorkspace):
     H, W = int(cam.height), int(cam.width)
     if (ws.n, ws.width, ws.height) != (n, W, H):
         raise RgaError("splat workspace was sized for another problem")
+    if not ws.binned:
+        raise RgaError("splat_blend: the workspace holds no lists (run splat_bin first)")
     image = torch.empty((3, H, W), dtype=torch.float32, device=color.device)
     T = torch.empty((H, W), dtype=torch.float32, device=color.device)
     c = camera(cam)

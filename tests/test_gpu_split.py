@@ -109,6 +109,9 @@ def test_split_entry_points_refuse_bad_arguments():
     assert L.back_face(None, -1, None, None, None, None) == -1
     assert L.back_face(None, 4, None, None, None, None) == -1
     assert L.back_face(None, 0, None, None, None, None) == 0
+    # the binding refuses a blend on a workspace no binning has filled
+    with pytest.raises(rga.RgaError, match="splat_bin first"):
+        rga.splat_blend(cam, torch.zeros((3, n), dtype=torch.float32, device="cuda"), ws)
 
 
 @pytest.mark.parametrize("cfg", [1, 2])

@@ -609,7 +609,7 @@ def measure_form(args, s, d, precision: str, capacity=None):
                      "vis_count", "shade_fwd", "shade_fwd_bf16x3", "splat_fill", "back_face",
                      "splat_preprocess", "radix_upsweep", "radix_binscan", "radix_downsweep",
                      "touched_scan", "splat_duplicate", "tile_ranges",
-                     "chunk_index", "colour_pack", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
+                     "chunk_index", "blend_chunk", "blend_prefix", "blend_restart", "l1_partial",
                      "l1_final", "blend_bwd", "preprocess_bwd", "shade_bwd",
                      "shade_bwd_bf16x3", "shade_denv", "lbs_bwd"):
             ms, cnt = rga.timing_read(name)

@@ -269,8 +269,8 @@ int splat_forward(void* stream, int n, const rga_camera* cam, const float* x, co
 /* splat_forward in two calls, so that the part the colours do not enter can
  * run while the shading computes them.  splat_bin: projection, depth sort,
  * duplication, tile sort, tile ranges and work items (arguments as for
- * splat_forward).  splat_blend: the colours [3][n] into the per-splat
- * records, then the compositing; image and T_final as for splat_forward.
+ * splat_forward).  splat_blend: the compositing of the colours [3][n];
+ * image and T_final as for splat_forward.
  * splat_blend reads what the last splat_bin left in ws (same n, camera and
  * capacity): the caller orders the two (one stream, or an event between
  * two); a workspace no splat_bin (or splat_forward) has filled holds no
@@ -321,7 +321,7 @@ int splat_state(void* ws, int n, int width, int height, int64_t capacity, rga_sp
 
 /* Adjoint of splat_forward given dL/dimage.  Re-walks every tile list front to
  * back recomputing the transmittance (nothing per (pixel, splat) is stored);
- * `image` is the forward output.  Outputs (overwritten): dx [3][n],
+ * `image` is the forward output and `color` the colours it composited.  Outputs (overwritten): dx [3][n],
  * dquat [4][n], dlog_s [3][n], dopac [n], dcolor [3][n], and, unless NULL,
  * dA [9][n]: the gradient with respect to the skinning's linear part A
  * through the covariance (A R S), which the pose gradient needs.           */

@@ -326,8 +326,8 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
     }
   }
   // the blend evaluates the exponent of alpha in base 2: the record holds
-  // the conic scaled by -log2(e) / 2 (cross term by -log2(e)); its colour
-  // slots are filled by colour_pack_kernel once the colours exist
+  // the conic scaled by -log2(e) / 2 (cross term by -log2(e)); the blend
+  // passes put the colour into its empty slots when they stage it
   rec[3 * g + 0] = make_float4(u, v, ca * kHalfNegLog2e, cb * (2.f * kHalfNegLog2e));
   rec[3 * g + 1] = make_float4(cc * kHalfNegLog2e, o, 0.f, 0.f);
   // for the blend's per-wave culling: the slopes of the exponent's maxima
@@ -352,18 +352,6 @@ preprocess_kernel(int n, CamDev cam, int TX, int TY, const float* __restrict__ x
   vals[g] = (uint32_t)g;
 }
 
-// The splat colours into their records (rec[3g+1].zw, rec[3g+2].x): the
-// binning does not need them, so it can run before the shading has them.
-__global__ void __launch_bounds__(256)
-colour_pack_kernel(int n, const float* __restrict__ color, float4* __restrict__ rec) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  float* r = reinterpret_cast<float*>(rec + 3 * (size_t)g);
-  r[6] = color[g];
-  r[7] = color[n + g];
-  r[8] = color[2 * (size_t)n + g];
-}
-
 // The back-face rule (a Gaussian whose normal faces away from the camera
 // gets zero opacity), for a caller that bins before it shades: the same
 // FP32 expression, in the same order, as the shading kernels' decision, so
@@ -376,6 +364,20 @@ back_face_kernel(int n, const float* __restrict__ x, const float* __restrict__ n
   const float w0 = c0 - x[g], w1 = c1 - x[n + g], w2 = c2 - x[2 * (size_t)n + g];
   const float m0 = nrm[g], m1 = nrm[n + g], m2 = nrm[2 * (size_t)n + g];
   front[g] = fmaf(m2, w2, fmaf(m1, w1, m0 * w0)) > 0.f ? 1 : 0;
+}
+
+// A splat's record for the blend passes, with its colour (slots 6-8, left
+// empty by the projection: the binning runs before the colours exist).
+struct SplatRec {
+  float4 r0, r1, r2;
+};
+__device__ inline SplatRec load_rec(const float4* __restrict__ rec, const float* __restrict__ color,
+                                    int n, uint32_t g) {
+  SplatRec R{rec[3 * g], rec[3 * g + 1], rec[3 * g + 2]};
+  R.r1.z = color[g];
+  R.r1.w = color[(size_t)n + g];
+  R.r2.x = color[2 * (size_t)n + g];
+  return R;
 }
 
 // ---- blend work items -------------------------------------------------------
@@ -885,8 +887,9 @@ __device__ inline int next_item(uint32_t* queue, int* slot) {
 }
 
 __global__ void __launch_bounds__(256)
-blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+blend_chunk_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                    const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                   const float* __restrict__ color,
                    const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                    const int64_t* __restrict__ counters, int64_t max_items,
                    const uint32_t* __restrict__ item_sub, uint32_t* __restrict__ sub_item,
@@ -910,10 +913,10 @@ blend_chunk_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
     const bool ok = (int)threadIdx.x < cnt;
     float4 r0 = {}, r1 = {}, r2 = {};
     if (ok) {
-      const uint32_t g = sorted[e0 + threadIdx.x];
-      r0 = rec[3 * g];
-      r1 = rec[3 * g + 1];
-      r2 = rec[3 * g + 2];
+      const SplatRec R = load_rec(rec, color, n, sorted[e0 + threadIdx.x]);
+      r0 = R.r0;
+      r1 = R.r1;
+      r2 = R.r2;
       s0[threadIdx.x] = r0;
       s1[threadIdx.x] = r1;
       s2[threadIdx.x] = r2;
@@ -1046,8 +1049,9 @@ blend_prefix_kernel(int W, int H, int TX, const uint32_t* __restrict__ item_off,
 // write their final colour and transmittance.  (A pixel whose stop test
 // does not fire here because of rounding keeps the chunk's end state.)
 __global__ void __launch_bounds__(256)
-blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
+blend_restart_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                      const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                     const float* __restrict__ color,
                      const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                      const int64_t* __restrict__ counters, int64_t max_items,
                      const float* __restrict__ cstate, float* __restrict__ sstate,
@@ -1068,10 +1072,10 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
   const int e0 = ranges[2 * t] + j * kChunk;
   const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
   if ((int)threadIdx.x < cnt) {
-    const uint32_t g = sorted[e0 + threadIdx.x];
-    s0[threadIdx.x] = rec[3 * g];
-    s1[threadIdx.x] = rec[3 * g + 1];
-    s2[threadIdx.x] = rec[3 * g + 2];
+    const SplatRec R = load_rec(rec, color, n, sorted[e0 + threadIdx.x]);
+    s0[threadIdx.x] = R.r0;
+    s1[threadIdx.x] = R.r1;
+    s2[threadIdx.x] = R.r2;
   }
   __syncthreads();
   if (!mine || !(px < W && py < H)) continue;
@@ -1135,6 +1139,7 @@ blend_restart_kernel(int W, int H, int TX, const int32_t* __restrict__ ranges,
 __global__ void __launch_bounds__(256)
 blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges,
                  const uint32_t* __restrict__ sorted, const float4* __restrict__ rec,
+                 const float* __restrict__ color,
                  const uint32_t* __restrict__ item_tile, const uint32_t* __restrict__ item_chunk,
                  const uint32_t* __restrict__ sub_item, const int64_t* __restrict__ counters,
                  int64_t max_items, int64_t max_subs, uint32_t* __restrict__ queue,
@@ -1173,9 +1178,13 @@ blend_bwd_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ranges
       r1 = rec[3 * g + 1];
       r2 = rec[3 * g + 2];
       if (wave == 0) {
+        float4 c1 = r1, c2 = r2;
+        c1.z = color[g];
+        c1.w = color[(size_t)n + g];
+        c2.x = color[2 * (size_t)n + g];
         s0[lane] = r0;
-        s1[lane] = r1;
-        s2[lane] = r2;
+        s1[lane] = c1;
+        s2[lane] = c2;
         sg[lane] = g;
       }
     }
@@ -1701,16 +1710,13 @@ extern "C" int splat_blend(void* stream, int n, const rga_camera* cam, const flo
   const int64_t tiles = (int64_t)L.tiles_x * L.tiles_y;
   int64_t* cnt = at<int64_t>(ws, L.count);
   int32_t* ranges = at<int32_t>(ws, L.ranges);
-  if (n > 0)
-    RGA_LAUNCH("colour_pack", colour_pack_kernel, dim3(rga::ceil_div(n, 256)), dim3(256), 0, s, n,
-               color, at<float4>(ws, L.rec));
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   const int64_t g_chunk =
       std::min<int64_t>(L.max_items, resident_groups<0>((const void*)blend_chunk_kernel));
   const int64_t g_restart =
       std::min<int64_t>(L.max_items, resident_groups<1>((const void*)blend_restart_kernel));
   RGA_LAUNCH("blend_chunk", blend_chunk_kernel, dim3(g_chunk), dim3(256), 0, s, W, H, L.tiles_x,
-             ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
+             n, ranges, sorted, at<float4>(ws, L.rec), color, at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<uint32_t>(ws, L.item_sub),
              at<uint32_t>(ws, L.sub_item), L.max_subs, at<float>(ws, L.cstate),
              at<float>(ws, L.sstate));
@@ -1718,7 +1724,7 @@ extern "C" int splat_blend(void* stream, int n, const rga_camera* cam, const flo
              at<uint32_t>(ws, L.item_off), at<float>(ws, L.cstate), L.max_items, image, T_final,
              (const int64_t*)cnt, capacity);
   RGA_LAUNCH("blend_restart", blend_restart_kernel, dim3(g_restart), dim3(256), 0, s, W, H,
-             L.tiles_x, ranges, sorted, at<float4>(ws, L.rec), at<uint32_t>(ws, L.item_tile),
+             L.tiles_x, n, ranges, sorted, at<float4>(ws, L.rec), color, at<uint32_t>(ws, L.item_tile),
              at<uint32_t>(ws, L.item_chunk), cnt, L.max_items, at<float>(ws, L.cstate),
              at<float>(ws, L.sstate), image, T_final, capacity);
   RGA_CHECK_LAUNCH("splat_blend");
@@ -1747,13 +1753,12 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
                               void* ws, size_t ws_bytes, int64_t capacity, const float* image,
                               const float* dimage, float* dx, float* dquat, float* dlog_s,
                               float* dopac, float* dcolor, float* dA) {
-  (void)color;
   Layout L;
   int rc = check_common("splat_backward", n, cam, ws, ws_bytes, capacity, L);
   if (rc) return rc;
   if (n == 0) return RGA_OK;
-  if (!x || !A || !quat || !log_s || !opac || !front || !image || !dimage || !dx || !dquat ||
-      !dlog_s || !dopac || !dcolor)
+  if (!x || !A || !quat || !log_s || !opac || !color || !front || !image || !dimage || !dx ||
+      !dquat || !dlog_s || !dopac || !dcolor)
     return rga::fail(RGA_EINVAL, "splat_backward: null pointer");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const CamDev cd = to_dev(cam);
@@ -1766,6 +1771,7 @@ extern "C" int splat_backward(void* stream, int n, const rga_camera* cam, const 
   const uint32_t* sorted = at<uint32_t>(ws, (L.tile_passes & 1) ? L.tv1 : L.tv0);
   RGA_LAUNCH("blend_bwd", blend_bwd_kernel, dim3(g_bwd), dim3(256), 0, s, cam->width,
              cam->height, L.tiles_x, n, at<int32_t>(ws, L.ranges), sorted, at<float4>(ws, L.rec),
+             color,
              at<uint32_t>(ws, L.item_tile), at<uint32_t>(ws, L.item_chunk),
              at<uint32_t>(ws, L.sub_item), at<int64_t>(ws, L.count), L.max_items, L.max_subs,
              queue, at<float>(ws, L.cstate), at<float>(ws, L.sstate), image, dimage, grad9,

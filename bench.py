@@ -570,14 +570,15 @@ def measure_form(args, s, d, precision: str, capacity=None):
         torch.cuda.synchronize()
         run = graph.replay
 
-    # the roofline entry is the step's longest kernel: the blend adjoint in
-    # the FP32 form, the MFMA shading adjoint in the BF16X3 form; the other
-    # adjoint is timed on a few eager steps after the timed region and
-    # reported beside it (the longer of the two becomes the entry)
+    # the roofline entry is the step's longest kernel, the blend adjoint
+    # here; beside it the shading kernel of the form (the FP32 adjoint, or
+    # the BF16X3 form's MFMA forward: both forms' adjoints replay the tape),
+    # timed on a few eager steps after the timed region (the longer of the
+    # two becomes the entry)
     if args.kernel:
         kernels = [args.kernel]
     elif precision == "bf16x3":
-        kernels = ["shade_bwd_bf16x3", "blend_bwd"]
+        kernels = ["blend_bwd", "shade_fwd_bf16x3"]
     else:
         kernels = ["blend_bwd", "shade_bwd"]
     kernel = kernels[0]
@@ -675,7 +676,7 @@ def measure_form(args, s, d, precision: str, capacity=None):
 
     def roofline_of(kn):
         if kn.startswith("shade_bwd") or kn.startswith("shade_fwd"):
-            # the FP32 renderer's adjoint replays the forward's tape
+            # the renderer's adjoint replays the forward's tape
             replay = kn == "shade_bwd" and R.tape is not None
             flops = shade_flops(wl["live"], wl["tested"], kn.startswith("shade_bwd"),
                                 tested=not replay)

@@ -192,9 +192,10 @@ int mesh_visibility_noalloc(void* stream, int nv, int nf, const float* verts,
  * precision  RGA_FP32 or RGA_BF16X3
  * color      [3][n] out;  front [n] uint8 out
  * tape       NULL, or tape_bytes >= shade_tape_bytes(n, he, we) of device
- *            memory (16-byte aligned, RGA_FP32 only) that receives the live
- *            (Gaussian, direction) pairs the sum visited: per Gaussian their
- *            number and, in the order visited, each pair's direction and
+ *            memory (16-byte aligned) that receives the live (Gaussian,
+ *            direction) pairs the sum visited: per Gaussian their number
+ *            and, in the order visited (the FP32 walk's, or the BF16X3
+ *            form's 32-direction steps), each pair's direction and
  *            interpolated visibility.  The adjoint of the same inputs can
  *            read them instead of testing every direction again.
  * Limits (RGA_EUNSUPPORTED otherwise): V % 16 == 0 and V <= 2048; hv | he
@@ -224,7 +225,9 @@ size_t shade_tape_bytes(int n, int he, int we);
  * shade_gaussians wrote for these same inputs (x, nrm, rough, vidx, vw,
  * count, env, cam_pos, the grids): the live pairs are read from it, which
  * gives the same sums with less work.  A tape from other inputs gives wrong
- * gradients (it is not checked).  RGA_FP32 only.                            */
+ * gradients (it is not checked).  Given a tape the adjoint is the FP32
+ * replay in either form (for RGA_BF16X3 the tape of its MFMA forward); the
+ * MFMA adjoint runs for RGA_BF16X3 without one.                             */
 size_t shade_gaussians_workspace(int n, int he, int we);
 int shade_gaussians_backward(void* stream, int n, const float* x, const float* nrm,
                              const float* albedo, const float* rough, const float* tint,

@@ -19,7 +19,9 @@
 // visibility) pairs, in the order and 64-pair groups of its walk; the
 // adjoint of the same inputs then replays them instead of walking every
 // direction again (same pairs, same lanes, same sums), which removes the
-// direction test, the count rows and the ring from the adjoint.
+// direction test, the count rows and the ring from the adjoint.  The BF16X3
+// form's MFMA forward writes the same tape (its pairs in step order), and
+// its adjoint given one is this replay.
 #include "common.h"
 
 #include <math.h>
@@ -38,8 +40,8 @@ struct ShadeArgs {
   const int32_t* vidx;
   const uint8_t* count;
   int patch;   // table slots in 4 x 8 texel patches (the MFMA kernels), else texel order
-  // the live-pair tape of the FP32 form (NULL: none): per Gaussian its count
-  // and its live (direction, visibility) pairs in walk order, [n][K]
+  // the live-pair tape (NULL: none): per Gaussian its count and its live
+  // (direction, visibility) pairs in the order visited, [n][K]
   int32_t* tape_n;
   uint2* tape;
 };
@@ -676,12 +678,31 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
     const uint8_t* r1 = a.count + (size_t)A.vidx[1] * V;
     const uint8_t* r2 = a.count + (size_t)A.vidx[2] * V;
     f32x4 accD = {0.f, 0.f, 0.f, 0.f}, accS = {0.f, 0.f, 0.f, 0.f};
+    // the tape: this Gaussian's live pairs so far (the same in the four
+    // lanes of its row), written step by step in (step, lane group, i) order
+    int tcount = 0;
+    uint2* const trow = (a.tape && on) ? a.tape + (size_t)g * K : nullptr;
     for (int k0 = 0; k0 < K; k0 += 32) {
       const int kb = k0 + 8 * kg;
       float vv[8];
       const uint32_t lm = live8(a, G, tab, r0, r1, r2, kb, ratio, on, vv);
       // a step with no live pair in the tile adds nothing
       if (__ballot(lm != 0u) == 0ull) continue;
+      if (a.tape) {
+        // this lane's pairs follow those of the row's lanes with smaller kg
+        const int p = __popc(lm);
+        const int p0 = __shfl(p, row), p1 = __shfl(p, row + 16), p2 = __shfl(p, row + 32),
+                  p3 = __shfl(p, row + 48);
+        int pos = tcount + (kg > 0 ? p0 : 0) + (kg > 1 ? p1 : 0) + (kg > 2 ? p2 : 0);
+        if (trow) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            if ((lm >> i) & 1u)
+              trow[pos++] = make_uint2((uint32_t)slot_k(kb + i, a.we, a.patch),
+                                       __float_as_uint(vv[i]));
+        }
+        tcount += p0 + p1 + p2 + p3;
+      }
       bf16x8 dh, dl, sh, sl;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
@@ -705,6 +726,7 @@ shade_fwd_mfma_kernel(ShadeArgs a, int ratio, float* __restrict__ color,
       accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sh, b, accS, 0, 0, 0);
       accS = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sl, b, accS, 0, 0, 0);
     }
+    if (a.tape_n && have && kg == 0) a.tape_n[g] = tcount;
     // D[row 4 kg + i][col] -> stage; then one lane per (Gaussian, channel)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1343,10 +1365,8 @@ extern "C" size_t shade_tape_bytes(int n, int he, int we) {
 }
 
 namespace {
-int attach_tape(const char* fn, ShadeArgs& a, int precision, const void* tape, size_t tape_bytes) {
+int attach_tape(const char* fn, ShadeArgs& a, const void* tape, size_t tape_bytes) {
   if (!tape) return RGA_OK;
-  if (precision != RGA_FP32)
-    return rga::fail(RGA_EUNSUPPORTED, "%s: the tape belongs to the FP32 form", fn);
   if (!rga::aligned16(tape)) return rga::fail(RGA_EINVAL, "%s: tape must be 16-byte aligned", fn);
   if (tape_bytes < shade_tape_bytes(a.n, a.he, a.we))
     return rga::fail(RGA_ECAPACITY, "%s: tape %zu < %zu bytes", fn, tape_bytes,
@@ -1371,7 +1391,7 @@ extern "C" int shade_gaussians(void* stream, int n, const float* x, const float*
   if (!color || !front) return rga::fail(RGA_EINVAL, "shade_gaussians: null output");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
-  rc = attach_tape("shade_gaussians", a, precision, tape, tape_bytes);
+  rc = attach_tape("shade_gaussians", a, tape, tape_bytes);
   if (rc) return rc;
   if (precision == RGA_BF16X3) {
     if (a.K % 32 != 0)
@@ -1445,9 +1465,11 @@ extern "C" int shade_gaussians_backward(void* stream, int n, const float* x, con
     return rga::fail(RGA_EINVAL, "shade_gaussians_backward: null pointer");
   ShadeArgs a = make_args(n, x, nrm, albedo, rough, tint, vidx, vw, count, nv, kv, he, we, hv, wv,
                           env, cam_pos);
-  rc = attach_tape("shade_gaussians_backward", a, precision, tape, tape_bytes);
+  rc = attach_tape("shade_gaussians_backward", a, tape, tape_bytes);
   if (rc) return rc;
-  if (precision == RGA_BF16X3) {
+  // given a tape (of either form's forward), the adjoint replays its live
+  // pairs in FP32; the MFMA adjoint is the BF16X3 form's without one
+  if (precision == RGA_BF16X3 && !a.tape) {
     if (a.K % 32 != 0)
       return rga::fail(RGA_EUNSUPPORTED, "shade_gaussians_backward: BF16X3 needs a multiple of 32 directions");
     const int ratio = (hv == he && we == wv) ? 1 : ((hv == he && we == 2 * wv && we % 8 == 0) ? 2 : 0);

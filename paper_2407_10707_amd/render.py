@@ -129,8 +129,8 @@ class Renderer:
                 for_backward: bool = True):
         """One frame.  count: the visibility of the current pose
         (mesh_visibility), or None to compute it in this frame.  With
-        for_backward (the default) the FP32 shading also records the tape its
-        adjoint replays; a frame only for display skips it (a backward of
+        for_backward (the default) the shading (either form) also records
+        the tape its adjoint replays; a frame only for display skips it (a backward of
         such a frame still works: it tests every direction again).
 
         With overlap (the default from OVERLAP_MIN_GAUSSIANS Gaussians on),
@@ -164,7 +164,7 @@ class Renderer:
                               self.ws)
                 self.binned.record(self.side)
         tape = None
-        if for_backward and self.precision == "fp32":
+        if for_backward:
             if self.tape is None:
                 self.tape = rga.shade_tape(self.n, s["he"], s["we"], xo.device)
             tape = self.tape

@@ -327,7 +327,7 @@ def _tape(tape):
 def shade_gaussians(x, nrm, albedo, rough, tint, vidx, vw, count, kv, he, we, hv, wv, env,
                     cam_pos, precision: str = "fp32", tape=None):
     """tape: None, or a buffer from shade_tape that receives the live pairs
-    (FP32 form) for a shade_gaussians_backward of the same inputs."""
+    (either form) for a shade_gaussians_backward of the same inputs."""
     n = x.shape[1]
     nv = count.shape[0]
     _f32(x, "x", (3, n))

@@ -1,6 +1,7 @@
-"""The live-pair tape of the FP32 shading (Sec. 3.1 rendering equation, App.
+"""The live-pair tape of the shading (Sec. 3.1 rendering equation, App.
 A BRDF): shade_gaussians records, per Gaussian, the live (direction,
-visibility) pairs it summed, and shade_gaussians_backward replays them
+visibility) pairs it summed (the FP32 walk; the BF16X3 form's MFMA forward
+too, tested last), and shade_gaussians_backward replays them
 instead of testing every direction again.  The adjoint with the tape
 matches the adjoint without it (per-Gaussian gradients to 1e-6 relative,
 the environment gradient, summed with LDS atomics in either case, to 1e-5)
@@ -131,8 +132,8 @@ def test_tape_refused_when_misused():
     with pytest.raises(rga.RgaError, match="tape"):
         rga.shade_gaussians(*args, campos, tape=small)
     tape = rga.shade_tape(50, s["he"], s["we"], "cuda")
-    with pytest.raises(rga.RgaError, match="FP32"):
-        rga.shade_gaussians(*args, campos, precision="bf16x3", tape=tape)
+    with pytest.raises(rga.RgaError, match="aligned"):
+        rga.shade_gaussians(*args, campos, tape=tape[1:])
 
 
 def test_renderer_frames_with_and_without_tape():
@@ -157,3 +158,65 @@ def test_renderer_frames_with_and_without_tape():
         ok, err = _close(g1[k], g2[k], 1e-5)
         print(f"  {k:8s} {err:.1e}", flush=True)
         assert ok, (k, err)
+
+
+@pytest.mark.parametrize("grid", [(16, 32, 16, 16), (16, 32, 16, 32), (6, 16, 6, 16)])
+def test_bf16x3_forward_tape(grid):
+    """The BF16X3 form's MFMA forward writes the same tape (its pairs in step
+    order; texel patches or not): its colours are unchanged by recording,
+    its counts are those of the FP32 walk up to directions within rounding
+    of the horizon, and the replay of its tape (the adjoint given one)
+    matches the FP32 form's replay and the FP64 oracle."""
+    he, we, hv, wv = grid
+    n = 500
+    print(f"[tape] bf16x3 grid={grid}", flush=True)
+    s = synth.micro_scene(47, n, 40, 48, he=he, we=we, hv=hv, wv=wv)
+    xo, no, _ = cpu.lbs_f32(s["skin"], s["jidx"], s["jw"], s["pos"], s["nrm"])
+    _, _, cnt = helpers.oracle_visibility(s)
+    campos = s["cam"].centre.astype(np.float32)
+    args = (dev(xo), dev(no), dev(s["albedo"]), dev(s["rough"]), dev(s["tint"]), dev(s["vidx"]),
+            dev(s["vw"]), dev(cnt), s["kv"], he, we, hv, wv, dev(s["env"]))
+    tb = rga.shade_tape(n, he, we, "cuda")
+    tf = rga.shade_tape(n, he, we, "cuda")
+    c0, f0 = rga.shade_gaussians(*args, campos, precision="bf16x3")
+    cb, fb = rga.shade_gaussians(*args, campos, precision="bf16x3", tape=tb)
+    assert torch.equal(c0, cb) and torch.equal(f0, fb)
+    cf, ff = rga.shade_gaussians(*args, campos, tape=tf)
+    assert torch.equal(ff, fb)
+    nb = host(tb[:4 * n].view(torch.int32))
+    nf = host(tf[:4 * n].view(torch.int32))
+    dirs, _ = ref64.env_geometry(he, we)
+    nn = no.astype(np.float64) / np.linalg.norm(no, axis=0)
+    near = (np.abs(dirs.numpy() @ nn) < 1e-5).sum(0)
+    assert np.all(np.abs(nb - nf) <= near), np.abs(nb - nf).max()
+    # the pairs themselves: the same (direction, visibility) sets per Gaussian
+    K = he * we
+    pairs_b = host(tb[256 * ((4 * n + 255) // 256):].view(torch.int32)).reshape(n, K, 2)
+    pairs_f = host(tf[256 * ((4 * n + 255) // 256):].view(torch.int32)).reshape(n, K, 2)
+    for g in np.nonzero((nb == nf) & (nb > 0))[0][:50]:
+        a = sorted(map(tuple, pairs_b[g, :nb[g]]))
+        b = sorted(map(tuple, pairs_f[g, :nf[g]]))
+        assert a == b, g
+    w = np.random.default_rng(5).uniform(-1, 1, (3, n)).astype(np.float32)
+    gb = rga.shade_gaussians_backward(*args, campos, cb, fb, dev(w), precision="bf16x3", tape=tb)
+    gf = rga.shade_gaussians_backward(*args, campos, cf, ff, dev(w), tape=tf)
+    for k in ("dx", "dn", "dalbedo", "drough", "dtint", "denv"):
+        ok, err = _close(gb[k], gf[k], 1e-4)
+        print(f"  {k:8s} replay of the BF16X3 tape vs the FP32 tape {err:.1e}", flush=True)
+        assert ok, (k, err)
+    c64 = campos.astype(np.float64)
+    ecol, _ = ref64.shade(ref64.t64(xo), ref64.t64(no), s["albedo"], s["rough"], s["tint"],
+                          s["vidx"], s["vw"], cnt, s["kv"], he, we, hv, wv, s["env"], c64,
+                          host(fb).astype(np.uint8))
+    w[np.abs(ecol.numpy() - 0.04045) <= 2e-5 * 0.04045] = 0.0
+    gb = rga.shade_gaussians_backward(*args, campos, cb, fb, dev(w), precision="bf16x3", tape=tb)
+    leaves = {k: torch.tensor(np.asarray(v, np.float64), requires_grad=True)
+              for k, v in (("x", xo), ("n", no), ("albedo", s["albedo"]), ("rough", s["rough"]),
+                           ("tint", s["tint"]), ("env", s["env"]))}
+    e2, _ = ref64.shade(leaves["x"], leaves["n"], leaves["albedo"], leaves["rough"],
+                        leaves["tint"], s["vidx"], s["vw"], cnt, s["kv"], he, we, hv, wv,
+                        leaves["env"], c64, host(fb).astype(np.uint8))
+    (e2 * torch.tensor(w.astype(np.float64))).sum().backward()
+    for gk, lk in (("dx", "x"), ("dn", "n"), ("dalbedo", "albedo"), ("drough", "rough"),
+                   ("dtint", "tint"), ("denv", "env")):
+        helpers.check_grad(lk, host(gb[gk]), leaves[lk].grad.numpy())

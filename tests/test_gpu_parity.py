@@ -433,28 +433,37 @@ def test_splat_capacity_overflow_is_reported():
     assert torch.isfinite(img2).all()
 
 
-def test_renderer_refuses_stale_backward_and_overflow():
+@pytest.mark.parametrize("overlap", [False, True])
+def test_renderer_refuses_stale_backward_and_overflow(overlap):
     """A backward whose forward's splat state has been overwritten by a later
     render on the same Renderer is refused; the autograd path raises on an
-    overflowed frame, and train_step re-renders it in a larger workspace."""
+    overflowed frame, and train_step re-renders it in a larger workspace --
+    with the splats binned after the shading or on the second stream."""
     s = scene(1)
     d = render.upload(s)
-    R = render.Renderer(s, d, capacity=64 * s["n"])
+    R = render.Renderer(s, d, capacity=64 * s["n"], overlap=overlap)
     p = {k: d[k] for k in render.TRAINABLE}
     count = R.visibility()
     _, _, ctx1 = R.forward(p, count)
     R.render_map(p, count, "albedo")
     with pytest.raises(rga.RgaError, match="overwritten"):
         R.backward(p, ctx1, torch.zeros(3, s["height"], s["width"], device="cuda"))
-    R2 = render.Renderer(s, d, capacity=16)
+    R2 = render.Renderer(s, d, capacity=16, overlap=overlap)
     q = {k: v.clone().requires_grad_(True) for k, v in p.items()}
     img, _ = render.render(R2, count, q)
     with pytest.raises(rga.RgaError, match="overflowed"):
         img.sum().backward()
-    R3 = render.Renderer(s, d, capacity=16)
+    R3 = render.Renderer(s, d, capacity=16, overlap=overlap)
     loss, g = R3.train_step(p, count, d["target"])
     assert R3.ws.capacity > 16 and torch.isfinite(loss).all()
     assert all(torch.isfinite(t).all() for t in g.values())
+    # the frame computing its own visibility overflows and recovers the same way
+    R4 = render.Renderer(s, d, capacity=16, overlap=overlap)
+    loss4, g4 = R4.train_step(p, None, d["target"])
+    assert R4.ws.capacity > 16 and torch.equal(loss4, loss)
+    for k in g:
+        a4, a3 = g4[k].cpu().numpy(), g[k].cpu().numpy()
+        assert np.abs(a4 - a3).max() <= 1e-5 * (np.abs(a3).max() + 1e-30), k
 
 
 # ------------------------------------------------------------------ gradients

@@ -54,6 +54,8 @@ typedef struct rga_camera {
 } rga_camera;
 
 const char* rga_last_error(void);
+/* 3: splat_bin / splat_blend / back_face; splat_backward reads `color`;
+ * the live-pair tape in both shading forms.                                */
 int rga_abi_version(void);
 
 /* ------------------------------------------------------------------------

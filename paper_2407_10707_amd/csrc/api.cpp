@@ -101,7 +101,7 @@ extern "C" {
 
 const char* rga_last_error(void) { return rga::g_err; }
 
-int rga_abi_version(void) { return 2; }
+int rga_abi_version(void) { return 3; }
 
 int rga_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(rga::g_mu);

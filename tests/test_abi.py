@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_abi_version_and_error_string():
     L = rga.lib()
-    assert L.rga_abi_version() == 2
+    assert L.rga_abi_version() == 3
     assert isinstance(L.rga_last_error(), bytes)
 
 

@@ -45,6 +45,7 @@ constexpr float kHalfNegLog2e = -0.72134752f;   // -log2(e) / 2
 constexpr float kInvHalfLog2e = 1.38629436f;    // 2 / log2(e) = 2 ln 2
 constexpr int kDigitBits = 11;   // radix digit width of the tile sort: 2048 bins
 constexpr int kRadix = 1 << kDigitBits;
+constexpr int kWideBits = 12;    // one tile pass of 4096 bins for 2049 .. 4096 tiles
 constexpr int kDepthBits = 11;   // digit width of the depth sort: 3 passes over 32-bit keys
 constexpr int kDepthPasses = (32 + kDepthBits - 1) / kDepthBits;
 
@@ -53,6 +54,7 @@ struct Layout {
   size_t tk0, tv0, tk1, tv1, ranges, hist, binoff, bintot, bsum, boff, count, queue, grad;
   size_t item_off, item_tile, item_chunk, item_sub, cstate, sstate, sub_item, total;
   int tiles_x, tiles_y, nb_n, nb_cap, nb_max, tile_passes;
+  int tile_bits;   // digit width of a one-pass tile sort: kDigitBits or kWideBits
   int64_t max_items, max_subs;
 };
 
@@ -66,7 +68,8 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.nb_max = L.nb_n > L.nb_cap ? L.nb_n : L.nb_cap;
   int bits = 0;
   while ((1ll << bits) < tiles) ++bits;
-  L.tile_passes = bits <= kDigitBits ? 1 : (bits <= 2 * kDigitBits ? 2 : 3);
+  L.tile_passes = bits <= kWideBits ? 1 : (bits <= 2 * kDigitBits ? 2 : 3);
+  L.tile_bits = (bits > kDigitBits && bits <= kWideBits) ? kWideBits : kDigitBits;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -92,9 +95,9 @@ Layout make_layout(int n, int width, int height, int64_t cap) {
   L.tk1 = take(C * 4);
   L.tv1 = take(C * 4);
   L.ranges = take((size_t)tiles * 8);
-  L.hist = take((size_t)L.nb_max * kRadix * 4);
-  L.binoff = take((size_t)L.nb_max * kRadix * 4);
-  L.bintot = take(kRadix * 4);
+  L.hist = take((size_t)L.nb_max * (1 << kWideBits) * 4);
+  L.binoff = take((size_t)L.nb_max * (1 << kWideBits) * 4);
+  L.bintot = take((1 << kWideBits) * 4);
   L.bsum = take((size_t)L.nb_n * 4);
   L.boff = take((size_t)L.nb_n * 4);
   L.count = take(32);   // int64 [0] = D, [1] = work items, [3] = adjoint items; uint32 [4] = scan ticket
@@ -1668,7 +1671,21 @@ extern "C" int splat_bin(void* stream, int n, const rga_camera* cam, const float
     const ItemOut items{at<uint32_t>(ws, L.item_off), at<uint32_t>(ws, L.item_tile),
                         at<uint32_t>(ws, L.item_chunk), at<uint32_t>(ws, L.item_sub), L.max_items,
                         cnt};
-    for (int pass = 0; pass < L.tile_passes; ++pass) {
+    if (L.tile_passes == 1 && L.tile_bits == kWideBits) {
+      // 2049 .. 4096 tiles: one pass of 12-bit digits, whose scatter also
+      // writes the tile ranges and the work items
+      constexpr int kWide = 1 << kWideBits;
+      RGA_LAUNCH("radix_upsweep", (radix_upsweep<kItemsD, kWideBits>), dim3(L.nb_cap),
+                 dim3(kRadixThreads), 0, s, tk0, (const int64_t*)cnt, (int64_t)0, capacity, 0, hist);
+      RGA_LAUNCH("radix_binscan", radix_binscan<kWideBits>, dim3(kWide / 8), dim3(256), 0, s, hist,
+                 L.nb_cap, (const int64_t*)cnt, (int64_t)0, capacity, kBlockD, binoff, bintot);
+      RGA_LAUNCH("radix_downsweep", (radix_downsweep<kItemsD, kWideBits>), dim3(L.nb_cap),
+                 dim3(kRadixThreads), 0, s, tk0, tv0, tk1, tv1, (const int64_t*)cnt, (int64_t)0,
+                 capacity, 0, binoff, bintot, ranges, (int)tiles, items);
+      uint32_t* t = tk0; tk0 = tk1; tk1 = t;
+      t = tv0; tv0 = tv1; tv1 = t;
+    }
+    for (int pass = 0; pass < L.tile_passes && L.tile_bits == kDigitBits; ++pass) {
       const int shift = kDigitBits * pass;
       RGA_LAUNCH("radix_upsweep", (radix_upsweep<kItemsD, kDigitBits>), dim3(L.nb_cap), dim3(kRadixThreads), 0, s, tk0,
                  (const int64_t*)cnt, (int64_t)0, capacity, shift, hist);

@@ -235,15 +235,25 @@ def _splat_case(s, color):
     return xo, Ao, front
 
 
-@pytest.mark.parametrize("name", list(_scenes()))
+def _tile_scenes():
+    """Image sizes at the tile sort's pass boundaries: 2048 tiles (one pass of
+    11-bit digits), 2080 and 4096 (one pass of 12-bit digits), 4160 (two
+    passes, then the tile-range and work-item launches)."""
+    return {f"tiles_{h // 16 * ((w + 15) // 16)}": (lambda h=h, w=w: synth.micro_scene(
+        21, 3000, h, w, log_scale_mean=-3.0)) for h, w in ((512, 1024), (512, 1040),
+                                                           (1024, 1024), (1024, 1040))}
+
+
+@pytest.mark.parametrize("name", list(_scenes()) + list(_tile_scenes()))
 def test_splat_forward_parity(name):
     print(f"[splat] {name}", flush=True)
-    s = _scenes()[name]()
+    s = {**_scenes(), **_tile_scenes()}[name]()
     rng = np.random.default_rng(1)
     col = rng.random((3, s["n"])).astype(np.float32)
     xo, Ao, front = _splat_case(s, col)
     cam = s["cam"]
-    ws = rga.SplatWorkspace(s["n"], cam.width, cam.height, 64 * s["n"] + 1024, "cuda")
+    # room for every (tile, splat) pair: the 1024^2 scenes reach about 107 per Gaussian
+    ws = rga.SplatWorkspace(s["n"], cam.width, cam.height, 160 * s["n"] + 1024, "cuda")
     img, T = rga.splat_forward(cam, dev(xo), dev(Ao), dev(s["quat"]), dev(s["log_s"]),
                                dev(s["opac"]), dev(col), dev(front), ws)
     pre = cpu.splat_preprocess(cam, xo, Ao, s["quat"], s["log_s"], s["opac"], front)
@@ -251,6 +261,7 @@ def test_splat_forward_parity(name):
     eimg, eT, margin = cpu.composite_tiles(cam, ranges, vals, pre, s["opac"], col)
     D = ws.count()
     assert D == len(keys)
+    assert D <= ws.capacity, "workspace too small for this scene's lists"
     st = ws.state()
     n = s["n"]
 

@@ -1064,16 +1064,29 @@ blend_restart_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ra
   const int64_t nitems = min(counters[1], max_items);
   for (int b = blockIdx.x; b < nitems; b += gridDim.x) {
   __syncthreads();                        // the previous item's records are done
-  if (item_chunk[b] == 0) continue;        // finished by the prefix pass
+  const int j = item_chunk[b], t = item_tile[b];
   const float* st = cstate + (size_t)b * 1024;
   const float code = st[768 + threadIdx.x];
+  if (j == 0) continue;                    // finished by the prefix pass
   const bool mine = code < 0.f && code >= -1.f;
   if (!__syncthreads_or(mine)) continue;
-  const int t = item_tile[b], j = item_chunk[b];
   int px, py;
   tile_pixel(t, TX, px, py);
   const int e0 = ranges[2 * t] + j * kChunk;
   const int cnt = min(kChunk, ranges[2 * t + 1] - e0);
+  // This pixel's colour before the chunk and its states at the sub-chunk
+  // boundaries, read while the records are staged.
+  float* sub = sstate + (size_t)b * (kSubs - 1) * 1024;
+  float B0 = 0.f, B1 = 0.f, B2 = 0.f, bq[kSubs - 1][4];
+  if (mine) {
+    B0 = st[threadIdx.x];
+    B1 = st[256 + threadIdx.x];
+    B2 = st[512 + threadIdx.x];
+#pragma unroll
+    for (int q = 0; q < kSubs - 1; ++q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bq[q][c] = sub[q * 1024 + c * 256 + threadIdx.x];
+  }
   if ((int)threadIdx.x < cnt) {
     const SplatRec R = load_rec(rec, color, n, sorted[e0 + threadIdx.x]);
     s0[threadIdx.x] = R.r0;
@@ -1084,24 +1097,25 @@ blend_restart_kernel(int W, int H, int TX, int n, const int32_t* __restrict__ ra
   if (!mine || !(px < W && py < H)) continue;
   const float fpx = (float)px + 0.5f, fpy = (float)py + 0.5f;
   const float Tin = -code;
-  const float B0 = st[threadIdx.x], B1 = st[256 + threadIdx.x], B2 = st[512 + threadIdx.x];
   float T = Tin, C0 = B0, C1 = B1, C2 = B2;
   bool stopped = false;
   // Skip the sub-chunks that cannot hold the stop (chunk pass not
   // saturated there and T_in * T_local >= 1e-4; T is monotone): start from
   // the product state at the last such boundary, and leave the absolute
   // states for the adjoint.
-  float* sub = sstate + (size_t)b * (kSubs - 1) * 1024;
   int m = 1;                              // next sub-chunk boundary to record
-  for (; m < kSubs && m * kSub < cnt; ++m) {
-    float* q = sub + (m - 1) * 1024;
-    const float Tr = q[768 + threadIdx.x];
-    if (Tr < 0.f || Tin * Tr < 1e-4f) break;
-    T = Tin * Tr;
-    C0 = fmaf(Tin, q[threadIdx.x], B0);
-    C1 = fmaf(Tin, q[256 + threadIdx.x], B1);
-    C2 = fmaf(Tin, q[512 + threadIdx.x], B2);
-    put_state(q, C0, C1, C2, T);
+  bool skip = true;
+#pragma unroll
+  for (int q = 1; q < kSubs; ++q) {
+    skip = skip && q * kSub < cnt && !(bq[q - 1][3] < 0.f || Tin * bq[q - 1][3] < 1e-4f);
+    if (skip) {
+      T = Tin * bq[q - 1][3];
+      C0 = fmaf(Tin, bq[q - 1][0], B0);
+      C1 = fmaf(Tin, bq[q - 1][1], B1);
+      C2 = fmaf(Tin, bq[q - 1][2], B2);
+      put_state(sub + (q - 1) * 1024, C0, C1, C2, T);
+      m = q + 1;
+    }
   }
   for (int k0 = (m - 1) * kSub; k0 < cnt && !stopped; k0 += 32) {
     if (k0 == m * kSub) put_state(sub + (m++ - 1) * 1024, C0, C1, C2, T);
